@@ -1,0 +1,283 @@
+"""Plain FP64 CPU oracle for the Lindblad master equation and the Monte-Carlo wave-function method.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP library: the integrator,
+right-hand sides, expectation values and random numbers live in ``qtoracle.c`` (plain loops,
+complex double), the superoperator in ``liouvillian.py`` (scipy Kronecker products) and the model
+operators in ``models.py``.  Each function names the passage of arXiv:2504.21440 it follows in
+its docstring or in the C source.
+
+Parity notes: every function here is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``
+against closed forms, brute-force matrix exponentials, order conditions or invariants.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qtoracle.c")
+_LIB = os.path.join(_HERE, "libqtoracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the C oracle with gcc (OpenMP over rows and trajectories)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("nnz", ctypes.c_int64),
+        ("indptr", ctypes.c_void_p),
+        ("indices", ctypes.c_void_p),
+        ("values", ctypes.c_void_p),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("abstol", ctypes.c_double),
+        ("reltol", ctypes.c_double),
+        ("max_steps", ctypes.c_int64),
+        ("h0", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_accept", ctypes.c_int64),
+        ("n_reject", ctypes.c_int64),
+        ("n_rhs", ctypes.c_int64),
+        ("n_jumps", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        _lib.or_mesolve.restype = ctypes.c_int32
+        _lib.or_mesolve.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, P, P, P, P]
+        _lib.or_mcsolve.restype = ctypes.c_int32
+        _lib.or_mcsolve.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, P,
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P, P, ctypes.c_int32, P, P,
+                                    P, P]
+        _lib.or_linear_solve.restype = ctypes.c_int32
+        _lib.or_linear_solve.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P, P, P, P]
+        _lib.or_linear_fixed.restype = None
+        _lib.or_linear_fixed.argtypes = [ctypes.c_int64, P, P, ctypes.c_double, ctypes.c_int64, P, P]
+        _lib.or_dp5_tableau.argtypes = [P, P, P, P]
+        _lib.or_lindblad_apply.argtypes = [P, ctypes.c_int32, P, P, P]
+        _lib.or_expect_dm.argtypes = [P, P, P]
+        _lib.or_expect_ket.argtypes = [P, P, P]
+        _lib.or_philox4x32_10.argtypes = [P, P, P]
+        _lib.or_uniform_from_words.restype = ctypes.c_double
+        _lib.or_uniform_from_words.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        _lib.or_traj_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, P, P]
+        _lib.or_ensemble_stats.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _OpPack:
+    """Keeps the numpy buffers of a list of CSR operators alive while C reads them."""
+
+    def __init__(self, ops):
+        self.keep = []
+        self.arr = (_CSR * max(1, len(ops)))()
+        for k, op in enumerate(ops):
+            op = sp.csr_matrix(op, dtype=complex)
+            op.sort_indices()
+            ip = np.ascontiguousarray(op.indptr, dtype=np.int64)
+            ix = np.ascontiguousarray(op.indices, dtype=np.int32)
+            vals = np.ascontiguousarray(op.data, dtype=np.complex128)
+            self.keep += [ip, ix, vals]
+            self.arr[k] = _CSR(op.shape[0], op.nnz, ip.ctypes.data, ix.ctypes.data, vals.ctypes.data)
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.arr, ctypes.c_void_p)
+
+
+def tableau():
+    """Dormand-Prince 5(4) coefficients (c, A, b, bhat) as used by the oracle integrator."""
+    lib = _load()
+    c = np.zeros(7)
+    a = np.zeros((7, 7))
+    b = np.zeros(7)
+    bh = np.zeros(7)
+    lib.or_dp5_tableau(_ptr(c), _ptr(a), _ptr(b), _ptr(bh))
+    return c, a, b, bh
+
+
+def opts(abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0):
+    return Opts(abstol, reltol, max_steps, h0)
+
+
+def linear_solve(M, y0, tlist, abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0):
+    """Adaptive DP5 integration of y' = M y with the oracle's controller and tstop policy."""
+    lib = _load()
+    M = np.ascontiguousarray(M, dtype=np.complex128)
+    y0 = np.ascontiguousarray(y0, dtype=np.complex128)
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    out = np.zeros((len(tl), len(y0)), dtype=np.complex128)
+    st = Stats()
+    o = opts(abstol, reltol, max_steps, h0)
+    rc = lib.or_linear_solve(len(y0), _ptr(M), _ptr(y0), len(tl), _ptr(tl), ctypes.byref(o), _ptr(out),
+                             ctypes.byref(st))
+    return out, st.as_dict(), rc
+
+
+def linear_fixed(M, y0, h, nsteps):
+    """Fixed-step DP5 on y' = M y: returns (y(nsteps*h), last embedded error vector)."""
+    lib = _load()
+    M = np.ascontiguousarray(M, dtype=np.complex128)
+    y0 = np.ascontiguousarray(y0, dtype=np.complex128)
+    y = np.zeros_like(y0)
+    e = np.zeros_like(y0)
+    lib.or_linear_fixed(len(y0), _ptr(M), _ptr(y0), float(h), int(nsteps), _ptr(y), _ptr(e))
+    return y, e
+
+
+def lindblad_apply(H, c_ops, rho):
+    """One application of the Lindblad right-hand side (Sec. 3.2) to a dense rho."""
+    lib = _load()
+    Hp = _OpPack([H])
+    Cp = _OpPack(c_ops)
+    rho = np.ascontiguousarray(rho, dtype=np.complex128)
+    out = np.zeros_like(rho)
+    lib.or_lindblad_apply(Hp.ptr, len(c_ops), Cp.ptr, _ptr(rho), _ptr(out))
+    return out
+
+
+def expect_dm(O, rho):
+    """Tr(O rho)."""
+    lib = _load()
+    Op = _OpPack([O])
+    rho = np.ascontiguousarray(rho, dtype=np.complex128)
+    out = np.zeros(2)
+    lib.or_expect_dm(Op.ptr, _ptr(rho), _ptr(out))
+    return complex(out[0], out[1])
+
+
+def expect_ket(O, psi):
+    """<psi|O|psi> / <psi|psi>."""
+    lib = _load()
+    Op = _OpPack([O])
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.zeros(2)
+    lib.or_expect_ket(Op.ptr, _ptr(psi), _ptr(out))
+    return complex(out[0], out[1])
+
+
+def mesolve(H, c_ops, rho0, tlist, e_ops, abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0,
+            want_final=False):
+    """Lindblad master equation (Sec. 3.2) integrated by the oracle's adaptive DP5.
+
+    rho0 may be a ket (turned into |psi><psi|) or a density matrix (used as given).
+    Returns (expect [ne][nt] complex, stats dict, status, rho_final or None)."""
+    lib = _load()
+    rho0 = np.asarray(rho0, dtype=np.complex128)
+    if rho0.ndim == 1:
+        rho0 = np.outer(rho0, rho0.conj())
+    rho0 = np.ascontiguousarray(rho0)
+    d = rho0.shape[0]
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    Hp = _OpPack([H])
+    Cp = _OpPack(c_ops)
+    Ep = _OpPack(e_ops)
+    ex = np.zeros((len(e_ops), len(tl)), dtype=np.complex128)
+    fin = np.zeros((d, d), dtype=np.complex128) if want_final else None
+    st = Stats()
+    o = opts(abstol, reltol, max_steps, h0)
+    rc = lib.or_mesolve(Hp.ptr, len(c_ops), Cp.ptr, _ptr(rho0), len(tl), _ptr(tl), len(e_ops), Ep.ptr,
+                        ctypes.byref(o), _ptr(ex), _ptr(fin) if want_final else None, ctypes.byref(st))
+    return ex, st.as_dict(), rc, fin
+
+
+def mcsolve(H, c_ops, psi0, tlist, e_ops, ntraj, seed, traj0=0, abstol=1e-8, reltol=1e-6,
+            max_steps=1_000_000, h0=0.0, max_jump_record=0):
+    """Monte-Carlo wave function (Sec. 3.3) with Philox-4x32-10 draws.
+
+    Returns a dict with per-trajectory expectations ``expect_tr`` [ntraj][ne][nt], ensemble ``mean``
+    [ne][nt] (complex), ``se`` [ne][nt] (standard error of the real part), ``njumps``, ``status``,
+    and optionally the first ``max_jump_record`` jump times and channels."""
+    lib = _load()
+    psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    Hp = _OpPack([H])
+    Cp = _OpPack(c_ops)
+    Ep = _OpPack(e_ops)
+    ne, nt = len(e_ops), len(tl)
+    ex = np.zeros((ntraj, ne, nt), dtype=np.complex128)
+    nj = np.zeros(ntraj, dtype=np.int64)
+    stt = np.zeros(ntraj, dtype=np.int32)
+    mj = int(max_jump_record)
+    jt = np.zeros((ntraj, max(mj, 1)))
+    jc = np.zeros((ntraj, max(mj, 1)), dtype=np.int32)
+    nrhs = ctypes.c_int64(0)
+    o = opts(abstol, reltol, max_steps, h0)
+    rc = lib.or_mcsolve(Hp.ptr, len(c_ops), Cp.ptr, _ptr(psi0), nt, _ptr(tl), ne, Ep.ptr, ctypes.byref(o),
+                        ctypes.c_uint64(seed), ctypes.c_uint64(traj0), ctypes.c_int64(ntraj), _ptr(ex), _ptr(nj), mj,
+                        _ptr(jt), _ptr(jc), _ptr(stt), ctypes.byref(nrhs))
+    mean = np.zeros((ne, nt), dtype=np.complex128)
+    se = np.zeros((ne, nt))
+    lib.or_ensemble_stats(ntraj, ne, nt, _ptr(ex), _ptr(mean), _ptr(se))
+    out = {"expect_tr": ex, "mean": mean, "se": se, "njumps": nj, "status": stt, "rc": rc,
+           "n_rhs": nrhs.value}
+    if mj:
+        out["jump_times"] = jt
+        out["jump_channels"] = jc
+    return out
+
+
+def ensemble_stats(expect_tr):
+    lib = _load()
+    ex = np.ascontiguousarray(expect_tr, dtype=np.complex128)
+    ntraj, ne, nt = ex.shape
+    mean = np.zeros((ne, nt), dtype=np.complex128)
+    se = np.zeros((ne, nt))
+    lib.or_ensemble_stats(ntraj, ne, nt, _ptr(ex), _ptr(mean), _ptr(se))
+    return mean, se
+
+
+def philox(ctr, key):
+    """Philox-4x32-10 block: four uint32 words."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform_from_words(w0, w1):
+    return _load().or_uniform_from_words(int(w0), int(w1))
+
+
+def traj_draw(seed, traj, event):
+    """The two uniforms a trajectory draws at an event (event 0: first threshold)."""
+    lib = _load()
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    lib.or_traj_draw(ctypes.c_uint64(seed), ctypes.c_uint64(traj), ctypes.c_uint32(event), ctypes.byref(a),
+                     ctypes.byref(b))
+    return a.value, b.value

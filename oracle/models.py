@@ -1,0 +1,84 @@
+"""Operators of the model systems, built independently for the oracle.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Conventions (arXiv:2504.21440, Sec. 2 and the constructor table of App. C):
+  * ``destroy(N)``: a|n> = sqrt(n)|n-1>, Fock basis 0..N-1.
+  * spin-1/2 basis: index 0 = "up" (sigma_z = +1, the excited state of Sec. 3.1),
+    index 1 = "down"; sigma_- = |down><up| lowers up to down.
+  * ``tensor`` is the Kronecker product with the first factor most significant.
+
+Model Hamiltonians follow the workloads this build measures:
+  * driven Kerr cavity (Sec. 6): H = Delta a^dag a + (U/2) a^dag a^dag a a + F (a + a^dag),
+    C = sqrt(kappa) a;
+  * open transverse-field Ising chain (Secs. 4 and 6):
+    H = J sum_i sz_i sz_{i+1} + h sum_i sx_i, C_i = sqrt(gamma) sm_i.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+
+def destroy(N):
+    return sp.diags(np.sqrt(np.arange(1, N, dtype=float)), 1, shape=(N, N), format="csr").astype(complex)
+
+
+def qeye(N):
+    return sp.identity(N, dtype=complex, format="csr")
+
+
+def sigmax():
+    return sp.csr_matrix(np.array([[0, 1], [1, 0]], dtype=complex))
+
+
+def sigmaz():
+    return sp.csr_matrix(np.array([[1, 0], [0, -1]], dtype=complex))
+
+
+def sigmam():
+    return sp.csr_matrix(np.array([[0, 0], [1, 0]], dtype=complex))
+
+
+def tensor(*ops):
+    out = ops[0]
+    for op in ops[1:]:
+        out = sp.kron(out, op, format="csr")
+    return sp.csr_matrix(out)
+
+
+def site_op(L, i, op):
+    """op acting on spin i (0-based, i = 0 most significant) of an L-spin chain."""
+    return tensor(*[op if k == i else qeye(2) for k in range(L)])
+
+
+def kerr(N, delta, U, F, kappa):
+    a = destroy(N)
+    ad = a.conj().T
+    H = delta * (ad @ a) + 0.5 * U * (ad @ ad @ a @ a) + F * (a + ad)
+    return sp.csr_matrix(H), [sp.csr_matrix(np.sqrt(kappa) * a)]
+
+
+def ising(L, J, h, gamma):
+    H = sp.csr_matrix((2 ** L, 2 ** L), dtype=complex)
+    for i in range(L - 1):
+        H = H + J * (site_op(L, i, sigmaz()) @ site_op(L, i + 1, sigmaz()))
+    for i in range(L):
+        H = H + h * site_op(L, i, sigmax())
+    c_ops = [sp.csr_matrix(np.sqrt(gamma) * site_op(L, i, sigmam())) for i in range(L)]
+    return sp.csr_matrix(H), c_ops
+
+
+def number(N):
+    a = destroy(N)
+    return sp.csr_matrix(a.conj().T @ a)
+
+
+def fock_dm(N, n):
+    rho = np.zeros((N, N), dtype=complex)
+    rho[n, n] = 1.0
+    return rho
+
+
+def all_up_ket(L):
+    psi = np.zeros(2 ** L, dtype=complex)
+    psi[0] = 1.0
+    return psi

@@ -1,0 +1,70 @@
+"""Writes the stored expected values under tests/golden/ by calling only the oracle.
+
+Run from the repository root:  python tests/golden/make_golden.py [name ...]
+Each file records the workload parameters, tolerances and the oracle's statistics beside the values.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from oracle import models as om  # noqa: E402
+import workloads  # noqa: E402
+
+OUT = os.path.dirname(os.path.abspath(__file__))
+
+
+def _write(name, meta, expect):
+    path = os.path.join(OUT, name + ".json")
+    meta = dict(meta)
+    meta["expect_re"] = np.asarray(expect).real.tolist()
+    meta["expect_im"] = np.asarray(expect).imag.tolist()
+    with open(path, "w") as f:
+        json.dump(meta, f)
+    print("wrote", path)
+
+
+def ising_me(L, h, gamma, t_end, nt, e_kind, abstol, reltol, name):
+    H, cs = om.ising(L, 1.0, h, gamma)
+    if e_kind == "sz_each":
+        e_ops = [om.site_op(L, i, om.sigmaz()) for i in range(L)]
+    else:
+        e_ops = [sum(om.site_op(L, i, om.sigmaz()) for i in range(L))]
+    tl = workloads.tlist(t_end, nt)
+    t0 = time.time()
+    ex, st, rc, _ = oracle.mesolve(H, cs, om.all_up_ket(L), tl, e_ops, abstol=abstol, reltol=reltol)
+    assert rc == 0, rc
+    _write(name, {"workload": "ising", "L": L, "J": 1.0, "h": h, "gamma": gamma, "t_end": t_end, "nt": nt,
+                  "e_ops": e_kind, "abstol": abstol, "reltol": reltol, "oracle_stats": st,
+                  "oracle_seconds": time.time() - t0, "source": "oracle.mesolve"}, ex)
+
+
+def kerr_me(U, abstol, reltol, name):
+    p = workloads.kerr_single(U=U)
+    N = p["N"]
+    H, cs = om.kerr(N, p["delta"], p["U"], p["F"], p["kappa"])
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    t0 = time.time()
+    ex, st, rc, _ = oracle.mesolve(H, cs, om.fock_dm(N, 0), tl, [om.number(N)], abstol=abstol, reltol=reltol)
+    assert rc == 0
+    _write(name, dict(p, abstol=abstol, reltol=reltol, oracle_stats=st, oracle_seconds=time.time() - t0,
+                      source="oracle.mesolve"), ex)
+
+
+JOBS = {
+    "kerr_n20_u05": lambda: kerr_me(0.5, 1e-8, 1e-6, "kerr_n20_u05"),
+    "ising_l8": lambda: ising_me(8, 0.7, 0.2, 10.0, 100, "sz_each", 1e-8, 1e-6, "ising_l8"),
+    "ising_l8_tight": lambda: ising_me(8, 0.7, 0.2, 10.0, 100, "sz_each", 1e-12, 1e-10, "ising_l8_tight"),
+    "ising_l10_me": lambda: ising_me(10, 1.0, 0.1, 10.0, 100, "sz_sum", 1e-8, 1e-6, "ising_l10_me"),
+}
+
+if __name__ == "__main__":
+    oracle.build()
+    for n in (sys.argv[1:] or list(JOBS)):
+        JOBS[n]()
