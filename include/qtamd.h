@@ -1,0 +1,219 @@
+/*
+ * qtamd.h -- C ABI of the MI355X (gfx950) Lindblad / quantum-jump solver library (libqtamd.so).
+ *
+ * The library integrates the Lindblad master equation (arXiv:2504.21440, Sec. 3.2,
+ * eq. eq-lindblad-master-equation, dissipator in its trace-preserving anticommutator form)
+ *
+ *     d rho/dt = L rho = -i[H, rho] + sum_k ( C_k rho C_k^dag - 1/2 {C_k^dag C_k, rho} )
+ *
+ * with an adaptive Dormand-Prince 5(4) scheme run entirely on the GPU (step control included),
+ * and its Monte-Carlo wave-function counterpart (Sec. 3.3): pure states evolved under
+ * H_eff = H - (i/2) sum_k C_k^dag C_k, a quantum jump when the squared norm falls to a uniform
+ * threshold, the channel drawn with P_k = <C_k^dag C_k> / sum_j <C_j^dag C_j>.
+ * Expectation values are taken at every point of tlist (Sec. 3.1, e_ops).
+ *
+ * Conventions used throughout
+ *  - Complex numbers are interleaved (re, im) pairs of double on the host.
+ *  - Matrices are d x d, row-major; vec(rho)[i*d + j] = rho_ij.
+ *  - Operators cross the boundary as host CSR (qt_csr) with int64 row pointers, int32 column
+ *    indices, complex128 values; indices in a row need not be sorted; duplicates are summed.
+ *  - Ownership: the caller owns every host array it passes; the library reads them during the
+ *    call only and never keeps a pointer.  Handles (qt_ctx, qt_liouv, qt_me_plan, qt_mc_plan,
+ *    qt_server) own their device memory until the matching *_destroy.  Arrays the library fills
+ *    into a qt_csr (qt_model_*) are released with qt_csr_free.
+ *  - Errors: every function returns a qt_status; nothing throws across the ABI.  On an error the
+ *    outputs are unspecified except qt_stats.status; qt_last_error() gives a message (per thread).
+ *  - Threads: one thread at a time per qt_ctx; different contexts are independent.
+ *  - Precision: QT_F64 computes everything in FP64.  QT_MIXED stores the Liouvillian, the states
+ *    and the Runge-Kutta stages in complex FP32 and applies them in FP32, while step-size control,
+ *    the error-norm reduction, trace renormalisation and expectation values stay FP64 on the GPU.
+ */
+#ifndef QTAMD_H
+#define QTAMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qt_status;
+#define QT_OK 0
+#define QT_EINVAL 1      /* malformed argument (shape, CSR, tlist not strictly increasing, ...) */
+#define QT_ENOMEM 2      /* device or pool memory exhausted / request larger than the pool     */
+#define QT_EDEVICE 3     /* HIP runtime error                                                  */
+#define QT_EMAXSTEPS 4   /* opts.max_steps reached before the last tlist point                */
+#define QT_EDTMIN 5      /* step size fell below 1e-14 max(1, |t|)                             */
+#define QT_ENONFINITE 6  /* non-finite error norm or state                                     */
+#define QT_EBUSY 7       /* server cannot admit the request now; try again after a step        */
+
+#define QT_F64 0
+#define QT_MIXED 1
+
+#define QT_FORM_CSR 0   /* sparse Liouvillian superoperator, applied by CSR SpMV          */
+#define QT_FORM_DENSE 1 /* dense operator form L(rho) = A rho + (A rho)^dag + sum C rho C^dag */
+
+typedef struct qt_ctx qt_ctx;
+typedef struct qt_liouv qt_liouv;
+typedef struct qt_me_plan qt_me_plan;
+typedef struct qt_mc_plan qt_mc_plan;
+typedef struct qt_server qt_server;
+
+/* Host CSR operator (square). */
+typedef struct {
+    int32_t rows;
+    int32_t cols;
+    int64_t nnz;
+    const int64_t *indptr;  /* rows + 1 */
+    const int32_t *indices; /* nnz */
+    const double *values;   /* 2 * nnz, interleaved re/im */
+} qt_csr;
+
+/* Integrator options.  Defaults (qt_opts_default): abstol 1e-8, reltol 1e-6, max_steps 1e6,
+ * h0 = 0 (automatic starting step), precision QT_F64, form QT_FORM_CSR, steps_per_launch 0
+ * (library default). */
+typedef struct {
+    double abstol;
+    double reltol;
+    int64_t max_steps;
+    double h0;
+    int32_t precision;
+    int32_t form;
+    int32_t steps_per_launch; /* RK steps recorded per graph replay (CSR form) */
+    int32_t reserved;
+} qt_opts;
+
+typedef struct {
+    int64_t n_accept;
+    int64_t n_reject;
+    int64_t n_rhs;     /* right-hand-side applications (per trajectory summed for mcsolve) */
+    int64_t n_jumps;
+    int32_t status;
+    int32_t reserved;
+    double device_ms;  /* wall time of the device-resident part of the call */
+} qt_stats;
+
+void qt_opts_default(qt_opts *o);
+const char *qt_last_error(void);
+const char *qt_version(void);
+
+/* Context: binds a HIP device and a stream (hipStream_t, may be NULL for the null stream). */
+qt_status qt_ctx_create(int32_t device, void *hip_stream, qt_ctx **out);
+qt_status qt_ctx_destroy(qt_ctx *ctx);
+
+/* Model operators (host CSR filled by the library; release each with qt_csr_free).
+ * Driven Kerr cavity (Sec. 6 benchmark family), Fock cutoff N:
+ *     H = delta a^dag a + (U/2) a^dag a^dag a a + F (a + a^dag),  c = sqrt(kappa) a.
+ * Open transverse-field Ising chain (Secs. 4, 6), L spins, spin 0 most significant,
+ * basis state 0 = up (sigma_z = +1), sigma_- = |down><up|:
+ *     H = J sum_i sz_i sz_{i+1} + h sum_i sx_i,  c_i = sqrt(gamma) sm_i  (c_ops has L entries). */
+qt_status qt_model_kerr(int32_t N, double delta, double U, double F, double kappa, qt_csr *H, qt_csr *c);
+qt_status qt_model_ising(int32_t L, double J, double h, double gamma, qt_csr *H, qt_csr *c_ops);
+void qt_csr_free(qt_csr *A);
+
+/* Liouvillian (Sec. 3.2; the precomputed-superoperator use of Sec. 5).
+ * form QT_FORM_CSR: assembles on the device, in FP64, the superoperator
+ *     L = A (x) I + I (x) conj(A) + sum_k C_k (x) conj(C_k),   A = -i H - 1/2 sum_k C_k^dag C_k,
+ * for the row-major vec, drops exact zeros, stores values as complex128 (QT_F64) or complex64
+ * (QT_MIXED) with int32 indices (nnz < 2^31).
+ * form QT_FORM_DENSE: stores A and the C_k as dense d x d matrices (d <= 128) for the batched
+ * MFMA right-hand side.  Errors: QT_EINVAL for mismatched sizes or malformed CSR. */
+qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const qt_csr *c_ops, int32_t form,
+                               int32_t precision, qt_liouv **out);
+/* d, stored non-zeros (CSR form; 0 for dense), device bytes held. */
+qt_status qt_liouv_info(const qt_liouv *L, int32_t *d, int64_t *nnz, int64_t *bytes);
+/* Copies the assembled CSR back to the host (values widened to complex128).  indptr: d*d + 1,
+ * indices and values: nnz from qt_liouv_info.  CSR form only. */
+qt_status qt_liouv_export(const qt_liouv *L, int64_t *indptr, int32_t *indices, double *values);
+qt_status qt_liouv_destroy(qt_liouv *L);
+
+/* One master-equation problem.  rho0 is a host d x d matrix (used as given, not normalised) or,
+ * with is_ket, a length-d ket turned into |psi><psi|.  tlist is strictly increasing; tlist[0] is
+ * the initial time and its expectation values are recorded.  e_ops are n_e host CSR operators. */
+typedef struct {
+    const qt_liouv *L;
+    const double *rho0;
+    int32_t is_ket;
+    int32_t n_t;
+    const double *tlist;
+    int32_t n_e;
+    const qt_csr *e_ops;
+} qt_me_problem;
+
+/* One-shot solve: expect_out [n_e][n_t] complex (host), rho_final d x d complex (host, nullable). */
+qt_status qt_mesolve(qt_ctx *ctx, const qt_me_problem *prob, const qt_opts *opts, double *expect_out,
+                     double *rho_final, qt_stats *stats);
+/* Many problems advanced together in the same launches (each with its own step size, accept /
+ * reject decisions and save times).  expect_out[i] is [n_e][n_t] of problem i. */
+qt_status qt_mesolve_batch(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts,
+                           double *const *expect_out, qt_stats *stats);
+
+/* Device-resident plans: create uploads every input once; run integrates all problems from their
+ * resident initial states to their resident expectation values with no host transfer beyond a
+ * status word; result copies one problem's outputs back.  run may be called repeatedly. */
+qt_status qt_me_plan_create(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts,
+                            qt_me_plan **out);
+qt_status qt_me_plan_run(qt_me_plan *plan);
+qt_status qt_me_plan_result(qt_me_plan *plan, int32_t i, double *expect_out, double *rho_final, qt_stats *stats);
+qt_status qt_me_plan_destroy(qt_me_plan *plan);
+
+/* Expectation value (Sec. 3.1 e_ops; App. C expect): out = Tr(O rho) for a device density
+ * matrix, or <psi|O|psi>/<psi|psi> for a device ket (is_ket), state stored complex128
+ * (QT_F64) or complex64 (QT_MIXED), accumulated in FP64.  out: one complex (host). */
+qt_status qt_expect(qt_ctx *ctx, int32_t d, const qt_csr *O, const void *dev_state, int32_t is_ket,
+                    int32_t precision, double *out);
+
+/* Monte-Carlo wave function (Sec. 3.3).  Trajectory j draws from Philox-4x32-10 keyed by seed
+ * with counter (j_lo, j_hi, event, 0): event 0 gives the first threshold, event m >= 1 the channel
+ * uniform of jump m and the threshold after it.  psi0 is normalised before use. */
+typedef struct {
+    const qt_csr *H;
+    int32_t n_c;
+    const qt_csr *c_ops;
+    const double *psi0;
+    int32_t n_t;
+    const double *tlist;
+    int32_t n_e;
+    const qt_csr *e_ops;
+    int64_t ntraj;
+    uint64_t seed;
+} qt_mc_problem;
+
+/* mean_out [n_e][n_t] complex; se_out [n_e][n_t] standard error of the real part (nullable);
+ * expect_tr [ntraj][n_e][n_t] complex (nullable); njumps [ntraj] (nullable); jump_times and
+ * jump_channels [ntraj][max_jump_record] (nullable when max_jump_record == 0). */
+qt_status qt_mcsolve(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, double *mean_out, double *se_out,
+                     double *expect_tr, int64_t *njumps, int32_t max_jump_record, double *jump_times,
+                     int32_t *jump_channels, qt_stats *stats);
+qt_status qt_mc_plan_create(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, int32_t max_jump_record,
+                            qt_mc_plan **out);
+qt_status qt_mc_plan_run(qt_mc_plan *plan);
+qt_status qt_mc_plan_result(qt_mc_plan *plan, double *mean_out, double *se_out, double *expect_tr, int64_t *njumps,
+                            double *jump_times, int32_t *jump_channels, qt_stats *stats);
+qt_status qt_mc_plan_destroy(qt_mc_plan *plan);
+
+/* Continuous-batching server.  Requests are admitted while their device footprint fits in the
+ * pool and a slot is free; admitted requests keep rho and solver state resident and are advanced
+ * together, epoch by epoch, with requests that arrived earlier.  submit returns QT_EBUSY when the
+ * request does not fit now (QT_ENOMEM if it can never fit).  step runs one epoch and retires
+ * finished requests; poll reports completion and copies results. */
+typedef struct {
+    int64_t pool_bytes;      /* device memory budget for resident requests */
+    int32_t max_slots;       /* resident requests at most */
+    int32_t steps_per_epoch; /* RK steps per request per epoch */
+    qt_opts opts;
+} qt_server_cfg;
+
+qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **out);
+/* The problem's L must stay alive until the request completes. */
+qt_status qt_server_submit(qt_server *srv, const qt_me_problem *prob, uint64_t *ticket);
+qt_status qt_server_step(qt_server *srv, int32_t *n_active, int32_t *n_finished);
+qt_status qt_server_poll(qt_server *srv, uint64_t ticket, int32_t *done, double *expect_out, qt_stats *stats);
+qt_status qt_server_footprint(const qt_server *srv, const qt_me_problem *prob, int64_t *bytes);
+qt_status qt_server_destroy(qt_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

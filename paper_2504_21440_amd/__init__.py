@@ -1,0 +1,432 @@
+"""Python binding of libqtamd: argument marshalling over the C ABI declared in include/qtamd.h.
+
+Every step of the solvers runs in the HIP library; this module only converts numpy / scipy inputs
+to the ABI's plain arrays and structs and raises on error statuses.  Importing it never falls back
+to anything else: if libqtamd.so is missing, :func:`lib` raises.
+
+Names follow the C ABI (arXiv:2504.21440 Sec. 3: ``mesolve``, ``mcsolve``, ``liouvillian``,
+``expect``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqtamd.so")
+
+QT_OK, QT_EINVAL, QT_ENOMEM, QT_EDEVICE, QT_EMAXSTEPS, QT_EDTMIN, QT_ENONFINITE, QT_EBUSY = range(8)
+F64, MIXED = 0, 1
+FORM_CSR, FORM_DENSE = 0, 1
+
+EXPORTED = [
+    "qt_opts_default", "qt_last_error", "qt_version", "qt_ctx_create", "qt_ctx_destroy", "qt_model_kerr",
+    "qt_model_ising", "qt_csr_free", "qt_liouvillian_build", "qt_liouv_info", "qt_liouv_export",
+    "qt_liouv_destroy", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
+    "qt_me_plan_result", "qt_me_plan_destroy", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
+    "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_server_create", "qt_server_submit", "qt_server_step",
+    "qt_server_poll", "qt_server_footprint", "qt_server_destroy",
+]
+
+
+class QtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qtamd status {code}: {msg}")
+        self.code = code
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p), ("values", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("abstol", ctypes.c_double), ("reltol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("h0", ctypes.c_double), ("precision", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_accept", ctypes.c_int64), ("n_reject", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
+                ("n_jumps", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class MeProblem(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_void_p), ("rho0", ctypes.c_void_p), ("is_ket", ctypes.c_int32),
+                ("n_t", ctypes.c_int32), ("tlist", ctypes.c_void_p), ("n_e", ctypes.c_int32),
+                ("e_ops", ctypes.c_void_p)]
+
+
+class McProblem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_void_p), ("n_c", ctypes.c_int32), ("c_ops", ctypes.c_void_p),
+                ("psi0", ctypes.c_void_p), ("n_t", ctypes.c_int32), ("tlist", ctypes.c_void_p),
+                ("n_e", ctypes.c_int32), ("e_ops", ctypes.c_void_p), ("ntraj", ctypes.c_int64),
+                ("seed", ctypes.c_uint64)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("steps_per_epoch", ctypes.c_int32),
+                ("opts", Opts)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libqtamd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2504_21440_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.qt_last_error.restype = ctypes.c_char_p
+        L.qt_version.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if not hasattr(L, name):
+                continue
+            if name not in ("qt_last_error", "qt_version", "qt_opts_default", "qt_csr_free"):
+                getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != QT_OK:
+        raise QtError(code, lib().qt_last_error().decode())
+    return code
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def opts(abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0, precision=F64, form=FORM_CSR, steps_per_launch=0):
+    return Opts(abstol, reltol, max_steps, h0, precision, form, steps_per_launch, 0)
+
+
+class _Ops:
+    """Host CSR operators marshalled into a qt_csr array (buffers kept alive by this object)."""
+
+    def __init__(self, ops):
+        import scipy.sparse as sp
+        self.keep = []
+        self.arr = (CSR * max(1, len(ops)))()
+        for k, op in enumerate(ops):
+            m = sp.csr_matrix(op, dtype=np.complex128)
+            ip = np.ascontiguousarray(m.indptr, dtype=np.int64)
+            ix = np.ascontiguousarray(m.indices, dtype=np.int32)
+            v = np.ascontiguousarray(m.data, dtype=np.complex128)
+            self.keep += [ip, ix, v]
+            self.arr[k] = CSR(m.shape[0], m.shape[1], m.nnz, ip.ctypes.data, ix.ctypes.data, v.ctypes.data)
+        self.n = len(ops)
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.arr, ctypes.c_void_p)
+
+
+def _csr_to_scipy(c):
+    import scipy.sparse as sp
+    n, nnz = c.rows, c.nnz
+    ip = np.ctypeslib.as_array(ctypes.cast(c.indptr, ctypes.POINTER(ctypes.c_int64)), (n + 1,)).copy()
+    ix = (np.ctypeslib.as_array(ctypes.cast(c.indices, ctypes.POINTER(ctypes.c_int32)), (nnz,)).copy()
+          if nnz else np.zeros(0, np.int32))
+    v = (np.ctypeslib.as_array(ctypes.cast(c.values, ctypes.POINTER(ctypes.c_double)), (2 * nnz,)).copy()
+         .view(np.complex128) if nnz else np.zeros(0, np.complex128))
+    lib().qt_csr_free(ctypes.byref(c))
+    return sp.csr_matrix((v, ix, ip), shape=(n, n))
+
+
+def model_kerr(N, delta, U, F, kappa):
+    """Driven Kerr cavity operators built by the library: (H, [c])."""
+    H, c = CSR(), CSR()
+    _check(lib().qt_model_kerr(N, ctypes.c_double(delta), ctypes.c_double(U), ctypes.c_double(F),
+                               ctypes.c_double(kappa), ctypes.byref(H), ctypes.byref(c)))
+    return _csr_to_scipy(H), [_csr_to_scipy(c)]
+
+
+def model_ising(L, J, h, gamma):
+    """Open transverse-field Ising chain operators built by the library: (H, [c_0..c_{L-1}])."""
+    H = CSR()
+    cs = (CSR * L)()
+    _check(lib().qt_model_ising(L, ctypes.c_double(J), ctypes.c_double(h), ctypes.c_double(gamma),
+                                ctypes.byref(H), cs))
+    return _csr_to_scipy(H), [_csr_to_scipy(cs[i]) for i in range(L)]
+
+
+class Context:
+    """A device and stream binding (qt_ctx).  stream: a HIP stream handle (int) or None."""
+
+    def __init__(self, device=0, stream=None):
+        self.h = ctypes.c_void_p()
+        _check(lib().qt_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().qt_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Liouvillian:
+    """qt_liouvillian_build: device Liouvillian (CSR superoperator or dense operator form)."""
+
+    def __init__(self, ctx, H, c_ops, form=FORM_CSR, precision=F64):
+        self.ctx = ctx
+        Hs = _Ops([H])
+        Cs = _Ops(c_ops)
+        self.h = ctypes.c_void_p()
+        _check(lib().qt_liouvillian_build(ctx.h, Hs.ptr, len(c_ops), Cs.ptr, form, precision, ctypes.byref(self.h)))
+        self.form, self.precision = form, precision
+
+    def info(self):
+        d, nnz, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().qt_liouv_info(self.h, ctypes.byref(d), ctypes.byref(nnz), ctypes.byref(b)))
+        return d.value, nnz.value, b.value
+
+    def export(self):
+        import scipy.sparse as sp
+        d, nnz, _ = self.info()
+        n = d * d
+        ip = np.zeros(n + 1, np.int64)
+        ix = np.zeros(max(1, nnz), np.int32)
+        v = np.zeros(max(1, nnz), np.complex128)
+        _check(lib().qt_liouv_export(self.h, _p(ip), _p(ix), _p(v)))
+        return sp.csr_matrix((v[:nnz], ix[:nnz], ip), shape=(n, n))
+
+    def close(self):
+        if self.h:
+            lib().qt_liouv_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _rho0_array(rho0):
+    r = np.ascontiguousarray(rho0, dtype=np.complex128)
+    return r, (1 if r.ndim == 1 else 0)
+
+
+class _MeProblems:
+    def __init__(self, problems):
+        self.keep = []
+        self.arr = (MeProblem * len(problems))()
+        self.meta = []
+        for i, (L, rho0, tlist, e_ops) in enumerate(problems):
+            r, is_ket = _rho0_array(rho0)
+            tl = np.ascontiguousarray(tlist, dtype=np.float64)
+            E = _Ops(e_ops)
+            self.keep += [r, tl, E]
+            self.arr[i] = MeProblem(L.h, r.ctypes.data, is_ket, len(tl), tl.ctypes.data, len(e_ops), E.ptr)
+            d = L.info()[0]
+            self.meta.append((d, len(tl), len(e_ops)))
+
+
+def mesolve(ctx, L, rho0, tlist, e_ops, options=None, want_final=False):
+    """qt_mesolve: returns (expect [n_e][n_t] complex, stats dict, rho_final or None)."""
+    P = _MeProblems([(L, rho0, tlist, e_ops)])
+    d, nt, ne = P.meta[0]
+    ex = np.zeros((max(ne, 1), nt), np.complex128)
+    fin = np.zeros((d, d), np.complex128) if want_final else None
+    st = Stats()
+    o = options or opts(precision=L.precision)
+    _check(lib().qt_mesolve(ctx.h, ctypes.byref(P.arr[0]), ctypes.byref(o), _p(ex), _p(fin), ctypes.byref(st)))
+    return ex[:ne], st.as_dict(), fin
+
+
+class MePlan:
+    """qt_me_plan_*: device-resident batch of master-equation problems."""
+
+    def __init__(self, ctx, problems, options=None):
+        self.P = _MeProblems(problems)
+        o = options or opts(precision=problems[0][0].precision)
+        self.h = ctypes.c_void_p()
+        _check(lib().qt_me_plan_create(ctx.h, len(problems), self.P.arr, ctypes.byref(o), ctypes.byref(self.h)))
+
+    def run(self):
+        _check(lib().qt_me_plan_run(self.h))
+
+    def result(self, i, want_final=False, check=True):
+        d, nt, ne = self.P.meta[i]
+        ex = np.zeros((max(ne, 1), nt), np.complex128)
+        fin = np.zeros((d, d), np.complex128) if want_final else None
+        st = Stats()
+        rc = lib().qt_me_plan_result(self.h, i, _p(ex), _p(fin), ctypes.byref(st))
+        if check:
+            _check(rc)
+        return ex[:ne], st.as_dict(), fin
+
+    def close(self):
+        if self.h:
+            lib().qt_me_plan_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mesolve_batch(ctx, problems, options=None):
+    """qt_mesolve_batch over (L, rho0, tlist, e_ops) tuples: list of (expect, stats)."""
+    P = _MeProblems(problems)
+    outs = [np.zeros((max(ne, 1), nt), np.complex128) for (d, nt, ne) in P.meta]
+    ptrs = (ctypes.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
+    sts = (Stats * len(outs))()
+    o = options or opts(precision=problems[0][0].precision)
+    _check(lib().qt_mesolve_batch(ctx.h, len(outs), P.arr, ctypes.byref(o), ptrs, sts))
+    return [(outs[i][:P.meta[i][2]], sts[i].as_dict()) for i in range(len(outs))]
+
+
+def expect(ctx, O, dev_state_ptr, d, is_ket=False, precision=F64):
+    """qt_expect on a device state (pointer as int): Tr(O rho) or <psi|O|psi>/<psi|psi>."""
+    E = _Ops([O])
+    out = np.zeros(2)
+    _check(lib().qt_expect(ctx.h, d, E.ptr, ctypes.c_void_p(dev_state_ptr), int(is_ket), precision, _p(out)))
+    return complex(out[0], out[1])
+
+
+class _McProblem:
+    def __init__(self, H, c_ops, psi0, tlist, e_ops, ntraj, seed):
+        self.H = _Ops([H])
+        self.C = _Ops(c_ops)
+        self.E = _Ops(e_ops)
+        self.psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+        self.tl = np.ascontiguousarray(tlist, dtype=np.float64)
+        self.s = McProblem(self.H.ptr.value, len(c_ops), self.C.ptr.value, self.psi0.ctypes.data, len(self.tl),
+                           self.tl.ctypes.data, len(e_ops), self.E.ptr.value, int(ntraj), int(seed))
+        self.ne, self.nt, self.ntraj = len(e_ops), len(self.tl), int(ntraj)
+
+
+def _mc_outputs(p, want_traj, max_jump_record):
+    mean = np.zeros((max(p.ne, 1), p.nt), np.complex128)
+    se = np.zeros((max(p.ne, 1), p.nt))
+    tr = np.zeros((p.ntraj, max(p.ne, 1), p.nt), np.complex128) if want_traj else None
+    nj = np.zeros(p.ntraj, np.int64)
+    mj = int(max_jump_record)
+    jt = np.zeros((p.ntraj, max(mj, 1))) if mj else None
+    jc = np.zeros((p.ntraj, max(mj, 1)), np.int32) if mj else None
+    return mean, se, tr, nj, mj, jt, jc
+
+
+def _mc_pack(p, mean, se, tr, nj, mj, jt, jc, st):
+    out = {"mean": mean[:p.ne], "se": se[:p.ne], "njumps": nj, "stats": st.as_dict()}
+    if tr is not None:
+        out["expect_tr"] = tr[:, :p.ne]
+    if mj:
+        out["jump_times"] = jt
+        out["jump_channels"] = jc
+    return out
+
+
+def mcsolve(ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, want_traj=False, max_jump_record=0):
+    """qt_mcsolve: dict with mean, se, njumps, stats and optionally per-trajectory data."""
+    p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed)
+    mean, se, tr, nj, mj, jt, jc = _mc_outputs(p, want_traj, max_jump_record)
+    st = Stats()
+    o = options or opts(precision=MIXED)
+    _check(lib().qt_mcsolve(ctx.h, ctypes.byref(p.s), ctypes.byref(o), _p(mean), _p(se), _p(tr), _p(nj), mj,
+                            _p(jt), _p(jc), ctypes.byref(st)))
+    return _mc_pack(p, mean, se, tr, nj, mj, jt, jc, st)
+
+
+class McPlan:
+    """qt_mc_plan_*: device-resident trajectory ensemble."""
+
+    def __init__(self, ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, max_jump_record=0):
+        self.p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed)
+        o = options or opts(precision=MIXED)
+        self.mj = int(max_jump_record)
+        self.h = ctypes.c_void_p()
+        _check(lib().qt_mc_plan_create(ctx.h, ctypes.byref(self.p.s), ctypes.byref(o), self.mj,
+                                       ctypes.byref(self.h)))
+
+    def run(self):
+        _check(lib().qt_mc_plan_run(self.h))
+
+    def result(self, want_traj=False):
+        mean, se, tr, nj, mj, jt, jc = _mc_outputs(self.p, want_traj, self.mj)
+        st = Stats()
+        _check(lib().qt_mc_plan_result(self.h, _p(mean), _p(se), _p(tr), _p(nj), _p(jt), _p(jc),
+                                       ctypes.byref(st)))
+        return _mc_pack(self.p, mean, se, tr, nj, mj, jt, jc, st)
+
+    def close(self):
+        if self.h:
+            lib().qt_mc_plan_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """qt_server_*: continuous-batching master-equation server."""
+
+    def __init__(self, ctx, pool_bytes=16 << 30, max_slots=256, steps_per_epoch=32, options=None):
+        o = options or opts(precision=MIXED)
+        self.cfg = ServerCfg(int(pool_bytes), int(max_slots), int(steps_per_epoch), o)
+        self.h = ctypes.c_void_p()
+        _check(lib().qt_server_create(ctx.h, ctypes.byref(self.cfg), ctypes.byref(self.h)))
+        self.pending = {}
+
+    def footprint(self, L, rho0, tlist, e_ops):
+        P = _MeProblems([(L, rho0, tlist, e_ops)])
+        b = ctypes.c_int64()
+        _check(lib().qt_server_footprint(self.h, ctypes.byref(P.arr[0]), ctypes.byref(b)))
+        return b.value
+
+    def submit(self, L, rho0, tlist, e_ops):
+        """Returns a ticket, or None when the request cannot be admitted now (QT_EBUSY)."""
+        P = _MeProblems([(L, rho0, tlist, e_ops)])
+        t = ctypes.c_uint64()
+        rc = lib().qt_server_submit(self.h, ctypes.byref(P.arr[0]), ctypes.byref(t))
+        if rc == QT_EBUSY:
+            return None
+        _check(rc)
+        self.pending[t.value] = P.meta[0]
+        return t.value
+
+    def step(self):
+        na, nf = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qt_server_step(self.h, ctypes.byref(na), ctypes.byref(nf)))
+        return na.value, nf.value
+
+    def poll(self, ticket):
+        d, nt, ne = self.pending[ticket]
+        ex = np.zeros((max(ne, 1), nt), np.complex128)
+        done = ctypes.c_int32()
+        st = Stats()
+        _check(lib().qt_server_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(done), _p(ex), ctypes.byref(st)))
+        if done.value:
+            del self.pending[ticket]
+            return ex[:ne], st.as_dict()
+        return None
+
+    def close(self):
+        if self.h:
+            lib().qt_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,180 @@
+// kernels_assembly.hip -- device assembly of the CSR Liouvillian superoperator.
+//
+// For the row-major vectorisation vec(rho)[i*d + j] = rho_ij one has vec(X rho Y) = (X kron Y^T)
+// vec(rho), so the master-equation generator (arXiv:2504.21440, Sec. 3.2) is
+//     L = A kron I + I kron conj(A) + sum_k C_k kron conj(C_k),   A = -i H - 1/2 sum_k C_k^dag C_k.
+// Row (i, j) of L therefore collects
+//     A_ik at column (k, j),  conj(A_jl) at column (i, l),  C_ip conj(C_jq) at column (p, q).
+// Each thread builds one row: it gathers these candidates, sorts them by column, sums duplicates
+// and drops exact zeros.  A count pass, a three-kernel scan and a fill pass produce CSR directly
+// in device memory, values computed in FP64 and stored in the solve precision.
+#include "qt_common.h"
+#include "qt_asm.h"
+
+namespace qt {
+
+constexpr int ASM_MAXC = 128;  // candidates per Liouvillian row handled by the device builder
+
+
+// Insert (c, v) into the sorted candidate list, summing a duplicate column.
+__device__ __forceinline__ void cand_insert(int *cols, double2 *vals, int &n, int c, double2 v, int *overflow)
+{
+    int pos = n;
+    while (pos > 0 && cols[pos - 1] > c) --pos;
+    if (pos > 0 && cols[pos - 1] == c) {
+        vals[pos - 1].x += v.x;
+        vals[pos - 1].y += v.y;
+        return;
+    }
+    if (n >= ASM_MAXC) {
+        *overflow = 1;
+        return;
+    }
+    for (int m = n; m > pos; --m) {
+        cols[m] = cols[m - 1];
+        vals[m] = vals[m - 1];
+    }
+    cols[pos] = c;
+    vals[pos] = v;
+    ++n;
+}
+
+__device__ int build_row(const AsmOps &op, int64_t r, int *cols, double2 *vals, int *overflow)
+{
+    const int d = op.d;
+    const int i = (int)(r / d), j = (int)(r % d);
+    int n = 0;
+    for (int p = op.arp[i]; p < op.arp[i + 1]; ++p) cand_insert(cols, vals, n, op.aci[p] * d + j, op.av[p], overflow);
+    for (int p = op.arp[j]; p < op.arp[j + 1]; ++p) {
+        const double2 a = op.av[p];
+        cand_insert(cols, vals, n, i * d + op.aci[p], make_double2(a.x, -a.y), overflow);
+    }
+    for (int k = 0; k < op.nc; ++k) {
+        const int32_t *rp = op.crp + (size_t)k * (d + 1);
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const double2 ci = op.cv[p];
+            for (int q = rp[j]; q < rp[j + 1]; ++q) {
+                const double2 cj = op.cv[q];
+                // C_ip * conj(C_jq)
+                const double2 v = make_double2(ci.x * cj.x + ci.y * cj.y, ci.y * cj.x - ci.x * cj.y);
+                cand_insert(cols, vals, n, op.cci[p] * d + op.cci[q], v, overflow);
+            }
+        }
+    }
+    return n;
+}
+
+__global__ __launch_bounds__(128) void k_asm_count(AsmOps op, int32_t *counts, int *flags)
+{
+    const int64_t n = (int64_t)op.d * op.d;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int cols[ASM_MAXC];
+    double2 vals[ASM_MAXC];
+    int ovf = 0;
+    const int m = build_row(op, r, cols, vals, &ovf);
+    int cnt = 0;
+    for (int k = 0; k < m; ++k) cnt += (vals[k].x != 0.0 || vals[k].y != 0.0);
+    counts[r] = cnt;
+    if (ovf) atomicOr(&flags[0], 1);
+}
+
+template <typename V>
+__global__ __launch_bounds__(128) void k_asm_fill(AsmOps op, const int32_t *rowptr, int32_t *col, V *val)
+{
+    const int64_t n = (int64_t)op.d * op.d;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int cols[ASM_MAXC];
+    double2 vals[ASM_MAXC];
+    int ovf = 0;
+    const int m = build_row(op, r, cols, vals, &ovf);
+    int o = rowptr[r];
+    for (int k = 0; k < m; ++k) {
+        if (vals[k].x == 0.0 && vals[k].y == 0.0) continue;
+        col[o] = cols[k];
+        val[o] = from_d2<V>(vals[k]);
+        ++o;
+    }
+}
+
+// ---- exclusive scan of int32 counts into int32 row pointers (total checked against 2^31) ----
+constexpr int SCAN_B = 1024;
+
+__global__ __launch_bounds__(SCAN_B) void k_scan_sums(const int32_t *counts, int64_t n, int64_t *bsum)
+{
+    __shared__ double scr[16];
+    const int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
+    const double v = (i < n) ? (double)counts[i] : 0.0;  // exact: partial sums < 2^53
+    const double s = block_sum(v, scr);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (int64_t)s;
+}
+
+__global__ __launch_bounds__(SCAN_B) void k_scan_top(int64_t *bsum, int64_t nb, int32_t *rowptr, int64_t n,
+                                                     int *flags)
+{
+    __shared__ int64_t sh[SCAN_B];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += SCAN_B) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = (i < nb) ? bsum[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < SCAN_B; off <<= 1) {
+            const int64_t t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;  // exclusive
+        const int64_t tot = sh[SCAN_B - 1];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        if (carry >= 2147483647LL) flags[1] = 1;
+        rowptr[n] = (int32_t)carry;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_B) void k_scan_apply(const int32_t *counts, int64_t n, const int64_t *boff,
+                                                       int32_t *rowptr)
+{
+    __shared__ int32_t sh[SCAN_B];
+    const int64_t i = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
+    const int32_t v = (i < n) ? counts[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_B; off <<= 1) {
+        const int32_t t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) rowptr[i] = (int32_t)(boff[blockIdx.x] + sh[threadIdx.x] - v);
+}
+
+// Host launchers ------------------------------------------------------------------------------
+void asm_launch_count(const AsmOps &op, int32_t *counts, int *flags, hipStream_t s)
+{
+    const int64_t n = (int64_t)op.d * op.d;
+    hipLaunchKernelGGL(k_asm_count, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, op, counts, flags);
+}
+
+void asm_launch_scan(const int32_t *counts, int64_t n, int64_t *bsum, int32_t *rowptr, int *flags, hipStream_t s)
+{
+    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SCAN_B), 0, s, counts, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_B), 0, s, bsum, nb, rowptr, n, flags);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_B), 0, s, counts, n, bsum, rowptr);
+}
+
+void asm_launch_fill(const AsmOps &op, const int32_t *rowptr, int32_t *col, void *val, bool f64, hipStream_t s)
+{
+    const int64_t n = (int64_t)op.d * op.d;
+    const dim3 g((unsigned)((n + 127) / 128)), t(128);
+    if (f64) hipLaunchKernelGGL(k_asm_fill<double2>, g, t, 0, s, op, rowptr, col, (double2 *)val);
+    else hipLaunchKernelGGL(k_asm_fill<float2>, g, t, 0, s, op, rowptr, col, (float2 *)val);
+}
+
+}  // namespace qt

@@ -1,0 +1,527 @@
+// kernels_csr.hip -- CSR-form master-equation solver kernels for gfx950.
+//
+// The right-hand side is the sparse Liouvillian superoperator applied to vec(rho)
+// (arXiv:2504.21440, Sec. 3.2, eq. eq-lindblad-master-equation): an HBM-bound complex CSR SpMV.
+// A Dormand-Prince 5(4) step is six SpMV launches (stages 2..7; stage 1 is the previous step's
+// stage 7).  Each SpMV carries the Runge-Kutta work of its row in its epilogue: the next stage
+// input (stages 2..5), the fifth-order solution (stage 6), or the weighted error contribution
+// (stage 7).  The last block of each instance to finish stage 7 reduces the error in FP64,
+// accepts or rejects, picks the next step size, lands on save times, renormalises the trace
+// (mixed precision) and records Tr(O rho) -- so the host never sits inside the step loop.
+//
+// Rows are split over LPR lanes (vector CSR): the LPR lanes of a group stride the row's
+// non-zeros with coalesced loads and combine with xor shuffles inside the 64-wide wavefront.
+#include "qt_common.h"
+#include "qt_csr.h"
+
+namespace qt {
+
+constexpr int CSR_THREADS = 256;
+enum : int32_t { PH_STEP = 0, PH_INIT1 = 1, PH_INIT0 = 2 };
+
+template <int LPR> struct CsrGeom {
+    static constexpr int RPW = 64 / LPR;
+    static constexpr int RPB = (CSR_THREADS / 64) * RPW;
+};
+
+template <typename V> __device__ __forceinline__ V shfl_xor_c(V v, int m)
+{
+    v.x = __shfl_xor(v.x, m, 64);
+    v.y = __shfl_xor(v.y, m, 64);
+    return v;
+}
+
+// Row sum  sum_k val[k] * x(col[k])  for the LPR-lane group owning `row`; every lane of the
+// group returns the full sum.  X is a functor returning the (stage) input at a column.
+template <typename V, int LPR, typename X>
+__device__ __forceinline__ V csr_row(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                     const V *__restrict__ val, int row, bool valid, int q, X x)
+{
+    V acc;
+    acc.x = 0;
+    acc.y = 0;
+    if (valid) {
+        const int s = rowptr[row], e = rowptr[row + 1];
+        for (int k = s + q; k < e; k += LPR) cfma(acc, val[k], x(col[k]));
+    }
+#pragma unroll
+    for (int m = LPR / 2; m >= 1; m >>= 1) acc = cadd(acc, shfl_xor_c(acc, m));
+    return acc;
+}
+
+// Block-wide deterministic reduction of two doubles; result in thread 0 (and all threads).
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *scr)
+{
+    a = block_sum(a, scr);
+    b = block_sum(b, scr);
+}
+
+// Arrive at the per-instance counter; returns true (in every thread) for the last block.
+__device__ __forceinline__ bool arrive_last(CsrCtl *C, int nblocks, int *flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned prev = atomicAdd(&C->arrive, 1u);
+        *flag = (prev == (unsigned)(nblocks - 1));
+    }
+    __syncthreads();
+    bool last = *flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Expectation values of the state Y (times `scale`) into expect[k][idx], FP64 accumulation:
+// Tr(O rho) = sum_{(i,j) in nnz(O)} O_ij rho_ji.
+template <typename V>
+__device__ void csr_record_expect(const CsrInst &I, const V *__restrict__ Y, double scale, int idx, double *scr)
+{
+    const int d = I.d;
+    for (int k = 0; k < I.ne; ++k) {
+        const int32_t *ep = I.eptr + (size_t)k * (d + 1);
+        double sr = 0.0, si = 0.0;
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            for (int p = ep[i]; p < ep[i + 1]; ++p) {
+                const double2 o = I.eval[p];
+                const double2 r = to_d2(Y[(size_t)I.ecol[p] * d + i]);
+                sr += o.x * r.x - o.y * r.y;
+                si += o.x * r.y + o.y * r.x;
+            }
+        }
+        block_sum2(sr, si, scr);
+        if (threadIdx.x == 0) I.expect[(size_t)k * I.nt + idx] = make_double2(sr * scale, si * scale);
+    }
+}
+
+template <typename V> __device__ double csr_trace(const CsrInst &I, const V *__restrict__ Y, double *scr)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < I.d; i += blockDim.x) s += (double)Y[(size_t)i * I.d + i].x;
+    return block_sum(s, scr);
+}
+
+__global__ void k_csr_reset(const CsrInst *__restrict__ insts, CsrCtl *__restrict__ ctls, int ninst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    CsrCtl c;
+    c.t = insts[i].tlist[0];
+    c.h = 0.0;
+    c.h_try = 0.0;
+    c.err_prev = 1e-4;
+    c.scale = 1.0;
+    c.tr0 = 1.0;
+    c.h0 = 0.0;
+    c.last_err = 0.0;
+    c.status = ST_RUNNING;
+    c.phase = PH_INIT0;
+    c.land = 0;
+    c.last_rejected = 0;
+    c.save_idx = 1;
+    c.parity = 0;
+    c.arrive = 0u;
+    c.pad = 0;
+    c.n_accept = c.n_reject = c.n_steps = c.n_rhs = 0;
+    ctls[i] = c;
+}
+
+// Starting step, first evaluation: k1 = L rho0, y <- rho0, d0 = |y|, d1 = |f(y)| (weighted RMS).
+template <typename T, int LPR>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__restrict__ insts,
+                                                           CsrCtl *__restrict__ ctls,
+                                                           const int32_t *__restrict__ blk_inst,
+                                                           const int32_t *__restrict__ blk_row0)
+{
+    using V = typename vec2<T>::type;
+    __shared__ double scr[16];
+    __shared__ int flag;
+    const int b = blockIdx.x;
+    const int ii = blk_inst[b];
+    const CsrInst &I = insts[ii];
+    CsrCtl *C = ctls + ii;
+    if (C->status != ST_RUNNING || C->phase != PH_INIT0) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane % LPR;
+    const int row = blk_row0[b] + w * CsrGeom<LPR>::RPW + lane / LPR;
+    const bool valid = row < I.n;
+    const V *__restrict__ x0 = (const V *)I.rho0;
+    const V acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q,
+                                  [&](int c) { return x0[c]; });
+    double sa = 0.0, sb = 0.0;
+    if (valid && q == 0) {
+        const V y = x0[row];
+        ((V *)I.K[0])[row] = acc;
+        ((V *)I.Y[0])[row] = y;
+        const double sc = I.atol + I.rtol * sqrt(abs2d(y));
+        sa = abs2d(y) / (sc * sc);
+        sb = abs2d(acc) / (sc * sc);
+    }
+    block_sum2(sa, sb, scr);
+    if (threadIdx.x == 0) {
+        I.partials[2 * (b - I.block0)] = sa;
+        I.partials[2 * (b - I.block0) + 1] = sb;
+    }
+    if (!arrive_last(C, I.nblocks, &flag)) return;
+    // ---- last block of this instance ----
+    double ta = 0.0, tb = 0.0;
+    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) {
+        ta += I.partials[2 * k];
+        tb += I.partials[2 * k + 1];
+    }
+    block_sum2(ta, tb, scr);
+    const double tr = csr_trace(I, x0, scr);
+    csr_record_expect(I, x0, 1.0, 0, scr);
+    if (threadIdx.x == 0) {
+        C->tr0 = tr;
+        C->n_rhs += 1;
+        C->arrive = 0u;
+        if (I.nt <= 1) {
+            C->status = ST_DONE;
+        } else {
+            const double d0 = sqrt(ta / I.n), d1 = sqrt(tb / I.n);
+            if (I.use_h0) {
+                C->h = I.h0;
+                C->phase = PH_STEP;
+                int32_t land;
+                C->h_try = clip_step(C->t, C->h, I.tlist[1], &land);
+                C->land = land;
+            } else {
+                C->h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+                C->last_err = d1;
+                C->phase = PH_INIT1;
+            }
+        }
+    }
+}
+
+// Starting step, second evaluation: d2 = |f(y + h0 f(y)) - f(y)| / h0; h = min(100 h0, h1).
+template <typename T, int LPR>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__restrict__ insts,
+                                                           CsrCtl *__restrict__ ctls,
+                                                           const int32_t *__restrict__ blk_inst,
+                                                           const int32_t *__restrict__ blk_row0)
+{
+    using V = typename vec2<T>::type;
+    __shared__ double scr[16];
+    __shared__ int flag;
+    const int b = blockIdx.x;
+    const int ii = blk_inst[b];
+    const CsrInst &I = insts[ii];
+    CsrCtl *C = ctls + ii;
+    if (C->status != ST_RUNNING || C->phase != PH_INIT1) return;
+    const double h0 = C->h0;
+    const T th0 = (T)h0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane % LPR;
+    const int row = blk_row0[b] + w * CsrGeom<LPR>::RPW + lane / LPR;
+    const bool valid = row < I.n;
+    const V *__restrict__ y = (const V *)I.Y[0];
+    const V *__restrict__ k1 = (const V *)I.K[0];
+    const V acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q, [&](int c) {
+        V v = y[c];
+        caxpy(v, th0, k1[c]);
+        return v;
+    });
+    double sa = 0.0, sb = 0.0;
+    if (valid && q == 0) {
+        const double2 yr = to_d2(y[row]);
+        const double2 a = to_d2(acc), f0 = to_d2(k1[row]);
+        const double sc = I.atol + I.rtol * sqrt(yr.x * yr.x + yr.y * yr.y);
+        const double dx = (a.x - f0.x) / h0, dy = (a.y - f0.y) / h0;
+        sa = (dx * dx + dy * dy) / (sc * sc);
+    }
+    block_sum2(sa, sb, scr);
+    if (threadIdx.x == 0) I.partials[2 * (b - I.block0)] = sa;
+    if (!arrive_last(C, I.nblocks, &flag)) return;
+    double ta = 0.0;
+    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) ta += I.partials[2 * k];
+    ta = block_sum(ta, scr);
+    if (threadIdx.x == 0) {
+        const double d2 = sqrt(ta / I.n), d1 = C->last_err;
+        const double m = fmax(d1, d2);
+        const double h1 = (m <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / m, 0.2);
+        C->h = fmin(100.0 * h0, h1);
+        C->phase = PH_STEP;
+        C->n_rhs += 1;
+        C->arrive = 0u;
+        int32_t land;
+        C->h_try = clip_step(C->t, C->h, I.tlist[1], &land);
+        C->land = land;
+    }
+}
+
+// One Runge-Kutta stage S (2..7) of a DP5 step for every running instance.
+template <typename T, int LPR, int S>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__restrict__ insts,
+                                                           CsrCtl *__restrict__ ctls,
+                                                           const int32_t *__restrict__ blk_inst,
+                                                           const int32_t *__restrict__ blk_row0)
+{
+    using V = typename vec2<T>::type;
+    __shared__ double scr[16];
+    __shared__ int flag;
+    const int b = blockIdx.x;
+    const int ii = blk_inst[b];
+    const CsrInst &I = insts[ii];
+    CsrCtl *C = ctls + ii;
+    if (C->status != ST_RUNNING || C->phase != PH_STEP) return;
+    const double h = C->h_try;
+    const int p = C->parity;
+    const T s = (T)C->scale;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane % LPR;
+    const int row = blk_row0[b] + w * CsrGeom<LPR>::RPW + lane / LPR;
+    const bool valid = row < I.n;
+    const V *__restrict__ y = (const V *)I.Y[p];
+    const V *__restrict__ k1 = (const V *)I.K[p];
+    V *__restrict__ ynew = (V *)I.Y[1 - p];
+    V *__restrict__ const *ks = (V *__restrict__ const *)I.ks;
+    const V *__restrict__ xin;
+    if (S == 2) xin = nullptr;
+    else if (S == 3 || S == 5) xin = (const V *)I.ys[0];
+    else if (S == 4 || S == 6) xin = (const V *)I.ys[1];
+    else xin = ynew;
+
+    V acc;
+    if (S == 2) {
+        const T c = (T)(h * DP5::a21);
+        acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q, [&](int cc) {
+            V v = y[cc];
+            caxpy(v, c, k1[cc]);
+            return cscale(v, s);
+        });
+    } else {
+        acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q,
+                              [&](int cc) { return xin[cc]; });
+    }
+
+    double e2 = 0.0;
+    if (valid && q == 0) {
+        const V yr = cscale(y[row], s);
+        const V k1r = cscale(k1[row], s);
+        if (S == 2) {
+            ks[0][row] = acc;
+            V o = yr;
+            caxpy(o, (T)(h * DP5::a31), k1r);
+            caxpy(o, (T)(h * DP5::a32), acc);
+            ((V *)I.ys[0])[row] = o;
+        } else if (S == 3) {
+            ks[1][row] = acc;
+            V o = yr;
+            caxpy(o, (T)(h * DP5::a41), k1r);
+            caxpy(o, (T)(h * DP5::a42), ks[0][row]);
+            caxpy(o, (T)(h * DP5::a43), acc);
+            ((V *)I.ys[1])[row] = o;
+        } else if (S == 4) {
+            ks[2][row] = acc;
+            V o = yr;
+            caxpy(o, (T)(h * DP5::a51), k1r);
+            caxpy(o, (T)(h * DP5::a52), ks[0][row]);
+            caxpy(o, (T)(h * DP5::a53), ks[1][row]);
+            caxpy(o, (T)(h * DP5::a54), acc);
+            ((V *)I.ys[0])[row] = o;
+        } else if (S == 5) {
+            ks[3][row] = acc;
+            V o = yr;
+            caxpy(o, (T)(h * DP5::a61), k1r);
+            caxpy(o, (T)(h * DP5::a62), ks[0][row]);
+            caxpy(o, (T)(h * DP5::a63), ks[1][row]);
+            caxpy(o, (T)(h * DP5::a64), ks[2][row]);
+            caxpy(o, (T)(h * DP5::a65), acc);
+            ((V *)I.ys[1])[row] = o;
+        } else if (S == 6) {
+            ks[4][row] = acc;
+            V o = yr;
+            caxpy(o, (T)(h * DP5::b1), k1r);
+            caxpy(o, (T)(h * DP5::b3), ks[1][row]);
+            caxpy(o, (T)(h * DP5::b4), ks[2][row]);
+            caxpy(o, (T)(h * DP5::b5), ks[3][row]);
+            caxpy(o, (T)(h * DP5::b6), acc);
+            ynew[row] = o;
+        } else {
+            ((V *)I.K[1 - p])[row] = acc;
+            // error estimate e = h sum_j (b_j - bhat_j) k_j in FP64
+            double2 e = make_double2(0.0, 0.0);
+            caxpy(e, h * DP5::e1, to_d2(k1r));
+            caxpy(e, h * DP5::e3, to_d2(ks[1][row]));
+            caxpy(e, h * DP5::e4, to_d2(ks[2][row]));
+            caxpy(e, h * DP5::e5, to_d2(ks[3][row]));
+            caxpy(e, h * DP5::e6, to_d2(ks[4][row]));
+            caxpy(e, h * DP5::e7, to_d2(acc));
+            const double my = sqrt(abs2d(yr)), mn = sqrt(abs2d(ynew[row]));
+            const double sc = I.atol + I.rtol * fmax(my, mn);
+            e2 = (e.x * e.x + e.y * e.y) / (sc * sc);
+        }
+    }
+    if (S != 7) return;
+
+    // ---- stage 7: error reduction and step control ----
+    e2 = block_sum(e2, scr);
+    if (threadIdx.x == 0) I.partials[2 * (b - I.block0)] = e2;
+    if (!arrive_last(C, I.nblocks, &flag)) return;
+    double tot = 0.0;
+    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) tot += I.partials[2 * k];
+    tot = block_sum(tot, scr);
+    const double err = sqrt(tot / I.n);
+    const bool finite = isfinite(err);
+    const bool accept = finite && err <= 1.0;
+    const int land = C->land;
+    const int sidx = C->save_idx;
+    double scale_new = 1.0;
+    if (accept) {
+        if (I.renorm) {
+            const double tr = csr_trace(I, (const V *)ynew, scr);
+            scale_new = C->tr0 / tr;
+        }
+        if (land) csr_record_expect(I, (const V *)ynew, scale_new, sidx, scr);
+    }
+    if (threadIdx.x == 0) {
+        C->n_steps += 1;
+        C->n_rhs += 6;
+        C->arrive = 0u;
+        if (!finite) {
+            C->status = 6;  // QT_ENONFINITE
+        } else if (accept) {
+            C->n_accept += 1;
+            C->t = land ? I.tlist[sidx] : C->t + h;
+            C->parity = 1 - p;
+            double hn = h * pi_factor(err, C->err_prev);
+            if (C->last_rejected && hn > h) hn = h;
+            C->h = hn;
+            C->err_prev = fmax(err, 1e-4);
+            C->last_rejected = 0;
+            C->scale = scale_new;
+            if (land) {
+                C->save_idx = sidx + 1;
+                if (sidx + 1 >= I.nt) C->status = ST_DONE;
+            }
+        } else {
+            C->n_reject += 1;
+            C->h = h * reject_factor(err);
+            C->last_rejected = 1;
+        }
+        C->last_err = err;
+        if (C->status == ST_RUNNING) {
+            if (C->n_steps >= I.max_steps) {
+                C->status = 4;  // QT_EMAXSTEPS
+            } else if (C->h < 1e-14 * fmax(1.0, fabs(C->t))) {
+                C->status = 5;  // QT_EDTMIN
+            } else {
+                int32_t l2;
+                C->h_try = clip_step(C->t, C->h, I.tlist[C->save_idx], &l2);
+                C->land = l2;
+            }
+        }
+    }
+}
+
+// ---- standalone expectation value (qt_expect) ----
+template <typename T>
+__global__ __launch_bounds__(256) void k_expect(int d, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                const double2 *__restrict__ v, const void *state, int is_ket,
+                                                double2 *out)
+{
+    using V = typename vec2<T>::type;
+    __shared__ double scr[16];
+    const V *__restrict__ st = (const V *)state;
+    double sr = 0.0, si = 0.0, nn = 0.0;
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        double rr = 0.0, ri = 0.0;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const double2 o = v[p];
+            const double2 x = to_d2(is_ket ? st[ci[p]] : st[(size_t)ci[p] * d + i]);
+            rr += o.x * x.x - o.y * x.y;
+            ri += o.x * x.y + o.y * x.x;
+        }
+        if (is_ket) {
+            const double2 c = to_d2(st[i]);  // conj(psi_i) * (O psi)_i
+            sr += c.x * rr + c.y * ri;
+            si += c.x * ri - c.y * rr;
+            nn += c.x * c.x + c.y * c.y;
+        } else {
+            sr += rr;
+            si += ri;
+        }
+    }
+    sr = block_sum(sr, scr);
+    si = block_sum(si, scr);
+    nn = block_sum(nn, scr);
+    if (threadIdx.x == 0) out[0] = is_ket ? make_double2(sr / nn, si / nn) : make_double2(sr, si);
+}
+
+}  // namespace qt
+
+// ---------------------------------------------------------------------------------------------
+// Host-side launchers (called from the runtime in qtamd_runtime.cpp)
+// ---------------------------------------------------------------------------------------------
+namespace qt {
+
+int csr_rows_per_block(int lpr) { return (CSR_THREADS / 64) * (64 / lpr); }
+
+template <typename T, int LPR>
+static void launch_init_t(int which, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                          const int32_t *br, hipStream_t s)
+{
+    if (which == 0)
+        hipLaunchKernelGGL((k_csr_init0<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+    else
+        hipLaunchKernelGGL((k_csr_init1<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+}
+
+template <typename T, int LPR>
+static void launch_step_t(int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi, const int32_t *br,
+                          hipStream_t s)
+{
+    dim3 g(nblk), t(CSR_THREADS);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 2>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 3>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 4>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 5>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 6>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 7>), g, t, 0, s, insts, ctls, bi, br);
+}
+
+#define QT_LPR_DISPATCH(LPRV, CALL) \
+    switch (LPRV) {                 \
+    case 2: CALL(2); break;         \
+    case 4: CALL(4); break;         \
+    case 8: CALL(8); break;         \
+    case 16: CALL(16); break;       \
+    default: CALL(8); break;        \
+    }
+
+void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_csr_reset, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ctls, ninst);
+}
+
+void csr_launch_init(int which, bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                     const int32_t *br, hipStream_t s)
+{
+#define QT_CALL(L)                                                         \
+    if (f64) launch_init_t<double, L>(which, nblk, insts, ctls, bi, br, s); \
+    else launch_init_t<float, L>(which, nblk, insts, ctls, bi, br, s);
+    QT_LPR_DISPATCH(lpr, QT_CALL)
+#undef QT_CALL
+}
+
+void csr_launch_step(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                     const int32_t *br, hipStream_t s)
+{
+#define QT_CALL(L)                                                   \
+    if (f64) launch_step_t<double, L>(nblk, insts, ctls, bi, br, s); \
+    else launch_step_t<float, L>(nblk, insts, ctls, bi, br, s);
+    QT_LPR_DISPATCH(lpr, QT_CALL)
+#undef QT_CALL
+}
+
+void launch_expect(bool f64, int d, const int32_t *rp, const int32_t *ci, const double2 *v, const void *state,
+                   int is_ket, double2 *out, hipStream_t s)
+{
+    if (f64)
+        hipLaunchKernelGGL(k_expect<double>, dim3(1), dim3(256), 0, s, d, rp, ci, v, state, is_ket, out);
+    else
+        hipLaunchKernelGGL(k_expect<float>, dim3(1), dim3(256), 0, s, d, rp, ci, v, state, is_ket, out);
+}
+
+}  // namespace qt

@@ -1,0 +1,607 @@
+// kernels_dense.hip -- dense operator-form master-equation solver on the gfx950 matrix cores.
+//
+// L(rho) = A rho + (A rho)^dag + sum_k C_k rho C_k^dag (arXiv:2504.21440, Sec. 3.2, with
+// A = -i H - 1/2 sum_k C_k^dag C_k) is three complex matrix products per collapse channel set.
+// Complex products run on real MFMA instructions (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64):
+//     Re += Ar Br - Ai Bi,   Im += Ar Bi + Ai Br.
+// LDS holds two NP x (NP+1) planar (re, im) matrices: B0, the Runge-Kutta stage input rho_s, and
+// B1, the scratch for C_k rho_s and then A rho_s.  The odd row stride keeps column walks free of
+// bank conflicts.  The operators stream from L2 (they are shared by every stage of the solve).
+// Each wave owns a fixed set of 16 x 16 output tiles; the Runge-Kutta stages of its elements live
+// in a per-instance global buffer laid out in the same tile order, so every epilogue access is a
+// contiguous per-lane vector.  Step control, error norm (FP64), trace renormalisation (FP64) and
+// expectation values (FP64) run inside the same workgroup, which owns the problem for the launch.
+#include <algorithm>
+#include <vector>
+
+#include "qt_common.h"
+#include "qt_dense.h"
+
+namespace qt {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    using acc = v4f;
+    static __device__ __forceinline__ acc mma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    using acc = v4d;
+    static __device__ __forceinline__ acc mma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// Row of the 16x16 output tile held in accumulator slot v by a lane with k4 = lane / 16 (the
+// column is lane % 16).  Measured on gfx950: the f32 16x16x4 instruction gives each lane four
+// consecutive rows (4 k4 + v); the f64 one interleaves them (k4 + 4 v).
+template <typename T> __device__ __forceinline__ int mrow(int k4, int v)
+{
+    return sizeof(T) == 8 ? k4 + 4 * v : 4 * k4 + v;
+}
+
+template <typename T, int NP, int WAVES> struct DenseGeom {
+    static constexpr int S = NP + 1;                       // LDS row stride
+    static constexpr int NT = NP / 16;                     // tiles per side
+    static constexpr int TT = NT * NT;                     // tiles
+    static constexpr int MAXT = (TT + WAVES - 1) / WAVES;  // tiles per wave (upper bound)
+    static constexpr int PLANE = NP * S;
+    static constexpr size_t LDS_BYTES = (size_t)4 * PLANE * sizeof(T);
+};
+
+// Complex product of one 16x16 tile: acc(I,J) += sum_k L(I*16+r, k) R(k, J*16+c).
+// Left from global (row-major np x np, interleaved) or LDS (planar); right likewise.
+template <typename T, int NP, int S>
+__device__ __forceinline__ void tile_gemm_gl_lds(const typename vec2<T>::type *__restrict__ Lg, const T *Rre,
+                                                 const T *Rim, int I, int J, int lane,
+                                                 typename Mfma<T>::acc &aR, typename Mfma<T>::acc &aI)
+{
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const typename vec2<T>::type *lrow = Lg + (size_t)(I * 16 + r16) * NP + k4;
+#pragma unroll 4
+    for (int kk = 0; kk < NP; kk += 4) {
+        const typename vec2<T>::type a = lrow[kk];
+        const T br = Rre[(kk + k4) * S + J * 16 + r16];
+        const T bi = Rim[(kk + k4) * S + J * 16 + r16];
+        aR = Mfma<T>::mma(a.x, br, aR);
+        aR = Mfma<T>::mma(-a.y, bi, aR);
+        aI = Mfma<T>::mma(a.x, bi, aI);
+        aI = Mfma<T>::mma(a.y, br, aI);
+    }
+}
+
+// acc(I,J) += sum_k X(I*16+r, k) conj(C(J*16+c, k))   (X from LDS, C from global): X C^dag
+template <typename T, int NP, int S>
+__device__ __forceinline__ void tile_gemm_lds_gldag(const T *Xre, const T *Xim,
+                                                    const typename vec2<T>::type *__restrict__ Cg, int I, int J,
+                                                    int lane, typename Mfma<T>::acc &aR, typename Mfma<T>::acc &aI)
+{
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const typename vec2<T>::type *crow = Cg + (size_t)(J * 16 + r16) * NP + k4;
+#pragma unroll 4
+    for (int kk = 0; kk < NP; kk += 4) {
+        const T ar = Xre[(I * 16 + r16) * S + kk + k4];
+        const T ai = Xim[(I * 16 + r16) * S + kk + k4];
+        const typename vec2<T>::type c = crow[kk];
+        // b = conj(c)
+        aR = Mfma<T>::mma(ar, c.x, aR);
+        aR = Mfma<T>::mma(ai, c.y, aR);   // -ai * (-c.y)
+        aI = Mfma<T>::mma(-ar, c.y, aI);  // ar * (-c.y)
+        aI = Mfma<T>::mma(ai, c.x, aI);
+    }
+}
+
+template <typename T, int NP, int WAVES> struct DenseRhs {
+    using G = DenseGeom<T, NP, WAVES>;
+    using V = typename vec2<T>::type;
+    using Acc = typename Mfma<T>::acc;
+    static constexpr int S = G::S;
+
+    // out[t][v] (owned tiles) = L(B0); uses B1 as scratch.  Ends with B1 holding A B0.
+    static __device__ void eval(const V *__restrict__ ops, int nc, T *lds, V (&out)[G::MAXT][4])
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        T *B0re = lds, *B0im = lds + G::PLANE, *B1re = lds + 2 * G::PLANE, *B1im = lds + 3 * G::PLANE;
+        const size_t mat = (size_t)NP * NP;
+        const int r16 = lane & 15, k4 = lane >> 4;
+        Acc aR[G::MAXT], aI[G::MAXT];
+#pragma unroll
+        for (int q = 0; q < G::MAXT; ++q) {
+            aR[q] = Acc{0, 0, 0, 0};
+            aI[q] = Acc{0, 0, 0, 0};
+        }
+        for (int k = 0; k < nc; ++k) {
+            const V *C = ops + (1 + k) * mat;
+            // X = C B0 -> B1
+#pragma unroll
+            for (int q = 0; q < G::MAXT; ++q) {
+                const int t = w + q * WAVES;
+                if (t < G::TT) {
+                    const int I = t / G::NT, J = t % G::NT;
+                    Acc xR = {0, 0, 0, 0}, xI = {0, 0, 0, 0};
+                    tile_gemm_gl_lds<T, NP, S>(C, B0re, B0im, I, J, lane, xR, xI);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
+                        B1re[i * S + j] = xR[v];
+                        B1im[i * S + j] = xI[v];
+                    }
+                }
+            }
+            __syncthreads();
+            // acc += X C^dag
+#pragma unroll
+            for (int q = 0; q < G::MAXT; ++q) {
+                const int t = w + q * WAVES;
+                if (t < G::TT) {
+                    const int I = t / G::NT, J = t % G::NT;
+                    tile_gemm_lds_gldag<T, NP, S>(B1re, B1im, C, I, J, lane, aR[q], aI[q]);
+                }
+            }
+            __syncthreads();
+        }
+        // M = A B0 -> B1
+#pragma unroll
+        for (int q = 0; q < G::MAXT; ++q) {
+            const int t = w + q * WAVES;
+            if (t < G::TT) {
+                const int I = t / G::NT, J = t % G::NT;
+                Acc mR = {0, 0, 0, 0}, mI = {0, 0, 0, 0};
+                tile_gemm_gl_lds<T, NP, S>(ops, B0re, B0im, I, J, lane, mR, mI);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
+                    B1re[i * S + j] = mR[v];
+                    B1im[i * S + j] = mI[v];
+                }
+            }
+        }
+        __syncthreads();
+        // out = acc + M + M^dag
+#pragma unroll
+        for (int q = 0; q < G::MAXT; ++q) {
+            const int t = w + q * WAVES;
+            if (t < G::TT) {
+                const int I = t / G::NT, J = t % G::NT;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
+                    V o;
+                    o.x = aR[q][v] + B1re[i * S + j] + B1re[j * S + i];
+                    o.y = aI[q][v] + B1im[i * S + j] - B1im[j * S + i];
+                    out[q][v] = o;
+                }
+            }
+        }
+    }
+};
+
+// Element index of (tile t, lane, v) in the tile-ordered global vectors.
+__device__ __forceinline__ size_t tix(int t, int lane, int v) { return ((size_t)t * 64 + lane) * 4 + v; }
+
+template <typename T, int NP, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__restrict__ insts,
+                                                            DenseCtl *__restrict__ ctls,
+                                                            const int32_t *__restrict__ order, int max_steps_launch,
+                                                            int reset)
+{
+    using G = DenseGeom<T, NP, WAVES>;
+    using V = typename vec2<T>::type;
+    using R = DenseRhs<T, NP, WAVES>;
+    constexpr int S = G::S;
+    extern __shared__ char smem[];
+    T *lds = (T *)smem;
+    __shared__ double scr[16];
+    T *B0re = lds, *B0im = lds + G::PLANE;
+
+    const int ii = order[blockIdx.x];
+    const DenseInst &I = insts[ii];
+    DenseCtl *C = ctls + ii;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int d = I.d;
+    const size_t nvec = (size_t)NP * NP;
+    V *vec = (V *)I.vec;
+    V *Yb[2] = {vec, vec + nvec};
+    V *Kb[2] = {vec + 2 * nvec, vec + 3 * nvec};
+    V *ks[5] = {vec + 4 * nvec, vec + 5 * nvec, vec + 6 * nvec, vec + 7 * nvec, vec + 8 * nvec};
+    const V *ops = (const V *)I.ops;
+    const double nd = (double)d * d;
+    V out[G::MAXT][4];
+
+    auto owned = [&](int q, int &Ii, int &Jj) {
+        const int t = w + q * WAVES;
+        Ii = t / G::NT;
+        Jj = t % G::NT;
+        return t < G::TT;
+    };
+    auto record_expect = [&](int idx, double sc) {
+        for (int k = 0; k < I.ne; ++k) {
+            const int32_t *ep = I.eptr + (size_t)k * (d + 1);
+            double sr = 0.0, si = 0.0;
+            for (int i = threadIdx.x; i < d; i += blockDim.x)
+                for (int p = ep[i]; p < ep[i + 1]; ++p) {
+                    const double2 o = I.eval[p];
+                    const int j = I.ecol[p];
+                    const double rr = (double)B0re[j * S + i], ri = (double)B0im[j * S + i];
+                    sr += o.x * rr - o.y * ri;
+                    si += o.x * ri + o.y * rr;
+                }
+            sr = block_sum(sr, scr);
+            si = block_sum(si, scr);
+            if (threadIdx.x == 0) I.expect[(size_t)k * I.nt + idx] = make_double2(sr * sc, si * sc);
+        }
+    };
+    auto trace_b0 = [&]() {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < d; i += blockDim.x) s += (double)B0re[i * S + i];
+        return block_sum(s, scr);
+    };
+
+    double t, h, err_prev, scale, tr0;
+    int status, save_idx, last_rejected, parity;
+    int64_t n_accept, n_reject, n_steps, n_rhs;
+
+    if (reset || C->status == DENSE_ST_INIT) {
+        // ---- initial state into B0 (planar, zero padded) and Y[0] (tile order) ----
+        const V *r0 = (const V *)I.rho0;
+        for (int q = 0; q < G::MAXT; ++q) {
+            int Ii, Jj;
+            if (!owned(q, Ii, Jj)) continue;
+            for (int v = 0; v < 4; ++v) {
+                const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
+                V y;
+                y.x = 0;
+                y.y = 0;
+                if (i < d && j < d) y = r0[(size_t)i * d + j];
+                Yb[0][tix(w + q * WAVES, lane, v)] = y;
+                B0re[i * S + j] = y.x;
+                B0im[i * S + j] = y.y;
+            }
+        }
+        __syncthreads();
+        t = I.tlist[0];
+        err_prev = 1e-4;
+        scale = 1.0;
+        save_idx = 1;
+        last_rejected = 0;
+        parity = 0;
+        n_accept = n_reject = n_steps = 0;
+        n_rhs = 0;
+        status = ST_RUNNING;
+        tr0 = trace_b0();
+        record_expect(0, 1.0);
+        if (I.nt <= 1) status = ST_DONE;
+        h = 0.0;
+        if (status == ST_RUNNING) {
+            // k1 = L(y0); starting step from d0 = |y0|, d1 = |k1|, d2 = |f(y0 + h0 k1) - k1| / h0
+            R::eval(ops, I.nc, lds, out);
+            n_rhs += 1;
+            double s0 = 0.0, s1 = 0.0;
+            for (int q = 0; q < G::MAXT; ++q) {
+                int Ii, Jj;
+                if (!owned(q, Ii, Jj)) continue;
+                for (int v = 0; v < 4; ++v) {
+                    const size_t e = tix(w + q * WAVES, lane, v);
+                    Kb[0][e] = out[q][v];
+                    const double ya = sqrt(abs2d(Yb[0][e]));
+                    const double sc = I.atol + I.rtol * ya;
+                    s0 += ya * ya / (sc * sc);
+                    s1 += abs2d(out[q][v]) / (sc * sc);
+                }
+            }
+            s0 = block_sum(s0, scr);
+            s1 = block_sum(s1, scr);
+            const double d0 = sqrt(s0 / nd), d1 = sqrt(s1 / nd);
+            if (I.use_h0) {
+                h = I.h0;
+            } else {
+                const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+                __syncthreads();
+                for (int q = 0; q < G::MAXT; ++q) {
+                    int Ii, Jj;
+                    if (!owned(q, Ii, Jj)) continue;
+                    for (int v = 0; v < 4; ++v) {
+                        const size_t e = tix(w + q * WAVES, lane, v);
+                        const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
+                        V y = Yb[0][e];
+                        caxpy(y, (T)h0, Kb[0][e]);
+                        B0re[i * S + j] = y.x;
+                        B0im[i * S + j] = y.y;
+                    }
+                }
+                __syncthreads();
+                R::eval(ops, I.nc, lds, out);
+                n_rhs += 1;
+                double s2 = 0.0;
+                for (int q = 0; q < G::MAXT; ++q) {
+                    int Ii, Jj;
+                    if (!owned(q, Ii, Jj)) continue;
+                    for (int v = 0; v < 4; ++v) {
+                        const size_t e = tix(w + q * WAVES, lane, v);
+                        const double2 f1 = to_d2(out[q][v]), f0 = to_d2(Kb[0][e]);
+                        const double sc = I.atol + I.rtol * sqrt(abs2d(Yb[0][e]));
+                        const double dx = (f1.x - f0.x) / h0, dy = (f1.y - f0.y) / h0;
+                        s2 += (dx * dx + dy * dy) / (sc * sc);
+                    }
+                }
+                s2 = block_sum(s2, scr);
+                const double d2 = sqrt(s2 / nd);
+                const double m = fmax(d1, d2);
+                const double h1 = (m <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / m, 0.2);
+                h = fmin(100.0 * h0, h1);
+            }
+        }
+    } else {
+        t = C->t;
+        h = C->h;
+        err_prev = C->err_prev;
+        scale = C->scale;
+        tr0 = C->tr0;
+        status = C->status;
+        save_idx = C->save_idx;
+        last_rejected = C->last_rejected;
+        parity = C->parity;
+        n_accept = C->n_accept;
+        n_reject = C->n_reject;
+        n_steps = C->n_steps;
+        n_rhs = C->n_rhs;
+    }
+
+    int budget = max_steps_launch;
+    while (status == ST_RUNNING && budget != 0) {
+        if (budget > 0) --budget;
+        int32_t land;
+        const double ht = clip_step(t, h, I.tlist[save_idx], &land);
+        const T sc = (T)scale;
+        V *y = Yb[parity], *ynew = Yb[1 - parity], *k1 = Kb[parity], *k7 = Kb[1 - parity];
+        // stage-2 input: y + h a21 k1
+        __syncthreads();
+        for (int q = 0; q < G::MAXT; ++q) {
+            int Ii, Jj;
+            if (!owned(q, Ii, Jj)) continue;
+            for (int v = 0; v < 4; ++v) {
+                const size_t e = tix(w + q * WAVES, lane, v);
+                const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
+                V x = cscale(y[e], sc);
+                caxpy(x, (T)(ht * DP5::a21), cscale(k1[e], sc));
+                B0re[i * S + j] = x.x;
+                B0im[i * S + j] = x.y;
+            }
+        }
+        __syncthreads();
+        double e2 = 0.0;
+        for (int s = 2; s <= 7; ++s) {
+            R::eval(ops, I.nc, lds, out);
+            for (int q = 0; q < G::MAXT; ++q) {
+                int Ii, Jj;
+                if (!owned(q, Ii, Jj)) continue;
+                for (int v = 0; v < 4; ++v) {
+                    const size_t e = tix(w + q * WAVES, lane, v);
+                    const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
+                    const V a = out[q][v];
+                    const V yr = cscale(y[e], sc), k1r = cscale(k1[e], sc);
+                    V o = yr;
+                    if (s == 2) {
+                        ks[0][e] = a;
+                        caxpy(o, (T)(ht * DP5::a31), k1r);
+                        caxpy(o, (T)(ht * DP5::a32), a);
+                    } else if (s == 3) {
+                        ks[1][e] = a;
+                        caxpy(o, (T)(ht * DP5::a41), k1r);
+                        caxpy(o, (T)(ht * DP5::a42), ks[0][e]);
+                        caxpy(o, (T)(ht * DP5::a43), a);
+                    } else if (s == 4) {
+                        ks[2][e] = a;
+                        caxpy(o, (T)(ht * DP5::a51), k1r);
+                        caxpy(o, (T)(ht * DP5::a52), ks[0][e]);
+                        caxpy(o, (T)(ht * DP5::a53), ks[1][e]);
+                        caxpy(o, (T)(ht * DP5::a54), a);
+                    } else if (s == 5) {
+                        ks[3][e] = a;
+                        caxpy(o, (T)(ht * DP5::a61), k1r);
+                        caxpy(o, (T)(ht * DP5::a62), ks[0][e]);
+                        caxpy(o, (T)(ht * DP5::a63), ks[1][e]);
+                        caxpy(o, (T)(ht * DP5::a64), ks[2][e]);
+                        caxpy(o, (T)(ht * DP5::a65), a);
+                    } else if (s == 6) {
+                        ks[4][e] = a;
+                        caxpy(o, (T)(ht * DP5::b1), k1r);
+                        caxpy(o, (T)(ht * DP5::b3), ks[1][e]);
+                        caxpy(o, (T)(ht * DP5::b4), ks[2][e]);
+                        caxpy(o, (T)(ht * DP5::b5), ks[3][e]);
+                        caxpy(o, (T)(ht * DP5::b6), a);
+                        ynew[e] = o;
+                    } else {
+                        k7[e] = a;
+                        double2 er = make_double2(0.0, 0.0);
+                        caxpy(er, ht * DP5::e1, to_d2(k1r));
+                        caxpy(er, ht * DP5::e3, to_d2(ks[1][e]));
+                        caxpy(er, ht * DP5::e4, to_d2(ks[2][e]));
+                        caxpy(er, ht * DP5::e5, to_d2(ks[3][e]));
+                        caxpy(er, ht * DP5::e6, to_d2(ks[4][e]));
+                        caxpy(er, ht * DP5::e7, to_d2(a));
+                        const double scl = I.atol + I.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(ynew[e])));
+                        e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
+                    }
+                    if (s < 7) {
+                        B0re[i * S + j] = o.x;
+                        B0im[i * S + j] = o.y;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        n_rhs += 6;
+        ++n_steps;
+        // B0 now holds y_new (the stage-7 input)
+        e2 = block_sum(e2, scr);
+        const double err = sqrt(e2 / nd);
+        if (!isfinite(err)) {
+            status = 6;  // QT_ENONFINITE
+            break;
+        }
+        if (err <= 1.0) {
+            ++n_accept;
+            double sc_new = 1.0;
+            if (I.renorm) sc_new = tr0 / trace_b0();
+            if (land) record_expect(save_idx, sc_new);
+            t = land ? I.tlist[save_idx] : t + ht;
+            parity = 1 - parity;
+            double hn = ht * pi_factor(err, err_prev);
+            if (last_rejected && hn > ht) hn = ht;
+            h = hn;
+            err_prev = fmax(err, 1e-4);
+            last_rejected = 0;
+            scale = sc_new;
+            if (land) {
+                ++save_idx;
+                if (save_idx >= I.nt) status = ST_DONE;
+            }
+        } else {
+            ++n_reject;
+            h = ht * reject_factor(err);
+            last_rejected = 1;
+        }
+        if (status == ST_RUNNING) {
+            if (n_steps >= I.max_steps) status = 4;  // QT_EMAXSTEPS
+            else if (h < 1e-14 * fmax(1.0, fabs(t))) status = 5;  // QT_EDTMIN
+        }
+    }
+    if (threadIdx.x == 0) {
+        C->t = t;
+        C->h = h;
+        C->err_prev = err_prev;
+        C->scale = scale;
+        C->tr0 = tr0;
+        C->status = status;
+        C->save_idx = save_idx;
+        C->last_rejected = last_rejected;
+        C->parity = parity;
+        C->n_accept = n_accept;
+        C->n_reject = n_reject;
+        C->n_steps = n_steps;
+        C->n_rhs = n_rhs;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *ops, const void *rho0, void *vec,
+                     const double *tlist, const int32_t *eptr, const int32_t *ecol, const double2 *eval,
+                     double2 *expect, const qt_opts &opts, int prec)
+{
+    g->d = d;
+    g->np = dense_np(d);
+    g->nc = nc;
+    g->nt = nt;
+    g->ne = ne;
+    g->use_h0 = opts.h0 > 0 ? 1 : 0;
+    g->renorm = prec == QT_MIXED ? 1 : 0;
+    g->pad = 0;
+    g->atol = opts.abstol;
+    g->rtol = opts.reltol;
+    g->h0 = opts.h0;
+    g->max_steps = opts.max_steps;
+    g->ops = ops;
+    g->rho0 = rho0;
+    g->vec = vec;
+    g->tlist = tlist;
+    g->eptr = eptr;
+    g->ecol = ecol;
+    g->eval = eval;
+    g->expect = expect;
+}
+
+int dense_choose_config(int dmax, int prec)
+{
+    (void)dmax;
+    (void)prec;
+    return 4;  // waves per workgroup
+}
+
+const void *dense_state_ptr(const void *vec, int d, int prec)
+{
+    (void)d;
+    (void)prec;
+    return vec;
+}
+
+template <typename T, int NP, int WAVES>
+static void launch_np(const DenseInst *insts, DenseCtl *ctls, const int32_t *order, int count, int msl, int reset,
+                      hipStream_t s)
+{
+    using G = DenseGeom<T, NP, WAVES>;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_dense_solve<T, NP, WAVES>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::LDS_BYTES);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_dense_solve<T, NP, WAVES>), dim3(count), dim3(WAVES * 64), G::LDS_BYTES, s, insts, ctls,
+                       order, msl, reset);
+}
+
+template <typename T, int WAVES>
+static void launch_bucket(int np, const DenseInst *insts, DenseCtl *ctls, const int32_t *order, int count, int msl,
+                          int reset, hipStream_t s)
+{
+    switch (np) {
+    case 16: launch_np<T, 16, WAVES>(insts, ctls, order, count, msl, reset, s); break;
+    case 32: launch_np<T, 32, WAVES>(insts, ctls, order, count, msl, reset, s); break;
+    case 48: launch_np<T, 48, WAVES>(insts, ctls, order, count, msl, reset, s); break;
+    case 64: launch_np<T, 64, WAVES>(insts, ctls, order, count, msl, reset, s); break;
+    case 80:
+        if constexpr (sizeof(T) == 4) launch_np<T, 80, WAVES>(insts, ctls, order, count, msl, reset, s);
+        break;
+    case 96:
+        if constexpr (sizeof(T) == 4) launch_np<T, 96, WAVES>(insts, ctls, order, count, msl, reset, s);
+        break;
+    default: break;
+    }
+}
+
+void dense_launch_bucket(int np, bool f64, int waves, const DenseInst *insts, DenseCtl *ctls, const int32_t *order,
+                         int count, int msl, int reset, hipStream_t s)
+{
+    if (count <= 0) return;
+    if (f64) {
+        if (waves == 8) launch_bucket<double, 8>(np, insts, ctls, order, count, msl, reset, s);
+        else launch_bucket<double, 4>(np, insts, ctls, order, count, msl, reset, s);
+    } else {
+        if (waves == 8) launch_bucket<float, 8>(np, insts, ctls, order, count, msl, reset, s);
+        else launch_bucket<float, 4>(np, insts, ctls, order, count, msl, reset, s);
+    }
+}
+
+void dense_unpack(const void *host_vec, int d, int prec, double scale, double *out)
+{
+    const int np = dense_np(d), nt = np / 16;
+    for (int t = 0; t < nt * nt; ++t)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int v = 0; v < 4; ++v) {
+                const int q4 = lane >> 4;
+                const int i = (t / nt) * 16 + (prec == QT_F64 ? q4 + 4 * v : 4 * q4 + v), j = (t % nt) * 16 + (lane & 15);
+                if (i >= d || j >= d) continue;
+                const size_t e = ((size_t)t * 64 + lane) * 4 + v;
+                double re, im;
+                if (prec == QT_F64) {
+                    re = ((const double *)host_vec)[2 * e];
+                    im = ((const double *)host_vec)[2 * e + 1];
+                } else {
+                    re = ((const float *)host_vec)[2 * e];
+                    im = ((const float *)host_vec)[2 * e + 1];
+                }
+                out[2 * ((size_t)i * d + j)] = re * scale;
+                out[2 * ((size_t)i * d + j) + 1] = im * scale;
+            }
+}
+
+}  // namespace qt

@@ -1,0 +1,67 @@
+// qt_csr.h -- device-side descriptors of the CSR-form master-equation solver.
+//
+// One "instance" is one master-equation problem whose Liouvillian is a CSR superoperator
+// (row-major vec, n = d*d rows).  Several instances are advanced by the same kernel launches:
+// each thread block serves a fixed row range of one instance, and every instance carries its
+// own time, step size, accept/reject history and save index in a CsrCtl record in device
+// memory, so no host round trip is needed to control the integration.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qt {
+
+// Solve status kept in device control records (errors use the public QT_E* codes 1..7).
+enum : int32_t {
+    ST_RUNNING = 0,
+    ST_DONE = 100,
+};
+
+struct CsrInst {
+    int32_t n;  // rows of the superoperator (= d*d)
+    int32_t d;
+    int32_t nt;
+    int32_t ne;
+    int32_t block0;   // first block of this instance in the launch grid
+    int32_t nblocks;  // blocks of this instance
+    int32_t renorm;   // 1: rescale the trace back to its initial value after accepted steps
+    int32_t use_h0;   // 1: opts.h0 given
+    double atol, rtol, h0;
+    int64_t max_steps;
+    const int32_t *rowptr;
+    const int32_t *col;
+    const void *val;  // float2 / double2 [nnz]
+    const void *rho0; // resident initial state (state precision) [n]
+    void *Y[2];       // y and the candidate y_new, exchanged on acceptance via CsrCtl::parity
+    void *K[2];       // k1 and k7 (first same as last), exchanged on acceptance
+    void *ks[5];      // k2 .. k6
+    void *ys[2];      // stage inputs, alternating
+    const double *tlist;
+    const int32_t *eptr;  // ne * (d+1) row pointers into ecol/eval (instance-local offsets)
+    const int32_t *ecol;
+    const double2 *eval;
+    double2 *expect;      // [ne][nt]
+    double *partials;     // 2 * nblocks doubles
+};
+
+struct CsrCtl {
+    double t;
+    double h;        // proposed step
+    double h_try;    // step being tried (clipped to the next save time)
+    double err_prev;
+    double scale;    // trace renormalisation factor applied to y and k1
+    double tr0;      // initial trace (renormalisation target)
+    double h0;       // starting-step heuristic intermediate
+    double last_err;
+    int32_t status;
+    int32_t phase;  // 1: second starting-step evaluation pending, 0: stepping
+    int32_t land;
+    int32_t last_rejected;
+    int32_t save_idx;
+    int32_t parity;
+    uint32_t arrive;  // blocks arrived at the reduction of the current kernel
+    int32_t pad;
+    int64_t n_accept, n_reject, n_steps, n_rhs;
+};
+
+}  // namespace qt

@@ -1,0 +1,61 @@
+// qt_dense.h -- descriptors of the dense-form (oscillator) master-equation solver.
+//
+// For small dense operators the right-hand side of the master equation (arXiv:2504.21440,
+// Sec. 3.2) is evaluated in operator form,
+//     L(rho) = A rho + (A rho)^dag + sum_k C_k rho C_k^dag,   A = -i H - 1/2 sum_k C_k^dag C_k,
+// which uses rho = rho^dag and costs 1 + 2K complex matrix products per evaluation -- work for the
+// matrix cores.  One workgroup owns one problem for a whole launch and runs the adaptive
+// Dormand-Prince 5(4) loop itself, so problems of different size and step count never wait for
+// each other.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qtamd.h"
+
+namespace qt {
+
+constexpr int DENSE_MAX_NP_F32 = 96;  // padded dimension limit set by LDS (two planes of NP x (NP+1))
+constexpr int DENSE_MAX_NP_F64 = 64;
+
+struct DenseInst {
+    int32_t d, np, nc, nt, ne;
+    int32_t use_h0, renorm, pad;
+    double atol, rtol, h0;
+    int64_t max_steps;
+    const void *ops;   // A then C_k, np x np row-major, state precision, zero padded
+    const void *rho0;  // d x d row-major, state precision
+    void *vec;         // 9 state vectors of np*np elements in tile order
+    const double *tlist;
+    const int32_t *eptr;
+    const int32_t *ecol;
+    const double2 *eval;
+    double2 *expect;
+};
+
+enum : int32_t { DENSE_ST_INIT = 200 };
+
+struct DenseCtl {
+    double t, h, err_prev, scale, tr0;
+    int32_t status, save_idx, last_rejected, parity;
+    int64_t n_accept, n_reject, n_steps, n_rhs;
+};
+
+inline int dense_np(int d) { return ((d + 15) / 16) * 16; }
+inline int dense_state_vectors() { return 9; }
+
+void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *ops, const void *rho0, void *vec,
+                     const double *tlist, const int32_t *eptr, const int32_t *ecol, const double2 *eval,
+                     double2 *expect, const qt_opts &opts, int prec);
+// threads-per-block configuration (waves per workgroup) chosen for the largest padded size
+int dense_choose_config(int dmax, int prec);
+// pointer to the current state vector (tile order) of an instance, for diagnostics
+const void *dense_state_ptr(const void *vec, int d, int prec);
+// Launch the persistent solver for `count` instances of padded size np (order[] lists them).
+// max_steps_launch < 0: run to completion.  reset: start every instance from rho0.
+void dense_launch_bucket(int np, bool f64, int waves, const DenseInst *insts, DenseCtl *ctls, const int32_t *order,
+                         int count, int max_steps_launch, int reset, hipStream_t s);
+// Host-side conversion of a tile-ordered state vector to a row-major d x d matrix (complex128).
+void dense_unpack(const void *host_vec, int d, int prec, double scale, double *out);
+
+}  // namespace qt

@@ -1,0 +1,100 @@
+// qt_host.h -- host-side runtime types of libqtamd (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qtamd.h"
+
+namespace qt {
+
+using cd = std::complex<double>;
+
+// Error reporting ------------------------------------------------------------------------------
+qt_status set_error(qt_status code, const std::string &msg);
+#define QT_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::qt::set_error(QT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Canonical host CSR: square, rows sorted, duplicates summed, exact zeros dropped.
+struct HCsr {
+    int32_t d = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> idx;
+    std::vector<cd> val;
+    int64_t nnz() const { return (int64_t)idx.size(); }
+};
+
+qt_status csr_from_abi(const qt_csr *A, int32_t d_expect, HCsr *out, const char *what);
+HCsr csr_adjoint(const HCsr &A);
+HCsr csr_matmul(const HCsr &A, const HCsr &B);
+HCsr csr_axpby(cd a, const HCsr &A, cd b, const HCsr &B);
+HCsr csr_zero(int32_t d);
+
+// A device arena: one hipMalloc carved into 256-byte aligned pieces.
+struct Arena {
+    void *base = nullptr;
+    size_t size = 0, used = 0;
+    std::vector<std::pair<size_t, size_t>> plan;  // planned offsets
+    size_t reserve(size_t bytes)
+    {
+        size_t off = (size + 255) & ~size_t(255);
+        size = off + bytes;
+        return off;
+    }
+    qt_status alloc();
+    void *at(size_t off) const { return (char *)base + off; }
+    void release();
+};
+
+struct Ctx {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;  // second stream for overlapping independent work
+    static constexpr int NPOOL = 4;
+    hipStream_t pool[NPOOL] = {};  // streams for concurrent dense-size buckets
+    bool own_stream = false;
+};
+
+struct Liouv {
+    Ctx *ctx = nullptr;
+    int32_t form = QT_FORM_CSR;
+    int32_t precision = QT_F64;
+    int32_t d = 0;
+    int64_t nnz = 0;
+    int64_t bytes = 0;
+    int32_t nc = 0;
+    // CSR form
+    int32_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    void *val = nullptr;
+    // dense form: A then C_k, each d x d row-major, in the solve precision
+    void *dense = nullptr;
+    // host copies needed by the Monte-Carlo path and by the server footprint estimate
+};
+
+// Kernel launchers (defined in the .hip files)
+struct CsrInst;
+struct CsrCtl;
+int csr_rows_per_block(int lpr);
+void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s);
+void csr_launch_init(int which, bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                     const int32_t *br, hipStream_t s);
+void csr_launch_step(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                     const int32_t *br, hipStream_t s);
+void launch_expect(bool f64, int d, const int32_t *rp, const int32_t *ci, const double2 *v, const void *state,
+                   int is_ket, double2 *out, hipStream_t s);
+
+// Tile-shape choice for the CSR right-hand side (lanes per row), by rows and mean row length.
+int choose_lpr(int64_t n, double mean_row);
+
+}  // namespace qt
+
+struct qt_ctx : qt::Ctx {};
+struct qt_liouv : qt::Liouv {};

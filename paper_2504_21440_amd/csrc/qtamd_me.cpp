@@ -1,0 +1,525 @@
+// qtamd_me.cpp -- master-equation plans: device-resident batched mesolve (Sec. 3.2 of
+// arXiv:2504.21440) over CSR-form and dense-form Liouvillians.
+//
+// A plan uploads every input once (initial states, save times, e_ops) and lays out the solver
+// state of all its problems in one device arena.  Running it resets the per-problem control
+// records on the device, evaluates the starting step, then replays a captured graph of
+// `steps_per_launch` Runge-Kutta steps until every problem reports done; each problem keeps its
+// own step size and accept/reject history on the device, so the host only polls status words.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "qt_csr.h"
+#include "qt_dense.h"
+#include "qt_host.h"
+
+namespace qt {
+
+struct MeProb {
+    const qt_liouv *L = nullptr;
+    int32_t d = 0, nt = 0, ne = 0;
+    bool dense = false;
+    int32_t slot = -1;  // index inside its group
+    size_t o_rho0 = 0, o_tlist = 0, o_eptr = 0, o_ecol = 0, o_eval = 0, o_expect = 0;
+    size_t o_vec = 0;  // state vectors
+    size_t o_part = 0;
+    int32_t block0 = 0, nblocks = 0;
+    std::vector<char> rho0;  // host copy in state precision
+    std::vector<double> tlist;
+    std::vector<int32_t> eptr, ecol;
+    std::vector<double2> eval;
+};
+
+}  // namespace qt
+
+struct qt_me_plan {
+    qt::Ctx *ctx = nullptr;
+    qt_opts opts{};
+    int32_t prec = QT_F64;
+    std::vector<qt::MeProb> probs;
+    qt::Arena arena;
+    // CSR group
+    int32_t ncsr = 0, lpr = 8, nblk = 0;
+    size_t o_cinst = 0, o_cctl = 0, o_bi = 0, o_br = 0;
+    qt::CsrCtl *h_cctl = nullptr;  // pinned
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int32_t graph_steps = 16;
+    // dense group
+    int32_t ndense = 0;
+    size_t o_dinst = 0, o_dctl = 0, o_dorder = 0;
+    qt::DenseCtl *h_dctl = nullptr;  // pinned
+    int32_t dense_cfg = 4;
+    struct Bucket {
+        int32_t np, start, count;
+    };
+    std::vector<Bucket> buckets;  // dense problems grouped by padded size, largest first
+    double last_ms = 0.0;
+};
+
+namespace qt {
+
+static size_t state_es(int32_t prec) { return prec == QT_F64 ? sizeof(double2) : sizeof(float2); }
+
+static qt_status prep_problem(const qt_me_problem &p, int32_t prec, MeProb *m)
+{
+    if (!p.L) return set_error(QT_EINVAL, "problem without Liouvillian");
+    if (p.L->precision != prec)
+        return set_error(QT_EINVAL, "Liouvillian precision differs from opts.precision");
+    const int32_t d = p.L->d;
+    if (p.n_t < 1 || !p.tlist) return set_error(QT_EINVAL, "tlist must hold at least one time");
+    for (int32_t i = 0; i < p.n_t; ++i)
+        if (!std::isfinite(p.tlist[i]) || (i > 0 && !(p.tlist[i] > p.tlist[i - 1])))
+            return set_error(QT_EINVAL, "tlist must be finite and strictly increasing");
+    if (!p.rho0) return set_error(QT_EINVAL, "rho0 is null");
+    if (p.n_e < 0 || (p.n_e > 0 && !p.e_ops)) return set_error(QT_EINVAL, "bad e_ops");
+    m->L = p.L;
+    m->d = d;
+    m->nt = p.n_t;
+    m->ne = p.n_e;
+    m->dense = p.L->form == QT_FORM_DENSE;
+    m->tlist.assign(p.tlist, p.tlist + p.n_t);
+    // initial state (row-major d x d), converted to the state precision
+    const size_t n = (size_t)d * d;
+    std::vector<double> r(2 * n);
+    if (p.is_ket) {
+        for (int32_t i = 0; i < d; ++i)
+            for (int32_t j = 0; j < d; ++j) {
+                const cd a(p.rho0[2 * i], p.rho0[2 * i + 1]), b(p.rho0[2 * j], p.rho0[2 * j + 1]);
+                const cd v = a * std::conj(b);
+                r[2 * ((size_t)i * d + j)] = v.real();
+                r[2 * ((size_t)i * d + j) + 1] = v.imag();
+            }
+    } else {
+        std::memcpy(r.data(), p.rho0, sizeof(double) * 2 * n);
+    }
+    for (size_t i = 0; i < 2 * n; ++i)
+        if (!std::isfinite(r[i])) return set_error(QT_EINVAL, "rho0 has non-finite entries");
+    if (prec == QT_F64) {
+        m->rho0.resize(n * 16);
+        std::memcpy(m->rho0.data(), r.data(), n * 16);
+    } else {
+        m->rho0.resize(n * 8);
+        float *f = (float *)m->rho0.data();
+        for (size_t i = 0; i < 2 * n; ++i) f[i] = (float)r[i];
+    }
+    // e_ops as concatenated int32 CSR (instance-local offsets)
+    m->eptr.assign((size_t)p.n_e * (d + 1), 0);
+    m->ecol.clear();
+    m->eval.clear();
+    for (int32_t k = 0; k < p.n_e; ++k) {
+        HCsr o;
+        qt_status st = csr_from_abi(&p.e_ops[k], d, &o, "e_ops");
+        if (st) return st;
+        const int32_t base = (int32_t)m->ecol.size();
+        for (int32_t i = 0; i <= d; ++i) m->eptr[(size_t)k * (d + 1) + i] = base + (int32_t)o.ptr[i];
+        for (int64_t q = 0; q < o.nnz(); ++q) {
+            m->ecol.push_back(o.idx[q]);
+            m->eval.push_back(make_double2(o.val[q].real(), o.val[q].imag()));
+        }
+    }
+    return QT_OK;
+}
+
+static qt_status upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (!bytes) return QT_OK;
+    QT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    return QT_OK;
+}
+
+qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts_in, qt_me_plan **out)
+{
+    if (!ctx || n <= 0 || !probs || !out) return set_error(QT_EINVAL, "qt_me_plan_create: bad arguments");
+    qt_opts opts;
+    if (opts_in) opts = *opts_in;
+    else qt_opts_default(&opts);
+    if (!(opts.abstol > 0) || !(opts.reltol >= 0) || opts.max_steps <= 0)
+        return set_error(QT_EINVAL, "opts: abstol > 0, reltol >= 0 and max_steps > 0 required");
+    if (opts.precision != QT_F64 && opts.precision != QT_MIXED) return set_error(QT_EINVAL, "opts: bad precision");
+    QT_HIP(hipSetDevice(ctx->device));
+    qt_me_plan *P = new qt_me_plan();
+    P->ctx = ctx;
+    P->opts = opts;
+    P->prec = opts.precision;
+    P->probs.resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        qt_status st = prep_problem(probs[i], P->prec, &P->probs[i]);
+        if (st) {
+            delete P;
+            return st;
+        }
+    }
+    const size_t es = state_es(P->prec);
+    // ---- layout ----
+    Arena &A = P->arena;
+    int64_t nnz_tot = 0, rows_tot = 0;
+    for (auto &m : P->probs)
+        if (!m.dense) {
+            m.slot = P->ncsr++;
+            nnz_tot += m.L->nnz;
+            rows_tot += (int64_t)m.d * m.d;
+        } else {
+            m.slot = P->ndense++;
+        }
+    P->lpr = choose_lpr(rows_tot, rows_tot ? (double)nnz_tot / rows_tot : 8.0);
+    const int rpb = csr_rows_per_block(P->lpr);
+    for (auto &m : P->probs) {
+        const size_t nvec = (size_t)m.d * m.d;
+        m.o_rho0 = A.reserve(nvec * es);
+        m.o_tlist = A.reserve(m.tlist.size() * 8);
+        m.o_eptr = A.reserve(std::max<size_t>(1, m.eptr.size()) * 4);
+        m.o_ecol = A.reserve(std::max<size_t>(1, m.ecol.size()) * 4);
+        m.o_eval = A.reserve(std::max<size_t>(1, m.eval.size()) * 16);
+        m.o_expect = A.reserve(std::max<size_t>(1, (size_t)m.ne * m.nt) * 16);
+        if (!m.dense) {
+            m.nblocks = (int32_t)((nvec + rpb - 1) / rpb);
+            m.block0 = P->nblk;
+            P->nblk += m.nblocks;
+            m.o_vec = A.reserve(11 * nvec * es);  // Y[2], K[2], k2..k6, ys[2]
+            m.o_part = A.reserve((size_t)m.nblocks * 16);
+        } else {
+            const size_t np = (size_t)dense_np(m.d);
+            m.o_vec = A.reserve(dense_state_vectors() * np * np * es);
+        }
+    }
+    if (P->ncsr) {
+        P->o_cinst = A.reserve(sizeof(CsrInst) * P->ncsr);
+        P->o_cctl = A.reserve(sizeof(CsrCtl) * P->ncsr);
+        P->o_bi = A.reserve(sizeof(int32_t) * P->nblk);
+        P->o_br = A.reserve(sizeof(int32_t) * P->nblk);
+    }
+    if (P->ndense) {
+        P->o_dinst = A.reserve(sizeof(DenseInst) * P->ndense);
+        P->o_dctl = A.reserve(sizeof(DenseCtl) * P->ndense);
+        P->o_dorder = A.reserve(sizeof(int32_t) * P->ndense);
+    }
+    qt_status st = A.alloc();
+    if (st) {
+        delete P;
+        return st;
+    }
+    hipStream_t s = ctx->stream;
+    // ---- uploads ----
+    std::vector<CsrInst> ci(P->ncsr);
+    std::vector<DenseInst> di(P->ndense);
+    std::vector<int32_t> bi(P->nblk), br(P->nblk);
+    for (auto &m : P->probs) {
+        if ((st = upload(A.at(m.o_rho0), m.rho0.data(), m.rho0.size(), s))) break;
+        if ((st = upload(A.at(m.o_tlist), m.tlist.data(), m.tlist.size() * 8, s))) break;
+        if ((st = upload(A.at(m.o_eptr), m.eptr.data(), m.eptr.size() * 4, s))) break;
+        if ((st = upload(A.at(m.o_ecol), m.ecol.data(), m.ecol.size() * 4, s))) break;
+        if ((st = upload(A.at(m.o_eval), m.eval.data(), m.eval.size() * 16, s))) break;
+        const size_t nvec = (size_t)m.d * m.d;
+        if (!m.dense) {
+            CsrInst &c = ci[m.slot];
+            std::memset(&c, 0, sizeof(c));
+            c.n = (int32_t)nvec;
+            c.d = m.d;
+            c.nt = m.nt;
+            c.ne = m.ne;
+            c.block0 = m.block0;
+            c.nblocks = m.nblocks;
+            c.renorm = P->prec == QT_MIXED ? 1 : 0;
+            c.use_h0 = opts.h0 > 0 ? 1 : 0;
+            c.atol = opts.abstol;
+            c.rtol = opts.reltol;
+            c.h0 = opts.h0;
+            c.max_steps = opts.max_steps;
+            c.rowptr = m.L->rowptr;
+            c.col = m.L->col;
+            c.val = m.L->val;
+            c.rho0 = A.at(m.o_rho0);
+            char *v = (char *)A.at(m.o_vec);
+            c.Y[0] = v + 0 * nvec * es;
+            c.Y[1] = v + 1 * nvec * es;
+            c.K[0] = v + 2 * nvec * es;
+            c.K[1] = v + 3 * nvec * es;
+            for (int k = 0; k < 5; ++k) c.ks[k] = v + (4 + k) * nvec * es;
+            c.ys[0] = v + 9 * nvec * es;
+            c.ys[1] = v + 10 * nvec * es;
+            c.tlist = (const double *)A.at(m.o_tlist);
+            c.eptr = (const int32_t *)A.at(m.o_eptr);
+            c.ecol = (const int32_t *)A.at(m.o_ecol);
+            c.eval = (const double2 *)A.at(m.o_eval);
+            c.expect = (double2 *)A.at(m.o_expect);
+            c.partials = (double *)A.at(m.o_part);
+            for (int32_t b = 0; b < m.nblocks; ++b) {
+                bi[m.block0 + b] = m.slot;
+                br[m.block0 + b] = b * rpb;
+            }
+        } else {
+            DenseInst &g = di[m.slot];
+            dense_fill_inst(&g, m.d, m.L->nc, m.nt, m.ne, m.L->dense, A.at(m.o_rho0), A.at(m.o_vec),
+                            (const double *)A.at(m.o_tlist), (const int32_t *)A.at(m.o_eptr),
+                            (const int32_t *)A.at(m.o_ecol), (const double2 *)A.at(m.o_eval),
+                            (double2 *)A.at(m.o_expect), opts, P->prec);
+        }
+    }
+    if (!st && P->ncsr) {
+        if ((st = upload(A.at(P->o_cinst), ci.data(), sizeof(CsrInst) * P->ncsr, s)) == QT_OK &&
+            (st = upload(A.at(P->o_bi), bi.data(), 4 * bi.size(), s)) == QT_OK)
+            st = upload(A.at(P->o_br), br.data(), 4 * br.size(), s);
+        if (!st) {
+            hipError_t e = hipHostMalloc((void **)&P->h_cctl, sizeof(CsrCtl) * P->ncsr, hipHostMallocDefault);
+            if (e) st = set_error(QT_ENOMEM, "pinned host buffer");
+        }
+    }
+    if (!st && P->ndense) {
+        // largest problems first: the persistent kernel's blocks pick instances in this order
+        std::vector<int32_t> order(P->ndense);
+        for (int32_t i = 0; i < P->ndense; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return di[a].d > di[b].d; });
+        for (int32_t k = 0; k < P->ndense; ++k) {
+            const int32_t np = di[order[k]].np;
+            if (np > (P->prec == QT_F64 ? DENSE_MAX_NP_F64 : DENSE_MAX_NP_F32)) {
+                st = set_error(QT_EINVAL, "dense form: dimension too large for this precision");
+                break;
+            }
+            if (P->buckets.empty() || P->buckets.back().np != np) P->buckets.push_back({np, k, 0});
+            P->buckets.back().count++;
+        }
+        if (!st && (st = upload(A.at(P->o_dinst), di.data(), sizeof(DenseInst) * P->ndense, s)) == QT_OK)
+            st = upload(A.at(P->o_dorder), order.data(), 4 * order.size(), s);
+        if (!st) {
+            hipError_t e = hipHostMalloc((void **)&P->h_dctl, sizeof(DenseCtl) * P->ndense, hipHostMallocDefault);
+            if (e) st = set_error(QT_ENOMEM, "pinned host buffer");
+        }
+        int32_t dmax = 0;
+        for (auto &g : di) dmax = std::max(dmax, g.d);
+        P->dense_cfg = dense_choose_config(dmax, P->prec);
+    }
+    if (!st) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e) st = set_error(QT_EDEVICE, std::string("plan upload: ") + hipGetErrorString(e));
+    }
+    P->graph_steps = opts.steps_per_launch > 0 ? opts.steps_per_launch : 16;
+    if (st) {
+        qt_me_plan_destroy(P);
+        return st;
+    }
+    *out = P;
+    return QT_OK;
+}
+
+static qt_status capture_graph(qt_me_plan *P)
+{
+    if (P->gexec) return QT_OK;
+    hipStream_t s = P->ctx->stream;
+    const bool f64 = P->prec == QT_F64;
+    auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
+    auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
+    auto *bi = (const int32_t *)P->arena.at(P->o_bi);
+    auto *br = (const int32_t *)P->arena.at(P->o_br);
+    QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < P->graph_steps; ++k) csr_launch_step(f64, P->lpr, P->nblk, ci, cc, bi, br, s);
+    hipError_t e = hipStreamEndCapture(s, &P->graph);
+    if (e) return set_error(QT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    QT_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+    return QT_OK;
+}
+
+qt_status me_plan_run(qt_me_plan *P)
+{
+    Ctx *ctx = P->ctx;
+    QT_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const bool f64 = P->prec == QT_F64;
+    auto t0 = std::chrono::steady_clock::now();
+    // dense buckets run on the auxiliary streams, overlapping each other and the CSR group
+    hipEvent_t ev_start = nullptr;
+    if (P->ndense) {
+        QT_HIP(hipEventCreateWithFlags(&ev_start, hipEventDisableTiming));
+        QT_HIP(hipEventRecord(ev_start, s));
+        for (size_t b = 0; b < P->buckets.size(); ++b) {
+            hipStream_t bs = ctx->pool[b % Ctx::NPOOL];
+            QT_HIP(hipStreamWaitEvent(bs, ev_start, 0));
+            const auto &bk = P->buckets[b];
+            dense_launch_bucket(bk.np, f64, P->dense_cfg, (const DenseInst *)P->arena.at(P->o_dinst),
+                                (DenseCtl *)P->arena.at(P->o_dctl), (const int32_t *)P->arena.at(P->o_dorder) + bk.start,
+                                bk.count, /*max_steps_launch=*/-1, /*reset=*/1, bs);
+            QT_HIP(hipGetLastError());
+        }
+    }
+    qt_status st = QT_OK;
+    if (P->ncsr) {
+        auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
+        auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
+        auto *bi = (const int32_t *)P->arena.at(P->o_bi);
+        auto *br = (const int32_t *)P->arena.at(P->o_br);
+        csr_launch_reset(ci, cc, P->ncsr, s);
+        csr_launch_init(0, f64, P->lpr, P->nblk, ci, cc, bi, br, s);
+        csr_launch_init(1, f64, P->lpr, P->nblk, ci, cc, bi, br, s);
+        QT_HIP(hipGetLastError());
+        if ((st = capture_graph(P))) return st;
+        int replays = 1;
+        int64_t last_steps = -1;
+        for (;;) {
+            for (int r = 0; r < replays; ++r) QT_HIP(hipGraphLaunch(P->gexec, s));
+            QT_HIP(hipMemcpyAsync(P->h_cctl, cc, sizeof(CsrCtl) * P->ncsr, hipMemcpyDeviceToHost, s));
+            QT_HIP(hipStreamSynchronize(s));
+            // estimate the steps still needed from the slowest running problem
+            double need = 0.0;
+            bool running = false;
+            int64_t steps = 0;
+            for (int32_t i = 0; i < P->ncsr; ++i) steps += P->h_cctl[i].n_steps;
+            if (steps == last_steps) return set_error(QT_EDEVICE, "CSR solver made no progress in a graph replay");
+            last_steps = steps;
+            for (int32_t i = 0; i < P->ncsr; ++i) {
+                const CsrCtl &c = P->h_cctl[i];
+                if (c.status != ST_RUNNING) continue;
+                running = true;
+                double tend = 0.0;
+                for (auto &m : P->probs)
+                    if (!m.dense && m.slot == i) tend = m.tlist.back();
+                const double h = c.h > 0 ? c.h : 1e-6;
+                need = std::max(need, (tend - c.t) / h);
+            }
+            if (!running) break;
+            replays = (int)std::min(8.0, std::max(1.0, std::floor(need / P->graph_steps)));
+        }
+    }
+    if (P->ndense) {
+        for (int b = 0; b < Ctx::NPOOL; ++b) QT_HIP(hipStreamSynchronize(ctx->pool[b]));
+        QT_HIP(hipMemcpy(P->h_dctl, P->arena.at(P->o_dctl), sizeof(DenseCtl) * P->ndense, hipMemcpyDeviceToHost));
+        (void)hipEventDestroy(ev_start);
+    }
+    P->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return QT_OK;
+}
+
+static qt_status status_code(int32_t s)
+{
+    if (s == ST_DONE) return QT_OK;
+    if (s == ST_RUNNING) return QT_EMAXSTEPS;
+    return s;
+}
+
+qt_status me_plan_result(qt_me_plan *P, int32_t i, double *expect_out, double *rho_final, qt_stats *stats)
+{
+    if (i < 0 || i >= (int32_t)P->probs.size()) return set_error(QT_EINVAL, "problem index out of range");
+    QT_HIP(hipSetDevice(P->ctx->device));
+    const MeProb &m = P->probs[i];
+    const size_t es = state_es(P->prec);
+    const size_t nvec = (size_t)m.d * m.d;
+    int32_t status;
+    int32_t parity = 0;
+    double scale = 1.0;
+    qt_stats sst;
+    std::memset(&sst, 0, sizeof(sst));
+    const void *ystate = nullptr;
+    if (!m.dense) {
+        const CsrCtl &c = P->h_cctl[m.slot];
+        status = c.status;
+        parity = c.parity;
+        scale = c.scale;
+        sst.n_accept = c.n_accept;
+        sst.n_reject = c.n_reject;
+        sst.n_rhs = c.n_rhs;
+        ystate = (const char *)P->arena.at(m.o_vec) + parity * nvec * es;
+    } else {
+        const DenseCtl &c = P->h_dctl[m.slot];
+        status = c.status;
+        scale = c.scale;
+        parity = c.parity;
+        sst.n_accept = c.n_accept;
+        sst.n_reject = c.n_reject;
+        sst.n_rhs = c.n_rhs;
+        const size_t np = (size_t)dense_np(m.d);
+        ystate = (const char *)P->arena.at(m.o_vec) + parity * np * np * es;
+    }
+    sst.status = status_code(status);
+    sst.device_ms = P->last_ms;
+    if (stats) *stats = sst;
+    if (expect_out && m.ne > 0)
+        QT_HIP(hipMemcpy(expect_out, P->arena.at(m.o_expect), (size_t)m.ne * m.nt * 16, hipMemcpyDeviceToHost));
+    if (rho_final && m.dense) {
+        const size_t np = (size_t)dense_np(m.d);
+        std::vector<char> hv(np * np * es);
+        QT_HIP(hipMemcpy(hv.data(), ystate, hv.size(), hipMemcpyDeviceToHost));
+        dense_unpack(hv.data(), m.d, P->prec, scale, rho_final);
+    } else if (rho_final) {
+        if (P->prec == QT_F64) {
+            QT_HIP(hipMemcpy(rho_final, ystate, nvec * 16, hipMemcpyDeviceToHost));
+            for (size_t q = 0; q < 2 * nvec; ++q) rho_final[q] *= scale;
+        } else {
+            std::vector<float> f(2 * nvec);
+            QT_HIP(hipMemcpy(f.data(), ystate, nvec * 8, hipMemcpyDeviceToHost));
+            for (size_t q = 0; q < 2 * nvec; ++q) rho_final[q] = (double)f[q] * scale;
+        }
+    }
+    return sst.status == QT_OK ? QT_OK
+                               : set_error(sst.status, "integration stopped with status " + std::to_string(sst.status));
+}
+
+}  // namespace qt
+
+using namespace qt;
+
+extern "C" {
+
+qt_status qt_me_plan_create(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, qt_me_plan **out)
+{
+    return me_plan_create(ctx, n, probs, opts, out);
+}
+
+qt_status qt_me_plan_run(qt_me_plan *plan)
+{
+    if (!plan) return set_error(QT_EINVAL, "null plan");
+    return me_plan_run(plan);
+}
+
+qt_status qt_me_plan_result(qt_me_plan *plan, int32_t i, double *expect_out, double *rho_final, qt_stats *stats)
+{
+    if (!plan) return set_error(QT_EINVAL, "null plan");
+    return me_plan_result(plan, i, expect_out, rho_final, stats);
+}
+
+qt_status qt_me_plan_destroy(qt_me_plan *P)
+{
+    if (!P) return QT_OK;
+    (void)hipSetDevice(P->ctx->device);
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->h_cctl) (void)hipHostFree(P->h_cctl);
+    if (P->h_dctl) (void)hipHostFree(P->h_dctl);
+    P->arena.release();
+    delete P;
+    return QT_OK;
+}
+
+qt_status qt_mesolve(qt_ctx *ctx, const qt_me_problem *prob, const qt_opts *opts, double *expect_out,
+                     double *rho_final, qt_stats *stats)
+{
+    qt_me_plan *P = nullptr;
+    qt_status st = qt_me_plan_create(ctx, 1, prob, opts, &P);
+    if (st) {
+        if (stats) stats->status = st;
+        return st;
+    }
+    st = qt_me_plan_run(P);
+    if (!st) st = qt_me_plan_result(P, 0, expect_out, rho_final, stats);
+    else if (stats) stats->status = st;
+    qt_me_plan_destroy(P);
+    return st;
+}
+
+qt_status qt_mesolve_batch(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts,
+                           double *const *expect_out, qt_stats *stats)
+{
+    qt_me_plan *P = nullptr;
+    qt_status st = qt_me_plan_create(ctx, n, probs, opts, &P);
+    if (st) return st;
+    st = qt_me_plan_run(P);
+    qt_status first = st;
+    for (int32_t i = 0; i < n && !st; ++i) {
+        qt_status si = qt_me_plan_result(P, i, expect_out ? expect_out[i] : nullptr, nullptr, stats ? &stats[i] : nullptr);
+        if (si && !first) first = si;
+    }
+    qt_me_plan_destroy(P);
+    return first;
+}
+
+}  // extern "C"

@@ -1,0 +1,610 @@
+// qtamd_runtime.cpp -- contexts, errors, model operators, host sparse algebra, Liouvillian
+// construction and the standalone expectation value of libqtamd.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "qt_asm.h"
+#include "qt_dense.h"
+#include "qt_host.h"
+
+namespace qt {
+
+static thread_local std::string g_err;
+
+qt_status set_error(qt_status code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+qt_status Arena::alloc()
+{
+    if (size == 0) return QT_OK;
+    hipError_t e = hipMalloc(&base, size);
+    if (e != hipSuccess) {
+        base = nullptr;
+        return set_error(e == hipErrorOutOfMemory ? QT_ENOMEM : QT_EDEVICE,
+                         std::string("hipMalloc(") + std::to_string(size) + "): " + hipGetErrorString(e));
+    }
+    return QT_OK;
+}
+
+void Arena::release()
+{
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    size = used = 0;
+}
+
+// ---- host CSR -----------------------------------------------------------------------------
+qt_status csr_from_abi(const qt_csr *A, int32_t d_expect, HCsr *out, const char *what)
+{
+    if (!A) return set_error(QT_EINVAL, std::string(what) + ": null operator");
+    if (A->rows <= 0 || A->rows != A->cols)
+        return set_error(QT_EINVAL, std::string(what) + ": operator must be square with rows > 0");
+    if (d_expect > 0 && A->rows != d_expect)
+        return set_error(QT_EINVAL, std::string(what) + ": dimension " + std::to_string(A->rows) + " != " +
+                                        std::to_string(d_expect));
+    if (A->nnz < 0 || !A->indptr || (A->nnz > 0 && (!A->indices || !A->values)))
+        return set_error(QT_EINVAL, std::string(what) + ": malformed CSR arrays");
+    const int32_t d = A->rows;
+    if (A->indptr[0] != 0 || A->indptr[d] != A->nnz)
+        return set_error(QT_EINVAL, std::string(what) + ": indptr[0] must be 0 and indptr[rows] == nnz");
+    out->d = d;
+    out->ptr.assign(d + 1, 0);
+    out->idx.clear();
+    out->val.clear();
+    std::map<int32_t, cd> row;
+    for (int32_t i = 0; i < d; ++i) {
+        if (A->indptr[i + 1] < A->indptr[i]) return set_error(QT_EINVAL, std::string(what) + ": decreasing indptr");
+        row.clear();
+        for (int64_t p = A->indptr[i]; p < A->indptr[i + 1]; ++p) {
+            const int32_t j = A->indices[p];
+            if (j < 0 || j >= d) return set_error(QT_EINVAL, std::string(what) + ": column index out of range");
+            const double re = A->values[2 * p], im = A->values[2 * p + 1];
+            if (!std::isfinite(re) || !std::isfinite(im))
+                return set_error(QT_EINVAL, std::string(what) + ": non-finite value");
+            row[j] += cd(re, im);
+        }
+        for (auto &kv : row)
+            if (kv.second != cd(0.0, 0.0)) {
+                out->idx.push_back(kv.first);
+                out->val.push_back(kv.second);
+            }
+        out->ptr[i + 1] = (int64_t)out->idx.size();
+    }
+    return QT_OK;
+}
+
+HCsr csr_zero(int32_t d)
+{
+    HCsr z;
+    z.d = d;
+    z.ptr.assign(d + 1, 0);
+    return z;
+}
+
+HCsr csr_adjoint(const HCsr &A)
+{
+    HCsr B;
+    B.d = A.d;
+    B.ptr.assign(A.d + 1, 0);
+    B.idx.resize(A.idx.size());
+    B.val.resize(A.val.size());
+    for (int32_t j : A.idx) B.ptr[j + 1]++;
+    for (int32_t i = 0; i < A.d; ++i) B.ptr[i + 1] += B.ptr[i];
+    std::vector<int64_t> fill(B.ptr.begin(), B.ptr.end() - 1);
+    for (int32_t i = 0; i < A.d; ++i)
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            const int64_t q = fill[A.idx[p]]++;
+            B.idx[q] = i;
+            B.val[q] = std::conj(A.val[p]);
+        }
+    return B;
+}
+
+// Sparse accumulator over one output row.
+struct Spa {
+    std::vector<cd> v;
+    std::vector<char> used;
+    std::vector<int32_t> list;
+    explicit Spa(int32_t d) : v(d), used(d, 0) {}
+    void add(int32_t j, cd x)
+    {
+        if (!used[j]) {
+            used[j] = 1;
+            list.push_back(j);
+            v[j] = x;
+        } else {
+            v[j] += x;
+        }
+    }
+    void flush(HCsr &out)
+    {
+        std::sort(list.begin(), list.end());
+        for (int32_t j : list) {
+            if (v[j] != cd(0.0, 0.0)) {
+                out.idx.push_back(j);
+                out.val.push_back(v[j]);
+            }
+            used[j] = 0;
+        }
+        list.clear();
+    }
+};
+
+HCsr csr_matmul(const HCsr &A, const HCsr &B)
+{
+    HCsr C;
+    C.d = A.d;
+    C.ptr.assign(A.d + 1, 0);
+    Spa s(A.d);
+    for (int32_t i = 0; i < A.d; ++i) {
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            const int32_t k = A.idx[p];
+            for (int64_t q = B.ptr[k]; q < B.ptr[k + 1]; ++q) s.add(B.idx[q], A.val[p] * B.val[q]);
+        }
+        s.flush(C);
+        C.ptr[i + 1] = (int64_t)C.idx.size();
+    }
+    return C;
+}
+
+HCsr csr_axpby(cd a, const HCsr &A, cd b, const HCsr &B)
+{
+    HCsr C;
+    C.d = A.d;
+    C.ptr.assign(A.d + 1, 0);
+    Spa s(A.d);
+    for (int32_t i = 0; i < A.d; ++i) {
+        for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) s.add(A.idx[p], a * A.val[p]);
+        for (int64_t p = B.ptr[i]; p < B.ptr[i + 1]; ++p) s.add(B.idx[p], b * B.val[p]);
+        s.flush(C);
+        C.ptr[i + 1] = (int64_t)C.idx.size();
+    }
+    return C;
+}
+
+int choose_lpr(int64_t n, double mean_row)
+{
+    // Lanes per row: enough lanes that each strides ~2-3 non-zeros, fewer when rows are short.
+    (void)n;
+    if (mean_row <= 3.0) return 2;
+    if (mean_row <= 8.0) return 4;
+    if (mean_row <= 40.0) return 8;
+    return 16;
+}
+
+}  // namespace qt
+
+using namespace qt;
+
+// ===============================================================================================
+// Public ABI
+// ===============================================================================================
+extern "C" {
+
+void qt_opts_default(qt_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->abstol = 1e-8;
+    o->reltol = 1e-6;
+    o->max_steps = 1000000;
+    o->h0 = 0.0;
+    o->precision = QT_F64;
+    o->form = QT_FORM_CSR;
+    o->steps_per_launch = 0;
+}
+
+const char *qt_last_error(void) { return g_err.c_str(); }
+const char *qt_version(void) { return "qtamd 0.1 (gfx950)"; }
+
+qt_status qt_ctx_create(int32_t device, void *hip_stream, qt_ctx **out)
+{
+    if (!out) return set_error(QT_EINVAL, "qt_ctx_create: null out");
+    int n = 0;
+    QT_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return set_error(QT_EINVAL, "qt_ctx_create: no such device");
+    QT_HIP(hipSetDevice(device));
+    qt_ctx *c = new qt_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipSuccess;
+    if (!c->stream) {
+        // the legacy null stream cannot be captured into a graph: use a stream of our own
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        c->own_stream = true;
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    for (int k = 0; k < Ctx::NPOOL && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&c->pool[k], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return set_error(QT_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return QT_OK;
+}
+
+qt_status qt_ctx_destroy(qt_ctx *ctx)
+{
+    if (!ctx) return QT_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    for (int k = 0; k < Ctx::NPOOL; ++k)
+        if (ctx->pool[k]) (void)hipStreamDestroy(ctx->pool[k]);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return QT_OK;
+}
+
+// ---- model operators ----------------------------------------------------------------------------
+static void to_abi(const HCsr &A, qt_csr *out)
+{
+    int64_t *ip = (int64_t *)std::malloc(sizeof(int64_t) * (A.d + 1));
+    int32_t *ix = (int32_t *)std::malloc(sizeof(int32_t) * std::max<int64_t>(1, A.nnz()));
+    double *v = (double *)std::malloc(sizeof(double) * 2 * std::max<int64_t>(1, A.nnz()));
+    std::memcpy(ip, A.ptr.data(), sizeof(int64_t) * (A.d + 1));
+    for (int64_t p = 0; p < A.nnz(); ++p) {
+        ix[p] = A.idx[p];
+        v[2 * p] = A.val[p].real();
+        v[2 * p + 1] = A.val[p].imag();
+    }
+    out->rows = out->cols = A.d;
+    out->nnz = A.nnz();
+    out->indptr = ip;
+    out->indices = ix;
+    out->values = v;
+}
+
+void qt_csr_free(qt_csr *A)
+{
+    if (!A) return;
+    std::free((void *)A->indptr);
+    std::free((void *)A->indices);
+    std::free((void *)A->values);
+    A->indptr = nullptr;
+    A->indices = nullptr;
+    A->values = nullptr;
+    A->nnz = 0;
+}
+
+qt_status qt_model_kerr(int32_t N, double delta, double U, double F, double kappa, qt_csr *H, qt_csr *c)
+{
+    if (N < 1 || !H || !c || kappa < 0) return set_error(QT_EINVAL, "qt_model_kerr: bad arguments");
+    // Fock basis: a|n> = sqrt(n)|n-1>, so a_{n-1,n} = sqrt(n); a^dag a a^dag... in closed form:
+    // H_nn = delta n + (U/2) n (n-1);  H_{n,n+1} = H_{n+1,n} = F sqrt(n+1).
+    HCsr h;
+    h.d = N;
+    h.ptr.assign(N + 1, 0);
+    for (int32_t n = 0; n < N; ++n) {
+        if (n > 0 && F != 0.0) {
+            h.idx.push_back(n - 1);
+            h.val.push_back(cd(F * std::sqrt((double)n), 0.0));
+        }
+        const double diag = delta * n + 0.5 * U * n * (n - 1.0);
+        if (diag != 0.0) {
+            h.idx.push_back(n);
+            h.val.push_back(cd(diag, 0.0));
+        }
+        if (n + 1 < N && F != 0.0) {
+            h.idx.push_back(n + 1);
+            h.val.push_back(cd(F * std::sqrt((double)(n + 1)), 0.0));
+        }
+        h.ptr[n + 1] = (int64_t)h.idx.size();
+    }
+    HCsr a;
+    a.d = N;
+    a.ptr.assign(N + 1, 0);
+    const double sk = std::sqrt(kappa);
+    for (int32_t n = 0; n < N; ++n) {
+        if (n + 1 < N && sk != 0.0) {
+            a.idx.push_back(n + 1);
+            a.val.push_back(cd(sk * std::sqrt((double)(n + 1)), 0.0));
+        }
+        a.ptr[n + 1] = (int64_t)a.idx.size();
+    }
+    to_abi(h, H);
+    to_abi(a, c);
+    return QT_OK;
+}
+
+qt_status qt_model_ising(int32_t L, double J, double h, double gamma, qt_csr *H, qt_csr *c_ops)
+{
+    if (L < 1 || L > 14 || !H || !c_ops || gamma < 0) return set_error(QT_EINVAL, "qt_model_ising: bad arguments");
+    const int32_t d = 1 << L;
+    // basis index bit (L-1-i) holds spin i (spin 0 most significant); bit value 0 = up (sz = +1).
+    auto sz = [&](int32_t s, int i) { return ((s >> (L - 1 - i)) & 1) ? -1.0 : 1.0; };
+    HCsr hh;
+    hh.d = d;
+    hh.ptr.assign(d + 1, 0);
+    for (int32_t s = 0; s < d; ++s) {
+        std::vector<std::pair<int32_t, double>> row;
+        double diag = 0.0;
+        for (int i = 0; i + 1 < L; ++i) diag += J * sz(s, i) * sz(s, i + 1);
+        if (diag != 0.0) row.push_back({s, diag});
+        if (h != 0.0)
+            for (int i = 0; i < L; ++i) row.push_back({s ^ (1 << (L - 1 - i)), h});
+        std::sort(row.begin(), row.end());
+        for (auto &e : row) {
+            hh.idx.push_back(e.first);
+            hh.val.push_back(cd(e.second, 0.0));
+        }
+        hh.ptr[s + 1] = (int64_t)hh.idx.size();
+    }
+    to_abi(hh, H);
+    const double sg = std::sqrt(gamma);
+    for (int i = 0; i < L; ++i) {
+        // sigma_- on spin i: |down><up|, row = state with spin i down, column = same with spin i up
+        HCsr c;
+        c.d = d;
+        c.ptr.assign(d + 1, 0);
+        const int32_t bit = 1 << (L - 1 - i);
+        for (int32_t s = 0; s < d; ++s) {
+            if ((s & bit) && sg != 0.0) {
+                c.idx.push_back(s ^ bit);
+                c.val.push_back(cd(sg, 0.0));
+            }
+            c.ptr[s + 1] = (int64_t)c.idx.size();
+        }
+        to_abi(c, &c_ops[i]);
+    }
+    return QT_OK;
+}
+
+// ---- Liouvillian ----------------------------------------------------------------------------------
+static qt_status upload_csr32(const HCsr &A, std::vector<int32_t> &rp, std::vector<int32_t> &ci,
+                              std::vector<double2> &v)
+{
+    if (A.nnz() >= 2147483647LL) return set_error(QT_EINVAL, "operator has too many non-zeros");
+    rp.resize(A.d + 1);
+    for (int32_t i = 0; i <= A.d; ++i) rp[i] = (int32_t)A.ptr[i];
+    ci.assign(A.idx.begin(), A.idx.end());
+    v.resize(A.nnz());
+    for (int64_t p = 0; p < A.nnz(); ++p) v[p] = make_double2(A.val[p].real(), A.val[p].imag());
+    return QT_OK;
+}
+
+qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const qt_csr *c_ops, int32_t form,
+                               int32_t precision, qt_liouv **out)
+{
+    if (!ctx || !H || !out || n_c < 0 || (n_c > 0 && !c_ops))
+        return set_error(QT_EINVAL, "qt_liouvillian_build: null argument");
+    if (precision != QT_F64 && precision != QT_MIXED) return set_error(QT_EINVAL, "bad precision");
+    if (form != QT_FORM_CSR && form != QT_FORM_DENSE) return set_error(QT_EINVAL, "bad form");
+    HCsr h;
+    qt_status st = csr_from_abi(H, 0, &h, "H");
+    if (st) return st;
+    const int32_t d = h.d;
+    std::vector<HCsr> cs(n_c);
+    for (int k = 0; k < n_c; ++k)
+        if ((st = csr_from_abi(&c_ops[k], d, &cs[k], "c_ops"))) return st;
+    QT_HIP(hipSetDevice(ctx->device));
+    // A = -i H - 1/2 sum_k C_k^dag C_k
+    HCsr A = csr_axpby(cd(0.0, -1.0), h, cd(0.0, 0.0), csr_zero(d));
+    for (auto &c : cs) A = csr_axpby(cd(1.0, 0.0), A, cd(-0.5, 0.0), csr_matmul(csr_adjoint(c), c));
+
+    qt_liouv *L = new qt_liouv();
+    L->ctx = ctx;
+    L->form = form;
+    L->precision = precision;
+    L->d = d;
+    L->nc = n_c;
+    const size_t es = precision == QT_F64 ? sizeof(double2) : sizeof(float2);
+
+    if (form == QT_FORM_DENSE) {
+        const int32_t np = dense_np(d);
+        if (np > (precision == QT_F64 ? DENSE_MAX_NP_F64 : DENSE_MAX_NP_F32)) {
+            delete L;
+            return set_error(QT_EINVAL, "dense form supports d <= 96 (mixed) or d <= 64 (FP64)");
+        }
+        // A then C_k, each zero padded to np x np (np = d rounded up to a multiple of 16)
+        const size_t mat = (size_t)np * np;
+        std::vector<double2> host((1 + n_c) * mat, make_double2(0.0, 0.0));
+        auto put = [&](const HCsr &M, size_t base) {
+            for (int32_t i = 0; i < d; ++i)
+                for (int64_t p = M.ptr[i]; p < M.ptr[i + 1]; ++p)
+                    host[base + (size_t)i * np + M.idx[p]] = make_double2(M.val[p].real(), M.val[p].imag());
+        };
+        put(A, 0);
+        for (int k = 0; k < n_c; ++k) put(cs[k], (1 + k) * mat);
+        L->bytes = (int64_t)(host.size() * es);
+        hipError_t e = hipMalloc(&L->dense, L->bytes);
+        if (e != hipSuccess) {
+            delete L;
+            return set_error(QT_ENOMEM, "hipMalloc dense operators");
+        }
+        if (precision == QT_F64) {
+            e = hipMemcpy(L->dense, host.data(), L->bytes, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float2> hf(host.size());
+            for (size_t i = 0; i < host.size(); ++i) hf[i] = make_float2((float)host[i].x, (float)host[i].y);
+            e = hipMemcpy(L->dense, hf.data(), L->bytes, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            (void)hipFree(L->dense);
+            delete L;
+            return set_error(QT_EDEVICE, "upload dense operators");
+        }
+        *out = L;
+        return QT_OK;
+    }
+
+    // CSR form: device assembly
+    std::vector<int32_t> arp, aci;
+    std::vector<double2> av;
+    if ((st = upload_csr32(A, arp, aci, av))) {
+        delete L;
+        return st;
+    }
+    std::vector<int32_t> crp((size_t)n_c * (d + 1)), cci;
+    std::vector<double2> cv;
+    for (int k = 0; k < n_c; ++k) {
+        const int32_t base = (int32_t)cci.size();
+        for (int32_t i = 0; i <= d; ++i) crp[(size_t)k * (d + 1) + i] = base + (int32_t)cs[k].ptr[i];
+        for (int64_t p = 0; p < cs[k].nnz(); ++p) {
+            cci.push_back(cs[k].idx[p]);
+            cv.push_back(make_double2(cs[k].val[p].real(), cs[k].val[p].imag()));
+        }
+    }
+    const int64_t n = (int64_t)d * d;
+    if (n >= 2147483647LL) {
+        delete L;
+        return set_error(QT_EINVAL, "Liouvillian too large for int32 indexing");
+    }
+    Arena tmp;
+    const size_t o_arp = tmp.reserve(arp.size() * 4), o_aci = tmp.reserve(std::max<size_t>(1, aci.size()) * 4),
+                 o_av = tmp.reserve(std::max<size_t>(1, av.size()) * 16),
+                 o_crp = tmp.reserve(std::max<size_t>(1, crp.size()) * 4),
+                 o_cci = tmp.reserve(std::max<size_t>(1, cci.size()) * 4),
+                 o_cv = tmp.reserve(std::max<size_t>(1, cv.size()) * 16), o_cnt = tmp.reserve((size_t)n * 4),
+                 o_bs = tmp.reserve(((size_t)(n + 1023) / 1024 + 1) * 8), o_fl = tmp.reserve(64);
+    if ((st = tmp.alloc())) {
+        delete L;
+        return st;
+    }
+    hipStream_t s = ctx->stream;
+    auto cp = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(tmp.at(off), src, bytes, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e = hipSuccess;
+    e = e ? e : cp(o_arp, arp.data(), arp.size() * 4);
+    e = e ? e : cp(o_aci, aci.data(), aci.size() * 4);
+    e = e ? e : cp(o_av, av.data(), av.size() * 16);
+    e = e ? e : cp(o_crp, crp.data(), crp.size() * 4);
+    e = e ? e : cp(o_cci, cci.data(), cci.size() * 4);
+    e = e ? e : cp(o_cv, cv.data(), cv.size() * 16);
+    e = e ? e : hipMemsetAsync(tmp.at(o_fl), 0, 64, s);
+    AsmOps op{d,
+              n_c,
+              (const int32_t *)tmp.at(o_arp),
+              (const int32_t *)tmp.at(o_aci),
+              (const double2 *)tmp.at(o_av),
+              (const int32_t *)tmp.at(o_crp),
+              (const int32_t *)tmp.at(o_cci),
+              (const double2 *)tmp.at(o_cv)};
+    int32_t *counts = (int32_t *)tmp.at(o_cnt);
+    int *flags = (int *)tmp.at(o_fl);
+    e = e ? e : hipMalloc(&L->rowptr, (size_t)(n + 1) * 4);
+    if (e == hipSuccess) {
+        asm_launch_count(op, counts, flags, s);
+        asm_launch_scan(counts, n, (int64_t *)tmp.at(o_bs), L->rowptr, flags, s);
+        e = hipGetLastError();
+    }
+    int hflags[2] = {0, 0};
+    int32_t total = 0;
+    e = e ? e : hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s);
+    e = e ? e : hipMemcpyAsync(&total, L->rowptr + n, 4, hipMemcpyDeviceToHost, s);
+    e = e ? e : hipStreamSynchronize(s);
+    if (e == hipSuccess && (hflags[0] || hflags[1])) {
+        tmp.release();
+        (void)hipFree(L->rowptr);
+        delete L;
+        return set_error(QT_EINVAL, hflags[0] ? "Liouvillian row has too many candidate entries for CSR assembly "
+                                                "(use the dense form)"
+                                              : "Liouvillian has more than 2^31 non-zeros");
+    }
+    if (e == hipSuccess) {
+        L->nnz = total;
+        e = hipMalloc(&L->col, std::max<size_t>(1, (size_t)total) * 4);
+        if (e == hipSuccess) e = hipMalloc(&L->val, std::max<size_t>(1, (size_t)total) * es);
+        if (e == hipSuccess) {
+            asm_launch_fill(op, L->rowptr, L->col, L->val, precision == QT_F64, s);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    tmp.release();
+    if (e != hipSuccess) {
+        if (L->rowptr) (void)hipFree(L->rowptr);
+        if (L->col) (void)hipFree(L->col);
+        if (L->val) (void)hipFree(L->val);
+        delete L;
+        return set_error(QT_EDEVICE, std::string("Liouvillian assembly: ") + hipGetErrorString(e));
+    }
+    L->bytes = (int64_t)((n + 1) * 4 + L->nnz * (4 + (int64_t)es));
+    *out = L;
+    return QT_OK;
+}
+
+qt_status qt_liouv_info(const qt_liouv *L, int32_t *d, int64_t *nnz, int64_t *bytes)
+{
+    if (!L) return set_error(QT_EINVAL, "null Liouvillian");
+    if (d) *d = L->d;
+    if (nnz) *nnz = L->nnz;
+    if (bytes) *bytes = L->bytes;
+    return QT_OK;
+}
+
+qt_status qt_liouv_export(const qt_liouv *L, int64_t *indptr, int32_t *indices, double *values)
+{
+    if (!L || L->form != QT_FORM_CSR || !indptr || !indices || !values)
+        return set_error(QT_EINVAL, "qt_liouv_export: CSR Liouvillian and output arrays required");
+    QT_HIP(hipSetDevice(L->ctx->device));
+    const int64_t n = (int64_t)L->d * L->d;
+    std::vector<int32_t> rp(n + 1);
+    QT_HIP(hipMemcpy(rp.data(), L->rowptr, (n + 1) * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i <= n; ++i) indptr[i] = rp[i];
+    if (L->nnz) QT_HIP(hipMemcpy(indices, L->col, L->nnz * 4, hipMemcpyDeviceToHost));
+    if (L->precision == QT_F64) {
+        if (L->nnz) QT_HIP(hipMemcpy(values, L->val, L->nnz * 16, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float2> f(L->nnz);
+        if (L->nnz) QT_HIP(hipMemcpy(f.data(), L->val, L->nnz * 8, hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < L->nnz; ++p) {
+            values[2 * p] = f[p].x;
+            values[2 * p + 1] = f[p].y;
+        }
+    }
+    return QT_OK;
+}
+
+qt_status qt_liouv_destroy(qt_liouv *L)
+{
+    if (!L) return QT_OK;
+    (void)hipSetDevice(L->ctx->device);
+    if (L->rowptr) (void)hipFree(L->rowptr);
+    if (L->col) (void)hipFree(L->col);
+    if (L->val) (void)hipFree(L->val);
+    if (L->dense) (void)hipFree(L->dense);
+    delete L;
+    return QT_OK;
+}
+
+// ---- expectation value ------------------------------------------------------------------------------
+qt_status qt_expect(qt_ctx *ctx, int32_t d, const qt_csr *O, const void *dev_state, int32_t is_ket,
+                    int32_t precision, double *out)
+{
+    if (!ctx || !O || !dev_state || !out || d <= 0) return set_error(QT_EINVAL, "qt_expect: null argument");
+    if (precision != QT_F64 && precision != QT_MIXED) return set_error(QT_EINVAL, "qt_expect: bad precision");
+    HCsr o;
+    qt_status st = csr_from_abi(O, d, &o, "O");
+    if (st) return st;
+    std::vector<int32_t> rp, ci;
+    std::vector<double2> v;
+    if ((st = upload_csr32(o, rp, ci, v))) return st;
+    QT_HIP(hipSetDevice(ctx->device));
+    Arena a;
+    const size_t o_rp = a.reserve(rp.size() * 4), o_ci = a.reserve(std::max<size_t>(1, ci.size()) * 4),
+                 o_v = a.reserve(std::max<size_t>(1, v.size()) * 16), o_out = a.reserve(16);
+    if ((st = a.alloc())) return st;
+    hipStream_t s = ctx->stream;
+    hipError_t e = hipMemcpyAsync(a.at(o_rp), rp.data(), rp.size() * 4, hipMemcpyHostToDevice, s);
+    if (!e && !ci.empty()) e = hipMemcpyAsync(a.at(o_ci), ci.data(), ci.size() * 4, hipMemcpyHostToDevice, s);
+    if (!e && !v.empty()) e = hipMemcpyAsync(a.at(o_v), v.data(), v.size() * 16, hipMemcpyHostToDevice, s);
+    if (!e) {
+        launch_expect(precision == QT_F64, d, (const int32_t *)a.at(o_rp), (const int32_t *)a.at(o_ci),
+                      (const double2 *)a.at(o_v), dev_state, is_ket, (double2 *)a.at(o_out), s);
+        e = hipGetLastError();
+    }
+    if (!e) e = hipMemcpyAsync(out, a.at(o_out), 16, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    a.release();
+    if (e) return set_error(QT_EDEVICE, std::string("qt_expect: ") + hipGetErrorString(e));
+    return QT_OK;
+}
+
+}  // extern "C"
