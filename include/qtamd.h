@@ -117,8 +117,9 @@ void qt_csr_free(qt_csr *A);
  *     L = A (x) I + I (x) conj(A) + sum_k C_k (x) conj(C_k),   A = -i H - 1/2 sum_k C_k^dag C_k,
  * for the row-major vec, drops exact zeros, stores values as complex128 (QT_F64) or complex64
  * (QT_MIXED) with int32 indices (nnz < 2^31).
- * form QT_FORM_DENSE: stores A and the C_k as dense d x d matrices (d <= 128) for the batched
- * MFMA right-hand side.  Errors: QT_EINVAL for mismatched sizes or malformed CSR. */
+ * form QT_FORM_DENSE: stores A and the C_k as dense matrices zero-padded to a multiple of 16 for
+ * the batched MFMA right-hand side; d <= 80 (QT_MIXED) or d <= 48 (QT_F64).
+ * Errors: QT_EINVAL for mismatched sizes, malformed CSR, or a dense d above the limit. */
 qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const qt_csr *c_ops, int32_t form,
                                int32_t precision, qt_liouv **out);
 /* d, stored non-zeros (CSR form; 0 for dense), device bytes held. */
@@ -157,6 +158,12 @@ qt_status qt_me_plan_create(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, 
 qt_status qt_me_plan_run(qt_me_plan *plan);
 qt_status qt_me_plan_result(qt_me_plan *plan, int32_t i, double *expect_out, double *rho_final, qt_stats *stats);
 qt_status qt_me_plan_destroy(qt_me_plan *plan);
+/* Measurement: average device duration (HIP events on the plan's stream) of one right-hand-side
+ * launch over `reps` back-to-back launches.  CSR problems: one fused SpMV-stage kernel (the stage
+ * that forms the fourth stage input) over every CSR problem of the plan, from a freshly reset
+ * state.  Plans with only dense problems: one whole-solve launch of the dense kernels.  The plan's
+ * results are unspecified afterwards until the next qt_me_plan_run. */
+qt_status qt_me_plan_time_rhs(qt_me_plan *plan, int32_t reps, double *ms_per_launch);
 
 /* Expectation value (Sec. 3.1 e_ops; App. C expect): out = Tr(O rho) for a device density
  * matrix, or <psi|O|psi>/<psi|psi> for a device ket (is_ket), state stored complex128

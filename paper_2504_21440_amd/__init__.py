@@ -23,7 +23,7 @@ EXPORTED = [
     "qt_opts_default", "qt_last_error", "qt_version", "qt_ctx_create", "qt_ctx_destroy", "qt_model_kerr",
     "qt_model_ising", "qt_csr_free", "qt_liouvillian_build", "qt_liouv_info", "qt_liouv_export",
     "qt_liouv_destroy", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
-    "qt_me_plan_result", "qt_me_plan_destroy", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
+    "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
     "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_server_create", "qt_server_submit", "qt_server_step",
     "qt_server_poll", "qt_server_footprint", "qt_server_destroy",
 ]
@@ -268,6 +268,12 @@ class MePlan:
         if check:
             _check(rc)
         return ex[:ne], st.as_dict(), fin
+
+    def time_rhs(self, reps=100):
+        """Average device milliseconds of one right-hand-side launch (qt_me_plan_time_rhs)."""
+        ms = ctypes.c_double()
+        _check(lib().qt_me_plan_time_rhs(self.h, int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def close(self):
         if self.h:

@@ -3,25 +3,30 @@
 // The right-hand side is the sparse Liouvillian superoperator applied to vec(rho)
 // (arXiv:2504.21440, Sec. 3.2, eq. eq-lindblad-master-equation): an HBM-bound complex CSR SpMV.
 // A Dormand-Prince 5(4) step is six SpMV launches (stages 2..7; stage 1 is the previous step's
-// stage 7).  Each SpMV carries the Runge-Kutta work of its row in its epilogue: the next stage
-// input (stages 2..5), the fifth-order solution (stage 6), or the weighted error contribution
-// (stage 7).  The last block of each instance to finish stage 7 reduces the error in FP64,
-// accepts or rejects, picks the next step size, lands on save times, renormalises the trace
-// (mixed precision) and records Tr(O rho) -- so the host never sits inside the step loop.
+// stage 7) and one control launch.  Each SpMV carries the Runge-Kutta work of its row in its
+// epilogue: the next stage input (stages 2..5), the fifth-order solution (stage 6), or the weighted
+// error contribution (stage 7, reduced per block).  The control kernel -- one workgroup per problem
+// -- sums the block partials in a fixed order (FP64), accepts or rejects, picks the next step size,
+// lands on save times, renormalises the trace (mixed precision) and records Tr(O rho), so the host
+// never sits inside the step loop and no block waits on another.
 //
-// Rows are split over LPR lanes (vector CSR): the LPR lanes of a group stride the row's
-// non-zeros with coalesced loads and combine with xor shuffles inside the 64-wide wavefront.
+// Rows are split over LPR lanes (vector CSR): the LPR lanes of a group stride the row's non-zeros;
+// every lane first issues all of its column / value loads (non-temporal: the matrix is streamed
+// once per evaluation and should not evict the state vectors from L2 / MALL), then the gathers,
+// then the complex FMAs, and the group combines with xor shuffles inside the 64-wide wavefront.
 #include "qt_common.h"
 #include "qt_csr.h"
 
 namespace qt {
 
 constexpr int CSR_THREADS = 256;
+constexpr int CTL_THREADS = 256;
 enum : int32_t { PH_STEP = 0, PH_INIT1 = 1, PH_INIT0 = 2 };
 
 template <int LPR> struct CsrGeom {
     static constexpr int RPW = 64 / LPR;
     static constexpr int RPB = (CSR_THREADS / 64) * RPW;
+    static constexpr int U = (LPR >= 8) ? 4 : (LPR == 4 ? 6 : 8);  // non-zeros in flight per lane
 };
 
 template <typename V> __device__ __forceinline__ V shfl_xor_c(V v, int m)
@@ -31,44 +36,53 @@ template <typename V> __device__ __forceinline__ V shfl_xor_c(V v, int m)
     return v;
 }
 
+typedef float nf2 __attribute__((ext_vector_type(2)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_stream(const float2 *p)
+{
+    const nf2 v = __builtin_nontemporal_load((const nf2 *)p);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+    const nd2 v = __builtin_nontemporal_load((const nd2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ int32_t ld_stream(const int32_t *p) { return __builtin_nontemporal_load(p); }
+
 // Row sum  sum_k val[k] * x(col[k])  for the LPR-lane group owning `row`; every lane of the
 // group returns the full sum.  X is a functor returning the (stage) input at a column.
 template <typename V, int LPR, typename X>
 __device__ __forceinline__ V csr_row(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                      const V *__restrict__ val, int row, bool valid, int q, X x)
 {
+    constexpr int U = CsrGeom<LPR>::U;
     V acc;
     acc.x = 0;
     acc.y = 0;
     if (valid) {
         const int s = rowptr[row], e = rowptr[row + 1];
-        for (int k = s + q; k < e; k += LPR) cfma(acc, val[k], x(col[k]));
+        for (int base = s + q; base < e; base += LPR * U) {
+            int cc[U];
+            V vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = base + u * LPR;
+                if (k < e) {
+                    cc[u] = ld_stream(col + k);
+                    vv[u] = ld_stream(val + k);
+                } else {
+                    cc[u] = -1;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (cc[u] >= 0) cfma(acc, vv[u], x(cc[u]));
+        }
     }
 #pragma unroll
     for (int m = LPR / 2; m >= 1; m >>= 1) acc = cadd(acc, shfl_xor_c(acc, m));
     return acc;
-}
-
-// Block-wide deterministic reduction of two doubles; result in thread 0 (and all threads).
-__device__ __forceinline__ void block_sum2(double &a, double &b, double *scr)
-{
-    a = block_sum(a, scr);
-    b = block_sum(b, scr);
-}
-
-// Arrive at the per-instance counter; returns true (in every thread) for the last block.
-__device__ __forceinline__ bool arrive_last(CsrCtl *C, int nblocks, int *flag)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned prev = atomicAdd(&C->arrive, 1u);
-        *flag = (prev == (unsigned)(nblocks - 1));
-    }
-    __syncthreads();
-    bool last = *flag != 0;
-    if (last) __threadfence();
-    return last;
 }
 
 // Expectation values of the state Y (times `scale`) into expect[k][idx], FP64 accumulation:
@@ -88,7 +102,8 @@ __device__ void csr_record_expect(const CsrInst &I, const V *__restrict__ Y, dou
                 si += o.x * r.y + o.y * r.x;
             }
         }
-        block_sum2(sr, si, scr);
+        sr = block_sum(sr, scr);
+        si = block_sum(si, scr);
         if (threadIdx.x == 0) I.expect[(size_t)k * I.nt + idx] = make_double2(sr * scale, si * scale);
     }
 }
@@ -98,6 +113,14 @@ template <typename V> __device__ double csr_trace(const CsrInst &I, const V *__r
     double s = 0.0;
     for (int i = threadIdx.x; i < I.d; i += blockDim.x) s += (double)Y[(size_t)i * I.d + i].x;
     return block_sum(s, scr);
+}
+
+// Fixed-order sum of one partial column over the instance's blocks.
+__device__ __forceinline__ double sum_partials(const CsrInst &I, int col, double *scr)
+{
+    double t = 0.0;
+    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) t += I.partials[2 * k + col];
+    return block_sum(t, scr);
 }
 
 __global__ void k_csr_reset(const CsrInst *__restrict__ insts, CsrCtl *__restrict__ ctls, int ninst)
@@ -125,20 +148,19 @@ __global__ void k_csr_reset(const CsrInst *__restrict__ insts, CsrCtl *__restric
     ctls[i] = c;
 }
 
-// Starting step, first evaluation: k1 = L rho0, y <- rho0, d0 = |y|, d1 = |f(y)| (weighted RMS).
+// Starting step, first evaluation: k1 = L rho0, y <- rho0, partials of |y|^2/sc^2 and |f(y)|^2/sc^2.
 template <typename T, int LPR>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__restrict__ insts,
-                                                           CsrCtl *__restrict__ ctls,
+                                                           const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ blk_inst,
                                                            const int32_t *__restrict__ blk_row0)
 {
     using V = typename vec2<T>::type;
     __shared__ double scr[16];
-    __shared__ int flag;
     const int b = blockIdx.x;
     const int ii = blk_inst[b];
     const CsrInst &I = insts[ii];
-    CsrCtl *C = ctls + ii;
+    const CsrCtl *C = ctls + ii;
     if (C->status != ST_RUNNING || C->phase != PH_INIT0) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q = lane % LPR;
@@ -156,58 +178,27 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__rest
         sa = abs2d(y) / (sc * sc);
         sb = abs2d(acc) / (sc * sc);
     }
-    block_sum2(sa, sb, scr);
+    sa = block_sum(sa, scr);
+    sb = block_sum(sb, scr);
     if (threadIdx.x == 0) {
         I.partials[2 * (b - I.block0)] = sa;
         I.partials[2 * (b - I.block0) + 1] = sb;
     }
-    if (!arrive_last(C, I.nblocks, &flag)) return;
-    // ---- last block of this instance ----
-    double ta = 0.0, tb = 0.0;
-    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) {
-        ta += I.partials[2 * k];
-        tb += I.partials[2 * k + 1];
-    }
-    block_sum2(ta, tb, scr);
-    const double tr = csr_trace(I, x0, scr);
-    csr_record_expect(I, x0, 1.0, 0, scr);
-    if (threadIdx.x == 0) {
-        C->tr0 = tr;
-        C->n_rhs += 1;
-        C->arrive = 0u;
-        if (I.nt <= 1) {
-            C->status = ST_DONE;
-        } else {
-            const double d0 = sqrt(ta / I.n), d1 = sqrt(tb / I.n);
-            if (I.use_h0) {
-                C->h = I.h0;
-                C->phase = PH_STEP;
-                int32_t land;
-                C->h_try = clip_step(C->t, C->h, I.tlist[1], &land);
-                C->land = land;
-            } else {
-                C->h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-                C->last_err = d1;
-                C->phase = PH_INIT1;
-            }
-        }
-    }
 }
 
-// Starting step, second evaluation: d2 = |f(y + h0 f(y)) - f(y)| / h0; h = min(100 h0, h1).
+// Starting step, second evaluation: partials of |f(y + h0 f(y)) - f(y)|^2 / (h0 sc)^2.
 template <typename T, int LPR>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__restrict__ insts,
-                                                           CsrCtl *__restrict__ ctls,
+                                                           const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ blk_inst,
                                                            const int32_t *__restrict__ blk_row0)
 {
     using V = typename vec2<T>::type;
     __shared__ double scr[16];
-    __shared__ int flag;
     const int b = blockIdx.x;
     const int ii = blk_inst[b];
     const CsrInst &I = insts[ii];
-    CsrCtl *C = ctls + ii;
+    const CsrCtl *C = ctls + ii;
     if (C->status != ST_RUNNING || C->phase != PH_INIT1) return;
     const double h0 = C->h0;
     const T th0 = (T)h0;
@@ -222,7 +213,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__rest
         caxpy(v, th0, k1[c]);
         return v;
     });
-    double sa = 0.0, sb = 0.0;
+    double sa = 0.0;
     if (valid && q == 0) {
         const double2 yr = to_d2(y[row]);
         const double2 a = to_d2(acc), f0 = to_d2(k1[row]);
@@ -230,40 +221,23 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__rest
         const double dx = (a.x - f0.x) / h0, dy = (a.y - f0.y) / h0;
         sa = (dx * dx + dy * dy) / (sc * sc);
     }
-    block_sum2(sa, sb, scr);
+    sa = block_sum(sa, scr);
     if (threadIdx.x == 0) I.partials[2 * (b - I.block0)] = sa;
-    if (!arrive_last(C, I.nblocks, &flag)) return;
-    double ta = 0.0;
-    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) ta += I.partials[2 * k];
-    ta = block_sum(ta, scr);
-    if (threadIdx.x == 0) {
-        const double d2 = sqrt(ta / I.n), d1 = C->last_err;
-        const double m = fmax(d1, d2);
-        const double h1 = (m <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / m, 0.2);
-        C->h = fmin(100.0 * h0, h1);
-        C->phase = PH_STEP;
-        C->n_rhs += 1;
-        C->arrive = 0u;
-        int32_t land;
-        C->h_try = clip_step(C->t, C->h, I.tlist[1], &land);
-        C->land = land;
-    }
 }
 
 // One Runge-Kutta stage S (2..7) of a DP5 step for every running instance.
 template <typename T, int LPR, int S>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__restrict__ insts,
-                                                           CsrCtl *__restrict__ ctls,
+                                                           const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ blk_inst,
                                                            const int32_t *__restrict__ blk_row0)
 {
     using V = typename vec2<T>::type;
     __shared__ double scr[16];
-    __shared__ int flag;
     const int b = blockIdx.x;
     const int ii = blk_inst[b];
     const CsrInst &I = insts[ii];
-    CsrCtl *C = ctls + ii;
+    const CsrCtl *C = ctls + ii;
     if (C->status != ST_RUNNING || C->phase != PH_STEP) return;
     const double h = C->h_try;
     const int p = C->parity;
@@ -353,32 +327,85 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
             e2 = (e.x * e.x + e.y * e.y) / (sc * sc);
         }
     }
-    if (S != 7) return;
+    if (S == 7) {
+        e2 = block_sum(e2, scr);
+        if (threadIdx.x == 0) I.partials[2 * (b - I.block0)] = e2;
+    }
+}
 
-    // ---- stage 7: error reduction and step control ----
-    e2 = block_sum(e2, scr);
-    if (threadIdx.x == 0) I.partials[2 * (b - I.block0)] = e2;
-    if (!arrive_last(C, I.nblocks, &flag)) return;
-    double tot = 0.0;
-    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) tot += I.partials[2 * k];
-    tot = block_sum(tot, scr);
+// Control: one workgroup per problem.  Acts according to the problem's phase.
+template <typename T>
+__global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__restrict__ insts,
+                                                             CsrCtl *__restrict__ ctls)
+{
+    using V = typename vec2<T>::type;
+    __shared__ double scr[16];
+    const int ii = blockIdx.x;
+    const CsrInst &I = insts[ii];
+    CsrCtl *C = ctls + ii;
+    if (C->status != ST_RUNNING) return;
+    const int phase = C->phase;
+    if (phase == PH_INIT0) {
+        const double ta = sum_partials(I, 0, scr), tb = sum_partials(I, 1, scr);
+        const V *x0 = (const V *)I.rho0;
+        const double tr = csr_trace(I, x0, scr);
+        csr_record_expect(I, x0, 1.0, 0, scr);
+        if (threadIdx.x == 0) {
+            C->tr0 = tr;
+            C->n_rhs += 1;
+            if (I.nt <= 1) {
+                C->status = ST_DONE;
+            } else {
+                const double d0 = sqrt(ta / I.n), d1 = sqrt(tb / I.n);
+                if (I.use_h0) {
+                    C->h = I.h0;
+                    C->phase = PH_STEP;
+                    int32_t land;
+                    C->h_try = clip_step(C->t, C->h, I.tlist[1], &land);
+                    C->land = land;
+                } else {
+                    C->h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+                    C->last_err = d1;
+                    C->phase = PH_INIT1;
+                }
+            }
+        }
+        return;
+    }
+    if (phase == PH_INIT1) {
+        const double ta = sum_partials(I, 0, scr);
+        if (threadIdx.x == 0) {
+            const double h0 = C->h0;
+            const double d2 = sqrt(ta / I.n), d1 = C->last_err;
+            const double m = fmax(d1, d2);
+            const double h1 = (m <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / m, 0.2);
+            C->h = fmin(100.0 * h0, h1);
+            C->phase = PH_STEP;
+            C->n_rhs += 1;
+            int32_t land;
+            C->h_try = clip_step(C->t, C->h, I.tlist[1], &land);
+            C->land = land;
+        }
+        return;
+    }
+    // ---- step control after stage 7 ----
+    const double tot = sum_partials(I, 0, scr);
     const double err = sqrt(tot / I.n);
     const bool finite = isfinite(err);
     const bool accept = finite && err <= 1.0;
+    const double h = C->h_try;
+    const int p = C->parity;
     const int land = C->land;
     const int sidx = C->save_idx;
+    const V *ynew = (const V *)I.Y[1 - p];
     double scale_new = 1.0;
     if (accept) {
-        if (I.renorm) {
-            const double tr = csr_trace(I, (const V *)ynew, scr);
-            scale_new = C->tr0 / tr;
-        }
-        if (land) csr_record_expect(I, (const V *)ynew, scale_new, sidx, scr);
+        if (I.renorm) scale_new = C->tr0 / csr_trace(I, ynew, scr);
+        if (land) csr_record_expect(I, ynew, scale_new, sidx, scr);
     }
     if (threadIdx.x == 0) {
         C->n_steps += 1;
         C->n_rhs += 6;
-        C->arrive = 0u;
         if (!finite) {
             C->status = 6;  // QT_ENONFINITE
         } else if (accept) {
@@ -452,34 +479,11 @@ __global__ __launch_bounds__(256) void k_expect(int d, const int32_t *__restrict
 }  // namespace qt
 
 // ---------------------------------------------------------------------------------------------
-// Host-side launchers (called from the runtime in qtamd_runtime.cpp)
+// Host-side launchers (called from the runtime)
 // ---------------------------------------------------------------------------------------------
 namespace qt {
 
 int csr_rows_per_block(int lpr) { return (CSR_THREADS / 64) * (64 / lpr); }
-
-template <typename T, int LPR>
-static void launch_init_t(int which, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                          const int32_t *br, hipStream_t s)
-{
-    if (which == 0)
-        hipLaunchKernelGGL((k_csr_init0<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
-    else
-        hipLaunchKernelGGL((k_csr_init1<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
-}
-
-template <typename T, int LPR>
-static void launch_step_t(int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi, const int32_t *br,
-                          hipStream_t s)
-{
-    dim3 g(nblk), t(CSR_THREADS);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 2>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 3>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 4>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 5>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 6>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 7>), g, t, 0, s, insts, ctls, bi, br);
-}
 
 #define QT_LPR_DISPATCH(LPRV, CALL) \
     switch (LPRV) {                 \
@@ -490,27 +494,70 @@ static void launch_step_t(int nblk, const CsrInst *insts, CsrCtl *ctls, const in
     default: CALL(8); break;        \
     }
 
+template <typename T>
+static void launch_control(int ninst, const CsrInst *insts, CsrCtl *ctls, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_csr_control<T>, dim3(ninst), dim3(CTL_THREADS), 0, s, insts, ctls);
+}
+
+template <typename T, int LPR>
+static void launch_init_t(int which, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                          const int32_t *br, hipStream_t s)
+{
+    if (which == 0)
+        hipLaunchKernelGGL((k_csr_init0<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+    else
+        hipLaunchKernelGGL((k_csr_init1<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+    launch_control<T>(ninst, insts, ctls, s);
+}
+
+template <typename T, int LPR>
+static void launch_step_t(int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                          const int32_t *br, hipStream_t s)
+{
+    dim3 g(nblk), t(CSR_THREADS);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 2>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 3>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 4>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 5>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 6>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, 7>), g, t, 0, s, insts, ctls, bi, br);
+    launch_control<T>(ninst, insts, ctls, s);
+}
+
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_csr_reset, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ctls, ninst);
 }
 
-void csr_launch_init(int which, bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                     const int32_t *br, hipStream_t s)
+void csr_launch_init(int which, bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
+                     const int32_t *bi, const int32_t *br, hipStream_t s)
 {
-#define QT_CALL(L)                                                         \
-    if (f64) launch_init_t<double, L>(which, nblk, insts, ctls, bi, br, s); \
-    else launch_init_t<float, L>(which, nblk, insts, ctls, bi, br, s);
+#define QT_CALL(L)                                                                \
+    if (f64) launch_init_t<double, L>(which, nblk, ninst, insts, ctls, bi, br, s); \
+    else launch_init_t<float, L>(which, nblk, ninst, insts, ctls, bi, br, s);
     QT_LPR_DISPATCH(lpr, QT_CALL)
 #undef QT_CALL
 }
 
-void csr_launch_step(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+void csr_launch_step(bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
                      const int32_t *br, hipStream_t s)
 {
-#define QT_CALL(L)                                                   \
-    if (f64) launch_step_t<double, L>(nblk, insts, ctls, bi, br, s); \
-    else launch_step_t<float, L>(nblk, insts, ctls, bi, br, s);
+#define QT_CALL(L)                                                          \
+    if (f64) launch_step_t<double, L>(nblk, ninst, insts, ctls, bi, br, s); \
+    else launch_step_t<float, L>(nblk, ninst, insts, ctls, bi, br, s);
+    QT_LPR_DISPATCH(lpr, QT_CALL)
+#undef QT_CALL
+}
+
+void csr_launch_stage3(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                       const int32_t *br, hipStream_t s)
+{
+#define QT_CALL(L)                                                                                      \
+    if (f64)                                                                                            \
+        hipLaunchKernelGGL((k_csr_stage<double, L, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br); \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_csr_stage<float, L, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
     QT_LPR_DISPATCH(lpr, QT_CALL)
 #undef QT_CALL
 }

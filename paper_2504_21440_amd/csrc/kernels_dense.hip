@@ -1,16 +1,21 @@
 // kernels_dense.hip -- dense operator-form master-equation solver on the gfx950 matrix cores.
 //
 // L(rho) = A rho + (A rho)^dag + sum_k C_k rho C_k^dag (arXiv:2504.21440, Sec. 3.2, with
-// A = -i H - 1/2 sum_k C_k^dag C_k) is three complex matrix products per collapse channel set.
-// Complex products run on real MFMA instructions (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64):
-//     Re += Ar Br - Ai Bi,   Im += Ar Bi + Ai Br.
-// LDS holds two NP x (NP+1) planar (re, im) matrices: B0, the Runge-Kutta stage input rho_s, and
-// B1, the scratch for C_k rho_s and then A rho_s.  The odd row stride keeps column walks free of
-// bank conflicts.  The operators stream from L2 (they are shared by every stage of the solve).
-// Each wave owns a fixed set of 16 x 16 output tiles; the Runge-Kutta stages of its elements live
-// in a per-instance global buffer laid out in the same tile order, so every epilogue access is a
-// contiguous per-lane vector.  Step control, error norm (FP64), trace renormalisation (FP64) and
-// expectation values (FP64) run inside the same workgroup, which owns the problem for the launch.
+// A = -i H - 1/2 sum_k C_k^dag C_k).  For Hermitian rho, C rho C^dag = C (C rho)^dag, so every
+// product takes the operator as its left factor:
+//     X_k = C_k rho,   Z = sum_k C_k X_k^dag,   M = A rho,   L(rho) = Z + M + M^dag,
+// i.e. 1 + 2K complex matrix products.  Complex products run on real MFMA instructions
+// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64): Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+//
+// One workgroup owns one problem for the whole launch and runs the adaptive Dormand-Prince 5(4)
+// loop itself.  Wave w owns output tile row I = w / WPR (16 rows) and every WPR-th tile of it; it
+// loads its 16 operator rows from L2 once per product into registers (all loads in flight at
+// once), so the inner MFMA loop reads only LDS.  LDS holds two NP x (NP+1) planar (re, im)
+// matrices: B0 = the stage input rho_s, B1 = scratch for X_k and then M.  The odd row stride keeps
+// the transposed walks conflict-free.  Runge-Kutta stages of the elements a lane owns live in a
+// per-problem global buffer in tile order (contiguous per-lane accesses); the epilogue of each
+// stage is applied element by element as the right-hand side is produced.  Step control, error
+// norm, trace renormalisation and expectation values are FP64 and stay inside the workgroup.
 #include <algorithm>
 #include <vector>
 
@@ -46,138 +51,137 @@ template <typename T> __device__ __forceinline__ int mrow(int k4, int v)
     return sizeof(T) == 8 ? k4 + 4 * v : 4 * k4 + v;
 }
 
-template <typename T, int NP, int WAVES> struct DenseGeom {
-    static constexpr int S = NP + 1;                       // LDS row stride
-    static constexpr int NT = NP / 16;                     // tiles per side
-    static constexpr int TT = NT * NT;                     // tiles
-    static constexpr int MAXT = (TT + WAVES - 1) / WAVES;  // tiles per wave (upper bound)
+template <typename T, int NP, int WPR> struct DenseGeom {
+    static constexpr int S = NP + 1;                   // LDS row stride
+    static constexpr int NT = NP / 16;                 // tiles per side
+    static constexpr int WAVES = NT * WPR;             // wave w owns tile row w / WPR
+    static constexpr int MAXJ = (NT + WPR - 1) / WPR;  // tiles per wave (upper bound)
+    static constexpr int KF = NP / 4;                  // operator fragments per lane
     static constexpr int PLANE = NP * S;
-    static constexpr size_t LDS_BYTES = (size_t)4 * PLANE * sizeof(T);
+    static constexpr size_t LDS_BYTES = (size_t)6 * PLANE * sizeof(T);  // B0, B1, B2 (re, im)
 };
 
-// Complex product of one 16x16 tile: acc(I,J) += sum_k L(I*16+r, k) R(k, J*16+c).
-// Left from global (row-major np x np, interleaved) or LDS (planar); right likewise.
-template <typename T, int NP, int S>
-__device__ __forceinline__ void tile_gemm_gl_lds(const typename vec2<T>::type *__restrict__ Lg, const T *Rre,
-                                                 const T *Rim, int I, int J, int lane,
-                                                 typename Mfma<T>::acc &aR, typename Mfma<T>::acc &aI)
+// acc += a * b on the matrix cores, complex a = (ar, ai), b = (br, bi).
+template <typename T>
+__device__ __forceinline__ void cmma(typename Mfma<T>::acc &aR, typename Mfma<T>::acc &aI, T ar, T ai, T br, T bi)
 {
-    const int r16 = lane & 15, k4 = lane >> 4;
-    const typename vec2<T>::type *lrow = Lg + (size_t)(I * 16 + r16) * NP + k4;
-#pragma unroll 4
-    for (int kk = 0; kk < NP; kk += 4) {
-        const typename vec2<T>::type a = lrow[kk];
-        const T br = Rre[(kk + k4) * S + J * 16 + r16];
-        const T bi = Rim[(kk + k4) * S + J * 16 + r16];
-        aR = Mfma<T>::mma(a.x, br, aR);
-        aR = Mfma<T>::mma(-a.y, bi, aR);
-        aI = Mfma<T>::mma(a.x, bi, aI);
-        aI = Mfma<T>::mma(a.y, br, aI);
-    }
+    aR = Mfma<T>::mma(ar, br, aR);
+    aR = Mfma<T>::mma(-ai, bi, aR);
+    aI = Mfma<T>::mma(ar, bi, aI);
+    aI = Mfma<T>::mma(ai, br, aI);
 }
 
-// acc(I,J) += sum_k X(I*16+r, k) conj(C(J*16+c, k))   (X from LDS, C from global): X C^dag
-template <typename T, int NP, int S>
-__device__ __forceinline__ void tile_gemm_lds_gldag(const T *Xre, const T *Xim,
-                                                    const typename vec2<T>::type *__restrict__ Cg, int I, int J,
-                                                    int lane, typename Mfma<T>::acc &aR, typename Mfma<T>::acc &aI)
+// Lane fragments of rows [I*16, I*16+16) of an np x np operator: frag[f] = Op(I*16 + lane%16, 4f + lane/16).
+template <typename T, int NP>
+__device__ __forceinline__ void load_frag(const typename vec2<T>::type *__restrict__ op, int I, int lane,
+                                          typename vec2<T>::type (&frag)[NP / 4])
 {
-    const int r16 = lane & 15, k4 = lane >> 4;
-    const typename vec2<T>::type *crow = Cg + (size_t)(J * 16 + r16) * NP + k4;
-#pragma unroll 4
-    for (int kk = 0; kk < NP; kk += 4) {
-        const T ar = Xre[(I * 16 + r16) * S + kk + k4];
-        const T ai = Xim[(I * 16 + r16) * S + kk + k4];
-        const typename vec2<T>::type c = crow[kk];
-        // b = conj(c)
-        aR = Mfma<T>::mma(ar, c.x, aR);
-        aR = Mfma<T>::mma(ai, c.y, aR);   // -ai * (-c.y)
-        aI = Mfma<T>::mma(-ar, c.y, aI);  // ar * (-c.y)
-        aI = Mfma<T>::mma(ai, c.x, aI);
-    }
+    const typename vec2<T>::type *row = op + (size_t)(I * 16 + (lane & 15)) * NP + (lane >> 4);
+#pragma unroll
+    for (int f = 0; f < NP / 4; ++f) frag[f] = row[4 * f];
 }
 
-template <typename T, int NP, int WAVES> struct DenseRhs {
-    using G = DenseGeom<T, NP, WAVES>;
+template <typename T, int NP, int WPR> struct DenseRhs {
+    using G = DenseGeom<T, NP, WPR>;
     using V = typename vec2<T>::type;
     using Acc = typename Mfma<T>::acc;
     static constexpr int S = G::S;
 
-    // out[t][v] (owned tiles) = L(B0); uses B1 as scratch.  Ends with B1 holding A B0.
-    static __device__ void eval(const V *__restrict__ ops, int nc, T *lds, V (&out)[G::MAXT][4])
+    // C = frag (rows of this wave) times the LDS matrix R (re, im planes), one 16x16 tile J.
+    static __device__ __forceinline__ void tile_mm(const V (&frag)[G::KF], const T *Rre, const T *Rim, int J,
+                                                   int lane, Acc &cR, Acc &cI)
+    {
+        const int r16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+        for (int f = 0; f < G::KF; ++f) {
+            const int kr = (4 * f + k4) * S + J * 16 + r16;
+            cmma<T>(cR, cI, frag[f].x, frag[f].y, Rre[kr], Rim[kr]);
+        }
+    }
+    // Same with the right factor X^dag: X^dag(kk, j) = conj(X(j, kk)).
+    static __device__ __forceinline__ void tile_mm_dag(const V (&frag)[G::KF], const T *Xre, const T *Xim, int J,
+                                                       int lane, Acc &cR, Acc &cI)
+    {
+        const int r16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+        for (int f = 0; f < G::KF; ++f) {
+            const int kr = (J * 16 + r16) * S + 4 * f + k4;
+            cmma<T>(cR, cI, frag[f].x, frag[f].y, Xre[kr], -Xim[kr]);
+        }
+    }
+    static __device__ __forceinline__ void tile_store(T *Dre, T *Dim, int I, int J, int lane, const Acc &cR,
+                                                      const Acc &cI)
+    {
+        const int r16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
+            Dre[i * S + j] = cR[v];
+            Dim[i * S + j] = cI[v];
+        }
+    }
+
+    // Evaluates L(B0) and calls epi(q, v, value) for every element this lane owns (tile q of the
+    // wave's tile row, accumulator slot v).  B1 holds C_k B0, B2 holds A B0.  With several collapse
+    // channels the running sum Z is kept per element in zbuf (tile order, global).
+    template <typename Epi>
+    static __device__ __forceinline__ void eval(const V *__restrict__ ops, int nc, T *lds, V *__restrict__ zbuf,
+                                                Epi &&epi)
     {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        T *B0re = lds, *B0im = lds + G::PLANE, *B1re = lds + 2 * G::PLANE, *B1im = lds + 3 * G::PLANE;
-        const size_t mat = (size_t)NP * NP;
+        const int I = w / WPR, j0 = w % WPR;
         const int r16 = lane & 15, k4 = lane >> 4;
-        Acc aR[G::MAXT], aI[G::MAXT];
-#pragma unroll
-        for (int q = 0; q < G::MAXT; ++q) {
-            aR[q] = Acc{0, 0, 0, 0};
-            aI[q] = Acc{0, 0, 0, 0};
-        }
-        for (int k = 0; k < nc; ++k) {
-            const V *C = ops + (1 + k) * mat;
-            // X = C B0 -> B1
-#pragma unroll
-            for (int q = 0; q < G::MAXT; ++q) {
-                const int t = w + q * WAVES;
-                if (t < G::TT) {
-                    const int I = t / G::NT, J = t % G::NT;
+        T *B0re = lds, *B0im = lds + G::PLANE, *B1re = lds + 2 * G::PLANE, *B1im = lds + 3 * G::PLANE;
+        T *B2re = lds + 4 * G::PLANE, *B2im = lds + 5 * G::PLANE;
+        const size_t mat = (size_t)NP * NP;
+        const int kmax = nc > 0 ? nc : 1;
+        for (int k = 0; k < kmax; ++k) {
+            if (k == 0) {
+                // M = A B0 -> B2
+                V frag[G::KF];
+                load_frag<T, NP>(ops, I, lane, frag);
+#pragma unroll 1
+                for (int J = j0; J < G::NT; J += WPR) {
+                    Acc mR = {0, 0, 0, 0}, mI = {0, 0, 0, 0};
+                    tile_mm(frag, B0re, B0im, J, lane, mR, mI);
+                    tile_store(B2re, B2im, I, J, lane, mR, mI);
+                }
+            }
+            V frag[G::KF];
+            if (nc > 0) {
+                // X = C_k B0 -> B1
+                load_frag<T, NP>(ops + (1 + k) * mat, I, lane, frag);
+#pragma unroll 1
+                for (int J = j0; J < G::NT; J += WPR) {
                     Acc xR = {0, 0, 0, 0}, xI = {0, 0, 0, 0};
-                    tile_gemm_gl_lds<T, NP, S>(C, B0re, B0im, I, J, lane, xR, xI);
+                    tile_mm(frag, B0re, B0im, J, lane, xR, xI);
+                    tile_store(B1re, B1im, I, J, lane, xR, xI);
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int J = j0, q = 0; J < G::NT; J += WPR, ++q) {
+                Acc zR = {0, 0, 0, 0}, zI = {0, 0, 0, 0};
+                if (nc > 0) tile_mm_dag(frag, B1re, B1im, J, lane, zR, zI);  // Z_k = C_k X_k^dag
+                const size_t zb = ((size_t)(I * G::NT + J) * 64 + lane) * 4;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
+                for (int v = 0; v < 4; ++v) {
+                    V z;
+                    z.x = zR[v];
+                    z.y = zI[v];
+                    if (k > 0) z = cadd(z, zbuf[zb + v]);
+                    if (k + 1 < kmax) {
+                        zbuf[zb + v] = z;
+                    } else {
                         const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
-                        B1re[i * S + j] = xR[v];
-                        B1im[i * S + j] = xI[v];
+                        V o;
+                        o.x = z.x + B2re[i * S + j] + B2re[j * S + i];
+                        o.y = z.y + B2im[i * S + j] - B2im[j * S + i];
+                        epi(q, v, o);
                     }
                 }
             }
-            __syncthreads();
-            // acc += X C^dag
-#pragma unroll
-            for (int q = 0; q < G::MAXT; ++q) {
-                const int t = w + q * WAVES;
-                if (t < G::TT) {
-                    const int I = t / G::NT, J = t % G::NT;
-                    tile_gemm_lds_gldag<T, NP, S>(B1re, B1im, C, I, J, lane, aR[q], aI[q]);
-                }
-            }
-            __syncthreads();
-        }
-        // M = A B0 -> B1
-#pragma unroll
-        for (int q = 0; q < G::MAXT; ++q) {
-            const int t = w + q * WAVES;
-            if (t < G::TT) {
-                const int I = t / G::NT, J = t % G::NT;
-                Acc mR = {0, 0, 0, 0}, mI = {0, 0, 0, 0};
-                tile_gemm_gl_lds<T, NP, S>(ops, B0re, B0im, I, J, lane, mR, mI);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
-                    B1re[i * S + j] = mR[v];
-                    B1im[i * S + j] = mI[v];
-                }
-            }
-        }
-        __syncthreads();
-        // out = acc + M + M^dag
-#pragma unroll
-        for (int q = 0; q < G::MAXT; ++q) {
-            const int t = w + q * WAVES;
-            if (t < G::TT) {
-                const int I = t / G::NT, J = t % G::NT;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
-                    V o;
-                    o.x = aR[q][v] + B1re[i * S + j] + B1re[j * S + i];
-                    o.y = aI[q][v] + B1im[i * S + j] - B1im[j * S + i];
-                    out[q][v] = o;
-                }
-            }
+            if (k + 1 < kmax) __syncthreads();  // B1 is rewritten by the next channel
         }
     }
 };
@@ -185,15 +189,15 @@ template <typename T, int NP, int WAVES> struct DenseRhs {
 // Element index of (tile t, lane, v) in the tile-ordered global vectors.
 __device__ __forceinline__ size_t tix(int t, int lane, int v) { return ((size_t)t * 64 + lane) * 4 + v; }
 
-template <typename T, int NP, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__restrict__ insts,
-                                                            DenseCtl *__restrict__ ctls,
-                                                            const int32_t *__restrict__ order, int max_steps_launch,
-                                                            int reset)
+template <typename T, int NP, int WPR>
+__global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const DenseInst *__restrict__ insts,
+                                                                      DenseCtl *__restrict__ ctls,
+                                                                      const int32_t *__restrict__ order,
+                                                                      int max_steps_launch, int reset)
 {
-    using G = DenseGeom<T, NP, WAVES>;
+    using G = DenseGeom<T, NP, WPR>;
     using V = typename vec2<T>::type;
-    using R = DenseRhs<T, NP, WAVES>;
+    using R = DenseRhs<T, NP, WPR>;
     constexpr int S = G::S;
     extern __shared__ char smem[];
     T *lds = (T *)smem;
@@ -205,22 +209,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__r
     DenseCtl *C = ctls + ii;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r16 = lane & 15, k4 = lane >> 4;
+    const int Iw = w / WPR, j0 = w % WPR;  // this wave's tile row and first tile column
     const int d = I.d;
     const size_t nvec = (size_t)NP * NP;
     V *vec = (V *)I.vec;
     V *Yb[2] = {vec, vec + nvec};
     V *Kb[2] = {vec + 2 * nvec, vec + 3 * nvec};
     V *ks[5] = {vec + 4 * nvec, vec + 5 * nvec, vec + 6 * nvec, vec + 7 * nvec, vec + 8 * nvec};
+    V *zbuf = vec + 9 * nvec;  // running sum over collapse channels (used when nc > 1)
     const V *ops = (const V *)I.ops;
     const double nd = (double)d * d;
-    V out[G::MAXT][4];
 
-    auto owned = [&](int q, int &Ii, int &Jj) {
-        const int t = w + q * WAVES;
-        Ii = t / G::NT;
-        Jj = t % G::NT;
-        return t < G::TT;
-    };
+    // element (q, v) of this lane: tile-order index and (row, column)
+    auto eidx = [&](int q, int v) { return tix(Iw * G::NT + j0 + q * WPR, lane, v); };
+    auto erow = [&](int v) { return Iw * 16 + mrow<T>(k4, v); };
+    auto ecol = [&](int q) { return (j0 + q * WPR) * 16 + r16; };
     auto record_expect = [&](int idx, double sc) {
         for (int k = 0; k < I.ne; ++k) {
             const int32_t *ep = I.eptr + (size_t)k * (d + 1);
@@ -251,16 +254,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__r
     if (reset || C->status == DENSE_ST_INIT) {
         // ---- initial state into B0 (planar, zero padded) and Y[0] (tile order) ----
         const V *r0 = (const V *)I.rho0;
-        for (int q = 0; q < G::MAXT; ++q) {
-            int Ii, Jj;
-            if (!owned(q, Ii, Jj)) continue;
+        for (int q = 0; q < G::MAXJ; ++q) {
+            if (j0 + q * WPR >= G::NT) break;
             for (int v = 0; v < 4; ++v) {
-                const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
+                const int i = erow(v), j = ecol(q);
                 V y;
                 y.x = 0;
                 y.y = 0;
                 if (i < d && j < d) y = r0[(size_t)i * d + j];
-                Yb[0][tix(w + q * WAVES, lane, v)] = y;
+                Yb[0][eidx(q, v)] = y;
                 B0re[i * S + j] = y.x;
                 B0im[i * S + j] = y.y;
             }
@@ -281,21 +283,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__r
         h = 0.0;
         if (status == ST_RUNNING) {
             // k1 = L(y0); starting step from d0 = |y0|, d1 = |k1|, d2 = |f(y0 + h0 k1) - k1| / h0
-            R::eval(ops, I.nc, lds, out);
-            n_rhs += 1;
             double s0 = 0.0, s1 = 0.0;
-            for (int q = 0; q < G::MAXT; ++q) {
-                int Ii, Jj;
-                if (!owned(q, Ii, Jj)) continue;
-                for (int v = 0; v < 4; ++v) {
-                    const size_t e = tix(w + q * WAVES, lane, v);
-                    Kb[0][e] = out[q][v];
-                    const double ya = sqrt(abs2d(Yb[0][e]));
-                    const double sc = I.atol + I.rtol * ya;
-                    s0 += ya * ya / (sc * sc);
-                    s1 += abs2d(out[q][v]) / (sc * sc);
-                }
-            }
+            R::eval(ops, I.nc, lds, zbuf, [&](int q, int v, V a) {
+                const size_t e = eidx(q, v);
+                Kb[0][e] = a;
+                const double ya = sqrt(abs2d(Yb[0][e]));
+                const double sc = I.atol + I.rtol * ya;
+                s0 += ya * ya / (sc * sc);
+                s1 += abs2d(a) / (sc * sc);
+            });
+            n_rhs += 1;
             s0 = block_sum(s0, scr);
             s1 = block_sum(s1, scr);
             const double d0 = sqrt(s0 / nd), d1 = sqrt(s1 / nd);
@@ -303,13 +300,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__r
                 h = I.h0;
             } else {
                 const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-                __syncthreads();
-                for (int q = 0; q < G::MAXT; ++q) {
-                    int Ii, Jj;
-                    if (!owned(q, Ii, Jj)) continue;
+                for (int q = 0; q < G::MAXJ; ++q) {
+                    if (j0 + q * WPR >= G::NT) break;
                     for (int v = 0; v < 4; ++v) {
-                        const size_t e = tix(w + q * WAVES, lane, v);
-                        const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
+                        const size_t e = eidx(q, v);
+                        const int i = erow(v), j = ecol(q);
                         V y = Yb[0][e];
                         caxpy(y, (T)h0, Kb[0][e]);
                         B0re[i * S + j] = y.x;
@@ -317,20 +312,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__r
                     }
                 }
                 __syncthreads();
-                R::eval(ops, I.nc, lds, out);
-                n_rhs += 1;
                 double s2 = 0.0;
-                for (int q = 0; q < G::MAXT; ++q) {
-                    int Ii, Jj;
-                    if (!owned(q, Ii, Jj)) continue;
-                    for (int v = 0; v < 4; ++v) {
-                        const size_t e = tix(w + q * WAVES, lane, v);
-                        const double2 f1 = to_d2(out[q][v]), f0 = to_d2(Kb[0][e]);
-                        const double sc = I.atol + I.rtol * sqrt(abs2d(Yb[0][e]));
-                        const double dx = (f1.x - f0.x) / h0, dy = (f1.y - f0.y) / h0;
-                        s2 += (dx * dx + dy * dy) / (sc * sc);
-                    }
-                }
+                R::eval(ops, I.nc, lds, zbuf, [&](int q, int v, V a) {
+                    const size_t e = eidx(q, v);
+                    const double2 f1 = to_d2(a), f0 = to_d2(Kb[0][e]);
+                    const double sc = I.atol + I.rtol * sqrt(abs2d(Yb[0][e]));
+                    const double dx = (f1.x - f0.x) / h0, dy = (f1.y - f0.y) / h0;
+                    s2 += (dx * dx + dy * dy) / (sc * sc);
+                });
+                n_rhs += 1;
                 s2 = block_sum(s2, scr);
                 const double d2 = sqrt(s2 / nd);
                 const double m = fmax(d1, d2);
@@ -363,12 +353,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__r
         V *y = Yb[parity], *ynew = Yb[1 - parity], *k1 = Kb[parity], *k7 = Kb[1 - parity];
         // stage-2 input: y + h a21 k1
         __syncthreads();
-        for (int q = 0; q < G::MAXT; ++q) {
-            int Ii, Jj;
-            if (!owned(q, Ii, Jj)) continue;
+        for (int q = 0; q < G::MAXJ; ++q) {
+            if (j0 + q * WPR >= G::NT) break;
             for (int v = 0; v < 4; ++v) {
-                const size_t e = tix(w + q * WAVES, lane, v);
-                const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
+                const size_t e = eidx(q, v);
+                const int i = erow(v), j = ecol(q);
                 V x = cscale(y[e], sc);
                 caxpy(x, (T)(ht * DP5::a21), cscale(k1[e], sc));
                 B0re[i * S + j] = x.x;
@@ -378,64 +367,58 @@ __global__ __launch_bounds__(WAVES * 64) void k_dense_solve(const DenseInst *__r
         __syncthreads();
         double e2 = 0.0;
         for (int s = 2; s <= 7; ++s) {
-            R::eval(ops, I.nc, lds, out);
-            for (int q = 0; q < G::MAXT; ++q) {
-                int Ii, Jj;
-                if (!owned(q, Ii, Jj)) continue;
-                for (int v = 0; v < 4; ++v) {
-                    const size_t e = tix(w + q * WAVES, lane, v);
-                    const int i = Ii * 16 + mrow<T>(k4, v), j = Jj * 16 + r16;
-                    const V a = out[q][v];
-                    const V yr = cscale(y[e], sc), k1r = cscale(k1[e], sc);
-                    V o = yr;
-                    if (s == 2) {
-                        ks[0][e] = a;
-                        caxpy(o, (T)(ht * DP5::a31), k1r);
-                        caxpy(o, (T)(ht * DP5::a32), a);
-                    } else if (s == 3) {
-                        ks[1][e] = a;
-                        caxpy(o, (T)(ht * DP5::a41), k1r);
-                        caxpy(o, (T)(ht * DP5::a42), ks[0][e]);
-                        caxpy(o, (T)(ht * DP5::a43), a);
-                    } else if (s == 4) {
-                        ks[2][e] = a;
-                        caxpy(o, (T)(ht * DP5::a51), k1r);
-                        caxpy(o, (T)(ht * DP5::a52), ks[0][e]);
-                        caxpy(o, (T)(ht * DP5::a53), ks[1][e]);
-                        caxpy(o, (T)(ht * DP5::a54), a);
-                    } else if (s == 5) {
-                        ks[3][e] = a;
-                        caxpy(o, (T)(ht * DP5::a61), k1r);
-                        caxpy(o, (T)(ht * DP5::a62), ks[0][e]);
-                        caxpy(o, (T)(ht * DP5::a63), ks[1][e]);
-                        caxpy(o, (T)(ht * DP5::a64), ks[2][e]);
-                        caxpy(o, (T)(ht * DP5::a65), a);
-                    } else if (s == 6) {
-                        ks[4][e] = a;
-                        caxpy(o, (T)(ht * DP5::b1), k1r);
-                        caxpy(o, (T)(ht * DP5::b3), ks[1][e]);
-                        caxpy(o, (T)(ht * DP5::b4), ks[2][e]);
-                        caxpy(o, (T)(ht * DP5::b5), ks[3][e]);
-                        caxpy(o, (T)(ht * DP5::b6), a);
-                        ynew[e] = o;
-                    } else {
-                        k7[e] = a;
-                        double2 er = make_double2(0.0, 0.0);
-                        caxpy(er, ht * DP5::e1, to_d2(k1r));
-                        caxpy(er, ht * DP5::e3, to_d2(ks[1][e]));
-                        caxpy(er, ht * DP5::e4, to_d2(ks[2][e]));
-                        caxpy(er, ht * DP5::e5, to_d2(ks[3][e]));
-                        caxpy(er, ht * DP5::e6, to_d2(ks[4][e]));
-                        caxpy(er, ht * DP5::e7, to_d2(a));
-                        const double scl = I.atol + I.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(ynew[e])));
-                        e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
-                    }
-                    if (s < 7) {
-                        B0re[i * S + j] = o.x;
-                        B0im[i * S + j] = o.y;
-                    }
+            R::eval(ops, I.nc, lds, zbuf, [&](int q, int v, V a) {
+                const size_t e = eidx(q, v);
+                const V yr = cscale(y[e], sc), k1r = cscale(k1[e], sc);
+                V o = yr;
+                if (s == 2) {
+                    ks[0][e] = a;
+                    caxpy(o, (T)(ht * DP5::a31), k1r);
+                    caxpy(o, (T)(ht * DP5::a32), a);
+                } else if (s == 3) {
+                    ks[1][e] = a;
+                    caxpy(o, (T)(ht * DP5::a41), k1r);
+                    caxpy(o, (T)(ht * DP5::a42), ks[0][e]);
+                    caxpy(o, (T)(ht * DP5::a43), a);
+                } else if (s == 4) {
+                    ks[2][e] = a;
+                    caxpy(o, (T)(ht * DP5::a51), k1r);
+                    caxpy(o, (T)(ht * DP5::a52), ks[0][e]);
+                    caxpy(o, (T)(ht * DP5::a53), ks[1][e]);
+                    caxpy(o, (T)(ht * DP5::a54), a);
+                } else if (s == 5) {
+                    ks[3][e] = a;
+                    caxpy(o, (T)(ht * DP5::a61), k1r);
+                    caxpy(o, (T)(ht * DP5::a62), ks[0][e]);
+                    caxpy(o, (T)(ht * DP5::a63), ks[1][e]);
+                    caxpy(o, (T)(ht * DP5::a64), ks[2][e]);
+                    caxpy(o, (T)(ht * DP5::a65), a);
+                } else if (s == 6) {
+                    ks[4][e] = a;
+                    caxpy(o, (T)(ht * DP5::b1), k1r);
+                    caxpy(o, (T)(ht * DP5::b3), ks[1][e]);
+                    caxpy(o, (T)(ht * DP5::b4), ks[2][e]);
+                    caxpy(o, (T)(ht * DP5::b5), ks[3][e]);
+                    caxpy(o, (T)(ht * DP5::b6), a);
+                    ynew[e] = o;
+                } else {
+                    k7[e] = a;
+                    double2 er = make_double2(0.0, 0.0);
+                    caxpy(er, ht * DP5::e1, to_d2(k1r));
+                    caxpy(er, ht * DP5::e3, to_d2(ks[1][e]));
+                    caxpy(er, ht * DP5::e4, to_d2(ks[2][e]));
+                    caxpy(er, ht * DP5::e5, to_d2(ks[3][e]));
+                    caxpy(er, ht * DP5::e6, to_d2(ks[4][e]));
+                    caxpy(er, ht * DP5::e7, to_d2(a));
+                    const double scl = I.atol + I.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(ynew[e])));
+                    e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
                 }
-            }
+                if (s < 7) {
+                    const int i = erow(v), j = ecol(q);
+                    B0re[i * S + j] = o.x;
+                    B0im[i * S + j] = o.y;
+                }
+            });
             __syncthreads();
         }
         n_rhs += 6;
@@ -520,11 +503,13 @@ void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *op
     g->expect = expect;
 }
 
-int dense_choose_config(int dmax, int prec)
+int dense_choose_config(int d, int prec)
 {
-    (void)dmax;
-    (void)prec;
-    return 4;  // waves per workgroup
+    // waves per 16-row tile row of the output: two where the registers allow it (more waves in
+    // flight per CU), one for the largest padded sizes and for FP64
+    const int np = dense_np(d);
+    if (prec == QT_F64) return 1;
+    return np <= 64 ? 2 : 1;
 }
 
 const void *dense_state_ptr(const void *vec, int d, int prec)
@@ -534,50 +519,50 @@ const void *dense_state_ptr(const void *vec, int d, int prec)
     return vec;
 }
 
-template <typename T, int NP, int WAVES>
+template <typename T, int NP, int WPR>
 static void launch_np(const DenseInst *insts, DenseCtl *ctls, const int32_t *order, int count, int msl, int reset,
                       hipStream_t s)
 {
-    using G = DenseGeom<T, NP, WAVES>;
+    using G = DenseGeom<T, NP, WPR>;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_dense_solve<T, NP, WAVES>,
+        (void)hipFuncSetAttribute((const void *)k_dense_solve<T, NP, WPR>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::LDS_BYTES);
         attr = true;
     }
-    hipLaunchKernelGGL((k_dense_solve<T, NP, WAVES>), dim3(count), dim3(WAVES * 64), G::LDS_BYTES, s, insts, ctls,
+    hipLaunchKernelGGL((k_dense_solve<T, NP, WPR>), dim3(count), dim3(G::WAVES * 64), G::LDS_BYTES, s, insts, ctls,
                        order, msl, reset);
 }
 
-template <typename T, int WAVES>
+template <typename T, int WPR>
 static void launch_bucket(int np, const DenseInst *insts, DenseCtl *ctls, const int32_t *order, int count, int msl,
                           int reset, hipStream_t s)
 {
     switch (np) {
-    case 16: launch_np<T, 16, WAVES>(insts, ctls, order, count, msl, reset, s); break;
-    case 32: launch_np<T, 32, WAVES>(insts, ctls, order, count, msl, reset, s); break;
-    case 48: launch_np<T, 48, WAVES>(insts, ctls, order, count, msl, reset, s); break;
-    case 64: launch_np<T, 64, WAVES>(insts, ctls, order, count, msl, reset, s); break;
-    case 80:
-        if constexpr (sizeof(T) == 4) launch_np<T, 80, WAVES>(insts, ctls, order, count, msl, reset, s);
+    case 16: launch_np<T, 16, WPR>(insts, ctls, order, count, msl, reset, s); break;
+    case 32: launch_np<T, 32, WPR>(insts, ctls, order, count, msl, reset, s); break;
+    case 48: launch_np<T, 48, WPR>(insts, ctls, order, count, msl, reset, s); break;
+    case 64:
+        if constexpr (sizeof(T) == 4) launch_np<T, 64, WPR>(insts, ctls, order, count, msl, reset, s);
         break;
-    case 96:
-        if constexpr (sizeof(T) == 4) launch_np<T, 96, WAVES>(insts, ctls, order, count, msl, reset, s);
+    case 80:
+        if constexpr (sizeof(T) == 4) launch_np<T, 80, WPR>(insts, ctls, order, count, msl, reset, s);
         break;
     default: break;
     }
 }
 
-void dense_launch_bucket(int np, bool f64, int waves, const DenseInst *insts, DenseCtl *ctls, const int32_t *order,
+// wpr: waves per 16-row tile row of the output (1 or 2); the workgroup has (np/16)*wpr waves.
+void dense_launch_bucket(int np, bool f64, int wpr, const DenseInst *insts, DenseCtl *ctls, const int32_t *order,
                          int count, int msl, int reset, hipStream_t s)
 {
     if (count <= 0) return;
     if (f64) {
-        if (waves == 8) launch_bucket<double, 8>(np, insts, ctls, order, count, msl, reset, s);
-        else launch_bucket<double, 4>(np, insts, ctls, order, count, msl, reset, s);
+        if (wpr == 2) launch_bucket<double, 2>(np, insts, ctls, order, count, msl, reset, s);
+        else launch_bucket<double, 1>(np, insts, ctls, order, count, msl, reset, s);
     } else {
-        if (waves == 8) launch_bucket<float, 8>(np, insts, ctls, order, count, msl, reset, s);
-        else launch_bucket<float, 4>(np, insts, ctls, order, count, msl, reset, s);
+        if (wpr == 2) launch_bucket<float, 2>(np, insts, ctls, order, count, msl, reset, s);
+        else launch_bucket<float, 1>(np, insts, ctls, order, count, msl, reset, s);
     }
 }
 
@@ -588,7 +573,8 @@ void dense_unpack(const void *host_vec, int d, int prec, double scale, double *o
         for (int lane = 0; lane < 64; ++lane)
             for (int v = 0; v < 4; ++v) {
                 const int q4 = lane >> 4;
-                const int i = (t / nt) * 16 + (prec == QT_F64 ? q4 + 4 * v : 4 * q4 + v), j = (t % nt) * 16 + (lane & 15);
+                const int i = (t / nt) * 16 + (prec == QT_F64 ? q4 + 4 * v : 4 * q4 + v);
+                const int j = (t % nt) * 16 + (lane & 15);
                 if (i >= d || j >= d) continue;
                 const size_t e = ((size_t)t * 64 + lane) * 4 + v;
                 double re, im;

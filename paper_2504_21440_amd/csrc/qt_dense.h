@@ -15,8 +15,9 @@
 
 namespace qt {
 
-constexpr int DENSE_MAX_NP_F32 = 96;  // padded dimension limit set by LDS (two planes of NP x (NP+1))
-constexpr int DENSE_MAX_NP_F64 = 64;
+// padded dimension limits set by LDS: three complex NP x (NP+1) matrices must fit in 160 KB
+constexpr int DENSE_MAX_NP_F32 = 80;
+constexpr int DENSE_MAX_NP_F64 = 48;
 
 struct DenseInst {
     int32_t d, np, nc, nt, ne;
@@ -42,7 +43,7 @@ struct DenseCtl {
 };
 
 inline int dense_np(int d) { return ((d + 15) / 16) * 16; }
-inline int dense_state_vectors() { return 9; }
+inline int dense_state_vectors() { return 10; }
 
 void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *ops, const void *rho0, void *vec,
                      const double *tlist, const int32_t *eptr, const int32_t *ecol, const double2 *eval,

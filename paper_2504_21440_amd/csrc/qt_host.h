@@ -84,10 +84,12 @@ struct CsrInst;
 struct CsrCtl;
 int csr_rows_per_block(int lpr);
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s);
-void csr_launch_init(int which, bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+void csr_launch_init(int which, bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
                      const int32_t *br, hipStream_t s);
-void csr_launch_step(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+void csr_launch_step(bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
                      const int32_t *br, hipStream_t s);
+void csr_launch_stage3(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+                       const int32_t *br, hipStream_t s);
 void launch_expect(bool f64, int d, const int32_t *rp, const int32_t *ci, const double2 *v, const void *state,
                    int is_ket, double2 *out, hipStream_t s);
 

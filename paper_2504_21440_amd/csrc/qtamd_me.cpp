@@ -314,7 +314,7 @@ static qt_status capture_graph(qt_me_plan *P)
     auto *bi = (const int32_t *)P->arena.at(P->o_bi);
     auto *br = (const int32_t *)P->arena.at(P->o_br);
     QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < P->graph_steps; ++k) csr_launch_step(f64, P->lpr, P->nblk, ci, cc, bi, br, s);
+    for (int k = 0; k < P->graph_steps; ++k) csr_launch_step(f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
     hipError_t e = hipStreamEndCapture(s, &P->graph);
     if (e) return set_error(QT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     QT_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
@@ -337,7 +337,7 @@ qt_status me_plan_run(qt_me_plan *P)
             hipStream_t bs = ctx->pool[b % Ctx::NPOOL];
             QT_HIP(hipStreamWaitEvent(bs, ev_start, 0));
             const auto &bk = P->buckets[b];
-            dense_launch_bucket(bk.np, f64, P->dense_cfg, (const DenseInst *)P->arena.at(P->o_dinst),
+            dense_launch_bucket(bk.np, f64, dense_choose_config(bk.np, P->prec), (const DenseInst *)P->arena.at(P->o_dinst),
                                 (DenseCtl *)P->arena.at(P->o_dctl), (const int32_t *)P->arena.at(P->o_dorder) + bk.start,
                                 bk.count, /*max_steps_launch=*/-1, /*reset=*/1, bs);
             QT_HIP(hipGetLastError());
@@ -350,8 +350,8 @@ qt_status me_plan_run(qt_me_plan *P)
         auto *bi = (const int32_t *)P->arena.at(P->o_bi);
         auto *br = (const int32_t *)P->arena.at(P->o_br);
         csr_launch_reset(ci, cc, P->ncsr, s);
-        csr_launch_init(0, f64, P->lpr, P->nblk, ci, cc, bi, br, s);
-        csr_launch_init(1, f64, P->lpr, P->nblk, ci, cc, bi, br, s);
+        csr_launch_init(0, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
+        csr_launch_init(1, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
         QT_HIP(hipGetLastError());
         if ((st = capture_graph(P))) return st;
         int replays = 1;
@@ -475,6 +475,47 @@ qt_status qt_me_plan_result(qt_me_plan *plan, int32_t i, double *expect_out, dou
 {
     if (!plan) return set_error(QT_EINVAL, "null plan");
     return me_plan_result(plan, i, expect_out, rho_final, stats);
+}
+
+qt_status qt_me_plan_time_rhs(qt_me_plan *P, int32_t reps, double *ms_per_launch)
+{
+    if (!P || reps <= 0 || !ms_per_launch) return set_error(QT_EINVAL, "qt_me_plan_time_rhs: bad arguments");
+    Ctx *ctx = P->ctx;
+    QT_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const bool f64 = P->prec == QT_F64;
+    hipEvent_t e0, e1;
+    QT_HIP(hipEventCreate(&e0));
+    QT_HIP(hipEventCreate(&e1));
+    if (P->ncsr) {
+        auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
+        auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
+        auto *bi = (const int32_t *)P->arena.at(P->o_bi);
+        auto *br = (const int32_t *)P->arena.at(P->o_br);
+        csr_launch_reset(ci, cc, P->ncsr, s);
+        csr_launch_init(0, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
+        csr_launch_init(1, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
+        csr_launch_stage3(f64, P->lpr, P->nblk, ci, cc, bi, br, s);  // warm
+        QT_HIP(hipEventRecord(e0, s));
+        for (int32_t r = 0; r < reps; ++r) csr_launch_stage3(f64, P->lpr, P->nblk, ci, cc, bi, br, s);
+        QT_HIP(hipEventRecord(e1, s));
+    } else {
+        QT_HIP(hipEventRecord(e0, s));
+        for (int32_t r = 0; r < reps; ++r)
+            for (const auto &bk : P->buckets)
+                dense_launch_bucket(bk.np, f64, dense_choose_config(bk.np, P->prec), (const DenseInst *)P->arena.at(P->o_dinst),
+                                    (DenseCtl *)P->arena.at(P->o_dctl),
+                                    (const int32_t *)P->arena.at(P->o_dorder) + bk.start, bk.count, -1, 1, s);
+        QT_HIP(hipEventRecord(e1, s));
+    }
+    QT_HIP(hipGetLastError());
+    QT_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    QT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = (double)ms / reps;
+    return QT_OK;
 }
 
 qt_status qt_me_plan_destroy(qt_me_plan *P)

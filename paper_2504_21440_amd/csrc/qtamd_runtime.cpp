@@ -398,7 +398,7 @@ qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const 
         const int32_t np = dense_np(d);
         if (np > (precision == QT_F64 ? DENSE_MAX_NP_F64 : DENSE_MAX_NP_F32)) {
             delete L;
-            return set_error(QT_EINVAL, "dense form supports d <= 96 (mixed) or d <= 64 (FP64)");
+            return set_error(QT_EINVAL, "dense form supports d <= 80 (mixed) or d <= 48 (FP64)");
         }
         // A then C_k, each zero padded to np x np (np = d rounded up to a multiple of 16)
         const size_t mat = (size_t)np * np;

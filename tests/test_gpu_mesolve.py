@@ -154,8 +154,8 @@ def test_complex_operators_csr(ctx):
 # --------------------------------------------------------------------------------------------
 # dense operator form (MFMA)
 # --------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("N,prec", [(20, qt.F64), (37, qt.F64), (64, qt.F64), (20, qt.MIXED), (80, qt.MIXED),
-                                    (10, qt.MIXED), (96, qt.MIXED)])
+@pytest.mark.parametrize("N,prec", [(20, qt.F64), (37, qt.F64), (48, qt.F64), (20, qt.MIXED), (80, qt.MIXED),
+                                    (10, qt.MIXED), (64, qt.MIXED), (1, qt.MIXED)])
 def test_kerr_dense_vs_oracle(ctx, N, prec):
     print(f"[gpu] dense kerr N={N} prec={prec}", flush=True)
     p = dict(workloads.kerr_single(), N=N)
