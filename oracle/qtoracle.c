@@ -789,7 +789,7 @@ static int32_t mc_trajectory(mc_ctx *m, const cplx *psi0, int32_t nt, const doub
             err_prev = fmax(err, 1e-4);
             last_rejected = 0;
             double nrm_new = norm2(s.ynew, d);
-            if (nrm_new >= r) {
+            if (nrm_new >= r || m->nc == 0) { /* without collapse operators there is no jump */
                 /* ordinary accepted step */
                 s.t = land ? tlist[idx] : s.t + ht;
                 swap_ptr(&s.y, &s.ynew);
