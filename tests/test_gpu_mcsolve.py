@@ -1,0 +1,131 @@
+"""GPU parity of the quantum-jump path (Sec. 3.3) against the FP64 oracle.
+
+FP64 mode: trajectory by trajectory with the same Philox stream -- same jump count, channels and
+jump times (within 1e-8) and expectation values within 1e-6.  Mixed mode: the ensemble mean of
+<sum sz> over 10,000 trajectories of the L = 10 chain agrees with the oracle master equation within
+3 standard errors (the stored oracle values are in tests/golden/ising_l10_me.json)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from oracle import models as om
+import workloads
+import paper_2504_21440_amd as qt
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating context", flush=True)
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+def _sz_sum(L):
+    return sum(om.site_op(L, i, om.sigmaz()) for i in range(L))
+
+
+def test_single_spin_jump_times_exact(ctx):
+    print("[gpu] mc single spin", flush=True)
+    gam = 0.7
+    H = sp.csr_matrix((2, 2), dtype=complex)
+    cs = [np.sqrt(gam) * om.sigmam()]
+    tl = np.linspace(0, 10, 21)
+    seed = 99
+    res = qt.mcsolve(ctx, H, cs, np.array([1, 0], complex), tl, [om.sigmaz()], 64, seed,
+                     options=qt.opts(abstol=1e-12, reltol=1e-10, precision=qt.F64), want_traj=True,
+                     max_jump_record=2)
+    for j in range(64):
+        r0, _ = oracle.traj_draw(seed, j, 0)
+        tstar = -np.log(r0) / gam
+        if tstar < tl[-1]:
+            assert res["njumps"][j] == 1
+            assert abs(res["jump_times"][j, 0] - tstar) < 1e-8
+            assert res["jump_channels"][j, 0] == 0
+        else:
+            assert res["njumps"][j] == 0
+
+
+@pytest.mark.parametrize("prec", [qt.F64, qt.MIXED])
+def test_trajectory_parity_with_oracle(ctx, prec):
+    """Same seed, same trajectories: jump counts, channels and times equal the oracle's."""
+    print(f"[gpu] mc trajectory parity prec={prec}", flush=True)
+    L = 4
+    H, cs = qt.model_ising(L, 1.0, 0.8, 0.3)
+    e_ops = [_sz_sum(L), om.site_op(L, 1, om.sigmax())]
+    tl = np.linspace(0, 6, 25)
+    n, seed = 48, 7
+    ref = oracle.mcsolve(H, cs, om.all_up_ket(L), tl, e_ops, n, seed, max_jump_record=8)
+    res = qt.mcsolve(ctx, H, cs, om.all_up_ket(L), tl, e_ops, n, seed, options=qt.opts(precision=prec),
+                     want_traj=True, max_jump_record=8)
+    if prec == qt.F64:
+        np.testing.assert_array_equal(res["njumps"], ref["njumps"])
+        for j in range(n):
+            m = min(8, int(ref["njumps"][j]))
+            np.testing.assert_array_equal(res["jump_channels"][j, :m], ref["jump_channels"][j, :m])
+            assert np.abs(res["jump_times"][j, :m] - ref["jump_times"][j, :m]).max(initial=0) < 1e-8
+        assert np.abs(res["expect_tr"] - ref["expect_tr"]).max() < 1e-6
+    else:
+        # complex64 states: the same jumps in (nearly) every trajectory, times to FP32-limited accuracy
+        same = (res["njumps"] == ref["njumps"]).mean()
+        assert same > 0.9, same
+    assert res["stats"]["n_jumps"] == res["njumps"].sum()
+
+
+def test_kerr_trajectories_fp64(ctx):
+    """Oscillator with photon loss: a single channel, many jumps per trajectory."""
+    H, c = qt.model_kerr(12, 1.0, 0.5, 0.8, 1.0)
+    psi0 = np.zeros(12, complex)
+    psi0[3] = 1.0
+    tl = np.linspace(0, 5, 11)
+    ref = oracle.mcsolve(H, c, psi0, tl, [om.number(12)], 24, 5, max_jump_record=6)
+    res = qt.mcsolve(ctx, H, c, psi0, tl, [om.number(12)], 24, 5, options=qt.opts(precision=qt.F64),
+                     want_traj=True, max_jump_record=6)
+    np.testing.assert_array_equal(res["njumps"], ref["njumps"])
+    assert np.abs(res["expect_tr"] - ref["expect_tr"]).max() < 1e-6
+
+
+def test_ensemble_matches_master_equation_l10(ctx):
+    """10,000 trajectories of the L = 10 chain (J = 1, h = 1, gamma = 0.1), complex64 states with FP64
+    norms and jump times: the mean of <sum sz> is within 3 SE of the oracle master equation."""
+    print("[gpu] mc L=10 ensemble (10,000 trajectories, mixed)", flush=True)
+    p = workloads.ising_mc()
+    with open(os.path.join(GOLD, "ising_l10_me.json")) as f:
+        g = json.load(f)
+    me = np.array(g["expect_re"])[0]
+    H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    res = qt.mcsolve(ctx, H, cs, om.all_up_ket(p["L"]), tl, [_sz_sum(p["L"])], p["ntraj"], p["seed"],
+                     options=qt.opts(abstol=1e-6, reltol=1e-4, precision=qt.MIXED))
+    mean, se = res["mean"][0].real, res["se"][0]
+    z = np.abs(mean - me)[1:] / se[1:]
+    print(f"[gpu]   max z = {z.max():.2f}, points over 3 SE: {(z > 3).sum()} of {len(z)}; jumps/traj "
+          f"{res['njumps'].mean():.2f} (min {res['njumps'].min()}, max {res['njumps'].max()}); "
+          f"{res['stats']['device_ms']:.1f} ms", flush=True)
+    assert abs(mean[0] - 10.0) < 1e-6
+    assert (z > 3).sum() <= 3 and z.max() < 4.5
+    assert res["njumps"].max() > res["njumps"].min()
+
+
+def test_mc_error_paths(ctx):
+    H, cs = qt.model_ising(3, 1.0, 0.5, 0.2)
+    tl = np.linspace(0, 1, 3)
+    with pytest.raises(qt.QtError) as e:
+        qt.mcsolve(ctx, H, cs, np.zeros(8, complex), tl, [], 4, 1)
+    assert e.value.code == qt.QT_EINVAL
+    with pytest.raises(qt.QtError) as e:
+        qt.mcsolve(ctx, H, cs, om.all_up_ket(3), np.array([0.0, 0.0]), [], 4, 1)
+    assert e.value.code == qt.QT_EINVAL
+    with pytest.raises(qt.QtError) as e:
+        qt.mcsolve(ctx, H, cs, om.all_up_ket(3), np.linspace(0, 50, 3), [], 4, 1, options=qt.opts(max_steps=2))
+    assert e.value.code == qt.QT_EMAXSTEPS
+    # single time point: the initial expectation only, no integration
+    res = qt.mcsolve(ctx, H, cs, 3 * om.all_up_ket(3), np.array([0.5]), [_sz_sum(3)], 5, 1)
+    assert np.allclose(res["mean"], 3.0) and (res["njumps"] == 0).all()
