@@ -166,8 +166,8 @@ class Context:
         _check(lib().qt_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(self.h)))
 
     def close(self):
-        if self.h:
-            lib().qt_ctx_destroy(self.h)
+        """Destroys the context unless objects created on it are still alive (then a no-op)."""
+        if self.h and lib().qt_ctx_destroy(self.h) == QT_OK:
             self.h = ctypes.c_void_p()
 
     def __del__(self):
@@ -251,6 +251,7 @@ class MePlan:
     """qt_me_plan_*: device-resident batch of master-equation problems."""
 
     def __init__(self, ctx, problems, options=None):
+        self.ctx = ctx  # the context must outlive the plan
         self.P = _MeProblems(problems)
         o = options or opts(precision=problems[0][0].precision)
         self.h = ctypes.c_void_p()
@@ -354,6 +355,7 @@ class McPlan:
     """qt_mc_plan_*: device-resident trajectory ensemble."""
 
     def __init__(self, ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, max_jump_record=0):
+        self.ctx = ctx
         self.p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed)
         o = options or opts(precision=MIXED)
         self.mj = int(max_jump_record)
@@ -388,6 +390,7 @@ class Server:
 
     def __init__(self, ctx, pool_bytes=16 << 30, max_slots=256, steps_per_epoch=32, options=None):
         o = options or opts(precision=MIXED)
+        self.ctx = ctx
         self.cfg = ServerCfg(int(pool_bytes), int(max_slots), int(steps_per_epoch), o)
         self.h = ctypes.c_void_p()
         _check(lib().qt_server_create(ctx.h, ctypes.byref(self.cfg), ctypes.byref(self.h)))

@@ -333,10 +333,12 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
     }
 }
 
-// Control: one workgroup per problem.  Acts according to the problem's phase.
+// Control: one workgroup per problem.  step_mode 0 completes a pending starting-step evaluation
+// (phases INIT0 / INIT1) and leaves stepping problems alone; step_mode 1 closes a Runge-Kutta step
+// (phase STEP) and leaves problems still in their starting phases alone.
 template <typename T>
 __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__restrict__ insts,
-                                                             CsrCtl *__restrict__ ctls)
+                                                             CsrCtl *__restrict__ ctls, int step_mode)
 {
     using V = typename vec2<T>::type;
     __shared__ double scr[16];
@@ -345,6 +347,7 @@ __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__re
     CsrCtl *C = ctls + ii;
     if (C->status != ST_RUNNING) return;
     const int phase = C->phase;
+    if ((phase == PH_STEP) != (step_mode != 0)) return;
     if (phase == PH_INIT0) {
         const double ta = sum_partials(I, 0, scr), tb = sum_partials(I, 1, scr);
         const V *x0 = (const V *)I.rho0;
@@ -495,9 +498,9 @@ int csr_rows_per_block(int lpr) { return (CSR_THREADS / 64) * (64 / lpr); }
     }
 
 template <typename T>
-static void launch_control(int ninst, const CsrInst *insts, CsrCtl *ctls, hipStream_t s)
+static void launch_control(int ninst, const CsrInst *insts, CsrCtl *ctls, int step_mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_csr_control<T>, dim3(ninst), dim3(CTL_THREADS), 0, s, insts, ctls);
+    hipLaunchKernelGGL(k_csr_control<T>, dim3(ninst), dim3(CTL_THREADS), 0, s, insts, ctls, step_mode);
 }
 
 template <typename T, int LPR>
@@ -508,7 +511,7 @@ static void launch_init_t(int which, int nblk, int ninst, const CsrInst *insts, 
         hipLaunchKernelGGL((k_csr_init0<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
     else
         hipLaunchKernelGGL((k_csr_init1<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
-    launch_control<T>(ninst, insts, ctls, s);
+    launch_control<T>(ninst, insts, ctls, 0, s);
 }
 
 template <typename T, int LPR>
@@ -522,7 +525,7 @@ static void launch_step_t(int nblk, int ninst, const CsrInst *insts, CsrCtl *ctl
     hipLaunchKernelGGL((k_csr_stage<T, LPR, 5>), g, t, 0, s, insts, ctls, bi, br);
     hipLaunchKernelGGL((k_csr_stage<T, LPR, 6>), g, t, 0, s, insts, ctls, bi, br);
     hipLaunchKernelGGL((k_csr_stage<T, LPR, 7>), g, t, 0, s, insts, ctls, bi, br);
-    launch_control<T>(ninst, insts, ctls, s);
+    launch_control<T>(ninst, insts, ctls, 1, s);
 }
 
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s)

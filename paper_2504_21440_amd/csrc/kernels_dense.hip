@@ -135,6 +135,24 @@ template <typename T, int NP, int WPR> struct DenseRhs {
         T *B2re = lds + 4 * G::PLANE, *B2im = lds + 5 * G::PLANE;
         const size_t mat = (size_t)NP * NP;
         const int kmax = nc > 0 ? nc : 1;
+        // Project the stage input onto its Hermitian part.  The products below are exact only for
+        // Hermitian rho; without this, rounding noise in the anti-Hermitian part would evolve under a
+        // generator with the dissipative terms' signs flipped and grow exponentially.  Each pair
+        // (i, j), i <= j, is handled by one thread.
+        for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
+            const int i = e / NP, j = e % NP;
+            if (i < j) {
+                const T ar = T(0.5) * (B0re[i * S + j] + B0re[j * S + i]);
+                const T ai = T(0.5) * (B0im[i * S + j] - B0im[j * S + i]);
+                B0re[i * S + j] = ar;
+                B0im[i * S + j] = ai;
+                B0re[j * S + i] = ar;
+                B0im[j * S + i] = -ai;
+            } else if (i == j) {
+                B0im[i * S + i] = T(0);
+            }
+        }
+        __syncthreads();
         for (int k = 0; k < kmax; ++k) {
             if (k == 0) {
                 // M = A B0 -> B2

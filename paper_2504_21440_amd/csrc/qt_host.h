@@ -60,6 +60,7 @@ struct Ctx {
     static constexpr int NPOOL = 4;
     hipStream_t pool[NPOOL] = {};  // streams for concurrent dense-size buckets
     bool own_stream = false;
+    int refs = 0;  // live Liouvillians, plans and servers created on this context
 };
 
 struct Liouv {

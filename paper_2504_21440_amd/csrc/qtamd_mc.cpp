@@ -200,6 +200,7 @@ static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_opts
         return set_error(QT_EDEVICE, std::string("mc plan upload: ") + hipGetErrorString(e));
     }
     P->grid = mc_grid(p, f64, ctx->device);
+    ctx->refs++;
     *out = P;
     return QT_OK;
 }
@@ -297,6 +298,7 @@ qt_status qt_mc_plan_destroy(qt_mc_plan *plan)
     if (!plan) return QT_OK;
     (void)hipSetDevice(plan->ctx->device);
     plan->arena.release();
+    plan->ctx->refs--;
     delete plan;
     return QT_OK;
 }

@@ -57,6 +57,7 @@ struct qt_me_plan {
     };
     std::vector<Bucket> buckets;  // dense problems grouped by padded size, largest first
     double last_ms = 0.0;
+    bool counted = false;  // holds a reference on ctx
 };
 
 namespace qt {
@@ -300,6 +301,8 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         qt_me_plan_destroy(P);
         return st;
     }
+    ctx->refs++;
+    P->counted = true;
     *out = P;
     return QT_OK;
 }
@@ -527,6 +530,7 @@ qt_status qt_me_plan_destroy(qt_me_plan *P)
     if (P->h_cctl) (void)hipHostFree(P->h_cctl);
     if (P->h_dctl) (void)hipHostFree(P->h_dctl);
     P->arena.release();
+    if (P->counted) P->ctx->refs--;
     delete P;
     return QT_OK;
 }

@@ -231,6 +231,9 @@ qt_status qt_ctx_create(int32_t device, void *hip_stream, qt_ctx **out)
 qt_status qt_ctx_destroy(qt_ctx *ctx)
 {
     if (!ctx) return QT_OK;
+    if (ctx->refs > 0)
+        return set_error(QT_EBUSY, "qt_ctx_destroy: " + std::to_string(ctx->refs) +
+                                       " Liouvillian(s), plan(s) or server(s) created on this context are still alive");
     (void)hipSetDevice(ctx->device);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     for (int k = 0; k < Ctx::NPOOL; ++k)
@@ -428,7 +431,7 @@ qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const 
             delete L;
             return set_error(QT_EDEVICE, "upload dense operators");
         }
-        *out = L;
+        ctx->refs++, *out = L;
         return QT_OK;
     }
 
@@ -526,7 +529,7 @@ qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const 
         return set_error(QT_EDEVICE, std::string("Liouvillian assembly: ") + hipGetErrorString(e));
     }
     L->bytes = (int64_t)((n + 1) * 4 + L->nnz * (4 + (int64_t)es));
-    *out = L;
+    ctx->refs++, *out = L;
     return QT_OK;
 }
 
@@ -570,6 +573,7 @@ qt_status qt_liouv_destroy(qt_liouv *L)
     if (L->col) (void)hipFree(L->col);
     if (L->val) (void)hipFree(L->val);
     if (L->dense) (void)hipFree(L->dense);
+    L->ctx->refs--;
     delete L;
     return QT_OK;
 }

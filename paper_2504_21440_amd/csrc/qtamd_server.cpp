@@ -1,0 +1,542 @@
+// qtamd_server.cpp -- continuous-batching master-equation server.
+//
+// Requests (master-equation problems of any size, CSR or dense form) are admitted while their
+// device footprint fits in a fixed device pool and a slot is free.  Every admitted request keeps its
+// density matrix, Runge-Kutta stages and control record resident in the pool; an epoch advances
+// every resident request by up to `steps_per_epoch` adaptive steps in shared launches (CSR problems
+// through the fused SpMV-stage kernels over a block table of all active CSR slots, dense problems
+// through the persistent MFMA kernel with a step budget, resuming from their control records).
+// After each epoch finished requests are retired -- their expectation values copied to the host and
+// their pool memory released -- so requests that arrived meanwhile join the next epoch: a request's
+// work overlaps on the device with whatever else is resident.  A request's arithmetic does not
+// depend on what else is resident: its blocks, reductions and step decisions are its own.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <unordered_map>
+
+#include "qt_csr.h"
+#include "qt_dense.h"
+#include "qt_host.h"
+
+namespace qt {
+
+// First-fit allocator over offsets of the device pool (256-byte granules), coalescing on free.
+struct PoolAlloc {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    void init(size_t n)
+    {
+        size = n;
+        free_.clear();
+        free_[0] = n;
+    }
+    bool alloc(size_t n, size_t *off)
+    {
+        n = (n + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, o2 = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o2] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = (n + 255) & ~size_t(255);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t largest() const
+    {
+        size_t m = 0;
+        for (auto &kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    int32_t slot = -1;
+    bool dense = false;
+    int32_t d = 0, nt = 0, ne = 0, np = 0;
+    size_t off = 0, bytes = 0;
+    size_t o_expect = 0;  // offset inside the pool
+    int32_t nblocks = 0;
+    int64_t fp = 0;  // budget charged while resident
+    bool done = false;
+    int32_t status = 0;
+    std::vector<double> expect;  // [ne][nt] complex, filled at retirement
+    qt_stats stats{};
+};
+
+}  // namespace qt
+
+struct qt_server {
+    qt::Ctx *ctx = nullptr;
+    qt_server_cfg cfg{};
+    int32_t prec = QT_MIXED;
+    void *pool = nullptr;
+    qt::PoolAlloc alloc;
+    // slot-indexed device arrays
+    qt::CsrInst *d_cinst = nullptr;
+    qt::CsrCtl *d_cctl = nullptr;
+    qt::DenseInst *d_dinst = nullptr;
+    qt::DenseCtl *d_dctl = nullptr;
+    int32_t *d_bi = nullptr, *d_br = nullptr, *d_order = nullptr;
+    size_t blk_cap = 0;
+    qt::CsrCtl *h_cctl = nullptr;   // pinned
+    qt::DenseCtl *h_dctl = nullptr; // pinned
+    std::vector<int32_t> free_slots;
+    std::unordered_map<uint64_t, qt::Request> reqs;  // admitted or finished, not yet polled
+    std::vector<uint64_t> active;                    // tickets resident on the device
+    uint64_t next_ticket = 1;
+    int lpr = 8;
+    bool counted = false;  // holds a reference on ctx
+    int64_t accounted = 0; // footprint of the resident requests
+};
+
+namespace qt {
+
+static size_t es_of(int32_t prec) { return prec == QT_F64 ? 16 : 8; }
+
+struct Layout {
+    size_t o_rho0, o_tlist, o_eptr, o_ecol, o_eval, o_expect, o_vec, o_part, total;
+};
+
+static Layout layout_of(const qt_me_problem &p, int32_t prec, int lpr, size_t eptr_n, size_t ecol_n, int32_t *nblocks)
+{
+    const int32_t d = p.L->d;
+    const size_t n = (size_t)d * d, es = es_of(prec);
+    const bool dense = p.L->form == QT_FORM_DENSE;
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t r = o;
+        o += (std::max<size_t>(b, 1) + 255) & ~size_t(255);
+        return r;
+    };
+    L.o_rho0 = take(n * es);
+    L.o_tlist = take((size_t)p.n_t * 8);
+    L.o_eptr = take(eptr_n * 4);
+    L.o_ecol = take(ecol_n * 4);
+    L.o_eval = take(ecol_n * 16);
+    L.o_expect = take((size_t)p.n_e * p.n_t * 16);
+    if (dense) {
+        const size_t np = (size_t)dense_np(d);
+        L.o_vec = take(dense_state_vectors() * np * np * es);
+        L.o_part = 0;
+        *nblocks = 0;
+    } else {
+        const int rpb = csr_rows_per_block(lpr);
+        *nblocks = (int32_t)((n + rpb - 1) / rpb);
+        L.o_vec = take(11 * n * es);
+        L.o_part = take((size_t)*nblocks * 16);
+    }
+    L.total = o;
+    return L;
+}
+
+static size_t eops_nnz(const qt_me_problem &p)
+{
+    size_t s = 0;
+    for (int k = 0; k < p.n_e; ++k) s += (size_t)std::max<int64_t>(0, p.e_ops[k].nnz);
+    return s;
+}
+
+static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *ticket)
+{
+    if (!p || !p->L || !ticket) return set_error(QT_EINVAL, "qt_server_submit: null argument");
+    if (p->L->precision != S->prec) return set_error(QT_EINVAL, "request precision differs from the server's");
+    if (p->n_t < 1 || !p->tlist || !p->rho0 || p->n_e < 0 || (p->n_e > 0 && !p->e_ops))
+        return set_error(QT_EINVAL, "malformed request");
+    for (int32_t i = 0; i < p->n_t; ++i)
+        if (!std::isfinite(p->tlist[i]) || (i > 0 && !(p->tlist[i] > p->tlist[i - 1])))
+            return set_error(QT_EINVAL, "tlist must be finite and strictly increasing");
+    const int32_t d = p->L->d;
+    const bool dense = p->L->form == QT_FORM_DENSE;
+    // e_ops as concatenated int32 CSR
+    std::vector<int32_t> eptr((size_t)std::max(1, p->n_e) * (d + 1), 0), ecol;
+    std::vector<double2> eval;
+    for (int k = 0; k < p->n_e; ++k) {
+        HCsr o;
+        qt_status st = csr_from_abi(&p->e_ops[k], d, &o, "e_ops");
+        if (st) return st;
+        const int32_t base = (int32_t)ecol.size();
+        for (int32_t i = 0; i <= d; ++i) eptr[(size_t)k * (d + 1) + i] = base + (int32_t)o.ptr[i];
+        for (int64_t q = 0; q < o.nnz(); ++q) {
+            ecol.push_back(o.idx[q]);
+            eval.push_back(make_double2(o.val[q].real(), o.val[q].imag()));
+        }
+    }
+    int32_t nblocks = 0;
+    const Layout Ly = layout_of(*p, S->prec, S->lpr, eptr.size(), ecol.size(), &nblocks);
+    // the budget covers everything the request keeps resident: its state (carved from the pool) and
+    // its Liouvillian (owned by the caller)
+    const int64_t fp = (int64_t)Ly.total + p->L->bytes;
+    if (fp > S->cfg.pool_bytes) return set_error(QT_ENOMEM, "request footprint exceeds the server budget");
+    if (S->free_slots.empty()) return set_error(QT_EBUSY, "no free slot");
+    if (S->accounted + fp > S->cfg.pool_bytes) return set_error(QT_EBUSY, "budget in use by resident requests");
+    size_t off = 0;
+    if (!S->alloc.alloc(Ly.total, &off)) return set_error(QT_EBUSY, "pool full");
+    // initial state in the solve precision
+    const size_t n = (size_t)d * d, es = es_of(S->prec);
+    std::vector<double> r(2 * n);
+    if (p->is_ket) {
+        for (int32_t i = 0; i < d; ++i)
+            for (int32_t j = 0; j < d; ++j) {
+                const cd a(p->rho0[2 * i], p->rho0[2 * i + 1]), b(p->rho0[2 * j], p->rho0[2 * j + 1]);
+                const cd v = a * std::conj(b);
+                r[2 * ((size_t)i * d + j)] = v.real();
+                r[2 * ((size_t)i * d + j) + 1] = v.imag();
+            }
+    } else {
+        std::memcpy(r.data(), p->rho0, 16 * n);
+    }
+    std::vector<char> rb(n * es);
+    if (S->prec == QT_F64) std::memcpy(rb.data(), r.data(), n * 16);
+    else
+        for (size_t i = 0; i < 2 * n; ++i) ((float *)rb.data())[i] = (float)r[i];
+    const int32_t slot = S->free_slots.back();
+    S->free_slots.pop_back();
+    char *base = (char *)S->pool + off;
+    hipStream_t s = S->ctx->stream;
+    hipError_t e = hipSuccess;
+    auto up = [&](size_t o, const void *src, size_t b) {
+        if (e == hipSuccess && b) e = hipMemcpyAsync(base + o, src, b, hipMemcpyHostToDevice, s);
+    };
+    up(Ly.o_rho0, rb.data(), rb.size());
+    up(Ly.o_tlist, p->tlist, (size_t)p->n_t * 8);
+    up(Ly.o_eptr, eptr.data(), eptr.size() * 4);
+    up(Ly.o_ecol, ecol.data(), ecol.size() * 4);
+    up(Ly.o_eval, eval.data(), eval.size() * 16);
+    qt_opts o = S->cfg.opts;
+    if (dense) {
+        DenseInst g;
+        dense_fill_inst(&g, d, p->L->nc, p->n_t, p->n_e, p->L->dense, base + Ly.o_rho0, base + Ly.o_vec,
+                        (const double *)(base + Ly.o_tlist), (const int32_t *)(base + Ly.o_eptr),
+                        (const int32_t *)(base + Ly.o_ecol), (const double2 *)(base + Ly.o_eval),
+                        (double2 *)(base + Ly.o_expect), o, S->prec);
+        DenseCtl c;
+        std::memset(&c, 0, sizeof(c));
+        c.status = DENSE_ST_INIT;
+        S->h_dctl[slot] = c;
+        if (e == hipSuccess) e = hipMemcpyAsync(S->d_dinst + slot, &g, sizeof(g), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(S->d_dctl + slot, &S->h_dctl[slot], sizeof(c), hipMemcpyHostToDevice, s);
+    } else {
+        CsrInst c;
+        std::memset(&c, 0, sizeof(c));
+        c.n = (int32_t)n;
+        c.d = d;
+        c.nt = p->n_t;
+        c.ne = p->n_e;
+        c.block0 = 0;  // set per epoch
+        c.nblocks = nblocks;
+        c.renorm = S->prec == QT_MIXED ? 1 : 0;
+        c.use_h0 = o.h0 > 0 ? 1 : 0;
+        c.atol = o.abstol;
+        c.rtol = o.reltol;
+        c.h0 = o.h0;
+        c.max_steps = o.max_steps;
+        c.rowptr = p->L->rowptr;
+        c.col = p->L->col;
+        c.val = p->L->val;
+        c.rho0 = base + Ly.o_rho0;
+        char *v = base + Ly.o_vec;
+        c.Y[0] = v;
+        c.Y[1] = v + n * es;
+        c.K[0] = v + 2 * n * es;
+        c.K[1] = v + 3 * n * es;
+        for (int k = 0; k < 5; ++k) c.ks[k] = v + (4 + k) * n * es;
+        c.ys[0] = v + 9 * n * es;
+        c.ys[1] = v + 10 * n * es;
+        c.tlist = (const double *)(base + Ly.o_tlist);
+        c.eptr = (const int32_t *)(base + Ly.o_eptr);
+        c.ecol = (const int32_t *)(base + Ly.o_ecol);
+        c.eval = (const double2 *)(base + Ly.o_eval);
+        c.expect = (double2 *)(base + Ly.o_expect);
+        c.partials = (double *)(base + Ly.o_part);
+        CsrCtl t;
+        std::memset(&t, 0, sizeof(t));
+        t.t = p->tlist[0];
+        t.err_prev = 1e-4;
+        t.scale = 1.0;
+        t.tr0 = 1.0;
+        t.status = ST_RUNNING;
+        t.phase = 2;  // first starting-step evaluation pending
+        t.save_idx = 1;
+        S->h_cctl[slot] = t;
+        if (e == hipSuccess) e = hipMemcpyAsync(S->d_cinst + slot, &c, sizeof(c), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(S->d_cctl + slot, &S->h_cctl[slot], sizeof(t), hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging buffers go out of scope
+    if (e != hipSuccess) {
+        S->alloc.release(off, Ly.total);
+        S->free_slots.push_back(slot);
+        return set_error(QT_EDEVICE, std::string("qt_server_submit: ") + hipGetErrorString(e));
+    }
+    Request R;
+    R.ticket = S->next_ticket++;
+    R.slot = slot;
+    R.dense = dense;
+    R.d = d;
+    R.nt = p->n_t;
+    R.ne = p->n_e;
+    R.np = dense ? dense_np(d) : 0;
+    R.off = off;
+    R.bytes = Ly.total;
+    R.o_expect = off + Ly.o_expect;
+    R.nblocks = nblocks;
+    R.fp = fp;
+    S->accounted += fp;
+    S->reqs[R.ticket] = R;
+    S->active.push_back(R.ticket);
+    *ticket = R.ticket;
+    return QT_OK;
+}
+
+static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finished)
+{
+    Ctx *ctx = S->ctx;
+    QT_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const bool f64 = S->prec == QT_F64;
+    const int K = std::max(1, S->cfg.steps_per_epoch);
+    // ---- CSR slots: block table of all active CSR requests ----
+    std::vector<int32_t> bi, br, csr_slots;
+    std::vector<std::pair<int32_t, int32_t>> block0;  // (slot, first block)
+    const int rpb = csr_rows_per_block(S->lpr);
+    for (uint64_t tk : S->active) {
+        Request &R = S->reqs[tk];
+        if (R.dense) continue;
+        block0.push_back({R.slot, (int32_t)bi.size()});
+        for (int32_t b = 0; b < R.nblocks; ++b) {
+            bi.push_back(R.slot);
+            br.push_back(b * rpb);
+        }
+        csr_slots.push_back(R.slot);
+    }
+    if (!bi.empty()) {
+        if (bi.size() > S->blk_cap) {
+            if (S->d_bi) (void)hipFree(S->d_bi);
+            if (S->d_br) (void)hipFree(S->d_br);
+            S->blk_cap = bi.size() * 2;
+            QT_HIP(hipMalloc(&S->d_bi, S->blk_cap * 4));
+            QT_HIP(hipMalloc(&S->d_br, S->blk_cap * 4));
+        }
+        QT_HIP(hipMemcpyAsync(S->d_bi, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
+        QT_HIP(hipMemcpyAsync(S->d_br, br.data(), br.size() * 4, hipMemcpyHostToDevice, s));
+        // block0 of each slot's descriptor for this epoch's grid
+        for (auto &sb : block0)
+            QT_HIP(hipMemcpyAsync((char *)(S->d_cinst + sb.first) + offsetof(CsrInst, block0), &sb.second, 4,
+                                  hipMemcpyHostToDevice, s));
+        const int nb = (int)bi.size(), ns = S->cfg.max_slots;
+        csr_launch_init(0, f64, S->lpr, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
+        csr_launch_init(1, f64, S->lpr, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
+        for (int k = 0; k < K; ++k) csr_launch_step(f64, S->lpr, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
+        QT_HIP(hipGetLastError());
+    }
+    // ---- dense slots: one budgeted launch per padded size, on the auxiliary streams ----
+    std::map<int32_t, std::vector<int32_t>> buckets;
+    for (uint64_t tk : S->active) {
+        Request &R = S->reqs[tk];
+        if (R.dense) buckets[-R.np].push_back(R.slot);  // largest first
+    }
+    std::vector<int32_t> order;
+    for (auto &b : buckets) order.insert(order.end(), b.second.begin(), b.second.end());
+    hipEvent_t ev = nullptr;
+    if (!order.empty()) {
+        QT_HIP(hipMemcpyAsync(S->d_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+        QT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        QT_HIP(hipEventRecord(ev, s));
+        size_t start = 0;
+        int bn = 0;
+        for (auto &b : buckets) {
+            hipStream_t bs = ctx->pool[bn++ % Ctx::NPOOL];
+            QT_HIP(hipStreamWaitEvent(bs, ev, 0));
+            dense_launch_bucket(-b.first, f64, dense_choose_config(-b.first, S->prec), S->d_dinst, S->d_dctl,
+                                S->d_order + start, (int)b.second.size(), K, 0, bs);
+            start += b.second.size();
+        }
+        QT_HIP(hipGetLastError());
+    }
+    // ---- wait, then retire finished requests ----
+    QT_HIP(hipMemcpyAsync(S->h_cctl, S->d_cctl, sizeof(CsrCtl) * S->cfg.max_slots, hipMemcpyDeviceToHost, s));
+    QT_HIP(hipStreamSynchronize(s));
+    if (ev) {
+        for (int b = 0; b < Ctx::NPOOL; ++b) QT_HIP(hipStreamSynchronize(ctx->pool[b]));
+        (void)hipEventDestroy(ev);
+        QT_HIP(hipMemcpy(S->h_dctl, S->d_dctl, sizeof(DenseCtl) * S->cfg.max_slots, hipMemcpyDeviceToHost));
+    }
+    int32_t fin = 0;
+    std::vector<uint64_t> still;
+    for (uint64_t tk : S->active) {
+        Request &R = S->reqs[tk];
+        int32_t status;
+        qt_stats st;
+        std::memset(&st, 0, sizeof(st));
+        if (R.dense) {
+            const DenseCtl &c = S->h_dctl[R.slot];
+            status = c.status;
+            st.n_accept = c.n_accept;
+            st.n_reject = c.n_reject;
+            st.n_rhs = c.n_rhs;
+        } else {
+            const CsrCtl &c = S->h_cctl[R.slot];
+            status = c.status;
+            st.n_accept = c.n_accept;
+            st.n_reject = c.n_reject;
+            st.n_rhs = c.n_rhs;
+        }
+        if (status == ST_RUNNING || status == DENSE_ST_INIT) {
+            still.push_back(tk);
+            continue;
+        }
+        R.status = status == ST_DONE ? QT_OK : status;
+        st.status = R.status;
+        R.stats = st;
+        R.expect.assign((size_t)2 * R.ne * R.nt, 0.0);
+        if (R.ne) QT_HIP(hipMemcpy(R.expect.data(), (char *)S->pool + R.o_expect, (size_t)R.ne * R.nt * 16,
+                                   hipMemcpyDeviceToHost));
+        S->alloc.release(R.off, R.bytes);
+        S->accounted -= R.fp;
+        S->free_slots.push_back(R.slot);
+        R.slot = -1;
+        R.done = true;
+        ++fin;
+    }
+    S->active.swap(still);
+    if (n_active) *n_active = (int32_t)S->active.size();
+    if (n_finished) *n_finished = fin;
+    return QT_OK;
+}
+
+}  // namespace qt
+
+using namespace qt;
+
+extern "C" {
+
+qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **out)
+{
+    if (!ctx || !cfg || !out) return set_error(QT_EINVAL, "qt_server_create: null argument");
+    if (cfg->pool_bytes <= 0 || cfg->max_slots <= 0 || cfg->steps_per_epoch <= 0)
+        return set_error(QT_EINVAL, "server config: pool_bytes, max_slots and steps_per_epoch must be positive");
+    if (cfg->opts.precision != QT_F64 && cfg->opts.precision != QT_MIXED)
+        return set_error(QT_EINVAL, "server config: bad precision");
+    QT_HIP(hipSetDevice(ctx->device));
+    qt_server *S = new qt_server();
+    S->ctx = ctx;
+    S->cfg = *cfg;
+    S->prec = cfg->opts.precision;
+    const int ns = cfg->max_slots;
+    hipError_t e = hipMalloc(&S->pool, (size_t)cfg->pool_bytes);
+    if (e == hipSuccess) e = hipMalloc(&S->d_cinst, sizeof(CsrInst) * ns);
+    if (e == hipSuccess) e = hipMalloc(&S->d_cctl, sizeof(CsrCtl) * ns);
+    if (e == hipSuccess) e = hipMalloc(&S->d_dinst, sizeof(DenseInst) * ns);
+    if (e == hipSuccess) e = hipMalloc(&S->d_dctl, sizeof(DenseCtl) * ns);
+    if (e == hipSuccess) e = hipMalloc(&S->d_order, sizeof(int32_t) * ns);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_cctl, sizeof(CsrCtl) * ns, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_dctl, sizeof(DenseCtl) * ns, hipHostMallocDefault);
+    if (e == hipSuccess) {
+        // every slot starts finished: the kernels skip it until a request is admitted into it
+        for (int i = 0; i < ns; ++i) {
+            std::memset(&S->h_cctl[i], 0, sizeof(CsrCtl));
+            S->h_cctl[i].status = ST_DONE;
+            std::memset(&S->h_dctl[i], 0, sizeof(DenseCtl));
+            S->h_dctl[i].status = ST_DONE;
+        }
+        e = hipMemcpy(S->d_cctl, S->h_cctl, sizeof(CsrCtl) * ns, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S->d_dctl, S->h_dctl, sizeof(DenseCtl) * ns, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        qt_server_destroy(S);
+        return set_error(e == hipErrorOutOfMemory ? QT_ENOMEM : QT_EDEVICE,
+                         std::string("qt_server_create: ") + hipGetErrorString(e));
+    }
+    S->alloc.init((size_t)cfg->pool_bytes);
+    for (int i = ns - 1; i >= 0; --i) S->free_slots.push_back(i);
+    S->lpr = choose_lpr(0, 19.0);
+    ctx->refs++;
+    S->counted = true;
+    *out = S;
+    return QT_OK;
+}
+
+qt_status qt_server_footprint(const qt_server *srv, const qt_me_problem *prob, int64_t *bytes)
+{
+    if (!srv || !prob || !prob->L || !bytes) return set_error(QT_EINVAL, "qt_server_footprint: null argument");
+    const int32_t d = prob->L->d;
+    int32_t nb = 0;
+    const Layout L = layout_of(*prob, srv->prec, srv->lpr, (size_t)std::max(1, prob->n_e) * (d + 1),
+                               prob->n_e > 0 && prob->e_ops ? eops_nnz(*prob) : 0, &nb);
+    *bytes = (int64_t)L.total + prob->L->bytes;
+    return QT_OK;
+}
+
+qt_status qt_server_submit(qt_server *srv, const qt_me_problem *prob, uint64_t *ticket)
+{
+    if (!srv) return set_error(QT_EINVAL, "null server");
+    QT_HIP(hipSetDevice(srv->ctx->device));
+    return server_submit(srv, prob, ticket);
+}
+
+qt_status qt_server_step(qt_server *srv, int32_t *n_active, int32_t *n_finished)
+{
+    if (!srv) return set_error(QT_EINVAL, "null server");
+    return server_step(srv, n_active, n_finished);
+}
+
+qt_status qt_server_poll(qt_server *srv, uint64_t ticket, int32_t *done, double *expect_out, qt_stats *stats)
+{
+    if (!srv || !done) return set_error(QT_EINVAL, "qt_server_poll: null argument");
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return set_error(QT_EINVAL, "unknown ticket");
+    Request &R = it->second;
+    *done = R.done ? 1 : 0;
+    if (!R.done) return QT_OK;
+    if (expect_out && !R.expect.empty()) std::memcpy(expect_out, R.expect.data(), R.expect.size() * 8);
+    if (stats) *stats = R.stats;
+    const qt_status st = R.status;
+    srv->reqs.erase(it);
+    return st == QT_OK ? QT_OK : set_error(st, "request stopped with status " + std::to_string(st));
+}
+
+qt_status qt_server_destroy(qt_server *S)
+{
+    if (!S) return QT_OK;
+    (void)hipSetDevice(S->ctx->device);
+    (void)hipStreamSynchronize(S->ctx->stream);
+    for (int b = 0; b < Ctx::NPOOL; ++b)
+        if (S->ctx->pool[b]) (void)hipStreamSynchronize(S->ctx->pool[b]);
+    if (S->pool) (void)hipFree(S->pool);
+    if (S->d_cinst) (void)hipFree(S->d_cinst);
+    if (S->d_cctl) (void)hipFree(S->d_cctl);
+    if (S->d_dinst) (void)hipFree(S->d_dinst);
+    if (S->d_dctl) (void)hipFree(S->d_dctl);
+    if (S->d_order) (void)hipFree(S->d_order);
+    if (S->d_bi) (void)hipFree(S->d_bi);
+    if (S->d_br) (void)hipFree(S->d_br);
+    if (S->h_cctl) (void)hipHostFree(S->h_cctl);
+    if (S->h_dctl) (void)hipHostFree(S->h_dctl);
+    if (S->counted) S->ctx->refs--;
+    delete S;
+    return QT_OK;
+}
+
+}  // extern "C"

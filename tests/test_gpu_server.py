@@ -1,0 +1,129 @@
+"""Continuous-batching server: admission by device footprint, requests joining while others run,
+and every result the same alone and in the mix (bitwise: a request's arithmetic never depends on what
+else is resident), checked against the FP64 oracle as well."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import models as om
+import workloads
+import paper_2504_21440_amd as qt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating context", flush=True)
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+def _request(ctx, p, prec=qt.MIXED, nt=21):
+    if p["kind"] == "kerr":
+        H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
+        L = qt.Liouvillian(ctx, H, c, qt.FORM_DENSE, prec)
+        return (L, om.fock_dm(p["N"], 0), workloads.tlist(p["t_end"], nt), [om.number(p["N"])]), (H, c)
+    H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+    L = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
+    Lc = p["L"]
+    return (L, om.all_up_ket(Lc), workloads.tlist(p["t_end"], nt), [om.site_op(Lc, 0, om.sigmaz())]), (H, cs)
+
+
+def _trace(n, seed):
+    tr = workloads.serving_trace(n=n, seed=seed)
+    for p in tr:  # smaller sizes keep the oracle check quick
+        if p["kind"] == "kerr":
+            p["N"] = min(p["N"], 30)
+            p["U"] = min(p["U"], 0.3)
+        else:
+            p["L"] = min(p["L"], 6)
+    return tr
+
+
+def test_server_results_equal_alone_and_in_mix(ctx):
+    print("[gpu] server mix vs alone", flush=True)
+    trace = _trace(10, 3)
+    reqs = [_request(ctx, p) for p in trace]
+    o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED)
+    srv = qt.Server(ctx, pool_bytes=1 << 30, max_slots=64, steps_per_epoch=8, options=o)
+    tickets = {}
+    pending = list(range(len(reqs)))
+    results = {}
+    epochs = 0
+    # requests arrive two per epoch while earlier ones are still running
+    while pending or tickets:
+        for _ in range(2):
+            if pending:
+                i = pending.pop(0)
+                t = srv.submit(*reqs[i][0])
+                assert t is not None
+                tickets[t] = i
+        srv.step()
+        epochs += 1
+        for t in list(tickets):
+            r = srv.poll(t)
+            if r is not None:
+                results[tickets.pop(t)] = r
+        assert epochs < 100000
+    assert len(results) == len(reqs)
+    for i, (pr, ops) in enumerate(reqs):
+        alone = qt.mesolve_batch(ctx, [pr], o)[0]
+        np.testing.assert_array_equal(results[i][0], alone[0])
+        assert results[i][1]["n_accept"] == alone[1]["n_accept"]
+        H, cs = ops
+        ref, _, _, _ = oracle.mesolve(H, cs, pr[1], pr[2], pr[3])
+        assert np.abs(results[i][0] - ref).max() < 1e-4
+    srv.close()
+
+
+def test_server_admission_by_footprint(ctx):
+    print("[gpu] server admission", flush=True)
+    o = qt.opts(precision=qt.MIXED)
+    p_big = {"kind": "ising", "L": 6, "J": 1.0, "h": 0.7, "gamma": 0.2, "t_end": 2.0, "nt": 5}
+    big, _ = _request(ctx, p_big, nt=5)
+    probe = qt.Server(ctx, pool_bytes=1 << 30, max_slots=4, steps_per_epoch=16, options=o)
+    fp = probe.footprint(*big)
+    probe.close()
+    # pool for exactly one request of this size: the second must wait until the first retires
+    srv = qt.Server(ctx, pool_bytes=int(fp * 1.5), max_slots=8, steps_per_epoch=16, options=o)
+    t1 = srv.submit(*big)
+    assert t1 is not None
+    big2, _ = _request(ctx, dict(p_big, h=0.9), nt=5)
+    assert srv.submit(*big2) is None  # QT_EBUSY: does not fit now
+    done = None
+    while done is None:
+        srv.step()
+        done = srv.poll(t1)
+    t2 = srv.submit(*big2)
+    assert t2 is not None
+    while srv.poll(t2) is None:
+        srv.step()
+    # a request larger than the whole pool can never be admitted
+    huge, _ = _request(ctx, dict(p_big, L=8), nt=5)
+    with pytest.raises(qt.QtError) as e:
+        srv.submit(*huge)
+    assert e.value.code == qt.QT_ENOMEM
+    srv.close()
+
+
+def test_server_slot_limit_and_errors(ctx):
+    o = qt.opts(precision=qt.MIXED, max_steps=5)
+    srv = qt.Server(ctx, pool_bytes=1 << 28, max_slots=2, steps_per_epoch=4, options=o)
+    p = {"kind": "kerr", "N": 12, "delta": 1.0, "U": 0.5, "F": 0.8, "kappa": 1.0, "t_end": 20.0, "nt": 5}
+    r1, _ = _request(ctx, p, nt=5)
+    r2, _ = _request(ctx, dict(p, N=14), nt=5)
+    r3, _ = _request(ctx, dict(p, N=16), nt=5)
+    t1, t2 = srv.submit(*r1), srv.submit(*r2)
+    assert t1 is not None and t2 is not None
+    assert srv.submit(*r3) is None  # no free slot
+    for _ in range(10):
+        srv.step()
+    # max_steps = 5 cannot reach t = 20: both requests end with QT_EMAXSTEPS and free their slots
+    for t in (t1, t2):
+        with pytest.raises(qt.QtError) as e:
+            srv.poll(t)
+        assert e.value.code == qt.QT_EMAXSTEPS
+    assert srv.submit(*r3) is not None
+    srv.close()

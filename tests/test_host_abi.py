@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "qtamd.h")).read()
-    return sorted(set(re.findall(r"\b(qt_[a-z0-9_]+)\s*\(", src)))
+    decl = r"^(?:qt_status|void|const char \*)\s*(qt_[a-z0-9_]+)\s*\("
+    return sorted(set(re.findall(decl, src, flags=re.M)))
 
 
 def test_library_exports_every_declared_symbol():
