@@ -60,6 +60,9 @@ def load_golden(name):
     return np.array(g["expect_re"]) + 1j * np.array(g["expect_im"])
 
 
+CSR_SHAPES = [(l, r) for l in (4, 8, 16) for r in (1, 2, 4) if r <= l]
+
+
 def spmv_bytes(n, nnz, val_bytes):
     """Algorithmic HBM bytes of one CSR SpMV: values + column indices, row pointers, x read, y write."""
     return nnz * (val_bytes + 4) + (n + 1) * 4 + 2 * n * val_bytes
@@ -103,6 +106,7 @@ def section_ising(ctx, steps, warmup):
         rt, err = cal if cal else (1e-6, float("nan"))
         o = qt.opts(abstol=rt / 100, reltol=rt, precision=prec)
         plan = qt.MePlan(ctx, [(Lo, up_ket(p["L"]), tl, sz_ops(p["L"]))], o)
+        shape = plan.autotune(reps=100)  # untimed set-up: picks the CSR tile shape for this size
         dt = time_plan(plan, steps, warmup)
         ex, st, _ = plan.result(0)
         err = float(np.abs(ex - ref).max())
@@ -115,7 +119,7 @@ def section_ising(ctx, steps, warmup):
                      "n_reject": st["n_reject"], "n_rhs": n_rhs, "ms_per_solve": 1e3 * dt / steps,
                      "solves_per_s": steps / dt, "rhs_per_s": n_rhs * steps / dt,
                      "stage_kernel_ms": ms_stage, "spmv_bytes": b, "stage_kernel_GBs": b / (ms_stage * 1e-3) / 1e9,
-                     "nnz": nnz, "n": n}
+                     "nnz": nnz, "n": n, "csr_shape": list(shape[:2])}
         log(f"ising L=8 {name}: {out[name]}")
         plan.close()
         Lo.close()
@@ -131,12 +135,18 @@ def section_hbm_spmv(ctx):
         Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
         d, nnz, _ = Lo.info()
         plan = qt.MePlan(ctx, [(Lo, up_ket(10), tl, [])], qt.opts(precision=prec))
-        ms = plan.time_rhs(reps=50)
         n = d * d
         b = spmv_bytes(n, nnz, vb)
+        by_shape = {}
+        for lpr, rg in CSR_SHAPES:
+            plan.set_shape(lpr, rg)
+            by_shape[f"{lpr}x{rg}"] = round(b / (plan.time_rhs(reps=20) * 1e-3) / 1e9, 1)
+        shape = plan.autotune(reps=50)
+        ms = plan.time_rhs(reps=50)
         gbs = b / (ms * 1e-3) / 1e9
         out[name] = {"n": n, "nnz": nnz, "bytes_per_launch": b, "ms_per_launch": ms, "GBs": gbs,
-                     "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+                     "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "csr_shape": list(shape[:2]),
+                     "GBs_by_shape": by_shape}
         log(f"HBM SpMV L=10 {name}: {out[name]}")
         plan.close()
         Lo.close()
@@ -158,6 +168,7 @@ def section_sweep(ctx, n=512, check=12):
         probs.append((Lo, rho0, workloads.tlist(p["t_end"], p["nt"]), [num]))
     o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED)
     plan = qt.MePlan(ctx, probs, o)
+    wpr = plan.autotune(reps=5)[2]  # untimed set-up: waves per tile row for each padded size
     plan.run()
     t0 = time.perf_counter()
     plan.run()
@@ -174,9 +185,127 @@ def section_sweep(ctx, n=512, check=12):
     out = {"instances": n, "solves_per_s": n / dt, "ms_per_batch": dt * 1e3, "rhs_per_s": n_rhs / dt,
            "dense_kernel_ms": kern_ms, "algorithmic_TFLOPs": flops / (kern_ms * 1e-3) / 1e12,
            "frac_of_fp32_matrix_peak": flops / (kern_ms * 1e-3) / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
-           "rtol": o.reltol, "atol": o.abstol}
+           "rtol": o.reltol, "atol": o.abstol, "dense_waves_per_row_largest_bucket": wpr}
     plan.close()
     return out, sweep, res
+
+
+def section_mc(ctx):
+    """Quantum-jump ensemble: L = 10 chain, 10,000 trajectories, complex64 states with FP64 control."""
+    p = workloads.ising_mc()
+    H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    Sz = sum(sz_ops(p["L"]))
+    me = load_golden("ising_l10_me")[0].real
+    o = qt.opts(abstol=1e-6, reltol=1e-4, precision=qt.MIXED)
+    plan = qt.McPlan(ctx, H, cs, up_ket(p["L"]), tl, [Sz], p["ntraj"], p["seed"], options=o)
+    plan.run()
+    t0 = time.perf_counter()
+    plan.run()
+    dt = time.perf_counter() - t0
+    r = plan.result()
+    z = np.abs(r["mean"][0].real - me)[1:] / r["se"][0, 1:]
+    st = r["stats"]
+    out = {"ntraj": p["ntraj"], "seconds": dt, "trajectories_per_s": p["ntraj"] / dt,
+           "traj_rhs_per_s": st["n_rhs"] / dt, "device_ms": st["device_ms"],
+           "jumps_per_traj_mean": float(r["njumps"].mean()), "jumps_min": int(r["njumps"].min()),
+           "jumps_max": int(r["njumps"].max()), "max_z_vs_oracle_me": float(z.max()),
+           "points_over_3se": int((z > 3).sum()), "rtol": o.reltol, "atol": o.abstol}
+    log(f"mc: {out}")
+    plan.close()
+    return out
+
+
+def _serve_problem(ctx, p, prec, kerr_form=qt.FORM_CSR):
+    if p["kind"] == "kerr":
+        H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
+        L = qt.Liouvillian(ctx, H, c, kerr_form, prec)
+        rho0 = np.zeros((p["N"], p["N"]), complex)
+        rho0[0, 0] = 1
+        num = np.diag(np.arange(p["N"], dtype=float)).astype(complex)
+        return L, rho0, workloads.tlist(p["t_end"], p["nt"]), [num]
+    H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+    L = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
+    return L, up_ket(p["L"]), workloads.tlist(p["t_end"], p["nt"]), [sz_ops(p["L"])[0]]
+
+
+def _serve_mixed(ctx, trace, o, steps_per_epoch=32):
+    srv = qt.Server(ctx, pool_bytes=16 << 30, max_slots=1024, steps_per_epoch=steps_per_epoch, options=o)
+    probs = [_serve_problem(ctx, p, qt.MIXED) for p in trace]
+    lat, waiting, tickets = [], list(range(len(trace))), {}
+    t0 = time.perf_counter()
+    while waiting or tickets:
+        now = time.perf_counter() - t0
+        while waiting and trace[waiting[0]]["arrival"] <= now:
+            tk = srv.submit(*probs[waiting[0]])
+            if tk is None:
+                break  # no room yet: stays queued until requests retire
+            tickets[tk] = waiting.pop(0)
+        if not tickets:
+            time.sleep(max(0.0, trace[waiting[0]]["arrival"] - now))
+            continue
+        srv.step()
+        now = time.perf_counter() - t0
+        for tk in list(tickets):
+            if srv.poll(tk) is not None:
+                lat.append(now - trace[tickets.pop(tk)]["arrival"])
+    span = time.perf_counter() - t0
+    srv.close()
+    return np.array(lat), span
+
+
+def _serve_fp64_fifo(ctx, trace, o):
+    probs = [_serve_problem(ctx, p, qt.F64) for p in trace]
+    lat = []
+    t0 = time.perf_counter()
+    for p, pr in zip(trace, probs):
+        now = time.perf_counter() - t0
+        if p["arrival"] > now:
+            time.sleep(p["arrival"] - now)
+        qt.mesolve(ctx, *pr, options=o)
+        lat.append(time.perf_counter() - t0 - p["arrival"])
+    return np.array(lat), time.perf_counter() - t0
+
+
+def section_serving(ctx, n=240, qps=40.0, n_fifo=24):
+    """Poisson stream of 70% Kerr (N 10..80) and 30% Ising chains (L 4..9), mixed precision at the
+    1e-4 tolerances, served with continuous batching through the CSR form (the Kerr operators are
+    tridiagonal: the CSR right-hand side does ~30x fewer flops than the dense form); the plain FP64
+    single-solve path (CSR form, one request at a time, FIFO) runs the first n_fifo requests of the
+    same trace for comparison."""
+    trace = workloads.serving_trace(n=n, qps=qps)
+    om_ = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED)
+    lat, span = _serve_mixed(ctx, trace, om_)
+    out = {"requests": n, "qps": qps, "solves_per_s": n / span, "p50_s": float(np.percentile(lat, 50)),
+           "p99_s": float(np.percentile(lat, 99)), "makespan_s": span, "mixed_rtol": om_.reltol}
+    head = trace[:n_fifo]
+    lat_m, span_m = _serve_mixed(ctx, head, om_)
+    lat_f, span_f = _serve_fp64_fifo(ctx, head, qt.opts(precision=qt.F64))
+    out["prefix"] = {"requests": n_fifo,
+                     "mixed_batched": {"solves_per_s": n_fifo / span_m, "p50_s": float(np.percentile(lat_m, 50)),
+                                       "p99_s": float(np.percentile(lat_m, 99))},
+                     "fp64_single_fifo": {"solves_per_s": n_fifo / span_f,
+                                          "p50_s": float(np.percentile(lat_f, 50)),
+                                          "p99_s": float(np.percentile(lat_f, 99))}}
+    log(f"serving: {out}")
+    return out
+
+
+def copy_calibration(mbytes):
+    """One device-to-device copy of a known size (the HIP runtime's copy kernel), so that hardware
+    traffic counters collected on this run can be scaled to bytes."""
+    import ctypes
+    rt = ctypes.CDLL("/opt/rocm/lib/libamdhip64.so")
+    n = int(mbytes) << 20
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert rt.hipMalloc(ctypes.byref(a), ctypes.c_size_t(n)) == 0
+    assert rt.hipMalloc(ctypes.byref(b), ctypes.c_size_t(n)) == 0
+    assert rt.hipMemset(a, 1, ctypes.c_size_t(n)) == 0
+    assert rt.hipMemcpy(b, a, ctypes.c_size_t(n), 3) == 0  # device to device
+    assert rt.hipDeviceSynchronize() == 0
+    rt.hipFree(a)
+    rt.hipFree(b)
+    log(f"copy calibration: {n} bytes device to device")
 
 
 def cpu_oracle_baseline():
@@ -201,7 +330,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-extra", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (trajectories, sweep "
@@ -213,14 +345,24 @@ def main():
     ising = section_ising(ctx, args.steps, args.warmup)
     mixed = ising["mixed"]
     extra = {}
-    if not args.skip_extra:
+    only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving"}
+    if args.skip_extra:
+        only = set()
+    if "hbm" in only:
         log("hbm spmv")
         extra["spmv_hbm_L10"] = section_hbm_spmv(ctx)
+    if "sweep" in only:
         log("sweep")
         extra["kerr_sweep_512"], _, _ = section_sweep(ctx)
+    if "mc" in only:
+        log("mc")
+        extra["mcsolve_L10_10k"] = section_mc(ctx)
+    if "serving" in only:
+        log("serving")
+        extra["serving"] = section_serving(ctx)
     rl = {"bound": "hbm", "achieved": mixed["stage_kernel_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": mixed["stage_kernel_GBs"] / HBM_PEAK_GBS, "traffic": None,
-          "kernel": "k_csr_stage<float,8,3> (fused SpMV + stage epilogue), L=8 Liouvillian (MALL-resident)"}
+          "kernel": "k_csr_stage<float,%d,%d,3> (fused SpMV + stage epilogue), L=8 Liouvillian" % tuple(mixed["csr_shape"])}
     line = {
         "metric": METRIC, "value": mixed["rhs_per_s"], "unit": "RHS evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": mixed["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
@@ -233,6 +375,8 @@ def main():
         "roofline": rl,
     }
     line.update(extra)
+    if args.copy_calib_mb:
+        copy_calibration(args.copy_calib_mb)
     if not args.no_cpu:
         log("cpu oracle baseline")
         line["cpu_baseline"] = cpu_oracle_baseline()

@@ -72,7 +72,9 @@ typedef struct {
 
 /* Integrator options.  Defaults (qt_opts_default): abstol 1e-8, reltol 1e-6, max_steps 1e6,
  * h0 = 0 (automatic starting step), precision QT_F64, form QT_FORM_CSR, steps_per_launch 0
- * (library default). */
+ * (library default), autotune 0.  With autotune set, a plan whose size bucket the tuning table
+ * does not hold yet measures its candidate tile shapes once at creation and records the fastest
+ * (qt_me_plan_autotune). */
 typedef struct {
     double abstol;
     double reltol;
@@ -81,7 +83,7 @@ typedef struct {
     int32_t precision;
     int32_t form;
     int32_t steps_per_launch; /* RK steps recorded per graph replay (CSR form) */
-    int32_t reserved;
+    int32_t autotune;         /* nonzero: tune unseen size buckets at plan creation */
 } qt_opts;
 
 typedef struct {
@@ -165,6 +167,28 @@ qt_status qt_me_plan_destroy(qt_me_plan *plan);
  * results are unspecified afterwards until the next qt_me_plan_run. */
 qt_status qt_me_plan_time_rhs(qt_me_plan *plan, int32_t reps, double *ms_per_launch);
 
+/* Autotuner.  The CSR stage kernels take a tile shape (lanes per row group: 4, 8 or 16; rows per
+ * lane group: 1, 2 or 4, at most the lanes); the dense kernel takes 1 or 2 waves per 16-row tile
+ * row.  qt_me_plan_autotune times the fused SpMV-stage kernel of the plan's CSR problems for every
+ * candidate shape over `reps` launches (20 if reps <= 0), and each dense size bucket for its
+ * allowed waves-per-row choices over a budget of 8 steps; the fastest are kept for the plan and
+ * stored in a process-wide table keyed by precision and size bucket (log2 of the rows and mean
+ * row length for CSR, padded dimension for dense), which every later plan consults.  Results
+ * never depend on the shape beyond rounding of the row sums.  The plan's results are unspecified
+ * afterwards until the next qt_me_plan_run.  qt_me_plan_shape reports the shape in use (0 for a
+ * group the plan does not have); qt_me_plan_set_shape imposes a CSR shape (QT_EINVAL if the
+ * kernels do not support it).  One shape serves every CSR problem of a plan, and the row-sum
+ * and norm reduction orders follow it, so a problem's results are bitwise the same alone and in
+ * a batch when the shape is the same. */
+qt_status qt_me_plan_autotune(qt_me_plan *plan, int32_t reps);
+qt_status qt_me_plan_set_shape(qt_me_plan *plan, int32_t lanes_per_row, int32_t rows_per_group);
+qt_status qt_me_plan_shape(const qt_me_plan *plan, int32_t *lanes_per_row, int32_t *rows_per_group,
+                           int32_t *dense_waves_per_row);
+/* Persist the tuning table as a small JSON object {"key": [shape...], ...}.  load merges the
+ * entries of a file written by save, ignoring any shape the kernels do not support. */
+qt_status qt_tune_save(const char *path);
+qt_status qt_tune_load(const char *path);
+
 /* Expectation value (Sec. 3.1 e_ops; App. C expect): out = Tr(O rho) for a device density
  * matrix, or <psi|O|psi>/<psi|psi> for a device ket (is_ket), state stored complex128
  * (QT_F64) or complex64 (QT_MIXED), accumulated in FP64.  out: one complex (host). */
@@ -204,7 +228,9 @@ qt_status qt_mc_plan_destroy(qt_mc_plan *plan);
  * pool and a slot is free; admitted requests keep rho and solver state resident and are advanced
  * together, epoch by epoch, with requests that arrived earlier.  submit returns QT_EBUSY when the
  * request does not fit now (QT_ENOMEM if it can never fit).  step runs one epoch and retires
- * finished requests; poll reports completion and copies results. */
+ * finished requests; poll reports completion and copies results.  Requests of every size share
+ * the CSR launches, which use 8 lanes per row and one row per lane group; a request's results are
+ * bitwise those of a plan with that shape (qt_me_plan_set_shape(plan, 8, 1)). */
 typedef struct {
     int64_t pool_bytes;      /* device memory budget for resident requests */
     int32_t max_slots;       /* resident requests at most */

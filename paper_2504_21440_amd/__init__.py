@@ -23,7 +23,8 @@ EXPORTED = [
     "qt_opts_default", "qt_last_error", "qt_version", "qt_ctx_create", "qt_ctx_destroy", "qt_model_kerr",
     "qt_model_ising", "qt_csr_free", "qt_liouvillian_build", "qt_liouv_info", "qt_liouv_export",
     "qt_liouv_destroy", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
-    "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
+    "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_me_plan_autotune",
+    "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
     "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_server_create", "qt_server_submit", "qt_server_step",
     "qt_server_poll", "qt_server_footprint", "qt_server_destroy",
 ]
@@ -43,7 +44,7 @@ class CSR(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("abstol", ctypes.c_double), ("reltol", ctypes.c_double), ("max_steps", ctypes.c_int64),
                 ("h0", ctypes.c_double), ("precision", ctypes.c_int32), ("form", ctypes.c_int32),
-                ("steps_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("steps_per_launch", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -104,8 +105,9 @@ def _p(a):
     return ctypes.c_void_p(a.ctypes.data) if a is not None else None
 
 
-def opts(abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0, precision=F64, form=FORM_CSR, steps_per_launch=0):
-    return Opts(abstol, reltol, max_steps, h0, precision, form, steps_per_launch, 0)
+def opts(abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0, precision=F64, form=FORM_CSR, steps_per_launch=0,
+         autotune=False):
+    return Opts(abstol, reltol, max_steps, h0, precision, form, steps_per_launch, int(bool(autotune)))
 
 
 class _Ops:
@@ -276,6 +278,21 @@ class MePlan:
         _check(lib().qt_me_plan_time_rhs(self.h, int(reps), ctypes.byref(ms)))
         return ms.value
 
+    def autotune(self, reps=20):
+        """Measure the candidate tile shapes on this plan and keep the fastest (qt_me_plan_autotune)."""
+        _check(lib().qt_me_plan_autotune(self.h, int(reps)))
+        return self.shape()
+
+    def set_shape(self, lanes_per_row, rows_per_group):
+        """Impose a CSR tile shape (qt_me_plan_set_shape)."""
+        _check(lib().qt_me_plan_set_shape(self.h, int(lanes_per_row), int(rows_per_group)))
+
+    def shape(self):
+        """(lanes per row, rows per lane group, dense waves per row) in use (qt_me_plan_shape)."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qt_me_plan_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
     def close(self):
         if self.h:
             lib().qt_me_plan_destroy(self.h)
@@ -286,6 +303,16 @@ class MePlan:
             self.close()
         except Exception:
             pass
+
+
+def tune_save(path):
+    """Write the process-wide tuning table to a JSON file (qt_tune_save)."""
+    _check(lib().qt_tune_save(os.fsencode(path)))
+
+
+def tune_load(path):
+    """Merge a tuning table written by tune_save (qt_tune_load)."""
+    _check(lib().qt_tune_load(os.fsencode(path)))
 
 
 def mesolve_batch(ctx, problems, options=None):

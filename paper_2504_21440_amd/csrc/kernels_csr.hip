@@ -10,10 +10,13 @@
 // lands on save times, renormalises the trace (mixed precision) and records Tr(O rho), so the host
 // never sits inside the step loop and no block waits on another.
 //
-// Rows are split over LPR lanes (vector CSR): the LPR lanes of a group stride the row's non-zeros;
-// every lane first issues all of its column / value loads (non-temporal: the matrix is streamed
-// once per evaluation and should not evict the state vectors from L2 / MALL), then the gathers,
-// then the complex FMAs, and the group combines with xor shuffles inside the 64-wide wavefront.
+// Tile shape (LPR, RG): a group of LPR lanes of a 64-wide wavefront serves RG rows at once.  Every
+// lane first issues the column / value loads of all its rows (non-temporal: the matrix is streamed
+// once per evaluation and should not evict the state vectors from L2 / MALL), then the gathers and
+// complex FMAs; the group combines with xor shuffles, and lane g of the group runs the epilogue of
+// row g.  More rows per group put more bytes in flight per wave, which is what a latency-bound
+// SpMV needs; fewer keep small problems spread over more workgroups.  The shape is chosen per
+// problem size by the autotuner (qtamd_tune.cpp).
 #include "qt_common.h"
 #include "qt_csr.h"
 
@@ -23,10 +26,11 @@ constexpr int CSR_THREADS = 256;
 constexpr int CTL_THREADS = 256;
 enum : int32_t { PH_STEP = 0, PH_INIT1 = 1, PH_INIT0 = 2 };
 
-template <int LPR> struct CsrGeom {
-    static constexpr int RPW = 64 / LPR;
-    static constexpr int RPB = (CSR_THREADS / 64) * RPW;
-    static constexpr int U = (LPR >= 8) ? 4 : (LPR == 4 ? 6 : 8);  // non-zeros in flight per lane
+template <int LPR, int RG> struct CsrGeom {
+    static constexpr int RPW = 64 / LPR;                  // lane groups per wave
+    static constexpr int GPB = (CSR_THREADS / 64) * RPW;  // lane groups per block
+    static constexpr int RPB = GPB * RG;                  // rows per block
+    static constexpr int U = (LPR >= 8) ? 4 : (LPR == 4 ? 6 : 8);  // non-zeros per row in flight per lane
 };
 
 template <typename V> __device__ __forceinline__ V shfl_xor_c(V v, int m)
@@ -50,39 +54,65 @@ __device__ __forceinline__ double2 ld_stream(const double2 *p)
 }
 __device__ __forceinline__ int32_t ld_stream(const int32_t *p) { return __builtin_nontemporal_load(p); }
 
-// Row sum  sum_k val[k] * x(col[k])  for the LPR-lane group owning `row`; every lane of the
-// group returns the full sum.  X is a functor returning the (stage) input at a column.
-template <typename V, int LPR, typename X>
-__device__ __forceinline__ V csr_row(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                     const V *__restrict__ val, int row, bool valid, int q, X x)
+// Row sums  sum_k val[k] * x(col[k])  for the RG rows r0 + g * stride (g < RG) of this lane's
+// group; every lane of the group returns all RG sums.  X returns the (stage) input at a column.
+template <typename V, int LPR, int RG, typename X>
+__device__ __forceinline__ void csr_rows(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                         const V *__restrict__ val, int r0, int stride, int n, int q, X x,
+                                         V (&acc)[RG])
 {
-    constexpr int U = CsrGeom<LPR>::U;
-    V acc;
-    acc.x = 0;
-    acc.y = 0;
-    if (valid) {
-        const int s = rowptr[row], e = rowptr[row + 1];
-        for (int base = s + q; base < e; base += LPR * U) {
-            int cc[U];
-            V vv[U];
+    constexpr int U = CsrGeom<LPR, RG>::U;
+    int s[RG], e[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+        const int r = r0 + g * stride;
+        if (r < n) {
+            s[g] = rowptr[r];
+            e[g] = rowptr[r + 1];
+        } else {
+            s[g] = e[g] = 0;
+        }
+        acc[g].x = 0;
+        acc[g].y = 0;
+    }
+    for (int base = q;; base += LPR * U) {
+        int cc[RG][U];
+        V vv[RG][U];
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int k = base + u * LPR;
-                if (k < e) {
-                    cc[u] = ld_stream(col + k);
-                    vv[u] = ld_stream(val + k);
+                const int k = s[g] + base + u * LPR;
+                if (k < e[g]) {
+                    cc[g][u] = ld_stream(col + k);
+                    vv[g][u] = ld_stream(val + k);
+                    any = true;
                 } else {
-                    cc[u] = -1;
+                    cc[g][u] = -1;
                 }
             }
+        if (!any) break;
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (cc[u] >= 0) cfma(acc, vv[u], x(cc[u]));
-        }
+                if (cc[g][u] >= 0) cfma(acc[g], vv[g][u], x(cc[g][u]));
     }
 #pragma unroll
-    for (int m = LPR / 2; m >= 1; m >>= 1) acc = cadd(acc, shfl_xor_c(acc, m));
-    return acc;
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int m = LPR / 2; m >= 1; m >>= 1) acc[g] = cadd(acc[g], shfl_xor_c(acc[g], m));
+}
+
+// acc[q] without dynamic register indexing
+template <typename V, int RG> __device__ __forceinline__ V pick(const V (&a)[RG], int q)
+{
+    V r = a[0];
+#pragma unroll
+    for (int g = 1; g < RG; ++g)
+        if (q == g) r = a[g];
+    return r;
 }
 
 // Expectation values of the state Y (times `scale`) into expect[k][idx], FP64 accumulation:
@@ -148,8 +178,23 @@ __global__ void k_csr_reset(const CsrInst *__restrict__ insts, CsrCtl *__restric
     ctls[i] = c;
 }
 
+// Per-block row geometry shared by the SpMV kernels.
+template <int LPR, int RG> struct RowSlot {
+    int q, r0, row;
+    bool valid;
+    __device__ __forceinline__ RowSlot(int blk_row0, int n)
+    {
+        using G = CsrGeom<LPR, RG>;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        q = lane % LPR;
+        r0 = blk_row0 + w * G::RPW + lane / LPR;
+        row = r0 + q * G::GPB;  // the row whose epilogue this lane runs (q < RG)
+        valid = q < RG && row < n;
+    }
+};
+
 // Starting step, first evaluation: k1 = L rho0, y <- rho0, partials of |y|^2/sc^2 and |f(y)|^2/sc^2.
-template <typename T, int LPR>
+template <typename T, int LPR, int RG>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__restrict__ insts,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ blk_inst,
@@ -162,21 +207,20 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__rest
     const CsrInst &I = insts[ii];
     const CsrCtl *C = ctls + ii;
     if (C->status != ST_RUNNING || C->phase != PH_INIT0) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane % LPR;
-    const int row = blk_row0[b] + w * CsrGeom<LPR>::RPW + lane / LPR;
-    const bool valid = row < I.n;
+    const RowSlot<LPR, RG> rs(blk_row0[b], I.n);
     const V *__restrict__ x0 = (const V *)I.rho0;
-    const V acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q,
-                                  [&](int c) { return x0[c]; });
+    V acc[RG];
+    csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
+                         [&](int c) { return x0[c]; }, acc);
     double sa = 0.0, sb = 0.0;
-    if (valid && q == 0) {
-        const V y = x0[row];
-        ((V *)I.K[0])[row] = acc;
-        ((V *)I.Y[0])[row] = y;
+    if (rs.valid) {
+        const V a = pick(acc, rs.q);
+        const V y = x0[rs.row];
+        ((V *)I.K[0])[rs.row] = a;
+        ((V *)I.Y[0])[rs.row] = y;
         const double sc = I.atol + I.rtol * sqrt(abs2d(y));
         sa = abs2d(y) / (sc * sc);
-        sb = abs2d(acc) / (sc * sc);
+        sb = abs2d(a) / (sc * sc);
     }
     sa = block_sum(sa, scr);
     sb = block_sum(sb, scr);
@@ -187,7 +231,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__rest
 }
 
 // Starting step, second evaluation: partials of |f(y + h0 f(y)) - f(y)|^2 / (h0 sc)^2.
-template <typename T, int LPR>
+template <typename T, int LPR, int RG>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__restrict__ insts,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ blk_inst,
@@ -202,21 +246,21 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__rest
     if (C->status != ST_RUNNING || C->phase != PH_INIT1) return;
     const double h0 = C->h0;
     const T th0 = (T)h0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane % LPR;
-    const int row = blk_row0[b] + w * CsrGeom<LPR>::RPW + lane / LPR;
-    const bool valid = row < I.n;
+    const RowSlot<LPR, RG> rs(blk_row0[b], I.n);
     const V *__restrict__ y = (const V *)I.Y[0];
     const V *__restrict__ k1 = (const V *)I.K[0];
-    const V acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q, [&](int c) {
-        V v = y[c];
-        caxpy(v, th0, k1[c]);
-        return v;
-    });
+    V acc[RG];
+    csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
+                         [&](int c) {
+                             V v = y[c];
+                             caxpy(v, th0, k1[c]);
+                             return v;
+                         },
+                         acc);
     double sa = 0.0;
-    if (valid && q == 0) {
-        const double2 yr = to_d2(y[row]);
-        const double2 a = to_d2(acc), f0 = to_d2(k1[row]);
+    if (rs.valid) {
+        const double2 yr = to_d2(y[rs.row]);
+        const double2 a = to_d2(pick(acc, rs.q)), f0 = to_d2(k1[rs.row]);
         const double sc = I.atol + I.rtol * sqrt(yr.x * yr.x + yr.y * yr.y);
         const double dx = (a.x - f0.x) / h0, dy = (a.y - f0.y) / h0;
         sa = (dx * dx + dy * dy) / (sc * sc);
@@ -226,7 +270,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__rest
 }
 
 // One Runge-Kutta stage S (2..7) of a DP5 step for every running instance.
-template <typename T, int LPR, int S>
+template <typename T, int LPR, int RG, int S>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__restrict__ insts,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ blk_inst,
@@ -242,10 +286,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
     const double h = C->h_try;
     const int p = C->parity;
     const T s = (T)C->scale;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = lane % LPR;
-    const int row = blk_row0[b] + w * CsrGeom<LPR>::RPW + lane / LPR;
-    const bool valid = row < I.n;
+    const RowSlot<LPR, RG> rs(blk_row0[b], I.n);
     const V *__restrict__ y = (const V *)I.Y[p];
     const V *__restrict__ k1 = (const V *)I.K[p];
     V *__restrict__ ynew = (V *)I.Y[1 - p];
@@ -256,64 +297,68 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
     else if (S == 4 || S == 6) xin = (const V *)I.ys[1];
     else xin = ynew;
 
-    V acc;
+    V acc[RG];
     if (S == 2) {
         const T c = (T)(h * DP5::a21);
-        acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q, [&](int cc) {
-            V v = y[cc];
-            caxpy(v, c, k1[cc]);
-            return cscale(v, s);
-        });
+        csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
+                             [&](int cc) {
+                                 V v = y[cc];
+                                 caxpy(v, c, k1[cc]);
+                                 return cscale(v, s);
+                             },
+                             acc);
     } else {
-        acc = csr_row<V, LPR>(I.rowptr, I.col, (const V *)I.val, row, valid, q,
-                              [&](int cc) { return xin[cc]; });
+        csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
+                             [&](int cc) { return xin[cc]; }, acc);
     }
 
     double e2 = 0.0;
-    if (valid && q == 0) {
+    if (rs.valid) {
+        const int row = rs.row;
+        const V a = pick(acc, rs.q);
         const V yr = cscale(y[row], s);
         const V k1r = cscale(k1[row], s);
         if (S == 2) {
-            ks[0][row] = acc;
+            ks[0][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::a31), k1r);
-            caxpy(o, (T)(h * DP5::a32), acc);
+            caxpy(o, (T)(h * DP5::a32), a);
             ((V *)I.ys[0])[row] = o;
         } else if (S == 3) {
-            ks[1][row] = acc;
+            ks[1][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::a41), k1r);
             caxpy(o, (T)(h * DP5::a42), ks[0][row]);
-            caxpy(o, (T)(h * DP5::a43), acc);
+            caxpy(o, (T)(h * DP5::a43), a);
             ((V *)I.ys[1])[row] = o;
         } else if (S == 4) {
-            ks[2][row] = acc;
+            ks[2][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::a51), k1r);
             caxpy(o, (T)(h * DP5::a52), ks[0][row]);
             caxpy(o, (T)(h * DP5::a53), ks[1][row]);
-            caxpy(o, (T)(h * DP5::a54), acc);
+            caxpy(o, (T)(h * DP5::a54), a);
             ((V *)I.ys[0])[row] = o;
         } else if (S == 5) {
-            ks[3][row] = acc;
+            ks[3][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::a61), k1r);
             caxpy(o, (T)(h * DP5::a62), ks[0][row]);
             caxpy(o, (T)(h * DP5::a63), ks[1][row]);
             caxpy(o, (T)(h * DP5::a64), ks[2][row]);
-            caxpy(o, (T)(h * DP5::a65), acc);
+            caxpy(o, (T)(h * DP5::a65), a);
             ((V *)I.ys[1])[row] = o;
         } else if (S == 6) {
-            ks[4][row] = acc;
+            ks[4][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::b1), k1r);
             caxpy(o, (T)(h * DP5::b3), ks[1][row]);
             caxpy(o, (T)(h * DP5::b4), ks[2][row]);
             caxpy(o, (T)(h * DP5::b5), ks[3][row]);
-            caxpy(o, (T)(h * DP5::b6), acc);
+            caxpy(o, (T)(h * DP5::b6), a);
             ynew[row] = o;
         } else {
-            ((V *)I.K[1 - p])[row] = acc;
+            ((V *)I.K[1 - p])[row] = a;
             // error estimate e = h sum_j (b_j - bhat_j) k_j in FP64
             double2 e = make_double2(0.0, 0.0);
             caxpy(e, h * DP5::e1, to_d2(k1r));
@@ -321,7 +366,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
             caxpy(e, h * DP5::e4, to_d2(ks[2][row]));
             caxpy(e, h * DP5::e5, to_d2(ks[3][row]));
             caxpy(e, h * DP5::e6, to_d2(ks[4][row]));
-            caxpy(e, h * DP5::e7, to_d2(acc));
+            caxpy(e, h * DP5::e7, to_d2(a));
             const double my = sqrt(abs2d(yr)), mn = sqrt(abs2d(ynew[row]));
             const double sc = I.atol + I.rtol * fmax(my, mn);
             e2 = (e.x * e.x + e.y * e.y) / (sc * sc);
@@ -486,15 +531,24 @@ __global__ __launch_bounds__(256) void k_expect(int d, const int32_t *__restrict
 // ---------------------------------------------------------------------------------------------
 namespace qt {
 
-int csr_rows_per_block(int lpr) { return (CSR_THREADS / 64) * (64 / lpr); }
+int csr_rows_per_block(int lpr, int rg) { return (CSR_THREADS / 64) * (64 / lpr) * rg; }
 
-#define QT_LPR_DISPATCH(LPRV, CALL) \
-    switch (LPRV) {                 \
-    case 2: CALL(2); break;         \
-    case 4: CALL(4); break;         \
-    case 8: CALL(8); break;         \
-    case 16: CALL(16); break;       \
-    default: CALL(8); break;        \
+bool csr_shape_supported(int lpr, int rg)
+{
+    return (lpr == 4 || lpr == 8 || lpr == 16) && (rg == 1 || rg == 2 || rg == 4);
+}
+
+#define QT_SHAPE_DISPATCH(LPRV, RGV, CALL) \
+    switch (LPRV * 16 + RGV) {             \
+    case 4 * 16 + 1: CALL(4, 1); break;    \
+    case 4 * 16 + 2: CALL(4, 2); break;    \
+    case 4 * 16 + 4: CALL(4, 4); break;    \
+    case 8 * 16 + 2: CALL(8, 2); break;    \
+    case 8 * 16 + 4: CALL(8, 4); break;    \
+    case 16 * 16 + 1: CALL(16, 1); break;  \
+    case 16 * 16 + 2: CALL(16, 2); break;  \
+    case 16 * 16 + 4: CALL(16, 4); break;  \
+    default: CALL(8, 1); break;            \
     }
 
 template <typename T>
@@ -503,28 +557,28 @@ static void launch_control(int ninst, const CsrInst *insts, CsrCtl *ctls, int st
     hipLaunchKernelGGL(k_csr_control<T>, dim3(ninst), dim3(CTL_THREADS), 0, s, insts, ctls, step_mode);
 }
 
-template <typename T, int LPR>
+template <typename T, int LPR, int RG>
 static void launch_init_t(int which, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
                           const int32_t *br, hipStream_t s)
 {
     if (which == 0)
-        hipLaunchKernelGGL((k_csr_init0<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+        hipLaunchKernelGGL((k_csr_init0<T, LPR, RG>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
     else
-        hipLaunchKernelGGL((k_csr_init1<T, LPR>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+        hipLaunchKernelGGL((k_csr_init1<T, LPR, RG>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
     launch_control<T>(ninst, insts, ctls, 0, s);
 }
 
-template <typename T, int LPR>
+template <typename T, int LPR, int RG>
 static void launch_step_t(int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
                           const int32_t *br, hipStream_t s)
 {
     dim3 g(nblk), t(CSR_THREADS);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 2>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 3>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 4>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 5>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 6>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, 7>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 2>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 3>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 4>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 5>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 6>), g, t, 0, s, insts, ctls, bi, br);
+    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 7>), g, t, 0, s, insts, ctls, bi, br);
     launch_control<T>(ninst, insts, ctls, 1, s);
 }
 
@@ -533,35 +587,35 @@ void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t
     hipLaunchKernelGGL(k_csr_reset, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ctls, ninst);
 }
 
-void csr_launch_init(int which, bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
+void csr_launch_init(int which, bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
                      const int32_t *bi, const int32_t *br, hipStream_t s)
 {
-#define QT_CALL(L)                                                                \
-    if (f64) launch_init_t<double, L>(which, nblk, ninst, insts, ctls, bi, br, s); \
-    else launch_init_t<float, L>(which, nblk, ninst, insts, ctls, bi, br, s);
-    QT_LPR_DISPATCH(lpr, QT_CALL)
+#define QT_CALL(L, R)                                                                \
+    if (f64) launch_init_t<double, L, R>(which, nblk, ninst, insts, ctls, bi, br, s); \
+    else launch_init_t<float, L, R>(which, nblk, ninst, insts, ctls, bi, br, s);
+    QT_SHAPE_DISPATCH(lpr, rg, QT_CALL)
 #undef QT_CALL
 }
 
-void csr_launch_step(bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                     const int32_t *br, hipStream_t s)
+void csr_launch_step(bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
+                     const int32_t *bi, const int32_t *br, hipStream_t s)
 {
-#define QT_CALL(L)                                                          \
-    if (f64) launch_step_t<double, L>(nblk, ninst, insts, ctls, bi, br, s); \
-    else launch_step_t<float, L>(nblk, ninst, insts, ctls, bi, br, s);
-    QT_LPR_DISPATCH(lpr, QT_CALL)
+#define QT_CALL(L, R)                                                          \
+    if (f64) launch_step_t<double, L, R>(nblk, ninst, insts, ctls, bi, br, s); \
+    else launch_step_t<float, L, R>(nblk, ninst, insts, ctls, bi, br, s);
+    QT_SHAPE_DISPATCH(lpr, rg, QT_CALL)
 #undef QT_CALL
 }
 
-void csr_launch_stage3(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+void csr_launch_stage3(bool f64, int lpr, int rg, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
                        const int32_t *br, hipStream_t s)
 {
-#define QT_CALL(L)                                                                                      \
-    if (f64)                                                                                            \
-        hipLaunchKernelGGL((k_csr_stage<double, L, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br); \
-    else                                                                                                \
-        hipLaunchKernelGGL((k_csr_stage<float, L, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
-    QT_LPR_DISPATCH(lpr, QT_CALL)
+#define QT_CALL(L, R)                                                                                             \
+    if (f64)                                                                                                      \
+        hipLaunchKernelGGL((k_csr_stage<double, L, R, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br); \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_csr_stage<float, L, R, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+    QT_SHAPE_DISPATCH(lpr, rg, QT_CALL)
 #undef QT_CALL
 }
 

@@ -21,6 +21,7 @@
 
 #include "qt_common.h"
 #include "qt_dense.h"
+#include "qt_tune.h"
 
 namespace qt {
 
@@ -523,12 +524,16 @@ void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *op
 
 int dense_choose_config(int d, int prec)
 {
-    // waves per 16-row tile row of the output: two where the registers allow it (more waves in
-    // flight per CU), one for the largest padded sizes and for FP64
+    // waves per 16-row tile row of the output: the autotuner's measured choice for this padded
+    // size, else two where the registers allow it (more waves in flight per CU) and one for the
+    // largest padded sizes and for FP64
     const int np = dense_np(d);
-    if (prec == QT_F64) return 1;
-    return np <= 64 ? 2 : 1;
+    int wpr;
+    if (tune_lookup_dense(dense_tune_key(prec, np), &wpr) && dense_wpr_allowed(np, prec, wpr)) return wpr;
+    return dense_default_wpr(np, prec);
 }
+
+bool dense_wpr_allowed(int np, int prec, int wpr) { return wpr == 1 || (wpr == 2 && prec != QT_F64 && np <= 64); }
 
 const void *dense_state_ptr(const void *vec, int d, int prec)
 {

@@ -83,19 +83,19 @@ struct Liouv {
 // Kernel launchers (defined in the .hip files)
 struct CsrInst;
 struct CsrCtl;
-int csr_rows_per_block(int lpr);
+int csr_rows_per_block(int lpr, int rg);
+bool csr_shape_supported(int lpr, int rg);
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s);
-void csr_launch_init(int which, bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                     const int32_t *br, hipStream_t s);
-void csr_launch_step(bool f64, int lpr, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                     const int32_t *br, hipStream_t s);
-void csr_launch_stage3(bool f64, int lpr, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
+void csr_launch_init(int which, bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
+                     const int32_t *bi, const int32_t *br, hipStream_t s);
+void csr_launch_step(bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
+                     const int32_t *bi, const int32_t *br, hipStream_t s);
+void csr_launch_stage3(bool f64, int lpr, int rg, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
                        const int32_t *br, hipStream_t s);
+constexpr int CSR_MIN_ROWS_PER_BLOCK = 16;  // smallest tile (16 lanes per row, one row per group)
 void launch_expect(bool f64, int d, const int32_t *rp, const int32_t *ci, const double2 *v, const void *state,
                    int is_ket, double2 *out, hipStream_t s);
 
-// Tile-shape choice for the CSR right-hand side (lanes per row), by rows and mean row length.
-int choose_lpr(int64_t n, double mean_row);
 
 }  // namespace qt
 

@@ -6,6 +6,7 @@
 // records on the device, evaluates the starting step, then replays a captured graph of
 // `steps_per_launch` Runge-Kutta steps until every problem reports done; each problem keeps its
 // own step size and accept/reject history on the device, so the host only polls status words.
+// The CSR tile shape comes from the autotuner's table (or is measured on the plan when asked).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -14,6 +15,7 @@
 #include "qt_csr.h"
 #include "qt_dense.h"
 #include "qt_host.h"
+#include "qt_tune.h"
 
 namespace qt {
 
@@ -25,7 +27,6 @@ struct MeProb {
     size_t o_rho0 = 0, o_tlist = 0, o_eptr = 0, o_ecol = 0, o_eval = 0, o_expect = 0;
     size_t o_vec = 0;  // state vectors
     size_t o_part = 0;
-    int32_t block0 = 0, nblocks = 0;
     std::vector<char> rho0;  // host copy in state precision
     std::vector<double> tlist;
     std::vector<int32_t> eptr, ecol;
@@ -41,7 +42,10 @@ struct qt_me_plan {
     std::vector<qt::MeProb> probs;
     qt::Arena arena;
     // CSR group
-    int32_t ncsr = 0, lpr = 8, nblk = 0;
+    int32_t ncsr = 0, nblk = 0;
+    qt::CsrShape shape;
+    std::string tune_key;
+    std::vector<qt::CsrInst> h_ci;  // host copy of the descriptors (block ranges change with the shape)
     size_t o_cinst = 0, o_cctl = 0, o_bi = 0, o_br = 0;
     qt::CsrCtl *h_cctl = nullptr;  // pinned
     hipGraph_t graph = nullptr;
@@ -51,7 +55,6 @@ struct qt_me_plan {
     int32_t ndense = 0;
     size_t o_dinst = 0, o_dctl = 0, o_dorder = 0;
     qt::DenseCtl *h_dctl = nullptr;  // pinned
-    int32_t dense_cfg = 4;
     struct Bucket {
         int32_t np, start, count;
     };
@@ -96,8 +99,21 @@ static qt_status prep_problem(const qt_me_problem &p, int32_t prec, MeProb *m)
     } else {
         std::memcpy(r.data(), p.rho0, sizeof(double) * 2 * n);
     }
-    for (size_t i = 0; i < 2 * n; ++i)
+    double amax = 0.0, asym = 0.0;
+    for (size_t i = 0; i < 2 * n; ++i) {
         if (!std::isfinite(r[i])) return set_error(QT_EINVAL, "rho0 has non-finite entries");
+        amax = std::max(amax, std::fabs(r[i]));
+    }
+    if (m->dense) {
+        // the operator form evaluates L on Hermitian matrices only
+        for (int32_t i = 0; i < d; ++i)
+            for (int32_t j = 0; j < d; ++j) {
+                const size_t a = 2 * ((size_t)i * d + j), b = 2 * ((size_t)j * d + i);
+                asym = std::max(asym, std::fabs(r[a] - r[b]) + std::fabs(r[a + 1] + r[b + 1]));
+            }
+        if (asym > 1e-12 * std::max(1.0, amax))
+            return set_error(QT_EINVAL, "the dense form needs a Hermitian rho0 (use the CSR form otherwise)");
+    }
     if (prec == QT_F64) {
         m->rho0.resize(n * 16);
         std::memcpy(m->rho0.data(), r.data(), n * 16);
@@ -131,6 +147,38 @@ static qt_status upload(void *dst, const void *src, size_t bytes, hipStream_t s)
     return QT_OK;
 }
 
+// Lay the CSR problems out over the launch grid for a tile shape and upload the block tables.
+static qt_status apply_shape(qt_me_plan *P, CsrShape sh)
+{
+    if (!csr_shape_supported(sh.lpr, sh.rg)) return set_error(QT_EINVAL, "unsupported CSR tile shape");
+    const int rpb = csr_rows_per_block(sh.lpr, sh.rg);
+    std::vector<int32_t> bi, br;
+    for (int32_t i = 0; i < P->ncsr; ++i) {
+        CsrInst &c = P->h_ci[i];
+        c.nblocks = (c.n + rpb - 1) / rpb;
+        c.block0 = (int32_t)bi.size();
+        for (int32_t b = 0; b < c.nblocks; ++b) {
+            bi.push_back(i);
+            br.push_back(b * rpb);
+        }
+    }
+    hipStream_t s = P->ctx->stream;
+    qt_status st;
+    if ((st = upload(P->arena.at(P->o_cinst), P->h_ci.data(), sizeof(CsrInst) * P->ncsr, s))) return st;
+    if ((st = upload(P->arena.at(P->o_bi), bi.data(), 4 * bi.size(), s))) return st;
+    if ((st = upload(P->arena.at(P->o_br), br.data(), 4 * br.size(), s))) return st;
+    QT_HIP(hipStreamSynchronize(s));
+    P->nblk = (int32_t)bi.size();
+    P->shape = sh;
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+    return QT_OK;
+}
+
+qt_status me_plan_autotune(qt_me_plan *P, int32_t reps);
+
 qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts_in, qt_me_plan **out)
 {
     if (!ctx || n <= 0 || !probs || !out) return set_error(QT_EINVAL, "qt_me_plan_create: bad arguments");
@@ -154,9 +202,9 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         }
     }
     const size_t es = state_es(P->prec);
-    // ---- layout ----
+    // ---- layout (block tables sized for the smallest tile, so any shape fits) ----
     Arena &A = P->arena;
-    int64_t nnz_tot = 0, rows_tot = 0;
+    int64_t nnz_tot = 0, rows_tot = 0, max_blocks = 0;
     for (auto &m : P->probs)
         if (!m.dense) {
             m.slot = P->ncsr++;
@@ -165,8 +213,6 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         } else {
             m.slot = P->ndense++;
         }
-    P->lpr = choose_lpr(rows_tot, rows_tot ? (double)nnz_tot / rows_tot : 8.0);
-    const int rpb = csr_rows_per_block(P->lpr);
     for (auto &m : P->probs) {
         const size_t nvec = (size_t)m.d * m.d;
         m.o_rho0 = A.reserve(nvec * es);
@@ -176,11 +222,10 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         m.o_eval = A.reserve(std::max<size_t>(1, m.eval.size()) * 16);
         m.o_expect = A.reserve(std::max<size_t>(1, (size_t)m.ne * m.nt) * 16);
         if (!m.dense) {
-            m.nblocks = (int32_t)((nvec + rpb - 1) / rpb);
-            m.block0 = P->nblk;
-            P->nblk += m.nblocks;
+            const int64_t nb = ((int64_t)nvec + CSR_MIN_ROWS_PER_BLOCK - 1) / CSR_MIN_ROWS_PER_BLOCK;
+            max_blocks += nb;
             m.o_vec = A.reserve(11 * nvec * es);  // Y[2], K[2], k2..k6, ys[2]
-            m.o_part = A.reserve((size_t)m.nblocks * 16);
+            m.o_part = A.reserve((size_t)nb * 16);
         } else {
             const size_t np = (size_t)dense_np(m.d);
             m.o_vec = A.reserve(dense_state_vectors() * np * np * es);
@@ -189,8 +234,8 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
     if (P->ncsr) {
         P->o_cinst = A.reserve(sizeof(CsrInst) * P->ncsr);
         P->o_cctl = A.reserve(sizeof(CsrCtl) * P->ncsr);
-        P->o_bi = A.reserve(sizeof(int32_t) * P->nblk);
-        P->o_br = A.reserve(sizeof(int32_t) * P->nblk);
+        P->o_bi = A.reserve(sizeof(int32_t) * max_blocks);
+        P->o_br = A.reserve(sizeof(int32_t) * max_blocks);
     }
     if (P->ndense) {
         P->o_dinst = A.reserve(sizeof(DenseInst) * P->ndense);
@@ -204,9 +249,8 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
     }
     hipStream_t s = ctx->stream;
     // ---- uploads ----
-    std::vector<CsrInst> ci(P->ncsr);
+    P->h_ci.resize(P->ncsr);
     std::vector<DenseInst> di(P->ndense);
-    std::vector<int32_t> bi(P->nblk), br(P->nblk);
     for (auto &m : P->probs) {
         if ((st = upload(A.at(m.o_rho0), m.rho0.data(), m.rho0.size(), s))) break;
         if ((st = upload(A.at(m.o_tlist), m.tlist.data(), m.tlist.size() * 8, s))) break;
@@ -215,14 +259,12 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         if ((st = upload(A.at(m.o_eval), m.eval.data(), m.eval.size() * 16, s))) break;
         const size_t nvec = (size_t)m.d * m.d;
         if (!m.dense) {
-            CsrInst &c = ci[m.slot];
+            CsrInst &c = P->h_ci[m.slot];
             std::memset(&c, 0, sizeof(c));
             c.n = (int32_t)nvec;
             c.d = m.d;
             c.nt = m.nt;
             c.ne = m.ne;
-            c.block0 = m.block0;
-            c.nblocks = m.nblocks;
             c.renorm = P->prec == QT_MIXED ? 1 : 0;
             c.use_h0 = opts.h0 > 0 ? 1 : 0;
             c.atol = opts.abstol;
@@ -247,10 +289,6 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             c.eval = (const double2 *)A.at(m.o_eval);
             c.expect = (double2 *)A.at(m.o_expect);
             c.partials = (double *)A.at(m.o_part);
-            for (int32_t b = 0; b < m.nblocks; ++b) {
-                bi[m.block0 + b] = m.slot;
-                br[m.block0 + b] = b * rpb;
-            }
         } else {
             DenseInst &g = di[m.slot];
             dense_fill_inst(&g, m.d, m.L->nc, m.nt, m.ne, m.L->dense, A.at(m.o_rho0), A.at(m.o_vec),
@@ -260,16 +298,18 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         }
     }
     if (!st && P->ncsr) {
-        if ((st = upload(A.at(P->o_cinst), ci.data(), sizeof(CsrInst) * P->ncsr, s)) == QT_OK &&
-            (st = upload(A.at(P->o_bi), bi.data(), 4 * bi.size(), s)) == QT_OK)
-            st = upload(A.at(P->o_br), br.data(), 4 * br.size(), s);
+        const double mean_row = rows_tot ? (double)nnz_tot / rows_tot : 8.0;
+        P->tune_key = csr_tune_key(P->prec, rows_tot, mean_row);
+        CsrShape sh;
+        if (!tune_lookup_csr(P->tune_key, &sh)) sh = csr_default_shape(rows_tot, mean_row);
+        st = apply_shape(P, sh);
         if (!st) {
             hipError_t e = hipHostMalloc((void **)&P->h_cctl, sizeof(CsrCtl) * P->ncsr, hipHostMallocDefault);
             if (e) st = set_error(QT_ENOMEM, "pinned host buffer");
         }
     }
     if (!st && P->ndense) {
-        // largest problems first: the persistent kernel's blocks pick instances in this order
+        // largest problems first: the hardware dispatches workgroups in this order
         std::vector<int32_t> order(P->ndense);
         for (int32_t i = 0; i < P->ndense; ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return di[a].d > di[b].d; });
@@ -288,21 +328,28 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             hipError_t e = hipHostMalloc((void **)&P->h_dctl, sizeof(DenseCtl) * P->ndense, hipHostMallocDefault);
             if (e) st = set_error(QT_ENOMEM, "pinned host buffer");
         }
-        int32_t dmax = 0;
-        for (auto &g : di) dmax = std::max(dmax, g.d);
-        P->dense_cfg = dense_choose_config(dmax, P->prec);
     }
     if (!st) {
         hipError_t e = hipStreamSynchronize(s);
         if (e) st = set_error(QT_EDEVICE, std::string("plan upload: ") + hipGetErrorString(e));
     }
     P->graph_steps = opts.steps_per_launch > 0 ? opts.steps_per_launch : 16;
+    ctx->refs++;
+    P->counted = true;
+    if (!st && opts.autotune) {
+        bool known = true;
+        CsrShape tmp;
+        if (P->ncsr && !tune_lookup_csr(P->tune_key, &tmp)) known = false;
+        for (auto &bk : P->buckets) {
+            int w;
+            if (!tune_lookup_dense(dense_tune_key(P->prec, bk.np), &w)) known = false;
+        }
+        if (!known) st = me_plan_autotune(P, 20);
+    }
     if (st) {
         qt_me_plan_destroy(P);
         return st;
     }
-    ctx->refs++;
-    P->counted = true;
     *out = P;
     return QT_OK;
 }
@@ -317,11 +364,24 @@ static qt_status capture_graph(qt_me_plan *P)
     auto *bi = (const int32_t *)P->arena.at(P->o_bi);
     auto *br = (const int32_t *)P->arena.at(P->o_br);
     QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < P->graph_steps; ++k) csr_launch_step(f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
+    for (int k = 0; k < P->graph_steps; ++k)
+        csr_launch_step(f64, P->shape.lpr, P->shape.rg, P->nblk, P->ncsr, ci, cc, bi, br, s);
     hipError_t e = hipStreamEndCapture(s, &P->graph);
     if (e) return set_error(QT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     QT_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
     return QT_OK;
+}
+
+static void launch_dense_buckets(qt_me_plan *P, int max_steps_launch, hipStream_t single)
+{
+    const bool f64 = P->prec == QT_F64;
+    for (size_t b = 0; b < P->buckets.size(); ++b) {
+        const auto &bk = P->buckets[b];
+        hipStream_t bs = single ? single : P->ctx->pool[b % Ctx::NPOOL];
+        dense_launch_bucket(bk.np, f64, dense_choose_config(bk.np, P->prec), (const DenseInst *)P->arena.at(P->o_dinst),
+                            (DenseCtl *)P->arena.at(P->o_dctl), (const int32_t *)P->arena.at(P->o_dorder) + bk.start,
+                            bk.count, max_steps_launch, /*reset=*/1, bs);
+    }
 }
 
 qt_status me_plan_run(qt_me_plan *P)
@@ -336,15 +396,9 @@ qt_status me_plan_run(qt_me_plan *P)
     if (P->ndense) {
         QT_HIP(hipEventCreateWithFlags(&ev_start, hipEventDisableTiming));
         QT_HIP(hipEventRecord(ev_start, s));
-        for (size_t b = 0; b < P->buckets.size(); ++b) {
-            hipStream_t bs = ctx->pool[b % Ctx::NPOOL];
-            QT_HIP(hipStreamWaitEvent(bs, ev_start, 0));
-            const auto &bk = P->buckets[b];
-            dense_launch_bucket(bk.np, f64, dense_choose_config(bk.np, P->prec), (const DenseInst *)P->arena.at(P->o_dinst),
-                                (DenseCtl *)P->arena.at(P->o_dctl), (const int32_t *)P->arena.at(P->o_dorder) + bk.start,
-                                bk.count, /*max_steps_launch=*/-1, /*reset=*/1, bs);
-            QT_HIP(hipGetLastError());
-        }
+        for (int b = 0; b < Ctx::NPOOL; ++b) QT_HIP(hipStreamWaitEvent(ctx->pool[b], ev_start, 0));
+        launch_dense_buckets(P, -1, nullptr);
+        QT_HIP(hipGetLastError());
     }
     qt_status st = QT_OK;
     if (P->ncsr) {
@@ -353,8 +407,8 @@ qt_status me_plan_run(qt_me_plan *P)
         auto *bi = (const int32_t *)P->arena.at(P->o_bi);
         auto *br = (const int32_t *)P->arena.at(P->o_br);
         csr_launch_reset(ci, cc, P->ncsr, s);
-        csr_launch_init(0, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
-        csr_launch_init(1, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
+        csr_launch_init(0, f64, P->shape.lpr, P->shape.rg, P->nblk, P->ncsr, ci, cc, bi, br, s);
+        csr_launch_init(1, f64, P->shape.lpr, P->shape.rg, P->nblk, P->ncsr, ci, cc, bi, br, s);
         QT_HIP(hipGetLastError());
         if ((st = capture_graph(P))) return st;
         int replays = 1;
@@ -390,6 +444,94 @@ qt_status me_plan_run(qt_me_plan *P)
         (void)hipEventDestroy(ev_start);
     }
     P->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return QT_OK;
+}
+
+// Average milliseconds of one fused SpMV-stage launch over the CSR group (fresh starting state).
+static qt_status time_stage(qt_me_plan *P, int32_t reps, double *ms)
+{
+    hipStream_t s = P->ctx->stream;
+    const bool f64 = P->prec == QT_F64;
+    auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
+    auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
+    auto *bi = (const int32_t *)P->arena.at(P->o_bi);
+    auto *br = (const int32_t *)P->arena.at(P->o_br);
+    const int l = P->shape.lpr, r = P->shape.rg;
+    hipEvent_t e0, e1;
+    QT_HIP(hipEventCreate(&e0));
+    QT_HIP(hipEventCreate(&e1));
+    csr_launch_reset(ci, cc, P->ncsr, s);
+    csr_launch_init(0, f64, l, r, P->nblk, P->ncsr, ci, cc, bi, br, s);
+    csr_launch_init(1, f64, l, r, P->nblk, P->ncsr, ci, cc, bi, br, s);
+    csr_launch_stage3(f64, l, r, P->nblk, ci, cc, bi, br, s);  // warm
+    QT_HIP(hipEventRecord(e0, s));
+    for (int32_t k = 0; k < reps; ++k) csr_launch_stage3(f64, l, r, P->nblk, ci, cc, bi, br, s);
+    QT_HIP(hipEventRecord(e1, s));
+    QT_HIP(hipGetLastError());
+    QT_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    QT_HIP(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / reps;
+    return QT_OK;
+}
+
+// Measure every candidate CSR tile shape and, per dense bucket, both waves-per-row choices; keep
+// the fastest in the autotuner table and in this plan.
+qt_status me_plan_autotune(qt_me_plan *P, int32_t reps)
+{
+    QT_HIP(hipSetDevice(P->ctx->device));
+    if (reps <= 0) reps = 20;
+    if (P->ncsr) {
+        CsrShape cand[16];
+        const int nc = csr_candidates(cand, 16);
+        CsrShape best = P->shape;
+        double best_ms = 1e300;
+        for (int k = 0; k < nc; ++k) {
+            qt_status st = apply_shape(P, cand[k]);
+            if (st) return st;
+            double ms;
+            if ((st = time_stage(P, reps, &ms))) return st;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand[k];
+            }
+        }
+        qt_status st = apply_shape(P, best);
+        if (st) return st;
+        tune_store_csr(P->tune_key, best);
+    }
+    if (P->ndense) {
+        hipStream_t s = P->ctx->stream;
+        const bool f64 = P->prec == QT_F64;
+        for (const auto &bk : P->buckets) {
+            int best = dense_default_wpr(bk.np, P->prec);
+            double best_ms = 1e300;
+            for (int wpr = 1; wpr <= 2; ++wpr) {
+                if (!dense_wpr_allowed(bk.np, P->prec, wpr)) continue;
+                hipEvent_t e0, e1;
+                QT_HIP(hipEventCreate(&e0));
+                QT_HIP(hipEventCreate(&e1));
+                QT_HIP(hipEventRecord(e0, s));
+                dense_launch_bucket(bk.np, f64, wpr, (const DenseInst *)P->arena.at(P->o_dinst),
+                                    (DenseCtl *)P->arena.at(P->o_dctl),
+                                    (const int32_t *)P->arena.at(P->o_dorder) + bk.start, bk.count, 8, 1, s);
+                QT_HIP(hipEventRecord(e1, s));
+                QT_HIP(hipGetLastError());
+                QT_HIP(hipEventSynchronize(e1));
+                float t = 0.f;
+                QT_HIP(hipEventElapsedTime(&t, e0, e1));
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                if (t < best_ms) {
+                    best_ms = t;
+                    best = wpr;
+                }
+            }
+            tune_store_dense(dense_tune_key(P->prec, bk.np), best);
+        }
+    }
     return QT_OK;
 }
 
@@ -480,37 +622,45 @@ qt_status qt_me_plan_result(qt_me_plan *plan, int32_t i, double *expect_out, dou
     return me_plan_result(plan, i, expect_out, rho_final, stats);
 }
 
+qt_status qt_me_plan_autotune(qt_me_plan *plan, int32_t reps)
+{
+    if (!plan) return set_error(QT_EINVAL, "null plan");
+    return me_plan_autotune(plan, reps);
+}
+
+qt_status qt_me_plan_set_shape(qt_me_plan *plan, int32_t lanes_per_row, int32_t rows_per_group)
+{
+    if (!plan) return set_error(QT_EINVAL, "null plan");
+    if (!csr_shape_supported(lanes_per_row, rows_per_group))
+        return set_error(QT_EINVAL, "unsupported CSR tile shape");
+    if (!plan->ncsr) return QT_OK;
+    QT_HIP(hipSetDevice(plan->ctx->device));
+    return apply_shape(plan, CsrShape{lanes_per_row, rows_per_group});
+}
+
+qt_status qt_me_plan_shape(const qt_me_plan *plan, int32_t *lanes_per_row, int32_t *rows_per_group,
+                           int32_t *dense_waves_per_row)
+{
+    if (!plan) return set_error(QT_EINVAL, "null plan");
+    if (lanes_per_row) *lanes_per_row = plan->ncsr ? plan->shape.lpr : 0;
+    if (rows_per_group) *rows_per_group = plan->ncsr ? plan->shape.rg : 0;
+    if (dense_waves_per_row)
+        *dense_waves_per_row = plan->buckets.empty() ? 0 : dense_choose_config(plan->buckets[0].np, plan->prec);
+    return QT_OK;
+}
+
 qt_status qt_me_plan_time_rhs(qt_me_plan *P, int32_t reps, double *ms_per_launch)
 {
     if (!P || reps <= 0 || !ms_per_launch) return set_error(QT_EINVAL, "qt_me_plan_time_rhs: bad arguments");
-    Ctx *ctx = P->ctx;
-    QT_HIP(hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
-    const bool f64 = P->prec == QT_F64;
+    QT_HIP(hipSetDevice(P->ctx->device));
+    if (P->ncsr) return time_stage(P, reps, ms_per_launch);
+    hipStream_t s = P->ctx->stream;
     hipEvent_t e0, e1;
     QT_HIP(hipEventCreate(&e0));
     QT_HIP(hipEventCreate(&e1));
-    if (P->ncsr) {
-        auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
-        auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
-        auto *bi = (const int32_t *)P->arena.at(P->o_bi);
-        auto *br = (const int32_t *)P->arena.at(P->o_br);
-        csr_launch_reset(ci, cc, P->ncsr, s);
-        csr_launch_init(0, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
-        csr_launch_init(1, f64, P->lpr, P->nblk, P->ncsr, ci, cc, bi, br, s);
-        csr_launch_stage3(f64, P->lpr, P->nblk, ci, cc, bi, br, s);  // warm
-        QT_HIP(hipEventRecord(e0, s));
-        for (int32_t r = 0; r < reps; ++r) csr_launch_stage3(f64, P->lpr, P->nblk, ci, cc, bi, br, s);
-        QT_HIP(hipEventRecord(e1, s));
-    } else {
-        QT_HIP(hipEventRecord(e0, s));
-        for (int32_t r = 0; r < reps; ++r)
-            for (const auto &bk : P->buckets)
-                dense_launch_bucket(bk.np, f64, dense_choose_config(bk.np, P->prec), (const DenseInst *)P->arena.at(P->o_dinst),
-                                    (DenseCtl *)P->arena.at(P->o_dctl),
-                                    (const int32_t *)P->arena.at(P->o_dorder) + bk.start, bk.count, -1, 1, s);
-        QT_HIP(hipEventRecord(e1, s));
-    }
+    QT_HIP(hipEventRecord(e0, s));
+    for (int32_t r = 0; r < reps; ++r) launch_dense_buckets(P, -1, s);
+    QT_HIP(hipEventRecord(e1, s));
     QT_HIP(hipGetLastError());
     QT_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

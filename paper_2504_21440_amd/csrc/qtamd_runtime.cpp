@@ -167,16 +167,6 @@ HCsr csr_axpby(cd a, const HCsr &A, cd b, const HCsr &B)
     return C;
 }
 
-int choose_lpr(int64_t n, double mean_row)
-{
-    // Lanes per row: enough lanes that each strides ~2-3 non-zeros, fewer when rows are short.
-    (void)n;
-    if (mean_row <= 3.0) return 2;
-    if (mean_row <= 8.0) return 4;
-    if (mean_row <= 40.0) return 8;
-    return 16;
-}
-
 }  // namespace qt
 
 using namespace qt;

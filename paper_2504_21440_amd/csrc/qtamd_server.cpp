@@ -19,6 +19,7 @@
 #include "qt_csr.h"
 #include "qt_dense.h"
 #include "qt_host.h"
+#include "qt_tune.h"
 
 namespace qt {
 
@@ -106,7 +107,7 @@ struct qt_server {
     std::unordered_map<uint64_t, qt::Request> reqs;  // admitted or finished, not yet polled
     std::vector<uint64_t> active;                    // tickets resident on the device
     uint64_t next_ticket = 1;
-    int lpr = 8;
+    qt::CsrShape shape;  // CSR tile shape of every epoch launch
     bool counted = false;  // holds a reference on ctx
     int64_t accounted = 0; // footprint of the resident requests
 };
@@ -119,7 +120,7 @@ struct Layout {
     size_t o_rho0, o_tlist, o_eptr, o_ecol, o_eval, o_expect, o_vec, o_part, total;
 };
 
-static Layout layout_of(const qt_me_problem &p, int32_t prec, int lpr, size_t eptr_n, size_t ecol_n, int32_t *nblocks)
+static Layout layout_of(const qt_me_problem &p, int32_t prec, qt::CsrShape sh, size_t eptr_n, size_t ecol_n, int32_t *nblocks)
 {
     const int32_t d = p.L->d;
     const size_t n = (size_t)d * d, es = es_of(prec);
@@ -143,7 +144,7 @@ static Layout layout_of(const qt_me_problem &p, int32_t prec, int lpr, size_t ep
         L.o_part = 0;
         *nblocks = 0;
     } else {
-        const int rpb = csr_rows_per_block(lpr);
+        const int rpb = csr_rows_per_block(sh.lpr, sh.rg);
         *nblocks = (int32_t)((n + rpb - 1) / rpb);
         L.o_vec = take(11 * n * es);
         L.o_part = take((size_t)*nblocks * 16);
@@ -185,7 +186,7 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
         }
     }
     int32_t nblocks = 0;
-    const Layout Ly = layout_of(*p, S->prec, S->lpr, eptr.size(), ecol.size(), &nblocks);
+    const Layout Ly = layout_of(*p, S->prec, S->shape, eptr.size(), ecol.size(), &nblocks);
     // the budget covers everything the request keeps resident: its state (carved from the pool) and
     // its Liouvillian (owned by the caller)
     const int64_t fp = (int64_t)Ly.total + p->L->bytes;
@@ -320,7 +321,7 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
     // ---- CSR slots: block table of all active CSR requests ----
     std::vector<int32_t> bi, br, csr_slots;
     std::vector<std::pair<int32_t, int32_t>> block0;  // (slot, first block)
-    const int rpb = csr_rows_per_block(S->lpr);
+    const int rpb = csr_rows_per_block(S->shape.lpr, S->shape.rg);
     for (uint64_t tk : S->active) {
         Request &R = S->reqs[tk];
         if (R.dense) continue;
@@ -346,9 +347,9 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
             QT_HIP(hipMemcpyAsync((char *)(S->d_cinst + sb.first) + offsetof(CsrInst, block0), &sb.second, 4,
                                   hipMemcpyHostToDevice, s));
         const int nb = (int)bi.size(), ns = S->cfg.max_slots;
-        csr_launch_init(0, f64, S->lpr, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
-        csr_launch_init(1, f64, S->lpr, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
-        for (int k = 0; k < K; ++k) csr_launch_step(f64, S->lpr, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
+        csr_launch_init(0, f64, S->shape.lpr, S->shape.rg, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
+        csr_launch_init(1, f64, S->shape.lpr, S->shape.rg, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
+        for (int k = 0; k < K; ++k) csr_launch_step(f64, S->shape.lpr, S->shape.rg, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
         QT_HIP(hipGetLastError());
     }
     // ---- dense slots: one budgeted launch per padded size, on the auxiliary streams ----
@@ -471,7 +472,8 @@ qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **ou
     }
     S->alloc.init((size_t)cfg->pool_bytes);
     for (int i = ns - 1; i >= 0; --i) S->free_slots.push_back(i);
-    S->lpr = choose_lpr(0, 19.0);
+    // requests of many sizes share one grid: the shape for small spin and oscillator Liouvillians
+    S->shape = csr_default_shape(0, 19.0);
     ctx->refs++;
     S->counted = true;
     *out = S;
@@ -483,7 +485,7 @@ qt_status qt_server_footprint(const qt_server *srv, const qt_me_problem *prob, i
     if (!srv || !prob || !prob->L || !bytes) return set_error(QT_EINVAL, "qt_server_footprint: null argument");
     const int32_t d = prob->L->d;
     int32_t nb = 0;
-    const Layout L = layout_of(*prob, srv->prec, srv->lpr, (size_t)std::max(1, prob->n_e) * (d + 1),
+    const Layout L = layout_of(*prob, srv->prec, srv->shape, (size_t)std::max(1, prob->n_e) * (d + 1),
                                prob->n_e > 0 && prob->e_ops ? eops_nnz(*prob) : 0, &nb);
     *bytes = (int64_t)L.total + prob->L->bytes;
     return QT_OK;

@@ -203,11 +203,52 @@ def test_batch_alone_vs_mix_bitwise(ctx):
         probs.append((qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED), om.all_up_ket(Lc),
                       np.linspace(0, 10, 21), [om.site_op(Lc, 0, om.sigmaz())]))
     o = qt.opts(precision=qt.MIXED)
-    mix = qt.mesolve_batch(ctx, probs, o)
+
+    def solve(prs):
+        plan = qt.MePlan(ctx, prs, o)
+        plan.set_shape(8, 1)  # one CSR shape for both, so the reduction orders agree
+        plan.run()
+        out = [plan.result(i) for i in range(len(prs))]
+        plan.close()
+        return out
+
+    mix = solve(probs)
     for i, pr in enumerate(probs):
-        alone = qt.mesolve_batch(ctx, [pr], o)[0]
+        alone = solve([pr])[0]
         np.testing.assert_array_equal(alone[0], mix[i][0])
         assert alone[1]["n_accept"] == mix[i][1]["n_accept"]
+
+
+SHAPES = [(l, r) for l in (4, 8, 16) for r in (1, 2, 4) if r <= l]
+
+
+def test_csr_every_tile_shape_vs_oracle(ctx):
+    """Each (lanes per row, rows per lane group) shape of the CSR kernels against the oracle, on two
+    chains solved together (1024 and 64 rows: partial last blocks for every shape)."""
+    chains = [(5, 0.9), (3, 0.7)]
+    tl = np.linspace(0, 4, 21)
+    refs, probs = [], {qt.F64: [], qt.MIXED: []}
+    for Lc, h in chains:
+        H, cs = qt.model_ising(Lc, 1.0, h, 0.2)
+        e_ops = [om.site_op(Lc, i, om.sigmaz()) for i in range(Lc)]
+        refs.append(oracle.mesolve(H, cs, om.all_up_ket(Lc), tl, e_ops)[0])
+        for prec in (qt.F64, qt.MIXED):
+            probs[prec].append((qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec), om.all_up_ket(Lc), tl, e_ops))
+    for prec, tol in [(qt.F64, 1e-6), (qt.MIXED, 1e-4)]:
+        plan = qt.MePlan(ctx, probs[prec], qt.opts(precision=prec))
+        for lpr, rg in SHAPES:
+            print(f"[gpu] CSR shape lpr={lpr} rg={rg} prec={prec}", flush=True)
+            plan.set_shape(lpr, rg)
+            assert plan.shape()[:2] == (lpr, rg)
+            plan.run()
+            for i, ref in enumerate(refs):
+                ex, st, _ = plan.result(i)
+                assert st["status"] == 0
+                assert np.abs(ex - ref).max() <= tol, (lpr, rg, prec, i, np.abs(ex - ref).max())
+        plan.close()
+    with pytest.raises(qt.QtError):
+        plan = qt.MePlan(ctx, probs[qt.F64][:1], qt.opts())
+        plan.set_shape(8, 8)
 
 
 def test_plan_rerun_is_deterministic(ctx):
@@ -276,3 +317,28 @@ def test_expect_on_device_state(ctx):
     assert abs(qt.expect(ctx, O, k.address, d, True, qt.F64) - oracle.expect_ket(O, psi)) < 1e-12
     for x in (a, a32, k):
         x.free()
+
+
+def test_autotune_chooses_a_kernel_shape_and_keeps_parity(ctx, tmp_path):
+    print("[gpu] autotune CSR + dense", flush=True)
+    H, cs = qt.model_ising(6, 1.0, 0.7, 0.2)
+    e_ops = [om.site_op(6, 2, om.sigmaz())]
+    tl = np.linspace(0, 3, 11)
+    ref = oracle.mesolve(H, cs, om.all_up_ket(6), tl, e_ops)[0]
+    Hk, ck = qt.model_kerr(20, 1.0, 0.5, 0.8, 1.0)
+    refk = oracle.mesolve(Hk, ck, om.fock_dm(20, 0), tl, [om.number(20)])[0]
+    o = qt.opts(precision=qt.MIXED, autotune=True)
+    probs = [(qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED), om.all_up_ket(6), tl, e_ops),
+             (qt.Liouvillian(ctx, Hk, ck, qt.FORM_DENSE, qt.MIXED), om.fock_dm(20, 0), tl, [om.number(20)])]
+    plan = qt.MePlan(ctx, probs, o)
+    lpr, rg, wpr = plan.shape()
+    assert (lpr, rg) in SHAPES and wpr in (1, 2)
+    plan.run()
+    assert np.abs(plan.result(0)[0] - ref).max() <= 1e-4
+    assert np.abs(plan.result(1)[0] - refk).max() <= 1e-4
+    path = tmp_path / "tune.json"
+    qt.tune_save(str(path))
+    table = json.loads(path.read_text())
+    assert [lpr, rg] in table.values()
+    assert table.get("dense:mixed:np32") == [wpr]
+    plan.close()

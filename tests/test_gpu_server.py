@@ -69,7 +69,11 @@ def test_server_results_equal_alone_and_in_mix(ctx):
         assert epochs < 100000
     assert len(results) == len(reqs)
     for i, (pr, ops) in enumerate(reqs):
-        alone = qt.mesolve_batch(ctx, [pr], o)[0]
+        plan = qt.MePlan(ctx, [pr], o)
+        plan.set_shape(8, 1)  # the server's CSR launch shape
+        plan.run()
+        alone = plan.result(0)
+        plan.close()
         np.testing.assert_array_equal(results[i][0], alone[0])
         assert results[i][1]["n_accept"] == alone[1]["n_accept"]
         H, cs = ops

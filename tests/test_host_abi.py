@@ -61,3 +61,29 @@ def test_model_argument_errors():
     assert e.value.code == qt.QT_EINVAL
     with pytest.raises(qt.QtError):
         qt.model_ising(0, 1, 1, 1)
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    """The autotuner table persists as JSON; unsupported shapes in a file are ignored on load."""
+    src = tmp_path / "in.json"
+    src.write_text(
+        '{\n'
+        '  "csr:mixed:n20:r19": [16, 2],\n'
+        '  "csr:f64:n12:r7": [4, 4],\n'
+        '  "csr:f64:n13:r7": [4, 8],\n'      # rows per group above the lanes: not a kernel shape
+        '  "csr:f64:n14:r7": [32, 1],\n'     # 32 lanes per row: not a kernel shape
+        '  "dense:mixed:np32": [2],\n'
+        '  "dense:f64:np48": [2]\n'          # two waves per row are not built for FP64
+        '}\n')
+    qt.tune_load(str(src))
+    out = tmp_path / "out.json"
+    qt.tune_save(str(out))
+    import json
+    table = json.loads(out.read_text())
+    assert table["csr:mixed:n20:r19"] == [16, 2]
+    assert table["csr:f64:n12:r7"] == [4, 4]
+    assert table["dense:mixed:np32"] == [2]
+    for bad in ("csr:f64:n13:r7", "csr:f64:n14:r7", "dense:f64:np48"):
+        assert bad not in table
+    with pytest.raises(qt.QtError):
+        qt.tune_load(str(tmp_path / "missing.json"))
