@@ -104,9 +104,11 @@ def section_ising(ctx, steps, warmup):
         d, nnz, nbytes = Lo.info()
         cal = calibrate(ctx, Lo, p, prec, ref)
         rt, err = cal if cal else (1e-6, float("nan"))
-        o = qt.opts(abstol=rt / 100, reltol=rt, precision=prec)
+        # untimed set-up: the autotuner picks the CSR tile shape for this size (unless its table
+        # already holds one)
+        o = qt.opts(abstol=rt / 100, reltol=rt, precision=prec, autotune=True)
         plan = qt.MePlan(ctx, [(Lo, up_ket(p["L"]), tl, sz_ops(p["L"]))], o)
-        shape = plan.autotune(reps=100)  # untimed set-up: picks the CSR tile shape for this size
+        shape = plan.shape()
         dt = time_plan(plan, steps, warmup)
         ex, st, _ = plan.result(0)
         err = float(np.abs(ex - ref).max())
@@ -134,14 +136,15 @@ def section_hbm_spmv(ctx):
     for name, prec, vb in [("mixed", qt.MIXED, 8), ("fp64", qt.F64, 16)]:
         Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
         d, nnz, _ = Lo.info()
-        plan = qt.MePlan(ctx, [(Lo, up_ket(10), tl, [])], qt.opts(precision=prec))
+        plan = qt.MePlan(ctx, [(Lo, up_ket(10), tl, [])], qt.opts(precision=prec, autotune=True))
+        shape = plan.shape()
         n = d * d
         b = spmv_bytes(n, nnz, vb)
         by_shape = {}
         for lpr, rg in CSR_SHAPES:
             plan.set_shape(lpr, rg)
             by_shape[f"{lpr}x{rg}"] = round(b / (plan.time_rhs(reps=20) * 1e-3) / 1e9, 1)
-        shape = plan.autotune(reps=50)
+        plan.set_shape(*shape[:2])
         ms = plan.time_rhs(reps=50)
         gbs = b / (ms * 1e-3) / 1e9
         out[name] = {"n": n, "nnz": nnz, "bytes_per_launch": b, "ms_per_launch": ms, "GBs": gbs,
@@ -166,9 +169,10 @@ def section_sweep(ctx, n=512, check=12):
         rho0[0, 0] = 1
         num = np.diag(np.arange(p["N"], dtype=float)).astype(complex)
         probs.append((Lo, rho0, workloads.tlist(p["t_end"], p["nt"]), [num]))
-    o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED)
+    # untimed set-up: the autotuner picks the waves per tile row for each padded size
+    o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED, autotune=True)
     plan = qt.MePlan(ctx, probs, o)
-    wpr = plan.autotune(reps=5)[2]  # untimed set-up: waves per tile row for each padded size
+    wpr = plan.shape()[2]
     plan.run()
     t0 = time.perf_counter()
     plan.run()
@@ -308,6 +312,35 @@ def copy_calibration(mbytes):
     log(f"copy calibration: {n} bytes device to device")
 
 
+def kernel_source_digest():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2504_21440_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("kernels_csr.hip", "qt_csr.h", "qt_common.h"):
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """HBM-side bytes per dispatch of `kernel` from the committed counter summary, or None when the
+    summary does not cover it or the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_csr_stage_L8.traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest, table = None, {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if line.startswith("source_sha256_16:"):
+                digest = parts[1]
+            elif len(parts) == 5 and parts[1].startswith("k_csr_stage<"):
+                table[parts[1]] = int(parts[4])
+    if digest != kernel_source_digest():
+        return None
+    return table.get(kernel)
+
+
 def cpu_oracle_baseline():
     import oracle
     from oracle import models as om
@@ -315,13 +348,18 @@ def cpu_oracle_baseline():
     H, cs = om.ising(p["L"], p["J"], p["h"], p["gamma"])
     tl = workloads.tlist(p["t_end"], p["nt"])
     e_ops = [om.site_op(p["L"], i, om.sigmaz()) for i in range(p["L"])]
+    # bounded sample: whole FP64 solves of the headline chain, repeated until about 10 s of work
     t0 = time.perf_counter()
-    ex, st, rc, _ = oracle.mesolve(H, cs, om.all_up_ket(p["L"]), tl, e_ops)
+    solves, rhs = 0, 0
+    while solves == 0 or time.perf_counter() - t0 < 10.0:
+        ex, st, rc, _ = oracle.mesolve(H, cs, om.all_up_ket(p["L"]), tl, e_ops)
+        solves += 1
+        rhs += st["n_rhs"]
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": st["n_rhs"] / dt, "unit": "RHS evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full FP64 solve of the L=8 chain (abstol 1e-8, reltol 1e-6): {st['n_rhs']} RHS in "
-                      f"{dt:.1f} s", "seconds": dt}
+    return {"value": rhs / dt, "unit": "RHS evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{solves} full FP64 solves of the L=8 chain (abstol 1e-8, reltol 1e-6, OpenMP over rows): "
+                      f"{rhs} RHS in {dt:.1f} s", "seconds": dt, "solves_per_s": solves / dt}
 
 
 def main():
@@ -332,14 +370,18 @@ def main():
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-in", default="", help="load an autotuner table before measuring")
+    ap.add_argument("--tune-out", default="", help="save the autotuner table after measuring")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (trajectories, sweep "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (trajectories, sweep "
               "instances and served requests would shard by count across GPUs with one final FP64 "
-              "all-reduce; see DESIGN.md)", file=sys.stderr)
+              "all-reduce)", file=sys.stderr)
         sys.exit(2)
+    if args.tune_in and os.path.exists(args.tune_in):
+        qt.tune_load(args.tune_in)
     log("context")
     ctx = qt.Context(0)
     ising = section_ising(ctx, args.steps, args.warmup)
@@ -360,9 +402,11 @@ def main():
     if "serving" in only:
         log("serving")
         extra["serving"] = section_serving(ctx)
+    kname = "k_csr_stage<float,%d,%d,3>" % tuple(mixed["csr_shape"])
     rl = {"bound": "hbm", "achieved": mixed["stage_kernel_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-          "frac": mixed["stage_kernel_GBs"] / HBM_PEAK_GBS, "traffic": None,
-          "kernel": "k_csr_stage<float,%d,%d,3> (fused SpMV + stage epilogue), L=8 Liouvillian" % tuple(mixed["csr_shape"])}
+          "frac": mixed["stage_kernel_GBs"] / HBM_PEAK_GBS, "traffic": profiled_traffic(kname),
+          "kernel": kname + " (fused SpMV + stage epilogue), L=8 Liouvillian, one launch = one SpMV",
+          "algorithmic_bytes": mixed["spmv_bytes"]}
     line = {
         "metric": METRIC, "value": mixed["rhs_per_s"], "unit": "RHS evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": mixed["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
@@ -375,6 +419,8 @@ def main():
         "roofline": rl,
     }
     line.update(extra)
+    if args.tune_out:
+        qt.tune_save(args.tune_out)
     if args.copy_calib_mb:
         copy_calibration(args.copy_calib_mb)
     if not args.no_cpu:

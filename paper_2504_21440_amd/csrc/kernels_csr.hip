@@ -297,6 +297,22 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
     else if (S == 4 || S == 6) xin = (const V *)I.ys[1];
     else xin = ynew;
 
+    // The epilogue's own-row operands do not depend on the row sum: load them first, so their
+    // latency overlaps the matrix stream instead of following it.
+    V yr{}, k1r{}, kr[4]{}, ynr{};
+    if (rs.valid) {
+        const int row = rs.row;
+        yr = cscale(y[row], s);
+        k1r = cscale(k1[row], s);
+        if (S >= 3 && S <= 5) kr[0] = ks[0][row];
+        if (S >= 4) kr[1] = ks[1][row];
+        if (S >= 5) kr[2] = ks[2][row];
+        if (S >= 6) kr[3] = ks[3][row];
+        if (S == 7) {
+            kr[0] = ks[4][row];
+            ynr = ynew[row];
+        }
+    }
     V acc[RG];
     if (S == 2) {
         const T c = (T)(h * DP5::a21);
@@ -316,8 +332,6 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
     if (rs.valid) {
         const int row = rs.row;
         const V a = pick(acc, rs.q);
-        const V yr = cscale(y[row], s);
-        const V k1r = cscale(k1[row], s);
         if (S == 2) {
             ks[0][row] = a;
             V o = yr;
@@ -328,33 +342,33 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
             ks[1][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::a41), k1r);
-            caxpy(o, (T)(h * DP5::a42), ks[0][row]);
+            caxpy(o, (T)(h * DP5::a42), kr[0]);
             caxpy(o, (T)(h * DP5::a43), a);
             ((V *)I.ys[1])[row] = o;
         } else if (S == 4) {
             ks[2][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::a51), k1r);
-            caxpy(o, (T)(h * DP5::a52), ks[0][row]);
-            caxpy(o, (T)(h * DP5::a53), ks[1][row]);
+            caxpy(o, (T)(h * DP5::a52), kr[0]);
+            caxpy(o, (T)(h * DP5::a53), kr[1]);
             caxpy(o, (T)(h * DP5::a54), a);
             ((V *)I.ys[0])[row] = o;
         } else if (S == 5) {
             ks[3][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::a61), k1r);
-            caxpy(o, (T)(h * DP5::a62), ks[0][row]);
-            caxpy(o, (T)(h * DP5::a63), ks[1][row]);
-            caxpy(o, (T)(h * DP5::a64), ks[2][row]);
+            caxpy(o, (T)(h * DP5::a62), kr[0]);
+            caxpy(o, (T)(h * DP5::a63), kr[1]);
+            caxpy(o, (T)(h * DP5::a64), kr[2]);
             caxpy(o, (T)(h * DP5::a65), a);
             ((V *)I.ys[1])[row] = o;
         } else if (S == 6) {
             ks[4][row] = a;
             V o = yr;
             caxpy(o, (T)(h * DP5::b1), k1r);
-            caxpy(o, (T)(h * DP5::b3), ks[1][row]);
-            caxpy(o, (T)(h * DP5::b4), ks[2][row]);
-            caxpy(o, (T)(h * DP5::b5), ks[3][row]);
+            caxpy(o, (T)(h * DP5::b3), kr[1]);
+            caxpy(o, (T)(h * DP5::b4), kr[2]);
+            caxpy(o, (T)(h * DP5::b5), kr[3]);
             caxpy(o, (T)(h * DP5::b6), a);
             ynew[row] = o;
         } else {
@@ -362,12 +376,12 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
             // error estimate e = h sum_j (b_j - bhat_j) k_j in FP64
             double2 e = make_double2(0.0, 0.0);
             caxpy(e, h * DP5::e1, to_d2(k1r));
-            caxpy(e, h * DP5::e3, to_d2(ks[1][row]));
-            caxpy(e, h * DP5::e4, to_d2(ks[2][row]));
-            caxpy(e, h * DP5::e5, to_d2(ks[3][row]));
-            caxpy(e, h * DP5::e6, to_d2(ks[4][row]));
+            caxpy(e, h * DP5::e3, to_d2(kr[1]));
+            caxpy(e, h * DP5::e4, to_d2(kr[2]));
+            caxpy(e, h * DP5::e5, to_d2(kr[3]));
+            caxpy(e, h * DP5::e6, to_d2(kr[0]));
             caxpy(e, h * DP5::e7, to_d2(a));
-            const double my = sqrt(abs2d(yr)), mn = sqrt(abs2d(ynew[row]));
+            const double my = sqrt(abs2d(yr)), mn = sqrt(abs2d(ynr));
             const double sc = I.atol + I.rtol * fmax(my, mn);
             e2 = (e.x * e.x + e.y * e.y) / (sc * sc);
         }

@@ -57,7 +57,57 @@ def kerr_me(U, abstol, reltol, name):
                       source="oracle.mesolve"), ex)
 
 
+def sweep_sample_indices(n=512, extra=6, seed=11):
+    """Instances of the 512-cavity sweep checked one by one: the smallest and largest cutoff and a
+    seeded random draw of the others."""
+    Ns = np.array([p["N"] for p in workloads.kerr_sweep(n=n)])
+    pick = [int(Ns.argmin()), int(Ns.argmax())]
+    g = np.random.Generator(np.random.PCG64(seed))
+    for i in g.permutation(n):
+        if len(pick) >= 2 + extra:
+            break
+        if int(i) not in pick:
+            pick.append(int(i))
+    return pick
+
+
+def kerr_sweep_samples(name):
+    sweep = workloads.kerr_sweep(n=512)
+    out = {"workload": "kerr_sweep", "n": 512, "abstol": 1e-8, "reltol": 1e-6, "source": "oracle.mesolve",
+           "instances": []}
+    for i in sweep_sample_indices():
+        p = sweep[i]
+        H, cs = om.kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
+        tl = workloads.tlist(p["t_end"], p["nt"])
+        t0 = time.time()
+        ex, st, rc, _ = oracle.mesolve(H, cs, om.fock_dm(p["N"], 0), tl, [om.number(p["N"])])
+        assert rc == 0
+        out["instances"].append(dict(p, index=i, oracle_stats=st, oracle_seconds=time.time() - t0,
+                                     expect_re=ex.real.tolist(), expect_im=ex.imag.tolist()))
+        print("sweep instance", i, "N", p["N"], st)
+    path = os.path.join(OUT, name + ".json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path)
+
+
+def ising_l10_short(name):
+    """The HBM-sized chain (L = 10: 1,048,576 Liouville rows) over a short window."""
+    L, h, gamma = 10, 1.0, 0.1
+    H, cs = om.ising(L, 1.0, h, gamma)
+    e_ops = [om.site_op(L, 0, om.sigmaz()), om.site_op(L, 4, om.sigmax())]
+    tl = np.linspace(0.0, 0.3, 4)
+    t0 = time.time()
+    ex, st, rc, _ = oracle.mesolve(H, cs, om.all_up_ket(L), tl, e_ops)
+    assert rc == 0
+    _write(name, {"workload": "ising", "L": L, "J": 1.0, "h": h, "gamma": gamma, "t_end": 0.3, "nt": 4,
+                  "e_ops": "sz_0,sx_4", "abstol": 1e-8, "reltol": 1e-6, "oracle_stats": st,
+                  "oracle_seconds": time.time() - t0, "source": "oracle.mesolve"}, ex)
+
+
 JOBS = {
+    "kerr_sweep_samples": lambda: kerr_sweep_samples("kerr_sweep_samples"),
+    "ising_l10_short": lambda: ising_l10_short("ising_l10_short"),
     "kerr_n20_u05": lambda: kerr_me(0.5, 1e-8, 1e-6, "kerr_n20_u05"),
     "ising_l8": lambda: ising_me(8, 0.7, 0.2, 10.0, 100, "sz_each", 1e-8, 1e-6, "ising_l8"),
     "ising_l8_tight": lambda: ising_me(8, 0.7, 0.2, 10.0, 100, "sz_each", 1e-12, 1e-10, "ising_l8_tight"),

@@ -251,6 +251,29 @@ def test_csr_every_tile_shape_vs_oracle(ctx):
         plan.set_shape(8, 8)
 
 
+def test_ising_l10_hbm_sized_every_shape_vs_golden(ctx):
+    """The HBM-sized Liouvillian the SpMV bandwidth is measured on (1,048,576 rows, 24.6 M nnz),
+    integrated over a short window with every tile shape, FP64 and mixed, against stored oracle
+    values."""
+    g, ref = _gold("ising_l10_short")
+    H, cs = _ising_lib(g)
+    e_ops = [om.site_op(10, 0, om.sigmaz()), om.site_op(10, 4, om.sigmax())]
+    tl = np.linspace(0.0, g["t_end"], g["nt"])
+    for prec, tol in [(qt.F64, 1e-6), (qt.MIXED, 1e-4)]:
+        Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
+        assert Lo.info()[1] == 24_641_535
+        plan = qt.MePlan(ctx, [(Lo, om.all_up_ket(10), tl, e_ops)], qt.opts(precision=prec))
+        for lpr, rg in SHAPES:
+            print(f"[gpu] L=10 shape lpr={lpr} rg={rg} prec={prec}", flush=True)
+            plan.set_shape(lpr, rg)
+            plan.run()
+            ex, st, _ = plan.result(0)
+            assert st["status"] == 0
+            assert np.abs(ex - ref).max() <= tol, (lpr, rg, prec, np.abs(ex - ref).max())
+        plan.close()
+        Lo.close()
+
+
 def test_plan_rerun_is_deterministic(ctx):
     H, cs = qt.model_ising(6, 1.0, 0.7, 0.2)
     L = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED)

@@ -1,0 +1,56 @@
+"""Parity of the parameter sweep at full size: 512 driven Kerr cavities (N from 10 to 80) in one
+plan, dense MFMA form, mixed precision, at the tolerances and with the autotuned launch shape the
+benchmark uses.  Sampled instances are checked one by one against stored FP64 oracle values
+(max |d<a^dag a>| <= 1e-4); every instance is checked for properties that hold at any size."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import models as om
+import workloads
+import paper_2504_21440_amd as qt
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+def test_sweep_512_full_size(ctx):
+    print("[gpu] 512-cavity sweep, dense mixed, full size", flush=True)
+    sweep = workloads.kerr_sweep(n=512)
+    probs = []
+    for p in sweep:
+        H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
+        probs.append((qt.Liouvillian(ctx, H, c, qt.FORM_DENSE, qt.MIXED), om.fock_dm(p["N"], 0),
+                      workloads.tlist(p["t_end"], p["nt"]), [om.number(p["N"])]))
+    plan = qt.MePlan(ctx, probs, qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED))
+    plan.autotune(reps=5)
+    plan.run()
+    res = [plan.result(i) for i in range(len(sweep))]
+    for (ex, st, _), p in zip(res, sweep):
+        assert st["status"] == 0
+        n = ex[0]
+        assert np.all(np.isfinite(n))
+        assert abs(n[0]) < 1e-12  # vacuum start
+        assert np.all(n.real >= -1e-4) and np.all(n.real <= p["N"] - 1 + 1e-4)
+        assert np.abs(n.imag).max() <= 1e-5
+    with open(os.path.join(GOLD, "kerr_sweep_samples.json")) as f:
+        gold = json.load(f)
+    worst = 0.0
+    for g in gold["instances"]:
+        i = g["index"]
+        assert sweep[i]["N"] == g["N"] and sweep[i]["U"] == g["U"]
+        ref = np.array(g["expect_re"]) + 1j * np.array(g["expect_im"])
+        err = float(np.abs(res[i][0] - ref).max())
+        print(f"[gpu]   instance {i} N={g['N']}: max|d<n>| = {err:.2e}", flush=True)
+        worst = max(worst, err)
+    assert worst <= 1e-4
+    plan.close()
