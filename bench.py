@@ -121,9 +121,31 @@ def section_ising(ctx, steps, warmup):
                      "n_reject": st["n_reject"], "n_rhs": n_rhs, "ms_per_solve": 1e3 * dt / steps,
                      "solves_per_s": steps / dt, "rhs_per_s": n_rhs * steps / dt,
                      "stage_kernel_ms": ms_stage, "spmv_bytes": b, "stage_kernel_GBs": b / (ms_stage * 1e-3) / 1e9,
-                     "nnz": nnz, "n": n, "csr_shape": list(shape[:2])}
+                     "nnz": nnz, "n": n, "csr_shape": list(shape[:3])}
         log(f"ising L=8 {name}: {out[name]}")
         plan.close()
+        Lo.close()
+    return out
+
+
+def section_ising_batch(ctx, rt, steps, warmup, n=16):
+    """n L=8 chains (h = 0.3 + 0.08 i) advanced together by one plan, mixed precision at the
+    accuracy-matched tolerance of the single chain: batched solves/s."""
+    probs, Ls = [], []
+    for p in workloads.ising_batch(n=n):
+        H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+        Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED)
+        Ls.append(Lo)
+        probs.append((Lo, up_ket(p["L"]), workloads.tlist(p["t_end"], p["nt"]), sz_ops(p["L"])))
+    plan = qt.MePlan(ctx, probs, qt.opts(abstol=rt / 100, reltol=rt, precision=qt.MIXED, autotune=True))
+    dt = time_plan(plan, steps, warmup)
+    sts = [plan.result(i)[1] for i in range(n)]
+    out = {"instances": n, "rtol": rt, "atol": rt / 100, "solves_per_s": n * steps / dt,
+           "ms_per_batch": 1e3 * dt / steps, "rhs_per_s": sum(s["n_rhs"] for s in sts) * steps / dt,
+           "max_steps": max(s["n_accept"] + s["n_reject"] for s in sts), "csr_shape": list(plan.shape()[:3])}
+    log(f"ising L=8 batch of {n}: {out}")
+    plan.close()
+    for Lo in Ls:
         Lo.close()
     return out
 
@@ -141,14 +163,15 @@ def section_hbm_spmv(ctx):
         n = d * d
         b = spmv_bytes(n, nnz, vb)
         by_shape = {}
-        for lpr, rg in CSR_SHAPES:
-            plan.set_shape(lpr, rg)
-            by_shape[f"{lpr}x{rg}"] = round(b / (plan.time_rhs(reps=20) * 1e-3) / 1e9, 1)
-        plan.set_shape(*shape[:2])
+        for xcd in (0, 1):
+            for lpr, rg in CSR_SHAPES:
+                plan.set_shape(lpr, rg, xcd)
+                by_shape[f"{lpr}x{rg}" + ("x" if xcd else "")] = round(b / (plan.time_rhs(reps=20) * 1e-3) / 1e9, 1)
+        plan.set_shape(*shape[:3])
         ms = plan.time_rhs(reps=50)
         gbs = b / (ms * 1e-3) / 1e9
         out[name] = {"n": n, "nnz": nnz, "bytes_per_launch": b, "ms_per_launch": ms, "GBs": gbs,
-                     "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "csr_shape": list(shape[:2]),
+                     "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "csr_shape": list(shape[:3]),
                      "GBs_by_shape": by_shape}
         log(f"HBM SpMV L=10 {name}: {out[name]}")
         plan.close()
@@ -156,14 +179,17 @@ def section_hbm_spmv(ctx):
     return out
 
 
-def section_sweep(ctx, n=512, check=12):
-    """512 driven Kerr cavities, N ~ U{10..80}, dense MFMA form, mixed precision, one launch set."""
+def section_sweep(ctx, n=512, nmax_dense=80):
+    """512 driven Kerr cavities, N ~ U{10..80}, mixed precision, one plan.  Cavities with
+    N <= nmax_dense use the dense MFMA form; larger ones (if any) the CSR form, whose launches
+    run concurrently with the dense buckets."""
     sweep = workloads.kerr_sweep(n=n)
     probs = []
     Ls = []
     for p in sweep:
         H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
-        Lo = qt.Liouvillian(ctx, H, c, qt.FORM_DENSE, qt.MIXED)
+        form = qt.FORM_DENSE if p["N"] <= nmax_dense else qt.FORM_CSR
+        Lo = qt.Liouvillian(ctx, H, c, form, qt.MIXED)
         Ls.append(Lo)
         rho0 = np.zeros((p["N"], p["N"]), complex)
         rho0[0, 0] = 1
@@ -172,7 +198,7 @@ def section_sweep(ctx, n=512, check=12):
     # untimed set-up: the autotuner picks the waves per tile row for each padded size
     o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED, autotune=True)
     plan = qt.MePlan(ctx, probs, o)
-    wpr = plan.shape()[2]
+    wpr = plan.shape()[3]
     plan.run()
     t0 = time.perf_counter()
     plan.run()
@@ -185,11 +211,16 @@ def section_sweep(ctx, n=512, check=12):
         res.append(ex)
         n_rhs += st["n_rhs"]
         flops += st["n_rhs"] * 24.0 * p["N"] ** 3
-    kern_ms = plan.time_rhs(reps=1)
     out = {"instances": n, "solves_per_s": n / dt, "ms_per_batch": dt * 1e3, "rhs_per_s": n_rhs / dt,
-           "dense_kernel_ms": kern_ms, "algorithmic_TFLOPs": flops / (kern_ms * 1e-3) / 1e12,
-           "frac_of_fp32_matrix_peak": flops / (kern_ms * 1e-3) / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
-           "rtol": o.reltol, "atol": o.abstol, "dense_waves_per_row_largest_bucket": wpr}
+           "rtol": o.reltol, "atol": o.abstol, "nmax_dense": nmax_dense,
+           "csr_instances": sum(1 for p in sweep if p["N"] > nmax_dense)}
+    if nmax_dense >= 80:
+        kern_ms = plan.time_rhs(reps=1)  # every dense bucket, one after another on one stream
+        out.update({"dense_kernel_ms": kern_ms, "algorithmic_TFLOPs": flops / (kern_ms * 1e-3) / 1e12,
+                    "frac_of_fp32_matrix_peak": flops / (kern_ms * 1e-3) / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
+                    "dense_waves_per_row_largest_bucket": wpr})
+    else:
+        out["csr_shape"] = list(plan.shape()[:3])
     plan.close()
     return out, sweep, res
 
@@ -370,7 +401,9 @@ def main():
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tune-in", default="", help="load an autotuner table before measuring")
+    ap.add_argument("--tune-in", default=os.path.join(ROOT, "paper_2504_21440_amd", "tuning", "mi355x.json"),
+                    help="autotuner table loaded before measuring (size buckets it lacks are tuned live); "
+                         "'' for none")
     ap.add_argument("--tune-out", default="", help="save the autotuner table after measuring")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
@@ -386,6 +419,8 @@ def main():
     ctx = qt.Context(0)
     ising = section_ising(ctx, args.steps, args.warmup)
     mixed = ising["mixed"]
+    log("ising batch")
+    batch = section_ising_batch(ctx, mixed["rtol"], max(1, args.steps // 2), 1)
     extra = {}
     only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving"}
     if args.skip_extra:
@@ -396,13 +431,15 @@ def main():
     if "sweep" in only:
         log("sweep")
         extra["kerr_sweep_512"], _, _ = section_sweep(ctx)
+        for nd in (32, 48):
+            extra[f"kerr_sweep_512_dense_to_N{nd}_csr_above"], _, _ = section_sweep(ctx, nmax_dense=nd)
     if "mc" in only:
         log("mc")
         extra["mcsolve_L10_10k"] = section_mc(ctx)
     if "serving" in only:
         log("serving")
         extra["serving"] = section_serving(ctx)
-    kname = "k_csr_stage<float,%d,%d,3>" % tuple(mixed["csr_shape"])
+    kname = "k_csr_stage<float,%d,%d,%s,3>" % (mixed["csr_shape"][0], mixed["csr_shape"][1], "true")
     rl = {"bound": "hbm", "achieved": mixed["stage_kernel_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": mixed["stage_kernel_GBs"] / HBM_PEAK_GBS, "traffic": profiled_traffic(kname),
           "kernel": kname + " (fused SpMV + stage epilogue), L=8 Liouvillian, one launch = one SpMV",
@@ -416,6 +453,8 @@ def main():
                    "rtol": mixed["rtol"], "atol": mixed["atol"], "parallelism": "single GPU"},
         "solves_per_s": mixed["solves_per_s"], "max_err_vs_fp64": mixed["max_err_vs_tight_fp64"],
         "fp64_single_solve": ising["fp64"], "mixed_detail": mixed,
+        "mixed_batched_16xL8": batch,
+        "batched_vs_fp64_single_solves_per_s": batch["solves_per_s"] / ising["fp64"]["solves_per_s"],
         "roofline": rl,
     }
     line.update(extra)

@@ -283,15 +283,16 @@ class MePlan:
         _check(lib().qt_me_plan_autotune(self.h, int(reps)))
         return self.shape()
 
-    def set_shape(self, lanes_per_row, rows_per_group):
-        """Impose a CSR tile shape (qt_me_plan_set_shape)."""
-        _check(lib().qt_me_plan_set_shape(self.h, int(lanes_per_row), int(rows_per_group)))
+    def set_shape(self, lanes_per_row, rows_per_group, xcd_order=0):
+        """Impose a CSR tile shape and block order (qt_me_plan_set_shape)."""
+        _check(lib().qt_me_plan_set_shape(self.h, int(lanes_per_row), int(rows_per_group), int(xcd_order)))
 
     def shape(self):
-        """(lanes per row, rows per lane group, dense waves per row) in use (qt_me_plan_shape)."""
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().qt_me_plan_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        """(lanes per row, rows per lane group, XCD block order, dense waves per row) in use
+        (qt_me_plan_shape)."""
+        a, b, x, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qt_me_plan_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(x), ctypes.byref(c)))
+        return a.value, b.value, x.value, c.value
 
     def close(self):
         if self.h:

@@ -15,15 +15,32 @@
 // once per evaluation and should not evict the state vectors from L2 / MALL), then the gathers and
 // complex FMAs; the group combines with xor shuffles, and lane g of the group runs the epilogue of
 // row g.  More rows per group put more bytes in flight per wave, which is what a latency-bound
-// SpMV needs; fewer keep small problems spread over more workgroups.  The shape is chosen per
-// problem size by the autotuner (qtamd_tune.cpp).
+// SpMV needs; fewer keep small problems spread over more workgroups.
+//
+// Block order (xcd): the hardware hands consecutive workgroups to the 8 XCDs in turn, and each XCD
+// has its own L2.  With xcd = 1 the logical block index is remapped so that each XCD works through
+// one contiguous eighth of the rows; the gathers of vec(rho) then concentrate on a slice of the
+// state that fits that XCD's L2 instead of every XCD pulling the whole vector through its own L2.
+// The remap changes which rows run where, never how a row or a block partial is summed, so results
+// are bitwise the same either way.
+//
+// Launch forms: with several problems a block reads its problem index and first row from a block
+// table and the problem's descriptor from device memory; with one problem (ONE) the descriptor is
+// a kernel argument and the first row is the block index times the rows per block, which removes
+// two dependent memory round trips from every block's critical path.
+//
+// The shape and block order are chosen per problem size by the autotuner (qtamd_tune.cpp).
+#include <cstring>
+
 #include "qt_common.h"
 #include "qt_csr.h"
+#include "qt_host.h"
 
 namespace qt {
 
 constexpr int CSR_THREADS = 256;
 constexpr int CTL_THREADS = 256;
+constexpr int CTL_MAX_EOPS = 64;  // operators whose sums the control kernel holds in LDS
 enum : int32_t { PH_STEP = 0, PH_INIT1 = 1, PH_INIT0 = 2 };
 
 template <int LPR, int RG> struct CsrGeom {
@@ -54,24 +71,42 @@ __device__ __forceinline__ double2 ld_stream(const double2 *p)
 }
 __device__ __forceinline__ int32_t ld_stream(const int32_t *p) { return __builtin_nontemporal_load(p); }
 
-// Row sums  sum_k val[k] * x(col[k])  for the RG rows r0 + g * stride (g < RG) of this lane's
-// group; every lane of the group returns all RG sums.  X returns the (stage) input at a column.
-template <typename V, int LPR, int RG, typename X>
-__device__ __forceinline__ void csr_rows(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                         const V *__restrict__ val, int r0, int stride, int n, int q, X x,
-                                         V (&acc)[RG])
+// Logical block index of this workgroup (see "Block order" above).
+__device__ __forceinline__ int csr_block(int xcd)
 {
-    constexpr int U = CsrGeom<LPR, RG>::U;
+    const int b = blockIdx.x;
+    if (!xcd) return b;
+    const int n = gridDim.x, q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+// Row bounds of the RG rows r0 + g * stride (g < RG) of this lane's group.
+template <int RG> struct RowBounds {
     int s[RG], e[RG];
+};
+template <int RG>
+__device__ __forceinline__ RowBounds<RG> csr_bounds(const int32_t *__restrict__ rowptr, int r0, int stride, int n)
+{
+    RowBounds<RG> b;
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
         const int r = r0 + g * stride;
-        if (r < n) {
-            s[g] = rowptr[r];
-            e[g] = rowptr[r + 1];
-        } else {
-            s[g] = e[g] = 0;
-        }
+        const bool ok = r < n;
+        b.s[g] = ok ? rowptr[r] : 0;
+        b.e[g] = ok ? rowptr[r + 1] : 0;
+    }
+    return b;
+}
+
+// Row sums  sum_k val[k] * x(col[k])  over the bounds from csr_bounds; every lane of the group
+// returns all RG sums.  X returns the (stage) input at a column.
+template <typename V, int LPR, int RG, typename X>
+__device__ __forceinline__ void csr_rows(const RowBounds<RG> &b, const int32_t *__restrict__ col,
+                                         const V *__restrict__ val, int q, X x, V (&acc)[RG])
+{
+    constexpr int U = CsrGeom<LPR, RG>::U;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
         acc[g].x = 0;
         acc[g].y = 0;
     }
@@ -83,8 +118,8 @@ __device__ __forceinline__ void csr_rows(const int32_t *__restrict__ rowptr, con
         for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int k = s[g] + base + u * LPR;
-                if (k < e[g]) {
+                const int k = b.s[g] + base + u * LPR;
+                if (k < b.e[g]) {
                     cc[g][u] = ld_stream(col + k);
                     vv[g][u] = ld_stream(val + k);
                     any = true;
@@ -115,42 +150,72 @@ template <typename V, int RG> __device__ __forceinline__ V pick(const V (&a)[RG]
     return r;
 }
 
-// Expectation values of the state Y (times `scale`) into expect[k][idx], FP64 accumulation:
-// Tr(O rho) = sum_{(i,j) in nnz(O)} O_ij rho_ji.
+// Tr(O_k Y) for operator k, accumulated in FP64 by one wave: Tr(O rho) = sum_{(i,j) in nnz(O)}
+// O_ij rho_ji, one gather per entry through evidx, reduced with shuffles in a fixed order.
 template <typename V>
-__device__ void csr_record_expect(const CsrInst &I, const V *__restrict__ Y, double scale, int idx, double *scr)
+__device__ __forceinline__ double2 csr_expect_one(const CsrInst &I, const V *__restrict__ Y, int k)
 {
-    const int d = I.d;
-    for (int k = 0; k < I.ne; ++k) {
-        const int32_t *ep = I.eptr + (size_t)k * (d + 1);
-        double sr = 0.0, si = 0.0;
-        for (int i = threadIdx.x; i < d; i += blockDim.x) {
-            for (int p = ep[i]; p < ep[i + 1]; ++p) {
-                const double2 o = I.eval[p];
-                const double2 r = to_d2(Y[(size_t)I.ecol[p] * d + i]);
-                sr += o.x * r.x - o.y * r.y;
-                si += o.x * r.y + o.y * r.x;
-            }
-        }
-        sr = block_sum(sr, scr);
-        si = block_sum(si, scr);
-        if (threadIdx.x == 0) I.expect[(size_t)k * I.nt + idx] = make_double2(sr * scale, si * scale);
+    const int lane = threadIdx.x & 63;
+    const int32_t *ep = I.eptr + (size_t)k * (I.d + 1);
+    const int b = ep[0], e = ep[I.d];
+    double sr = 0.0, si = 0.0;
+#pragma unroll 4
+    for (int p = b + lane; p < e; p += 64) {
+        const double2 o = I.eval[p];
+        const double2 r = to_d2(Y[I.evidx[p]]);
+        sr += o.x * r.x - o.y * r.y;
+        si += o.x * r.y + o.y * r.x;
     }
+    return make_double2(wave_sum(sr), wave_sum(si));
+}
+
+// Expectation values of the state Y (times `scale`) into expect[k][idx]: one wave per operator,
+// the waves of the block taking the operators in turn, so no block barrier sits between them.
+template <typename V>
+__device__ void csr_record_expect(const CsrInst &I, const V *__restrict__ Y, double scale, int idx)
+{
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int k = threadIdx.x >> 6; k < I.ne; k += nw) {
+        const double2 s = csr_expect_one(I, Y, k);
+        if (lane == 0) I.expect[(size_t)k * I.nt + idx] = make_double2(s.x * scale, s.y * scale);
+    }
+}
+
+// This thread's share of Tr(Y) (real part), to be block-summed.
+template <typename V> __device__ __forceinline__ double csr_trace_part(const CsrInst &I, const V *__restrict__ Y)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < I.d; i += blockDim.x) s += (double)Y[(size_t)i * I.d + i].x;
+    return s;
 }
 
 template <typename V> __device__ double csr_trace(const CsrInst &I, const V *__restrict__ Y, double *scr)
 {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < I.d; i += blockDim.x) s += (double)Y[(size_t)i * I.d + i].x;
-    return block_sum(s, scr);
+    return block_sum(csr_trace_part(I, Y), scr);
 }
 
-// Fixed-order sum of one partial column over the instance's blocks.
+// This thread's share of one partial column over the instance's blocks, in a fixed order: eight
+// loads in flight per thread, then the strided tail.
+__device__ __forceinline__ double partials_part(const CsrInst &I, int col)
+{
+    const int nb = I.nblocks, T = blockDim.x;
+    const double *__restrict__ P = I.partials + col;
+    double t = 0.0;
+    int k = threadIdx.x;
+    for (; k + 7 * T < nb; k += 8 * T) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = P[2 * (k + u * T)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t += a[u];
+    }
+    for (; k < nb; k += T) t += P[2 * k];
+    return t;
+}
+
 __device__ __forceinline__ double sum_partials(const CsrInst &I, int col, double *scr)
 {
-    double t = 0.0;
-    for (int k = threadIdx.x; k < I.nblocks; k += blockDim.x) t += I.partials[2 * k + col];
-    return block_sum(t, scr);
+    return block_sum(partials_part(I, col), scr);
 }
 
 __global__ void k_csr_reset(const CsrInst *__restrict__ insts, CsrCtl *__restrict__ ctls, int ninst)
@@ -193,25 +258,24 @@ template <int LPR, int RG> struct RowSlot {
     }
 };
 
+// ---------------------------------------------------------------------------------------------
+// Per-block bodies.  I: the problem's descriptor; C: its control record; row0: first row of the
+// block; part: the block's index among the problem's blocks (its slot in I.partials).
+// ---------------------------------------------------------------------------------------------
+
 // Starting step, first evaluation: k1 = L rho0, y <- rho0, partials of |y|^2/sc^2 and |f(y)|^2/sc^2.
 template <typename T, int LPR, int RG>
-__global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__restrict__ insts,
-                                                           const CsrCtl *__restrict__ ctls,
-                                                           const int32_t *__restrict__ blk_inst,
-                                                           const int32_t *__restrict__ blk_row0)
+__device__ __forceinline__ void init0_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
+    using G = CsrGeom<LPR, RG>;
     __shared__ double scr[16];
-    const int b = blockIdx.x;
-    const int ii = blk_inst[b];
-    const CsrInst &I = insts[ii];
-    const CsrCtl *C = ctls + ii;
+    const RowSlot<LPR, RG> rs(row0, I.n);
+    const RowBounds<RG> rb = csr_bounds<RG>(I.rowptr, rs.r0, G::GPB, I.n);
     if (C->status != ST_RUNNING || C->phase != PH_INIT0) return;
-    const RowSlot<LPR, RG> rs(blk_row0[b], I.n);
     const V *__restrict__ x0 = (const V *)I.rho0;
     V acc[RG];
-    csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
-                         [&](int c) { return x0[c]; }, acc);
+    csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q, [&](int c) { return x0[c]; }, acc);
     double sa = 0.0, sb = 0.0;
     if (rs.valid) {
         const V a = pick(acc, rs.q);
@@ -225,32 +289,27 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__rest
     sa = block_sum(sa, scr);
     sb = block_sum(sb, scr);
     if (threadIdx.x == 0) {
-        I.partials[2 * (b - I.block0)] = sa;
-        I.partials[2 * (b - I.block0) + 1] = sb;
+        I.partials[2 * part] = sa;
+        I.partials[2 * part + 1] = sb;
     }
 }
 
 // Starting step, second evaluation: partials of |f(y + h0 f(y)) - f(y)|^2 / (h0 sc)^2.
 template <typename T, int LPR, int RG>
-__global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__restrict__ insts,
-                                                           const CsrCtl *__restrict__ ctls,
-                                                           const int32_t *__restrict__ blk_inst,
-                                                           const int32_t *__restrict__ blk_row0)
+__device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
+    using G = CsrGeom<LPR, RG>;
     __shared__ double scr[16];
-    const int b = blockIdx.x;
-    const int ii = blk_inst[b];
-    const CsrInst &I = insts[ii];
-    const CsrCtl *C = ctls + ii;
+    const RowSlot<LPR, RG> rs(row0, I.n);
+    const RowBounds<RG> rb = csr_bounds<RG>(I.rowptr, rs.r0, G::GPB, I.n);
     if (C->status != ST_RUNNING || C->phase != PH_INIT1) return;
     const double h0 = C->h0;
     const T th0 = (T)h0;
-    const RowSlot<LPR, RG> rs(blk_row0[b], I.n);
     const V *__restrict__ y = (const V *)I.Y[0];
     const V *__restrict__ k1 = (const V *)I.K[0];
     V acc[RG];
-    csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
+    csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q,
                          [&](int c) {
                              V v = y[c];
                              caxpy(v, th0, k1[c]);
@@ -266,27 +325,23 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__rest
         sa = (dx * dx + dy * dy) / (sc * sc);
     }
     sa = block_sum(sa, scr);
-    if (threadIdx.x == 0) I.partials[2 * (b - I.block0)] = sa;
+    if (threadIdx.x == 0) I.partials[2 * part] = sa;
 }
 
-// One Runge-Kutta stage S (2..7) of a DP5 step for every running instance.
+// One Runge-Kutta stage S (2..7) of a DP5 step.
 template <typename T, int LPR, int RG, int S>
-__global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__restrict__ insts,
-                                                           const CsrCtl *__restrict__ ctls,
-                                                           const int32_t *__restrict__ blk_inst,
-                                                           const int32_t *__restrict__ blk_row0)
+__device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
+    using G = CsrGeom<LPR, RG>;
     __shared__ double scr[16];
-    const int b = blockIdx.x;
-    const int ii = blk_inst[b];
-    const CsrInst &I = insts[ii];
-    const CsrCtl *C = ctls + ii;
+    const RowSlot<LPR, RG> rs(row0, I.n);
+    // the row bounds do not depend on the control record: issue them before waiting on it
+    const RowBounds<RG> rb = csr_bounds<RG>(I.rowptr, rs.r0, G::GPB, I.n);
     if (C->status != ST_RUNNING || C->phase != PH_STEP) return;
     const double h = C->h_try;
     const int p = C->parity;
     const T s = (T)C->scale;
-    const RowSlot<LPR, RG> rs(blk_row0[b], I.n);
     const V *__restrict__ y = (const V *)I.Y[p];
     const V *__restrict__ k1 = (const V *)I.K[p];
     V *__restrict__ ynew = (V *)I.Y[1 - p];
@@ -316,7 +371,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
     V acc[RG];
     if (S == 2) {
         const T c = (T)(h * DP5::a21);
-        csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
+        csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q,
                              [&](int cc) {
                                  V v = y[cc];
                                  caxpy(v, c, k1[cc]);
@@ -324,8 +379,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
                              },
                              acc);
     } else {
-        csr_rows<V, LPR, RG>(I.rowptr, I.col, (const V *)I.val, rs.r0, CsrGeom<LPR, RG>::GPB, I.n, rs.q,
-                             [&](int cc) { return xin[cc]; }, acc);
+        csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return xin[cc]; }, acc);
     }
 
     double e2 = 0.0;
@@ -388,22 +442,62 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
     }
     if (S == 7) {
         e2 = block_sum(e2, scr);
-        if (threadIdx.x == 0) I.partials[2 * (b - I.block0)] = e2;
+        if (threadIdx.x == 0) I.partials[2 * part] = e2;
     }
 }
+
+// ---------------------------------------------------------------------------------------------
+// Kernels: ONE = single problem with its descriptor `one` passed by value; otherwise the block
+// table (bi: problem, br: first row) of the logical block selects the problem.
+// ---------------------------------------------------------------------------------------------
+// Logical block -> (descriptor, control record, first row, partial slot), then the body.
+#define QT_CSR_DISPATCH_BODY(BODY)                                          \
+    const int lb = csr_block(xcd);                                          \
+    if constexpr (ONE) {                                                    \
+        BODY(one, ctls, lb * CsrGeom<LPR, RG>::RPB, lb);                    \
+    } else {                                                                \
+        const int ii = bi[lb];                                              \
+        const CsrInst &I = insts[ii];                                       \
+        BODY(I, ctls + ii, br[lb], lb - I.block0);                          \
+    }
+
+template <typename T, int LPR, int RG, bool ONE>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__restrict__ insts, const CsrInst one,
+                                                           const CsrCtl *__restrict__ ctls,
+                                                           const int32_t *__restrict__ bi,
+                                                           const int32_t *__restrict__ br, int xcd)
+{
+    QT_CSR_DISPATCH_BODY((init0_body<T, LPR, RG>))
+}
+
+template <typename T, int LPR, int RG, bool ONE>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__restrict__ insts, const CsrInst one,
+                                                           const CsrCtl *__restrict__ ctls,
+                                                           const int32_t *__restrict__ bi,
+                                                           const int32_t *__restrict__ br, int xcd)
+{
+    QT_CSR_DISPATCH_BODY((init1_body<T, LPR, RG>))
+}
+
+template <typename T, int LPR, int RG, bool ONE, int S>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__restrict__ insts, const CsrInst one,
+                                                           const CsrCtl *__restrict__ ctls,
+                                                           const int32_t *__restrict__ bi,
+                                                           const int32_t *__restrict__ br, int xcd)
+{
+    QT_CSR_DISPATCH_BODY((stage_body<T, LPR, RG, S>))
+}
+#undef QT_CSR_DISPATCH_BODY
 
 // Control: one workgroup per problem.  step_mode 0 completes a pending starting-step evaluation
 // (phases INIT0 / INIT1) and leaves stepping problems alone; step_mode 1 closes a Runge-Kutta step
 // (phase STEP) and leaves problems still in their starting phases alone.
 template <typename T>
-__global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__restrict__ insts,
-                                                             CsrCtl *__restrict__ ctls, int step_mode)
+__device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int step_mode)
 {
     using V = typename vec2<T>::type;
     __shared__ double scr[16];
-    const int ii = blockIdx.x;
-    const CsrInst &I = insts[ii];
-    CsrCtl *C = ctls + ii;
+    __shared__ double2 exs[CTL_MAX_EOPS];
     if (C->status != ST_RUNNING) return;
     const int phase = C->phase;
     if ((phase == PH_STEP) != (step_mode != 0)) return;
@@ -411,7 +505,7 @@ __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__re
         const double ta = sum_partials(I, 0, scr), tb = sum_partials(I, 1, scr);
         const V *x0 = (const V *)I.rho0;
         const double tr = csr_trace(I, x0, scr);
-        csr_record_expect(I, x0, 1.0, 0, scr);
+        csr_record_expect(I, x0, 1.0, 0);
         if (threadIdx.x == 0) {
             C->tr0 = tr;
             C->n_rhs += 1;
@@ -451,19 +545,38 @@ __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__re
         return;
     }
     // ---- step control after stage 7 ----
-    const double tot = sum_partials(I, 0, scr);
-    const double err = sqrt(tot / I.n);
-    const bool finite = isfinite(err);
-    const bool accept = finite && err <= 1.0;
     const double h = C->h_try;
     const int p = C->parity;
     const int land = C->land;
     const int sidx = C->save_idx;
     const V *ynew = (const V *)I.Y[1 - p];
+    // Everything that only reads is issued before the decision: the error partials, the
+    // candidate's trace and, at a save time, the expectation sums (wasted on a rejection).
+    const bool spec = land && I.ne <= CTL_MAX_EOPS;
+    if (spec) {
+        for (int k = threadIdx.x >> 6; k < I.ne; k += blockDim.x >> 6) {
+            const double2 sk = csr_expect_one(I, ynew, k);
+            if ((threadIdx.x & 63) == 0) exs[k] = sk;
+        }
+    }
+    const double part = partials_part(I, 0);
+    const double trp = I.renorm ? csr_trace_part(I, ynew) : 0.0;
+    const double tot = block_sum(part, scr);  // its barriers also publish exs
+    const double err = sqrt(tot / I.n);
+    const bool finite = isfinite(err);
+    const bool accept = finite && err <= 1.0;
     double scale_new = 1.0;
-    if (accept) {
-        if (I.renorm) scale_new = C->tr0 / csr_trace(I, ynew, scr);
-        if (land) csr_record_expect(I, ynew, scale_new, sidx, scr);
+    if (I.renorm) {
+        const double tr = block_sum(trp, scr);
+        if (accept) scale_new = C->tr0 / tr;
+    }
+    if (accept && land) {
+        if (spec) {
+            for (int k = threadIdx.x; k < I.ne; k += blockDim.x)
+                I.expect[(size_t)k * I.nt + sidx] = make_double2(exs[k].x * scale_new, exs[k].y * scale_new);
+        } else {
+            csr_record_expect(I, ynew, scale_new, sidx);
+        }
     }
     if (threadIdx.x == 0) {
         C->n_steps += 1;
@@ -502,6 +615,14 @@ __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__re
             }
         }
     }
+}
+
+template <typename T, bool ONE>
+__global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__restrict__ insts, const CsrInst one,
+                                                             CsrCtl *__restrict__ ctls, int step_mode)
+{
+    if constexpr (ONE) control_body<T>(one, ctls, step_mode);
+    else control_body<T>(insts[blockIdx.x], ctls + blockIdx.x, step_mode);
 }
 
 // ---- standalone expectation value (qt_expect) ----
@@ -565,35 +686,89 @@ bool csr_shape_supported(int lpr, int rg)
     default: CALL(8, 1); break;            \
     }
 
+// Launch arguments shared by every CSR launch of a step.
+struct CsrArgs {
+    const CsrInst *insts;
+    CsrInst one;  // used when ninst == 1 and the host descriptor was given
+    bool use_one;
+    CsrCtl *ctls;
+    const int32_t *bi, *br;
+    int nblk, ninst, xcd;
+    hipStream_t s;
+};
+
+static CsrArgs make_args(const CsrLaunch &L, hipStream_t s)
+{
+    CsrArgs a;
+    a.insts = L.insts;
+    a.use_one = L.ninst == 1 && L.one_host != nullptr;
+    if (a.use_one) a.one = *L.one_host;
+    else std::memset(&a.one, 0, sizeof(a.one));
+    a.ctls = L.ctls;
+    a.bi = L.bi;
+    a.br = L.br;
+    a.nblk = L.nblk;
+    a.ninst = L.ninst;
+    a.xcd = L.xcd;
+    a.s = s;
+    return a;
+}
+
 template <typename T>
-static void launch_control(int ninst, const CsrInst *insts, CsrCtl *ctls, int step_mode, hipStream_t s)
+static void launch_control(const CsrArgs &a, int step_mode)
 {
-    hipLaunchKernelGGL(k_csr_control<T>, dim3(ninst), dim3(CTL_THREADS), 0, s, insts, ctls, step_mode);
-}
-
-template <typename T, int LPR, int RG>
-static void launch_init_t(int which, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                          const int32_t *br, hipStream_t s)
-{
-    if (which == 0)
-        hipLaunchKernelGGL((k_csr_init0<T, LPR, RG>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
+    if (a.use_one)
+        hipLaunchKernelGGL((k_csr_control<T, true>), dim3(1), dim3(CTL_THREADS), 0, a.s, a.insts, a.one, a.ctls,
+                           step_mode);
     else
-        hipLaunchKernelGGL((k_csr_init1<T, LPR, RG>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
-    launch_control<T>(ninst, insts, ctls, 0, s);
+        hipLaunchKernelGGL((k_csr_control<T, false>), dim3(a.ninst), dim3(CTL_THREADS), 0, a.s, a.insts, a.one,
+                           a.ctls, step_mode);
+}
+
+#define QT_LAUNCH(KERNEL, a)                                                                                  \
+    do {                                                                                                      \
+        if ((a).use_one)                                                                                      \
+            hipLaunchKernelGGL((KERNEL<T, LPR, RG, true>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,      \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+        else                                                                                                  \
+            hipLaunchKernelGGL((KERNEL<T, LPR, RG, false>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,     \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+    } while (0)
+
+#define QT_LAUNCH_STAGE(SV, a)                                                                                \
+    do {                                                                                                      \
+        if ((a).use_one)                                                                                      \
+            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, true, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,    \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, false, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,   \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+    } while (0)
+
+template <typename T, int LPR, int RG>
+static void launch_init_t(int which, const CsrArgs &a)
+{
+    if (which == 0) QT_LAUNCH(k_csr_init0, a);
+    else QT_LAUNCH(k_csr_init1, a);
+    launch_control<T>(a, 0);
 }
 
 template <typename T, int LPR, int RG>
-static void launch_step_t(int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                          const int32_t *br, hipStream_t s)
+static void launch_step_t(const CsrArgs &a)
 {
-    dim3 g(nblk), t(CSR_THREADS);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 2>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 3>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 4>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 5>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 6>), g, t, 0, s, insts, ctls, bi, br);
-    hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 7>), g, t, 0, s, insts, ctls, bi, br);
-    launch_control<T>(ninst, insts, ctls, 1, s);
+    QT_LAUNCH_STAGE(2, a);
+    QT_LAUNCH_STAGE(3, a);
+    QT_LAUNCH_STAGE(4, a);
+    QT_LAUNCH_STAGE(5, a);
+    QT_LAUNCH_STAGE(6, a);
+    QT_LAUNCH_STAGE(7, a);
+    launch_control<T>(a, 1);
+}
+
+template <typename T, int LPR, int RG>
+static void launch_stage3_t(const CsrArgs &a)
+{
+    QT_LAUNCH_STAGE(3, a);
 }
 
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s)
@@ -601,37 +776,38 @@ void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t
     hipLaunchKernelGGL(k_csr_reset, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ctls, ninst);
 }
 
-void csr_launch_init(int which, bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
-                     const int32_t *bi, const int32_t *br, hipStream_t s)
+void csr_launch_init(int which, const CsrLaunch &L, hipStream_t s)
 {
-#define QT_CALL(L, R)                                                                \
-    if (f64) launch_init_t<double, L, R>(which, nblk, ninst, insts, ctls, bi, br, s); \
-    else launch_init_t<float, L, R>(which, nblk, ninst, insts, ctls, bi, br, s);
-    QT_SHAPE_DISPATCH(lpr, rg, QT_CALL)
+    const CsrArgs a = make_args(L, s);
+#define QT_CALL(LP, RR)                                  \
+    if (L.f64) launch_init_t<double, LP, RR>(which, a); \
+    else launch_init_t<float, LP, RR>(which, a);
+    QT_SHAPE_DISPATCH(L.lpr, L.rg, QT_CALL)
 #undef QT_CALL
 }
 
-void csr_launch_step(bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
-                     const int32_t *bi, const int32_t *br, hipStream_t s)
+void csr_launch_step(const CsrLaunch &L, hipStream_t s)
 {
-#define QT_CALL(L, R)                                                          \
-    if (f64) launch_step_t<double, L, R>(nblk, ninst, insts, ctls, bi, br, s); \
-    else launch_step_t<float, L, R>(nblk, ninst, insts, ctls, bi, br, s);
-    QT_SHAPE_DISPATCH(lpr, rg, QT_CALL)
+    const CsrArgs a = make_args(L, s);
+#define QT_CALL(LP, RR)                           \
+    if (L.f64) launch_step_t<double, LP, RR>(a); \
+    else launch_step_t<float, LP, RR>(a);
+    QT_SHAPE_DISPATCH(L.lpr, L.rg, QT_CALL)
 #undef QT_CALL
 }
 
-void csr_launch_stage3(bool f64, int lpr, int rg, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                       const int32_t *br, hipStream_t s)
+void csr_launch_stage3(const CsrLaunch &L, hipStream_t s)
 {
-#define QT_CALL(L, R)                                                                                             \
-    if (f64)                                                                                                      \
-        hipLaunchKernelGGL((k_csr_stage<double, L, R, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br); \
-    else                                                                                                          \
-        hipLaunchKernelGGL((k_csr_stage<float, L, R, 3>), dim3(nblk), dim3(CSR_THREADS), 0, s, insts, ctls, bi, br);
-    QT_SHAPE_DISPATCH(lpr, rg, QT_CALL)
+    const CsrArgs a = make_args(L, s);
+#define QT_CALL(LP, RR)                             \
+    if (L.f64) launch_stage3_t<double, LP, RR>(a); \
+    else launch_stage3_t<float, LP, RR>(a);
+    QT_SHAPE_DISPATCH(L.lpr, L.rg, QT_CALL)
 #undef QT_CALL
 }
+
+#undef QT_LAUNCH
+#undef QT_LAUNCH_STAGE
 
 void launch_expect(bool f64, int d, const int32_t *rp, const int32_t *ci, const double2 *v, const void *state,
                    int is_ket, double2 *out, hipStream_t s)

@@ -40,6 +40,7 @@ struct CsrInst {
     const int32_t *eptr;  // ne * (d+1) row pointers into ecol/eval (instance-local offsets)
     const int32_t *ecol;
     const double2 *eval;
+    const int32_t *evidx; // per e_op entry (i, j): index j*d + i of rho_ji in vec(rho)
     double2 *expect;      // [ne][nt]
     double *partials;     // 2 * nblocks doubles
 };

@@ -36,6 +36,10 @@ HCsr csr_adjoint(const HCsr &A);
 HCsr csr_matmul(const HCsr &A, const HCsr &B);
 HCsr csr_axpby(cd a, const HCsr &A, cd b, const HCsr &B);
 HCsr csr_zero(int32_t d);
+// For concatenated e_op CSR rows (ne blocks of d+1 row pointers into col): the vec(rho) index
+// j*d + i of rho_ji paired with each entry O_ij, so Tr(O rho) is one gather per entry.
+std::vector<int32_t> expect_vec_index(const std::vector<int32_t> &eptr, const std::vector<int32_t> &ecol, int32_t d,
+                                      int32_t ne);
 
 // A device arena: one hipMalloc carved into 256-byte aligned pieces.
 struct Arena {
@@ -85,13 +89,20 @@ struct CsrInst;
 struct CsrCtl;
 int csr_rows_per_block(int lpr, int rg);
 bool csr_shape_supported(int lpr, int rg);
+// One launch configuration of the CSR step kernels.
+struct CsrLaunch {
+    bool f64 = false;
+    int lpr = 8, rg = 1, xcd = 0;  // tile shape and block order
+    int nblk = 0, ninst = 0;       // workgroups, problems
+    const CsrInst *insts = nullptr;
+    CsrCtl *ctls = nullptr;
+    const int32_t *bi = nullptr, *br = nullptr;  // block table: problem, first row
+    const CsrInst *one_host = nullptr;           // host copy of the descriptor when ninst == 1
+};
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s);
-void csr_launch_init(int which, bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
-                     const int32_t *bi, const int32_t *br, hipStream_t s);
-void csr_launch_step(bool f64, int lpr, int rg, int nblk, int ninst, const CsrInst *insts, CsrCtl *ctls,
-                     const int32_t *bi, const int32_t *br, hipStream_t s);
-void csr_launch_stage3(bool f64, int lpr, int rg, int nblk, const CsrInst *insts, CsrCtl *ctls, const int32_t *bi,
-                       const int32_t *br, hipStream_t s);
+void csr_launch_init(int which, const CsrLaunch &L, hipStream_t s);
+void csr_launch_step(const CsrLaunch &L, hipStream_t s);
+void csr_launch_stage3(const CsrLaunch &L, hipStream_t s);
 constexpr int CSR_MIN_ROWS_PER_BLOCK = 16;  // smallest tile (16 lanes per row, one row per group)
 void launch_expect(bool f64, int d, const int32_t *rp, const int32_t *ci, const double2 *v, const void *state,
                    int is_ket, double2 *out, hipStream_t s);

@@ -12,6 +12,7 @@ namespace qt {
 struct CsrShape {
     int lpr = 8;  // lanes per row group
     int rg = 1;   // rows per lane group
+    int xcd = 0;  // 1: XCD-contiguous block order
 };
 
 // size bucket of a CSR right-hand side: log2 of the rows, rounded mean row length
@@ -27,7 +28,9 @@ void tune_store_dense(const std::string &key, int wpr);
 CsrShape csr_default_shape(int64_t rows, double mean_row);
 int dense_default_wpr(int np, int32_t prec);
 
-// candidate CSR shapes the autotuner measures
-int csr_candidates(CsrShape *out, int max);
+// Candidate CSR shapes the autotuner measures.  xcd_order: include the XCD-contiguous block
+// order.  Only single-problem plans use it: with several problems of unequal step counts, an XCD
+// whose problems have finished would sit idle while the others still work through theirs.
+int csr_candidates(CsrShape *out, int max, bool xcd_order);
 
 }  // namespace qt

@@ -24,12 +24,12 @@ struct MeProb {
     int32_t d = 0, nt = 0, ne = 0;
     bool dense = false;
     int32_t slot = -1;  // index inside its group
-    size_t o_rho0 = 0, o_tlist = 0, o_eptr = 0, o_ecol = 0, o_eval = 0, o_expect = 0;
+    size_t o_rho0 = 0, o_tlist = 0, o_eptr = 0, o_ecol = 0, o_eval = 0, o_evidx = 0, o_expect = 0;
     size_t o_vec = 0;  // state vectors
     size_t o_part = 0;
     std::vector<char> rho0;  // host copy in state precision
     std::vector<double> tlist;
-    std::vector<int32_t> eptr, ecol;
+    std::vector<int32_t> eptr, ecol, evidx;
     std::vector<double2> eval;
 };
 
@@ -137,6 +137,7 @@ static qt_status prep_problem(const qt_me_problem &p, int32_t prec, MeProb *m)
             m->eval.push_back(make_double2(o.val[q].real(), o.val[q].imag()));
         }
     }
+    m->evidx = expect_vec_index(m->eptr, m->ecol, d, p.n_e);
     return QT_OK;
 }
 
@@ -220,6 +221,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         m.o_eptr = A.reserve(std::max<size_t>(1, m.eptr.size()) * 4);
         m.o_ecol = A.reserve(std::max<size_t>(1, m.ecol.size()) * 4);
         m.o_eval = A.reserve(std::max<size_t>(1, m.eval.size()) * 16);
+        m.o_evidx = A.reserve(std::max<size_t>(1, m.evidx.size()) * 4);
         m.o_expect = A.reserve(std::max<size_t>(1, (size_t)m.ne * m.nt) * 16);
         if (!m.dense) {
             const int64_t nb = ((int64_t)nvec + CSR_MIN_ROWS_PER_BLOCK - 1) / CSR_MIN_ROWS_PER_BLOCK;
@@ -257,6 +259,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         if ((st = upload(A.at(m.o_eptr), m.eptr.data(), m.eptr.size() * 4, s))) break;
         if ((st = upload(A.at(m.o_ecol), m.ecol.data(), m.ecol.size() * 4, s))) break;
         if ((st = upload(A.at(m.o_eval), m.eval.data(), m.eval.size() * 16, s))) break;
+        if ((st = upload(A.at(m.o_evidx), m.evidx.data(), m.evidx.size() * 4, s))) break;
         const size_t nvec = (size_t)m.d * m.d;
         if (!m.dense) {
             CsrInst &c = P->h_ci[m.slot];
@@ -287,6 +290,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             c.eptr = (const int32_t *)A.at(m.o_eptr);
             c.ecol = (const int32_t *)A.at(m.o_ecol);
             c.eval = (const double2 *)A.at(m.o_eval);
+            c.evidx = (const int32_t *)A.at(m.o_evidx);
             c.expect = (double2 *)A.at(m.o_expect);
             c.partials = (double *)A.at(m.o_part);
         } else {
@@ -302,6 +306,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         P->tune_key = csr_tune_key(P->prec, rows_tot, mean_row);
         CsrShape sh;
         if (!tune_lookup_csr(P->tune_key, &sh)) sh = csr_default_shape(rows_tot, mean_row);
+        if (P->ncsr > 1) sh.xcd = 0;  // see csr_candidates: several problems keep the round-robin order
         st = apply_shape(P, sh);
         if (!st) {
             hipError_t e = hipHostMalloc((void **)&P->h_cctl, sizeof(CsrCtl) * P->ncsr, hipHostMallocDefault);
@@ -354,18 +359,31 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
     return QT_OK;
 }
 
+// Launch configuration of the plan's CSR group at its current shape.
+static CsrLaunch csr_args(const qt_me_plan *P)
+{
+    CsrLaunch L;
+    L.f64 = P->prec == QT_F64;
+    L.lpr = P->shape.lpr;
+    L.rg = P->shape.rg;
+    L.xcd = P->shape.xcd;
+    L.nblk = P->nblk;
+    L.ninst = P->ncsr;
+    L.insts = (const CsrInst *)P->arena.at(P->o_cinst);
+    L.ctls = (CsrCtl *)P->arena.at(P->o_cctl);
+    L.bi = (const int32_t *)P->arena.at(P->o_bi);
+    L.br = (const int32_t *)P->arena.at(P->o_br);
+    L.one_host = P->ncsr == 1 ? &P->h_ci[0] : nullptr;
+    return L;
+}
+
 static qt_status capture_graph(qt_me_plan *P)
 {
     if (P->gexec) return QT_OK;
     hipStream_t s = P->ctx->stream;
-    const bool f64 = P->prec == QT_F64;
-    auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
-    auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
-    auto *bi = (const int32_t *)P->arena.at(P->o_bi);
-    auto *br = (const int32_t *)P->arena.at(P->o_br);
+    const CsrLaunch L = csr_args(P);
     QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < P->graph_steps; ++k)
-        csr_launch_step(f64, P->shape.lpr, P->shape.rg, P->nblk, P->ncsr, ci, cc, bi, br, s);
+    for (int k = 0; k < P->graph_steps; ++k) csr_launch_step(L, s);
     hipError_t e = hipStreamEndCapture(s, &P->graph);
     if (e) return set_error(QT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     QT_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
@@ -402,13 +420,11 @@ qt_status me_plan_run(qt_me_plan *P)
     }
     qt_status st = QT_OK;
     if (P->ncsr) {
-        auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
-        auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
-        auto *bi = (const int32_t *)P->arena.at(P->o_bi);
-        auto *br = (const int32_t *)P->arena.at(P->o_br);
-        csr_launch_reset(ci, cc, P->ncsr, s);
-        csr_launch_init(0, f64, P->shape.lpr, P->shape.rg, P->nblk, P->ncsr, ci, cc, bi, br, s);
-        csr_launch_init(1, f64, P->shape.lpr, P->shape.rg, P->nblk, P->ncsr, ci, cc, bi, br, s);
+        const CsrLaunch L = csr_args(P);
+        auto *cc = L.ctls;
+        csr_launch_reset(L.insts, L.ctls, P->ncsr, s);
+        csr_launch_init(0, L, s);
+        csr_launch_init(1, L, s);
         QT_HIP(hipGetLastError());
         if ((st = capture_graph(P))) return st;
         int replays = 1;
@@ -451,21 +467,16 @@ qt_status me_plan_run(qt_me_plan *P)
 static qt_status time_stage(qt_me_plan *P, int32_t reps, double *ms)
 {
     hipStream_t s = P->ctx->stream;
-    const bool f64 = P->prec == QT_F64;
-    auto *ci = (const CsrInst *)P->arena.at(P->o_cinst);
-    auto *cc = (CsrCtl *)P->arena.at(P->o_cctl);
-    auto *bi = (const int32_t *)P->arena.at(P->o_bi);
-    auto *br = (const int32_t *)P->arena.at(P->o_br);
-    const int l = P->shape.lpr, r = P->shape.rg;
+    const CsrLaunch L = csr_args(P);
     hipEvent_t e0, e1;
     QT_HIP(hipEventCreate(&e0));
     QT_HIP(hipEventCreate(&e1));
-    csr_launch_reset(ci, cc, P->ncsr, s);
-    csr_launch_init(0, f64, l, r, P->nblk, P->ncsr, ci, cc, bi, br, s);
-    csr_launch_init(1, f64, l, r, P->nblk, P->ncsr, ci, cc, bi, br, s);
-    csr_launch_stage3(f64, l, r, P->nblk, ci, cc, bi, br, s);  // warm
+    csr_launch_reset(L.insts, L.ctls, P->ncsr, s);
+    csr_launch_init(0, L, s);
+    csr_launch_init(1, L, s);
+    csr_launch_stage3(L, s);  // warm
     QT_HIP(hipEventRecord(e0, s));
-    for (int32_t k = 0; k < reps; ++k) csr_launch_stage3(f64, l, r, P->nblk, ci, cc, bi, br, s);
+    for (int32_t k = 0; k < reps; ++k) csr_launch_stage3(L, s);
     QT_HIP(hipEventRecord(e1, s));
     QT_HIP(hipGetLastError());
     QT_HIP(hipEventSynchronize(e1));
@@ -484,8 +495,8 @@ qt_status me_plan_autotune(qt_me_plan *P, int32_t reps)
     QT_HIP(hipSetDevice(P->ctx->device));
     if (reps <= 0) reps = 20;
     if (P->ncsr) {
-        CsrShape cand[16];
-        const int nc = csr_candidates(cand, 16);
+        CsrShape cand[32];
+        const int nc = csr_candidates(cand, 32, P->ncsr == 1);
         CsrShape best = P->shape;
         double best_ms = 1e300;
         for (int k = 0; k < nc; ++k) {
@@ -628,22 +639,23 @@ qt_status qt_me_plan_autotune(qt_me_plan *plan, int32_t reps)
     return me_plan_autotune(plan, reps);
 }
 
-qt_status qt_me_plan_set_shape(qt_me_plan *plan, int32_t lanes_per_row, int32_t rows_per_group)
+qt_status qt_me_plan_set_shape(qt_me_plan *plan, int32_t lanes_per_row, int32_t rows_per_group, int32_t xcd_order)
 {
     if (!plan) return set_error(QT_EINVAL, "null plan");
     if (!csr_shape_supported(lanes_per_row, rows_per_group))
         return set_error(QT_EINVAL, "unsupported CSR tile shape");
     if (!plan->ncsr) return QT_OK;
     QT_HIP(hipSetDevice(plan->ctx->device));
-    return apply_shape(plan, CsrShape{lanes_per_row, rows_per_group});
+    return apply_shape(plan, CsrShape{lanes_per_row, rows_per_group, xcd_order ? 1 : 0});
 }
 
 qt_status qt_me_plan_shape(const qt_me_plan *plan, int32_t *lanes_per_row, int32_t *rows_per_group,
-                           int32_t *dense_waves_per_row)
+                           int32_t *xcd_order, int32_t *dense_waves_per_row)
 {
     if (!plan) return set_error(QT_EINVAL, "null plan");
     if (lanes_per_row) *lanes_per_row = plan->ncsr ? plan->shape.lpr : 0;
     if (rows_per_group) *rows_per_group = plan->ncsr ? plan->shape.rg : 0;
+    if (xcd_order) *xcd_order = plan->ncsr ? plan->shape.xcd : 0;
     if (dense_waves_per_row)
         *dense_waves_per_row = plan->buckets.empty() ? 0 : dense_choose_config(plan->buckets[0].np, plan->prec);
     return QT_OK;

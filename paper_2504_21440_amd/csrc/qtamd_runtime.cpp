@@ -78,6 +78,17 @@ qt_status csr_from_abi(const qt_csr *A, int32_t d_expect, HCsr *out, const char 
     return QT_OK;
 }
 
+std::vector<int32_t> expect_vec_index(const std::vector<int32_t> &eptr, const std::vector<int32_t> &ecol, int32_t d,
+                                      int32_t ne)
+{
+    std::vector<int32_t> v(ecol.size());
+    for (int32_t k = 0; k < ne; ++k)
+        for (int32_t i = 0; i < d; ++i)
+            for (int32_t q = eptr[(size_t)k * (d + 1) + i]; q < eptr[(size_t)k * (d + 1) + i + 1]; ++q)
+                v[q] = ecol[q] * d + i;
+    return v;
+}
+
 HCsr csr_zero(int32_t d)
 {
     HCsr z;

@@ -117,7 +117,7 @@ namespace qt {
 static size_t es_of(int32_t prec) { return prec == QT_F64 ? 16 : 8; }
 
 struct Layout {
-    size_t o_rho0, o_tlist, o_eptr, o_ecol, o_eval, o_expect, o_vec, o_part, total;
+    size_t o_rho0, o_tlist, o_eptr, o_ecol, o_eval, o_evidx, o_expect, o_vec, o_part, total;
 };
 
 static Layout layout_of(const qt_me_problem &p, int32_t prec, qt::CsrShape sh, size_t eptr_n, size_t ecol_n, int32_t *nblocks)
@@ -137,6 +137,7 @@ static Layout layout_of(const qt_me_problem &p, int32_t prec, qt::CsrShape sh, s
     L.o_eptr = take(eptr_n * 4);
     L.o_ecol = take(ecol_n * 4);
     L.o_eval = take(ecol_n * 16);
+    L.o_evidx = take(ecol_n * 4);
     L.o_expect = take((size_t)p.n_e * p.n_t * 16);
     if (dense) {
         const size_t np = (size_t)dense_np(d);
@@ -226,6 +227,8 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
     up(Ly.o_eptr, eptr.data(), eptr.size() * 4);
     up(Ly.o_ecol, ecol.data(), ecol.size() * 4);
     up(Ly.o_eval, eval.data(), eval.size() * 16);
+    const std::vector<int32_t> evidx = expect_vec_index(eptr, ecol, d, p->n_e);
+    up(Ly.o_evidx, evidx.data(), evidx.size() * 4);
     qt_opts o = S->cfg.opts;
     if (dense) {
         DenseInst g;
@@ -270,6 +273,7 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
         c.eptr = (const int32_t *)(base + Ly.o_eptr);
         c.ecol = (const int32_t *)(base + Ly.o_ecol);
         c.eval = (const double2 *)(base + Ly.o_eval);
+        c.evidx = (const int32_t *)(base + Ly.o_evidx);
         c.expect = (double2 *)(base + Ly.o_expect);
         c.partials = (double *)(base + Ly.o_part);
         CsrCtl t;
@@ -346,10 +350,20 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
         for (auto &sb : block0)
             QT_HIP(hipMemcpyAsync((char *)(S->d_cinst + sb.first) + offsetof(CsrInst, block0), &sb.second, 4,
                                   hipMemcpyHostToDevice, s));
-        const int nb = (int)bi.size(), ns = S->cfg.max_slots;
-        csr_launch_init(0, f64, S->shape.lpr, S->shape.rg, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
-        csr_launch_init(1, f64, S->shape.lpr, S->shape.rg, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
-        for (int k = 0; k < K; ++k) csr_launch_step(f64, S->shape.lpr, S->shape.rg, nb, ns, S->d_cinst, S->d_cctl, S->d_bi, S->d_br, s);
+        CsrLaunch L;
+        L.f64 = f64;
+        L.lpr = S->shape.lpr;
+        L.rg = S->shape.rg;
+        L.xcd = S->shape.xcd;
+        L.nblk = (int)bi.size();
+        L.ninst = S->cfg.max_slots;  // control records are slot-indexed; idle slots return at once
+        L.insts = S->d_cinst;
+        L.ctls = S->d_cctl;
+        L.bi = S->d_bi;
+        L.br = S->d_br;
+        csr_launch_init(0, L, s);
+        csr_launch_init(1, L, s);
+        for (int k = 0; k < K; ++k) csr_launch_step(L, s);
         QT_HIP(hipGetLastError());
     }
     // ---- dense slots: one budgeted launch per padded size, on the auxiliary streams ----

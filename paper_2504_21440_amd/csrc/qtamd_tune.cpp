@@ -74,18 +74,20 @@ CsrShape csr_default_shape(int64_t rows, double mean_row)
     s.lpr = mean_row <= 8.0 ? 4 : (mean_row <= 40.0 ? 8 : 16);
     // small problems: one row per group keeps enough workgroups in flight to fill 256 CUs
     s.rg = rows >= (int64_t(1) << 19) ? 2 : 1;
+    s.xcd = 0;
     return s;
 }
 
 int dense_default_wpr(int np, int32_t prec) { return (prec == QT_F64 || np > 64) ? 1 : 2; }
 
-int csr_candidates(CsrShape *out, int max)
+int csr_candidates(CsrShape *out, int max, bool xcd_order)
 {
     static const int lprs[] = {4, 8, 16}, rgs[] = {1, 2, 4};
     int n = 0;
-    for (int l : lprs)
-        for (int r : rgs)
-            if (r <= l && n < max) out[n++] = CsrShape{l, r};
+    for (int x = 0; x < (xcd_order ? 2 : 1); ++x)
+        for (int l : lprs)
+            for (int r : rgs)
+                if (r <= l && n < max) out[n++] = CsrShape{l, r, x};
     return n;
 }
 
@@ -113,7 +115,8 @@ qt_status qt_tune_save(const char *path)
     std::fprintf(f, "{\n");
     size_t k = 0, n = g_csr.size() + g_dense.size();
     for (auto &kv : g_csr)
-        std::fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.lpr, kv.second.rg, ++k < n ? "," : "");
+        std::fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.lpr, kv.second.rg, kv.second.xcd,
+                     ++k < n ? "," : "");
     for (auto &kv : g_dense)
         std::fprintf(f, "  \"%s\": [%d]%s\n", kv.first.c_str(), kv.second, ++k < n ? "," : "");
     std::fprintf(f, "}\n");
@@ -130,10 +133,10 @@ qt_status qt_tune_load(const char *path)
     int loaded = 0;
     while (std::fgets(line, sizeof line, f)) {
         char key[128];
-        int a = 0, b = 0;
-        const int m = std::sscanf(line, " \"%127[^\"]\": [%d, %d]", key, &a, &b);
-        if (m == 3 && std::strncmp(key, "csr:", 4) == 0 && csr_shape_supported(a, b)) {
-            tune_store_csr(key, CsrShape{a, b});
+        int a = 0, b = 0, c = 0;
+        const int m = std::sscanf(line, " \"%127[^\"]\": [%d, %d, %d]", key, &a, &b, &c);
+        if (m >= 3 && std::strncmp(key, "csr:", 4) == 0 && csr_shape_supported(a, b) && (c == 0 || c == 1)) {
+            tune_store_csr(key, CsrShape{a, b, c});
             ++loaded;
         } else if (m >= 2 && std::strncmp(key, "dense:", 6) == 0 && dense_key_accepts(key, a)) {
             tune_store_dense(key, a);

@@ -105,7 +105,27 @@ def ising_l10_short(name):
                   "oracle_seconds": time.time() - t0, "source": "oracle.mesolve"}, ex)
 
 
+def ising_batch_members(name, members=(0, 7, 15)):
+    """Members of the 16-chain batch (h = 0.3 + 0.08 i), <sigma_z^i> at 100 times."""
+    batch = workloads.ising_batch(n=16)
+    out = {"workload": "ising_batch", "n": 16, "abstol": 1e-8, "reltol": 1e-6, "source": "oracle.mesolve",
+           "members": []}
+    for i in members:
+        p = batch[i]
+        H, cs = om.ising(p["L"], p["J"], p["h"], p["gamma"])
+        e_ops = [om.site_op(p["L"], k, om.sigmaz()) for k in range(p["L"])]
+        ex, st, rc, _ = oracle.mesolve(H, cs, om.all_up_ket(p["L"]), workloads.tlist(p["t_end"], p["nt"]), e_ops)
+        assert rc == 0
+        out["members"].append(dict(p, index=i, oracle_stats=st, expect_re=ex.real.tolist(),
+                                   expect_im=ex.imag.tolist()))
+    path = os.path.join(OUT, name + ".json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path)
+
+
 JOBS = {
+    "ising_batch_members": lambda: ising_batch_members("ising_batch_members"),
     "kerr_sweep_samples": lambda: kerr_sweep_samples("kerr_sweep_samples"),
     "ising_l10_short": lambda: ising_l10_short("ising_l10_short"),
     "kerr_n20_u05": lambda: kerr_me(0.5, 1e-8, 1e-6, "kerr_n20_u05"),

@@ -236,10 +236,10 @@ def test_csr_every_tile_shape_vs_oracle(ctx):
             probs[prec].append((qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec), om.all_up_ket(Lc), tl, e_ops))
     for prec, tol in [(qt.F64, 1e-6), (qt.MIXED, 1e-4)]:
         plan = qt.MePlan(ctx, probs[prec], qt.opts(precision=prec))
-        for lpr, rg in SHAPES:
-            print(f"[gpu] CSR shape lpr={lpr} rg={rg} prec={prec}", flush=True)
-            plan.set_shape(lpr, rg)
-            assert plan.shape()[:2] == (lpr, rg)
+        for (lpr, rg), xcd in [(sh, x) for x in (0, 1) for sh in SHAPES]:
+            print(f"[gpu] CSR shape lpr={lpr} rg={rg} xcd={xcd} prec={prec}", flush=True)
+            plan.set_shape(lpr, rg, xcd)
+            assert plan.shape()[:3] == (lpr, rg, xcd)
             plan.run()
             for i, ref in enumerate(refs):
                 ex, st, _ = plan.result(i)
@@ -263,15 +263,41 @@ def test_ising_l10_hbm_sized_every_shape_vs_golden(ctx):
         Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
         assert Lo.info()[1] == 24_641_535
         plan = qt.MePlan(ctx, [(Lo, om.all_up_ket(10), tl, e_ops)], qt.opts(precision=prec))
-        for lpr, rg in SHAPES:
-            print(f"[gpu] L=10 shape lpr={lpr} rg={rg} prec={prec}", flush=True)
-            plan.set_shape(lpr, rg)
+        for (lpr, rg), xcd in [(sh, x) for x in (0, 1) for sh in SHAPES]:
+            print(f"[gpu] L=10 shape lpr={lpr} rg={rg} xcd={xcd} prec={prec}", flush=True)
+            plan.set_shape(lpr, rg, xcd)
             plan.run()
             ex, st, _ = plan.result(0)
             assert st["status"] == 0
             assert np.abs(ex - ref).max() <= tol, (lpr, rg, prec, np.abs(ex - ref).max())
         plan.close()
         Lo.close()
+
+
+def test_ising_batch_16_mixed_vs_golden(ctx):
+    """Sixteen L=8 chains in one plan (the batched configuration of the benchmark), mixed precision
+    at the accuracy-matched tolerance (rtol 1e-4, atol 1e-6): stored oracle values for three
+    members, the trace-bounded range of <sigma_z> for all."""
+    with open(os.path.join(GOLD, "ising_batch_members.json")) as f:
+        gold = json.load(f)
+    batch = workloads.ising_batch(n=16)
+    probs = []
+    for p in batch:
+        H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+        probs.append((qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED), om.all_up_ket(8),
+                      workloads.tlist(p["t_end"], p["nt"]), [om.site_op(8, i, om.sigmaz()) for i in range(8)]))
+    plan = qt.MePlan(ctx, probs, qt.opts(abstol=1e-6, reltol=1e-4, precision=qt.MIXED))
+    plan.run()
+    for i in range(16):
+        ex, st, _ = plan.result(i)
+        assert st["status"] == 0
+        assert np.all(np.abs(ex.real) <= 1 + 1e-4)
+    for g in gold["members"]:
+        ref = np.array(g["expect_re"]) + 1j * np.array(g["expect_im"])
+        err = np.abs(plan.result(g["index"])[0] - ref).max()
+        print(f"[gpu]   batch member {g['index']} (h={g['h']:.2f}): max|d<sz>| = {err:.2e}", flush=True)
+        assert err <= 1e-4
+    plan.close()
 
 
 def test_plan_rerun_is_deterministic(ctx):
@@ -354,14 +380,14 @@ def test_autotune_chooses_a_kernel_shape_and_keeps_parity(ctx, tmp_path):
     probs = [(qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED), om.all_up_ket(6), tl, e_ops),
              (qt.Liouvillian(ctx, Hk, ck, qt.FORM_DENSE, qt.MIXED), om.fock_dm(20, 0), tl, [om.number(20)])]
     plan = qt.MePlan(ctx, probs, o)
-    lpr, rg, wpr = plan.shape()
-    assert (lpr, rg) in SHAPES and wpr in (1, 2)
+    lpr, rg, xcd, wpr = plan.shape()
+    assert (lpr, rg) in SHAPES and xcd in (0, 1) and wpr in (1, 2)
     plan.run()
     assert np.abs(plan.result(0)[0] - ref).max() <= 1e-4
     assert np.abs(plan.result(1)[0] - refk).max() <= 1e-4
     path = tmp_path / "tune.json"
     qt.tune_save(str(path))
     table = json.loads(path.read_text())
-    assert [lpr, rg] in table.values()
+    assert [lpr, rg, xcd] in table.values()
     assert table.get("dense:mixed:np32") == [wpr]
     plan.close()

@@ -23,16 +23,19 @@ def ctx():
     c.close()
 
 
-def test_sweep_512_full_size(ctx):
-    print("[gpu] 512-cavity sweep, dense mixed, full size", flush=True)
+@pytest.mark.parametrize("nmax_dense", [80, 48, 32])
+def test_sweep_512_full_size(ctx, nmax_dense):
+    """nmax_dense: cavities up to this cutoff use the dense form, larger ones the CSR form (the
+    benchmark runs all three splits)."""
+    print(f"[gpu] 512-cavity sweep, mixed, dense up to N={nmax_dense}", flush=True)
     sweep = workloads.kerr_sweep(n=512)
     probs = []
     for p in sweep:
         H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
-        probs.append((qt.Liouvillian(ctx, H, c, qt.FORM_DENSE, qt.MIXED), om.fock_dm(p["N"], 0),
+        form = qt.FORM_DENSE if p["N"] <= nmax_dense else qt.FORM_CSR
+        probs.append((qt.Liouvillian(ctx, H, c, form, qt.MIXED), om.fock_dm(p["N"], 0),
                       workloads.tlist(p["t_end"], p["nt"]), [om.number(p["N"])]))
-    plan = qt.MePlan(ctx, probs, qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED))
-    plan.autotune(reps=5)
+    plan = qt.MePlan(ctx, probs, qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED, autotune=True))
     plan.run()
     res = [plan.result(i) for i in range(len(sweep))]
     for (ex, st, _), p in zip(res, sweep):
