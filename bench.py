@@ -121,7 +121,7 @@ def section_ising(ctx, steps, warmup):
                      "n_reject": st["n_reject"], "n_rhs": n_rhs, "ms_per_solve": 1e3 * dt / steps,
                      "solves_per_s": steps / dt, "rhs_per_s": n_rhs * steps / dt,
                      "stage_kernel_ms": ms_stage, "spmv_bytes": b, "stage_kernel_GBs": b / (ms_stage * 1e-3) / 1e9,
-                     "nnz": nnz, "n": n, "csr_shape": list(shape[:3])}
+                     "nnz": nnz, "n": n, "csr_shape": list(shape[:4])}
         log(f"ising L=8 {name}: {out[name]}")
         plan.close()
         Lo.close()
@@ -142,7 +142,7 @@ def section_ising_batch(ctx, rt, steps, warmup, n=16):
     sts = [plan.result(i)[1] for i in range(n)]
     out = {"instances": n, "rtol": rt, "atol": rt / 100, "solves_per_s": n * steps / dt,
            "ms_per_batch": 1e3 * dt / steps, "rhs_per_s": sum(s["n_rhs"] for s in sts) * steps / dt,
-           "max_steps": max(s["n_accept"] + s["n_reject"] for s in sts), "csr_shape": list(plan.shape()[:3])}
+           "max_steps": max(s["n_accept"] + s["n_reject"] for s in sts), "csr_shape": list(plan.shape()[:4])}
     log(f"ising L=8 batch of {n}: {out}")
     plan.close()
     for Lo in Ls:
@@ -163,15 +163,17 @@ def section_hbm_spmv(ctx):
         n = d * d
         b = spmv_bytes(n, nnz, vb)
         by_shape = {}
-        for xcd in (0, 1):
-            for lpr, rg in CSR_SHAPES:
-                plan.set_shape(lpr, rg, xcd)
-                by_shape[f"{lpr}x{rg}" + ("x" if xcd else "")] = round(b / (plan.time_rhs(reps=20) * 1e-3) / 1e9, 1)
-        plan.set_shape(*shape[:3])
+        for keep in (0, 1):
+            for xcd in (0, 1):
+                for lpr, rg in CSR_SHAPES:
+                    plan.set_shape(lpr, rg, xcd, keep)
+                    tag = f"{lpr}x{rg}" + ("x" if xcd else "") + ("k" if keep else "")
+                    by_shape[tag] = round(b / (plan.time_rhs(reps=20) * 1e-3) / 1e9, 1)
+        plan.set_shape(*shape[:4])
         ms = plan.time_rhs(reps=50)
         gbs = b / (ms * 1e-3) / 1e9
         out[name] = {"n": n, "nnz": nnz, "bytes_per_launch": b, "ms_per_launch": ms, "GBs": gbs,
-                     "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "csr_shape": list(shape[:3]),
+                     "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "csr_shape": list(shape[:4]),
                      "GBs_by_shape": by_shape}
         log(f"HBM SpMV L=10 {name}: {out[name]}")
         plan.close()
@@ -198,7 +200,7 @@ def section_sweep(ctx, n=512, nmax_dense=80):
     # untimed set-up: the autotuner picks the waves per tile row for each padded size
     o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED, autotune=True)
     plan = qt.MePlan(ctx, probs, o)
-    wpr = plan.shape()[3]
+    wpr = plan.shape()[4]
     plan.run()
     t0 = time.perf_counter()
     plan.run()
@@ -220,7 +222,7 @@ def section_sweep(ctx, n=512, nmax_dense=80):
                     "frac_of_fp32_matrix_peak": flops / (kern_ms * 1e-3) / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
                     "dense_waves_per_row_largest_bucket": wpr})
     else:
-        out["csr_shape"] = list(plan.shape()[:3])
+        out["csr_shape"] = list(plan.shape()[:4])
     plan.close()
     return out, sweep, res
 
@@ -308,11 +310,18 @@ def section_serving(ctx, n=240, qps=40.0, n_fifo=24):
     tridiagonal: the CSR right-hand side does ~30x fewer flops than the dense form); the plain FP64
     single-solve path (CSR form, one request at a time, FIFO) runs the first n_fifo requests of the
     same trace for comparison."""
-    trace = workloads.serving_trace(n=n, qps=qps)
     om_ = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED)
-    lat, span = _serve_mixed(ctx, trace, om_)
-    out = {"requests": n, "qps": qps, "solves_per_s": n / span, "p50_s": float(np.percentile(lat, 50)),
-           "p99_s": float(np.percentile(lat, 99)), "makespan_s": span, "mixed_rtol": om_.reltol}
+    # saturating throughput X: the same requests all arriving at once
+    lat_s, span_s = _serve_mixed(ctx, workloads.serving_trace(n=n, qps=1e9), om_)
+    x_sat = n / span_s
+    out = {"requests": n, "mixed_rtol": om_.reltol,
+           "saturated": {"solves_per_s": x_sat, "makespan_s": span_s, "p50_s": float(np.percentile(lat_s, 50)),
+                         "p99_s": float(np.percentile(lat_s, 99))}}
+    for name, q in [("at_qps", qps), ("at_0.7x_saturation", 0.7 * x_sat)]:
+        lat, span = _serve_mixed(ctx, workloads.serving_trace(n=n, qps=q), om_)
+        out[name] = {"qps": q, "solves_per_s": n / span, "p50_s": float(np.percentile(lat, 50)),
+                     "p99_s": float(np.percentile(lat, 99)), "makespan_s": span}
+    trace = workloads.serving_trace(n=n, qps=qps)
     head = trace[:n_fifo]
     lat_m, span_m = _serve_mixed(ctx, head, om_)
     lat_f, span_f = _serve_fp64_fifo(ctx, head, qt.opts(precision=qt.F64))
@@ -401,6 +410,8 @@ def main():
     ap.add_argument("--skip-extra", action="store_true")
     ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sweep-splits", default="80,48,32",
+                    help="largest cutoff N solved in the dense form, one sweep per value (80: all dense)")
     ap.add_argument("--tune-in", default=os.path.join(ROOT, "paper_2504_21440_amd", "tuning", "mi355x.json"),
                     help="autotuner table loaded before measuring (size buckets it lacks are tuned live); "
                          "'' for none")
@@ -430,16 +441,17 @@ def main():
         extra["spmv_hbm_L10"] = section_hbm_spmv(ctx)
     if "sweep" in only:
         log("sweep")
-        extra["kerr_sweep_512"], _, _ = section_sweep(ctx)
-        for nd in (32, 48):
-            extra[f"kerr_sweep_512_dense_to_N{nd}_csr_above"], _, _ = section_sweep(ctx, nmax_dense=nd)
+        for nd in [int(x) for x in args.sweep_splits.split(",") if x]:
+            key = "kerr_sweep_512" if nd >= 80 else f"kerr_sweep_512_dense_to_N{nd}_csr_above"
+            extra[key], _, _ = section_sweep(ctx, nmax_dense=nd)
     if "mc" in only:
         log("mc")
         extra["mcsolve_L10_10k"] = section_mc(ctx)
     if "serving" in only:
         log("serving")
         extra["serving"] = section_serving(ctx)
-    kname = "k_csr_stage<float,%d,%d,%s,3>" % (mixed["csr_shape"][0], mixed["csr_shape"][1], "true")
+    kname = "k_csr_stage<float,%d,%d,%d,3>" % (mixed["csr_shape"][0], mixed["csr_shape"][1],
+                                               2 if mixed["csr_shape"][3] else 1)
     rl = {"bound": "hbm", "achieved": mixed["stage_kernel_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": mixed["stage_kernel_GBs"] / HBM_PEAK_GBS, "traffic": profiled_traffic(kname),
           "kernel": kname + " (fused SpMV + stage epilogue), L=8 Liouvillian, one launch = one SpMV",

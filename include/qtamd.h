@@ -167,24 +167,34 @@ qt_status qt_me_plan_destroy(qt_me_plan *plan);
  * results are unspecified afterwards until the next qt_me_plan_run. */
 qt_status qt_me_plan_time_rhs(qt_me_plan *plan, int32_t reps, double *ms_per_launch);
 
-/* Autotuner.  The CSR stage kernels take a tile shape (lanes per row group: 4, 8 or 16; rows per
- * lane group: 1, 2 or 4, at most the lanes) and a block order (xcd_order 1: each of the 8 XCDs,
- * with its own L2, works through one contiguous eighth of the rows; 0: the hardware's round-robin
- * order); the dense kernel takes 1 or 2 waves per 16-row tile row.  qt_me_plan_autotune times the fused SpMV-stage kernel of the plan's CSR problems for every
- * candidate shape over `reps` launches (20 if reps <= 0), and each dense size bucket for its
- * allowed waves-per-row choices over a budget of 8 steps; the fastest are kept for the plan and
- * stored in a process-wide table keyed by precision and size bucket (log2 of the rows and mean
- * row length for CSR, padded dimension for dense), which every later plan consults.  Results
- * never depend on the shape beyond rounding of the row sums.  The plan's results are unspecified
- * afterwards until the next qt_me_plan_run.  qt_me_plan_shape reports the shape in use (0 for a
- * group the plan does not have); qt_me_plan_set_shape imposes a CSR shape (QT_EINVAL if the
- * kernels do not support it).  One shape serves every CSR problem of a plan, and the row-sum
- * and norm reduction orders follow it, so a problem's results are bitwise the same alone and in
- * a batch when the shape is the same. */
+/* Autotuner.  The CSR stage kernels take a launch shape (qt_csr_shape):
+ *   lanes_per_row   4, 8 or 16 lanes of a wavefront share a row;
+ *   rows_per_group  1, 2 or 4 rows per lane group (at most lanes_per_row);
+ *   xcd_order       1: each of the 8 XCDs (each with its own L2) works through one contiguous eighth
+ *                   of the rows; 0: the hardware's round-robin order;
+ *   cached_matrix   1: the matrix is read through the caches (temporal loads), so a matrix that
+ *                   fits the L2s can stay there across launches; 0: it is streamed past them.
+ * xcd_order and cached_matrix apply to plans with one CSR problem (a plan with several uses 0, 0).
+ * The dense kernel takes 1 or 2 waves per 16-row tile row.  qt_me_plan_autotune times the fused
+ * SpMV-stage kernel of the plan's CSR problems for every candidate shape over `reps` launches (20
+ * if reps <= 0), and each dense size bucket for its allowed waves-per-row choices over a budget of
+ * 8 steps; the fastest are kept for the plan and stored in a process-wide table keyed by precision
+ * and size bucket (log2 of the rows and mean row length for CSR, padded dimension for dense),
+ * which every later plan consults.  The plan's results are unspecified afterwards until the next
+ * qt_me_plan_run.  qt_me_plan_shape reports the shape in use (zeros for a group the plan does not
+ * have); qt_me_plan_set_shape imposes a CSR shape (QT_EINVAL if the kernels do not support it).
+ * One shape serves every CSR problem of a plan; the row-sum and norm reduction orders follow
+ * lanes_per_row and rows_per_group only, so a problem's results are bitwise the same alone and in
+ * a batch, and with either xcd_order or cached_matrix, when those two are the same. */
+typedef struct {
+    int32_t lanes_per_row;
+    int32_t rows_per_group;
+    int32_t xcd_order;
+    int32_t cached_matrix;
+} qt_csr_shape;
 qt_status qt_me_plan_autotune(qt_me_plan *plan, int32_t reps);
-qt_status qt_me_plan_set_shape(qt_me_plan *plan, int32_t lanes_per_row, int32_t rows_per_group, int32_t xcd_order);
-qt_status qt_me_plan_shape(const qt_me_plan *plan, int32_t *lanes_per_row, int32_t *rows_per_group,
-                           int32_t *xcd_order, int32_t *dense_waves_per_row);
+qt_status qt_me_plan_set_shape(qt_me_plan *plan, const qt_csr_shape *shape);
+qt_status qt_me_plan_shape(const qt_me_plan *plan, qt_csr_shape *csr, int32_t *dense_waves_per_row);
 /* Persist the tuning table as a small JSON object {"key": [shape...], ...}.  load merges the
  * entries of a file written by save, ignoring any shape the kernels do not support. */
 qt_status qt_tune_save(const char *path);
@@ -231,7 +241,7 @@ qt_status qt_mc_plan_destroy(qt_mc_plan *plan);
  * request does not fit now (QT_ENOMEM if it can never fit).  step runs one epoch and retires
  * finished requests; poll reports completion and copies results.  Requests of every size share
  * the CSR launches, which use 8 lanes per row and one row per lane group; a request's results are
- * bitwise those of a plan with that shape (qt_me_plan_set_shape(plan, 8, 1, 0)). */
+ * bitwise those of a plan with that shape (lanes_per_row 8, rows_per_group 1). */
 typedef struct {
     int64_t pool_bytes;      /* device memory budget for resident requests */
     int32_t max_slots;       /* resident requests at most */

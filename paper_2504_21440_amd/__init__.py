@@ -69,6 +69,11 @@ class McProblem(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class CsrShape(ctypes.Structure):
+    _fields_ = [("lanes_per_row", ctypes.c_int32), ("rows_per_group", ctypes.c_int32),
+                ("xcd_order", ctypes.c_int32), ("cached_matrix", ctypes.c_int32)]
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("steps_per_epoch", ctypes.c_int32),
                 ("opts", Opts)]
@@ -283,16 +288,17 @@ class MePlan:
         _check(lib().qt_me_plan_autotune(self.h, int(reps)))
         return self.shape()
 
-    def set_shape(self, lanes_per_row, rows_per_group, xcd_order=0):
-        """Impose a CSR tile shape and block order (qt_me_plan_set_shape)."""
-        _check(lib().qt_me_plan_set_shape(self.h, int(lanes_per_row), int(rows_per_group), int(xcd_order)))
+    def set_shape(self, lanes_per_row, rows_per_group, xcd_order=0, cached_matrix=0):
+        """Impose a CSR launch shape (qt_me_plan_set_shape)."""
+        sh = CsrShape(int(lanes_per_row), int(rows_per_group), int(xcd_order), int(cached_matrix))
+        _check(lib().qt_me_plan_set_shape(self.h, ctypes.byref(sh)))
 
     def shape(self):
-        """(lanes per row, rows per lane group, XCD block order, dense waves per row) in use
-        (qt_me_plan_shape)."""
-        a, b, x, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().qt_me_plan_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(x), ctypes.byref(c)))
-        return a.value, b.value, x.value, c.value
+        """(lanes per row, rows per lane group, XCD block order, cached matrix, dense waves per row)
+        in use (qt_me_plan_shape)."""
+        sh, w = CsrShape(), ctypes.c_int32()
+        _check(lib().qt_me_plan_shape(self.h, ctypes.byref(sh), ctypes.byref(w)))
+        return sh.lanes_per_row, sh.rows_per_group, sh.xcd_order, sh.cached_matrix, w.value
 
     def close(self):
         if self.h:

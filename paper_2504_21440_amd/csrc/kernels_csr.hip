@@ -25,9 +25,10 @@
 // are bitwise the same either way.
 //
 // Launch forms: with several problems a block reads its problem index and first row from a block
-// table and the problem's descriptor from device memory; with one problem (ONE) the descriptor is
-// a kernel argument and the first row is the block index times the rows per block, which removes
-// two dependent memory round trips from every block's critical path.
+// table (its slot among the problem's partials is the first row over the rows per block) and the
+// problem's descriptor from device memory; with one problem (ONE) the descriptor is a kernel
+// argument and the first row is the block index times the rows per block, which removes two
+// dependent memory round trips from every block's critical path.
 //
 // The shape and block order are chosen per problem size by the autotuner (qtamd_tune.cpp).
 #include <cstring>
@@ -100,7 +101,7 @@ __device__ __forceinline__ RowBounds<RG> csr_bounds(const int32_t *__restrict__ 
 
 // Row sums  sum_k val[k] * x(col[k])  over the bounds from csr_bounds; every lane of the group
 // returns all RG sums.  X returns the (stage) input at a column.
-template <typename V, int LPR, int RG, typename X>
+template <typename V, int LPR, int RG, bool KEEP, typename X>
 __device__ __forceinline__ void csr_rows(const RowBounds<RG> &b, const int32_t *__restrict__ col,
                                          const V *__restrict__ val, int q, X x, V (&acc)[RG])
 {
@@ -120,8 +121,8 @@ __device__ __forceinline__ void csr_rows(const RowBounds<RG> &b, const int32_t *
             for (int u = 0; u < U; ++u) {
                 const int k = b.s[g] + base + u * LPR;
                 if (k < b.e[g]) {
-                    cc[g][u] = ld_stream(col + k);
-                    vv[g][u] = ld_stream(val + k);
+                    cc[g][u] = KEEP ? col[k] : ld_stream(col + k);
+                    vv[g][u] = KEEP ? val[k] : ld_stream(val + k);
                     any = true;
                 } else {
                     cc[g][u] = -1;
@@ -264,7 +265,7 @@ template <int LPR, int RG> struct RowSlot {
 // ---------------------------------------------------------------------------------------------
 
 // Starting step, first evaluation: k1 = L rho0, y <- rho0, partials of |y|^2/sc^2 and |f(y)|^2/sc^2.
-template <typename T, int LPR, int RG>
+template <typename T, int LPR, int RG, bool KEEP>
 __device__ __forceinline__ void init0_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
@@ -275,7 +276,7 @@ __device__ __forceinline__ void init0_body(const CsrInst &I, const CsrCtl *C, in
     if (C->status != ST_RUNNING || C->phase != PH_INIT0) return;
     const V *__restrict__ x0 = (const V *)I.rho0;
     V acc[RG];
-    csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q, [&](int c) { return x0[c]; }, acc);
+    csr_rows<V, LPR, RG, KEEP>(rb, I.col, (const V *)I.val, rs.q, [&](int c) { return x0[c]; }, acc);
     double sa = 0.0, sb = 0.0;
     if (rs.valid) {
         const V a = pick(acc, rs.q);
@@ -295,7 +296,7 @@ __device__ __forceinline__ void init0_body(const CsrInst &I, const CsrCtl *C, in
 }
 
 // Starting step, second evaluation: partials of |f(y + h0 f(y)) - f(y)|^2 / (h0 sc)^2.
-template <typename T, int LPR, int RG>
+template <typename T, int LPR, int RG, bool KEEP>
 __device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
@@ -309,7 +310,7 @@ __device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, in
     const V *__restrict__ y = (const V *)I.Y[0];
     const V *__restrict__ k1 = (const V *)I.K[0];
     V acc[RG];
-    csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q,
+    csr_rows<V, LPR, RG, KEEP>(rb, I.col, (const V *)I.val, rs.q,
                          [&](int c) {
                              V v = y[c];
                              caxpy(v, th0, k1[c]);
@@ -329,7 +330,7 @@ __device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, in
 }
 
 // One Runge-Kutta stage S (2..7) of a DP5 step.
-template <typename T, int LPR, int RG, int S>
+template <typename T, int LPR, int RG, int S, bool KEEP>
 __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
@@ -371,7 +372,7 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
     V acc[RG];
     if (S == 2) {
         const T c = (T)(h * DP5::a21);
-        csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q,
+        csr_rows<V, LPR, RG, KEEP>(rb, I.col, (const V *)I.val, rs.q,
                              [&](int cc) {
                                  V v = y[cc];
                                  caxpy(v, c, k1[cc]);
@@ -379,7 +380,7 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
                              },
                              acc);
     } else {
-        csr_rows<V, LPR, RG>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return xin[cc]; }, acc);
+        csr_rows<V, LPR, RG, KEEP>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return xin[cc]; }, acc);
     }
 
     double e2 = 0.0;
@@ -451,43 +452,46 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
 // table (bi: problem, br: first row) of the logical block selects the problem.
 // ---------------------------------------------------------------------------------------------
 // Logical block -> (descriptor, control record, first row, partial slot), then the body.
-#define QT_CSR_DISPATCH_BODY(BODY)                                          \
-    const int lb = csr_block(xcd);                                          \
-    if constexpr (ONE) {                                                    \
-        BODY(one, ctls, lb * CsrGeom<LPR, RG>::RPB, lb);                    \
-    } else {                                                                \
-        const int ii = bi[lb];                                              \
-        const CsrInst &I = insts[ii];                                       \
-        BODY(I, ctls + ii, br[lb], lb - I.block0);                          \
+// FORM 0: several problems, block table.  FORM 1: one problem, descriptor by value.  FORM 2: as 1,
+// with the matrix read through the caches (temporal loads) instead of streamed past them, so that
+// with the XCD-contiguous order each XCD's slice of a matrix that fits the L2s stays there across
+// launches.
+#define QT_CSR_DISPATCH(BODY, ...)                                                                   \
+    const int lb = csr_block(xcd);                                                                   \
+    if constexpr (FORM > 0) {                                                                        \
+        BODY<__VA_ARGS__, FORM == 2>(one, ctls, lb * CsrGeom<LPR, RG>::RPB, lb);                     \
+    } else {                                                                                         \
+        const int ii = bi[lb], row0 = br[lb];                                                        \
+        BODY<__VA_ARGS__, false>(insts[ii], ctls + ii, row0, row0 / CsrGeom<LPR, RG>::RPB);         \
     }
 
-template <typename T, int LPR, int RG, bool ONE>
+template <typename T, int LPR, int RG, int FORM>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__restrict__ insts, const CsrInst one,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ bi,
                                                            const int32_t *__restrict__ br, int xcd)
 {
-    QT_CSR_DISPATCH_BODY((init0_body<T, LPR, RG>))
+    QT_CSR_DISPATCH(init0_body, T, LPR, RG)
 }
 
-template <typename T, int LPR, int RG, bool ONE>
+template <typename T, int LPR, int RG, int FORM>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__restrict__ insts, const CsrInst one,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ bi,
                                                            const int32_t *__restrict__ br, int xcd)
 {
-    QT_CSR_DISPATCH_BODY((init1_body<T, LPR, RG>))
+    QT_CSR_DISPATCH(init1_body, T, LPR, RG)
 }
 
-template <typename T, int LPR, int RG, bool ONE, int S>
+template <typename T, int LPR, int RG, int FORM, int S>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__restrict__ insts, const CsrInst one,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ bi,
                                                            const int32_t *__restrict__ br, int xcd)
 {
-    QT_CSR_DISPATCH_BODY((stage_body<T, LPR, RG, S>))
+    QT_CSR_DISPATCH(stage_body, T, LPR, RG, S)
 }
-#undef QT_CSR_DISPATCH_BODY
+#undef QT_CSR_DISPATCH
 
 // Control: one workgroup per problem.  step_mode 0 completes a pending starting-step evaluation
 // (phases INIT0 / INIT1) and leaves stepping problems alone; step_mode 1 closes a Runge-Kutta step
@@ -617,12 +621,18 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
     }
 }
 
+// ilist: the problems to visit (one workgroup each), or null for problems 0 .. gridDim.x - 1.
 template <typename T, bool ONE>
 __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__restrict__ insts, const CsrInst one,
-                                                             CsrCtl *__restrict__ ctls, int step_mode)
+                                                             CsrCtl *__restrict__ ctls, int step_mode,
+                                                             const int32_t *__restrict__ ilist)
 {
-    if constexpr (ONE) control_body<T>(one, ctls, step_mode);
-    else control_body<T>(insts[blockIdx.x], ctls + blockIdx.x, step_mode);
+    if constexpr (ONE) {
+        control_body<T>(one, ctls, step_mode);
+    } else {
+        const int ii = ilist ? ilist[blockIdx.x] : (int)blockIdx.x;
+        control_body<T>(insts[ii], ctls + ii, step_mode);
+    }
 }
 
 // ---- standalone expectation value (qt_expect) ----
@@ -691,8 +701,9 @@ struct CsrArgs {
     const CsrInst *insts;
     CsrInst one;  // used when ninst == 1 and the host descriptor was given
     bool use_one;
+    int form;  // kernel FORM: 0 block table, 1 one problem, 2 one problem with temporal matrix loads
     CsrCtl *ctls;
-    const int32_t *bi, *br;
+    const int32_t *bi, *br, *ilist;
     int nblk, ninst, xcd;
     hipStream_t s;
 };
@@ -704,9 +715,11 @@ static CsrArgs make_args(const CsrLaunch &L, hipStream_t s)
     a.use_one = L.ninst == 1 && L.one_host != nullptr;
     if (a.use_one) a.one = *L.one_host;
     else std::memset(&a.one, 0, sizeof(a.one));
+    a.form = a.use_one ? (L.keep ? 2 : 1) : 0;
     a.ctls = L.ctls;
     a.bi = L.bi;
     a.br = L.br;
+    a.ilist = L.ilist;
     a.nblk = L.nblk;
     a.ninst = L.ninst;
     a.xcd = L.xcd;
@@ -719,29 +732,35 @@ static void launch_control(const CsrArgs &a, int step_mode)
 {
     if (a.use_one)
         hipLaunchKernelGGL((k_csr_control<T, true>), dim3(1), dim3(CTL_THREADS), 0, a.s, a.insts, a.one, a.ctls,
-                           step_mode);
+                           step_mode, (const int32_t *)nullptr);
     else
         hipLaunchKernelGGL((k_csr_control<T, false>), dim3(a.ninst), dim3(CTL_THREADS), 0, a.s, a.insts, a.one,
-                           a.ctls, step_mode);
+                           a.ctls, step_mode, a.ilist);
 }
 
 #define QT_LAUNCH(KERNEL, a)                                                                                  \
     do {                                                                                                      \
-        if ((a).use_one)                                                                                      \
-            hipLaunchKernelGGL((KERNEL<T, LPR, RG, true>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,      \
+        if ((a).form == 2)                                                                                    \
+            hipLaunchKernelGGL((KERNEL<T, LPR, RG, 2>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+        else if ((a).form == 1)                                                                               \
+            hipLaunchKernelGGL((KERNEL<T, LPR, RG, 1>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
                                (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
         else                                                                                                  \
-            hipLaunchKernelGGL((KERNEL<T, LPR, RG, false>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,     \
+            hipLaunchKernelGGL((KERNEL<T, LPR, RG, 0>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
                                (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
     } while (0)
 
 #define QT_LAUNCH_STAGE(SV, a)                                                                                \
     do {                                                                                                      \
-        if ((a).use_one)                                                                                      \
-            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, true, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,    \
+        if ((a).form == 2)                                                                                    \
+            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 2, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+        else if ((a).form == 1)                                                                               \
+            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 1, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
                                (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
         else                                                                                                  \
-            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, false, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,   \
+            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 0, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
                                (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
     } while (0)
 

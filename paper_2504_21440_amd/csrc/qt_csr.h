@@ -22,8 +22,8 @@ struct CsrInst {
     int32_t d;
     int32_t nt;
     int32_t ne;
-    int32_t block0;   // first block of this instance in the launch grid
-    int32_t nblocks;  // blocks of this instance
+    int32_t block0;   // first block of this instance in the plan's block table (host bookkeeping)
+    int32_t nblocks;  // blocks of this instance (= its partial slots)
     int32_t renorm;   // 1: rescale the trace back to its initial value after accepted steps
     int32_t use_h0;   // 1: opts.h0 given
     double atol, rtol, h0;

@@ -93,10 +93,12 @@ bool csr_shape_supported(int lpr, int rg);
 struct CsrLaunch {
     bool f64 = false;
     int lpr = 8, rg = 1, xcd = 0;  // tile shape and block order
+    int keep = 0;                  // one problem: read the matrix through the caches (temporal loads)
     int nblk = 0, ninst = 0;       // workgroups, problems
     const CsrInst *insts = nullptr;
     CsrCtl *ctls = nullptr;
     const int32_t *bi = nullptr, *br = nullptr;  // block table: problem, first row
+    const int32_t *ilist = nullptr;              // problems the control launch visits (null: 0..ninst-1)
     const CsrInst *one_host = nullptr;           // host copy of the descriptor when ninst == 1
 };
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s);

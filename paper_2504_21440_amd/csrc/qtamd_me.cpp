@@ -46,7 +46,10 @@ struct qt_me_plan {
     qt::CsrShape shape;
     std::string tune_key;
     std::vector<qt::CsrInst> h_ci;  // host copy of the descriptors (block ranges change with the shape)
-    size_t o_cinst = 0, o_cctl = 0, o_bi = 0, o_br = 0;
+    std::vector<double> csr_tend;   // last save time of each CSR problem
+    size_t o_cinst = 0, o_cctl = 0, o_bi = 0, o_br = 0, o_ilist = 0;
+    bool compacted = false;  // block table holds only the problems still running
+    int32_t nctl = 0;        // problems the control launch visits when compacted
     qt::CsrCtl *h_cctl = nullptr;  // pinned
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -171,12 +174,48 @@ static qt_status apply_shape(qt_me_plan *P, CsrShape sh)
     QT_HIP(hipStreamSynchronize(s));
     P->nblk = (int32_t)bi.size();
     P->shape = sh;
+    P->compacted = false;
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     P->gexec = nullptr;
     P->graph = nullptr;
     return QT_OK;
 }
+
+// Rebuild the block table with only the problems in `live` (same shape): launches stop paying for
+// the workgroups of finished problems, which matters when step counts differ widely.  The graph
+// is recaptured at its next use.
+static qt_status compact(qt_me_plan *P, const std::vector<int32_t> &live)
+{
+    const int rpb = csr_rows_per_block(P->shape.lpr, P->shape.rg);
+    std::vector<int32_t> bi, br;
+    for (int32_t i : live) {
+        CsrInst &c = P->h_ci[i];
+        c.block0 = (int32_t)bi.size();
+        for (int32_t b = 0; b < c.nblocks; ++b) {
+            bi.push_back(i);
+            br.push_back(b * rpb);
+        }
+    }
+    hipStream_t s = P->ctx->stream;
+    qt_status st;
+    if ((st = upload(P->arena.at(P->o_cinst), P->h_ci.data(), sizeof(CsrInst) * P->ncsr, s))) return st;
+    if ((st = upload(P->arena.at(P->o_bi), bi.data(), 4 * bi.size(), s))) return st;
+    if ((st = upload(P->arena.at(P->o_br), br.data(), 4 * br.size(), s))) return st;
+    if ((st = upload(P->arena.at(P->o_ilist), live.data(), 4 * live.size(), s))) return st;
+    QT_HIP(hipStreamSynchronize(s));
+    P->nblk = (int32_t)bi.size();
+    P->nctl = (int32_t)live.size();
+    P->compacted = true;
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+    return QT_OK;
+}
+
+// Back to the full block table (every problem) if a run left it compacted.
+static qt_status restore_full(qt_me_plan *P) { return P->compacted ? apply_shape(P, P->shape) : QT_OK; }
 
 qt_status me_plan_autotune(qt_me_plan *P, int32_t reps);
 
@@ -238,6 +277,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         P->o_cctl = A.reserve(sizeof(CsrCtl) * P->ncsr);
         P->o_bi = A.reserve(sizeof(int32_t) * max_blocks);
         P->o_br = A.reserve(sizeof(int32_t) * max_blocks);
+        P->o_ilist = A.reserve(sizeof(int32_t) * P->ncsr);
     }
     if (P->ndense) {
         P->o_dinst = A.reserve(sizeof(DenseInst) * P->ndense);
@@ -252,6 +292,9 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
     hipStream_t s = ctx->stream;
     // ---- uploads ----
     P->h_ci.resize(P->ncsr);
+    P->csr_tend.resize(P->ncsr);
+    for (auto &m : P->probs)
+        if (!m.dense) P->csr_tend[m.slot] = m.tlist.back();
     std::vector<DenseInst> di(P->ndense);
     for (auto &m : P->probs) {
         if ((st = upload(A.at(m.o_rho0), m.rho0.data(), m.rho0.size(), s))) break;
@@ -306,7 +349,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         P->tune_key = csr_tune_key(P->prec, rows_tot, mean_row);
         CsrShape sh;
         if (!tune_lookup_csr(P->tune_key, &sh)) sh = csr_default_shape(rows_tot, mean_row);
-        if (P->ncsr > 1) sh.xcd = 0;  // see csr_candidates: several problems keep the round-robin order
+        if (P->ncsr > 1) sh.xcd = sh.keep = 0;  // see csr_candidates: single-problem options only
         st = apply_shape(P, sh);
         if (!st) {
             hipError_t e = hipHostMalloc((void **)&P->h_cctl, sizeof(CsrCtl) * P->ncsr, hipHostMallocDefault);
@@ -367,8 +410,10 @@ static CsrLaunch csr_args(const qt_me_plan *P)
     L.lpr = P->shape.lpr;
     L.rg = P->shape.rg;
     L.xcd = P->shape.xcd;
+    L.keep = P->shape.keep;
     L.nblk = P->nblk;
-    L.ninst = P->ncsr;
+    L.ninst = P->compacted ? P->nctl : P->ncsr;
+    L.ilist = P->compacted ? (const int32_t *)P->arena.at(P->o_ilist) : nullptr;
     L.insts = (const CsrInst *)P->arena.at(P->o_cinst);
     L.ctls = (CsrCtl *)P->arena.at(P->o_cctl);
     L.bi = (const int32_t *)P->arena.at(P->o_bi);
@@ -420,6 +465,7 @@ qt_status me_plan_run(qt_me_plan *P)
     }
     qt_status st = QT_OK;
     if (P->ncsr) {
+        if ((st = restore_full(P))) return st;
         const CsrLaunch L = csr_args(P);
         auto *cc = L.ctls;
         csr_launch_reset(L.insts, L.ctls, P->ncsr, s);
@@ -435,22 +481,25 @@ qt_status me_plan_run(qt_me_plan *P)
             QT_HIP(hipStreamSynchronize(s));
             // estimate the steps still needed from the slowest running problem
             double need = 0.0;
-            bool running = false;
-            int64_t steps = 0;
+            int64_t steps = 0, live_blocks = 0;
+            std::vector<int32_t> live;
             for (int32_t i = 0; i < P->ncsr; ++i) steps += P->h_cctl[i].n_steps;
             if (steps == last_steps) return set_error(QT_EDEVICE, "CSR solver made no progress in a graph replay");
             last_steps = steps;
             for (int32_t i = 0; i < P->ncsr; ++i) {
                 const CsrCtl &c = P->h_cctl[i];
                 if (c.status != ST_RUNNING) continue;
-                running = true;
-                double tend = 0.0;
-                for (auto &m : P->probs)
-                    if (!m.dense && m.slot == i) tend = m.tlist.back();
+                live.push_back(i);
+                live_blocks += P->h_ci[i].nblocks;
                 const double h = c.h > 0 ? c.h : 1e-6;
-                need = std::max(need, (tend - c.t) / h);
+                need = std::max(need, (P->csr_tend[i] - c.t) / h);
             }
-            if (!running) break;
+            if (live.empty()) break;
+            // drop finished problems from the launches once they hold half of the workgroups
+            if (P->ncsr > 1 && 2 * live_blocks <= P->nblk) {
+                if ((st = compact(P, live))) return st;
+                if ((st = capture_graph(P))) return st;
+            }
             replays = (int)std::min(8.0, std::max(1.0, std::floor(need / P->graph_steps)));
         }
     }
@@ -467,6 +516,8 @@ qt_status me_plan_run(qt_me_plan *P)
 static qt_status time_stage(qt_me_plan *P, int32_t reps, double *ms)
 {
     hipStream_t s = P->ctx->stream;
+    qt_status st = restore_full(P);
+    if (st) return st;
     const CsrLaunch L = csr_args(P);
     hipEvent_t e0, e1;
     QT_HIP(hipEventCreate(&e0));
@@ -639,23 +690,29 @@ qt_status qt_me_plan_autotune(qt_me_plan *plan, int32_t reps)
     return me_plan_autotune(plan, reps);
 }
 
-qt_status qt_me_plan_set_shape(qt_me_plan *plan, int32_t lanes_per_row, int32_t rows_per_group, int32_t xcd_order)
+qt_status qt_me_plan_set_shape(qt_me_plan *plan, const qt_csr_shape *shape)
 {
-    if (!plan) return set_error(QT_EINVAL, "null plan");
-    if (!csr_shape_supported(lanes_per_row, rows_per_group))
+    if (!plan || !shape) return set_error(QT_EINVAL, "qt_me_plan_set_shape: null argument");
+    if (!csr_shape_supported(shape->lanes_per_row, shape->rows_per_group) || shape->xcd_order < 0 ||
+        shape->xcd_order > 1 || shape->cached_matrix < 0 || shape->cached_matrix > 1)
         return set_error(QT_EINVAL, "unsupported CSR tile shape");
     if (!plan->ncsr) return QT_OK;
     QT_HIP(hipSetDevice(plan->ctx->device));
-    return apply_shape(plan, CsrShape{lanes_per_row, rows_per_group, xcd_order ? 1 : 0});
+    CsrShape sh{shape->lanes_per_row, shape->rows_per_group, shape->xcd_order, shape->cached_matrix};
+    if (plan->ncsr > 1) sh.xcd = sh.keep = 0;
+    return apply_shape(plan, sh);
 }
 
-qt_status qt_me_plan_shape(const qt_me_plan *plan, int32_t *lanes_per_row, int32_t *rows_per_group,
-                           int32_t *xcd_order, int32_t *dense_waves_per_row)
+qt_status qt_me_plan_shape(const qt_me_plan *plan, qt_csr_shape *csr, int32_t *dense_waves_per_row)
 {
     if (!plan) return set_error(QT_EINVAL, "null plan");
-    if (lanes_per_row) *lanes_per_row = plan->ncsr ? plan->shape.lpr : 0;
-    if (rows_per_group) *rows_per_group = plan->ncsr ? plan->shape.rg : 0;
-    if (xcd_order) *xcd_order = plan->ncsr ? plan->shape.xcd : 0;
+    if (csr) {
+        const bool c = plan->ncsr > 0;
+        csr->lanes_per_row = c ? plan->shape.lpr : 0;
+        csr->rows_per_group = c ? plan->shape.rg : 0;
+        csr->xcd_order = c ? plan->shape.xcd : 0;
+        csr->cached_matrix = c ? plan->shape.keep : 0;
+    }
     if (dense_waves_per_row)
         *dense_waves_per_row = plan->buckets.empty() ? 0 : dense_choose_config(plan->buckets[0].np, plan->prec);
     return QT_OK;

@@ -99,7 +99,7 @@ struct qt_server {
     qt::CsrCtl *d_cctl = nullptr;
     qt::DenseInst *d_dinst = nullptr;
     qt::DenseCtl *d_dctl = nullptr;
-    int32_t *d_bi = nullptr, *d_br = nullptr, *d_order = nullptr;
+    int32_t *d_bi = nullptr, *d_br = nullptr, *d_order = nullptr, *d_ilist = nullptr;
     size_t blk_cap = 0;
     qt::CsrCtl *h_cctl = nullptr;   // pinned
     qt::DenseCtl *h_dctl = nullptr; // pinned
@@ -249,7 +249,7 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
         c.d = d;
         c.nt = p->n_t;
         c.ne = p->n_e;
-        c.block0 = 0;  // set per epoch
+        c.block0 = 0;  // not used by the kernels (a block finds its partial slot from its first row)
         c.nblocks = nblocks;
         c.renorm = S->prec == QT_MIXED ? 1 : 0;
         c.use_h0 = o.h0 > 0 ? 1 : 0;
@@ -324,12 +324,10 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
     const int K = std::max(1, S->cfg.steps_per_epoch);
     // ---- CSR slots: block table of all active CSR requests ----
     std::vector<int32_t> bi, br, csr_slots;
-    std::vector<std::pair<int32_t, int32_t>> block0;  // (slot, first block)
     const int rpb = csr_rows_per_block(S->shape.lpr, S->shape.rg);
     for (uint64_t tk : S->active) {
         Request &R = S->reqs[tk];
         if (R.dense) continue;
-        block0.push_back({R.slot, (int32_t)bi.size()});
         for (int32_t b = 0; b < R.nblocks; ++b) {
             bi.push_back(R.slot);
             br.push_back(b * rpb);
@@ -346,17 +344,15 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
         }
         QT_HIP(hipMemcpyAsync(S->d_bi, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
         QT_HIP(hipMemcpyAsync(S->d_br, br.data(), br.size() * 4, hipMemcpyHostToDevice, s));
-        // block0 of each slot's descriptor for this epoch's grid
-        for (auto &sb : block0)
-            QT_HIP(hipMemcpyAsync((char *)(S->d_cinst + sb.first) + offsetof(CsrInst, block0), &sb.second, 4,
-                                  hipMemcpyHostToDevice, s));
         CsrLaunch L;
         L.f64 = f64;
         L.lpr = S->shape.lpr;
         L.rg = S->shape.rg;
         L.xcd = S->shape.xcd;
+        QT_HIP(hipMemcpyAsync(S->d_ilist, csr_slots.data(), csr_slots.size() * 4, hipMemcpyHostToDevice, s));
         L.nblk = (int)bi.size();
-        L.ninst = S->cfg.max_slots;  // control records are slot-indexed; idle slots return at once
+        L.ninst = (int)csr_slots.size();  // the control launch visits the resident CSR slots only
+        L.ilist = S->d_ilist;
         L.insts = S->d_cinst;
         L.ctls = S->d_cctl;
         L.bi = S->d_bi;
@@ -466,6 +462,7 @@ qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **ou
     if (e == hipSuccess) e = hipMalloc(&S->d_dinst, sizeof(DenseInst) * ns);
     if (e == hipSuccess) e = hipMalloc(&S->d_dctl, sizeof(DenseCtl) * ns);
     if (e == hipSuccess) e = hipMalloc(&S->d_order, sizeof(int32_t) * ns);
+    if (e == hipSuccess) e = hipMalloc(&S->d_ilist, sizeof(int32_t) * ns);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_cctl, sizeof(CsrCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_dctl, sizeof(DenseCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) {
@@ -546,6 +543,7 @@ qt_status qt_server_destroy(qt_server *S)
     if (S->d_dinst) (void)hipFree(S->d_dinst);
     if (S->d_dctl) (void)hipFree(S->d_dctl);
     if (S->d_order) (void)hipFree(S->d_order);
+    if (S->d_ilist) (void)hipFree(S->d_ilist);
     if (S->d_bi) (void)hipFree(S->d_bi);
     if (S->d_br) (void)hipFree(S->d_br);
     if (S->h_cctl) (void)hipHostFree(S->h_cctl);

@@ -80,14 +80,15 @@ CsrShape csr_default_shape(int64_t rows, double mean_row)
 
 int dense_default_wpr(int np, int32_t prec) { return (prec == QT_F64 || np > 64) ? 1 : 2; }
 
-int csr_candidates(CsrShape *out, int max, bool xcd_order)
+int csr_candidates(CsrShape *out, int max, bool single)
 {
     static const int lprs[] = {4, 8, 16}, rgs[] = {1, 2, 4};
     int n = 0;
-    for (int x = 0; x < (xcd_order ? 2 : 1); ++x)
-        for (int l : lprs)
-            for (int r : rgs)
-                if (r <= l && n < max) out[n++] = CsrShape{l, r, x};
+    for (int k = 0; k < (single ? 2 : 1); ++k)
+        for (int x = 0; x < (single ? 2 : 1); ++x)
+            for (int l : lprs)
+                for (int r : rgs)
+                    if (r <= l && n < max) out[n++] = CsrShape{l, r, x, k};
     return n;
 }
 
@@ -115,8 +116,8 @@ qt_status qt_tune_save(const char *path)
     std::fprintf(f, "{\n");
     size_t k = 0, n = g_csr.size() + g_dense.size();
     for (auto &kv : g_csr)
-        std::fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.lpr, kv.second.rg, kv.second.xcd,
-                     ++k < n ? "," : "");
+        std::fprintf(f, "  \"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.lpr, kv.second.rg,
+                     kv.second.xcd, kv.second.keep, ++k < n ? "," : "");
     for (auto &kv : g_dense)
         std::fprintf(f, "  \"%s\": [%d]%s\n", kv.first.c_str(), kv.second, ++k < n ? "," : "");
     std::fprintf(f, "}\n");
@@ -133,10 +134,11 @@ qt_status qt_tune_load(const char *path)
     int loaded = 0;
     while (std::fgets(line, sizeof line, f)) {
         char key[128];
-        int a = 0, b = 0, c = 0;
-        const int m = std::sscanf(line, " \"%127[^\"]\": [%d, %d, %d]", key, &a, &b, &c);
-        if (m >= 3 && std::strncmp(key, "csr:", 4) == 0 && csr_shape_supported(a, b) && (c == 0 || c == 1)) {
-            tune_store_csr(key, CsrShape{a, b, c});
+        int a = 0, b = 0, c = 0, e = 0;
+        const int m = std::sscanf(line, " \"%127[^\"]\": [%d, %d, %d, %d]", key, &a, &b, &c, &e);
+        if (m >= 3 && std::strncmp(key, "csr:", 4) == 0 && csr_shape_supported(a, b) && (c == 0 || c == 1) &&
+            (e == 0 || e == 1)) {
+            tune_store_csr(key, CsrShape{a, b, c, e});
             ++loaded;
         } else if (m >= 2 && std::strncmp(key, "dense:", 6) == 0 && dense_key_accepts(key, a)) {
             tune_store_dense(key, a);

@@ -239,7 +239,7 @@ def test_csr_every_tile_shape_vs_oracle(ctx):
         for (lpr, rg), xcd in [(sh, x) for x in (0, 1) for sh in SHAPES]:
             print(f"[gpu] CSR shape lpr={lpr} rg={rg} xcd={xcd} prec={prec}", flush=True)
             plan.set_shape(lpr, rg, xcd)
-            assert plan.shape()[:3] == (lpr, rg, xcd)
+            assert plan.shape()[:4] == (lpr, rg, 0, 0)  # two problems: the round-robin, streamed form
             plan.run()
             for i, ref in enumerate(refs):
                 ex, st, _ = plan.result(i)
@@ -263,9 +263,10 @@ def test_ising_l10_hbm_sized_every_shape_vs_golden(ctx):
         Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
         assert Lo.info()[1] == 24_641_535
         plan = qt.MePlan(ctx, [(Lo, om.all_up_ket(10), tl, e_ops)], qt.opts(precision=prec))
-        for (lpr, rg), xcd in [(sh, x) for x in (0, 1) for sh in SHAPES]:
-            print(f"[gpu] L=10 shape lpr={lpr} rg={rg} xcd={xcd} prec={prec}", flush=True)
-            plan.set_shape(lpr, rg, xcd)
+        for (lpr, rg), xcd, keep in [(sh, x, k) for k in (0, 1) for x in (0, 1) for sh in SHAPES]:
+            print(f"[gpu] L=10 shape lpr={lpr} rg={rg} xcd={xcd} keep={keep} prec={prec}", flush=True)
+            plan.set_shape(lpr, rg, xcd, keep)
+            assert plan.shape()[:4] == (lpr, rg, xcd, keep)
             plan.run()
             ex, st, _ = plan.result(0)
             assert st["status"] == 0
@@ -380,14 +381,14 @@ def test_autotune_chooses_a_kernel_shape_and_keeps_parity(ctx, tmp_path):
     probs = [(qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED), om.all_up_ket(6), tl, e_ops),
              (qt.Liouvillian(ctx, Hk, ck, qt.FORM_DENSE, qt.MIXED), om.fock_dm(20, 0), tl, [om.number(20)])]
     plan = qt.MePlan(ctx, probs, o)
-    lpr, rg, xcd, wpr = plan.shape()
-    assert (lpr, rg) in SHAPES and xcd in (0, 1) and wpr in (1, 2)
+    lpr, rg, xcd, keep, wpr = plan.shape()
+    assert (lpr, rg) in SHAPES and xcd in (0, 1) and keep in (0, 1) and wpr in (1, 2)
     plan.run()
     assert np.abs(plan.result(0)[0] - ref).max() <= 1e-4
     assert np.abs(plan.result(1)[0] - refk).max() <= 1e-4
     path = tmp_path / "tune.json"
     qt.tune_save(str(path))
     table = json.loads(path.read_text())
-    assert [lpr, rg, xcd] in table.values()
+    assert [lpr, rg, xcd, keep] in table.values()
     assert table.get("dense:mixed:np32") == [wpr]
     plan.close()

@@ -68,7 +68,7 @@ def test_tuning_table_roundtrip(tmp_path):
     src = tmp_path / "in.json"
     src.write_text(
         '{\n'
-        '  "csr:mixed:n20:r19": [16, 2, 1],\n'
+        '  "csr:mixed:n20:r19": [16, 2, 1, 1],\n'
         '  "csr:f64:n12:r7": [4, 4],\n'
         '  "csr:f64:n13:r7": [4, 8],\n'      # rows per group above the lanes: not a kernel shape
         '  "csr:f64:n14:r7": [32, 1],\n'     # 32 lanes per row: not a kernel shape
@@ -80,8 +80,8 @@ def test_tuning_table_roundtrip(tmp_path):
     qt.tune_save(str(out))
     import json
     table = json.loads(out.read_text())
-    assert table["csr:mixed:n20:r19"] == [16, 2, 1]
-    assert table["csr:f64:n12:r7"] == [4, 4, 0]  # a two-number entry reads as the round-robin order
+    assert table["csr:mixed:n20:r19"] == [16, 2, 1, 1]
+    assert table["csr:f64:n12:r7"] == [4, 4, 0, 0]  # a two-number entry reads as round-robin, streamed
     assert table["dense:mixed:np32"] == [2]
     for bad in ("csr:f64:n13:r7", "csr:f64:n14:r7", "dense:f64:np48"):
         assert bad not in table
