@@ -142,3 +142,21 @@ def test_trajectories_reproducible_and_independent_of_batching():
     a = oracle.mcsolve(H, cs, om.all_up_ket(L), tl, [Sz], 40, 11)
     b = oracle.mcsolve(H, cs, om.all_up_ket(L), tl, [Sz], 10, 11, traj0=30)
     np.testing.assert_array_equal(a["expect_tr"][30:], b["expect_tr"])
+
+
+def test_ensemble_stats_definition():
+    """Ensemble mean and standard error of the real part, against their definitions written out:
+    mean over trajectories, SE = sqrt(sum (x - mean)^2 / (N - 1) / N); one trajectory gives SE 0."""
+    g = np.random.default_rng(17)
+    ex = g.normal(size=(37, 2, 5)) + 1j * g.normal(size=(37, 2, 5))
+    mean, se = oracle.ensemble_stats(ex)
+    n = ex.shape[0]
+    for k in range(2):
+        for t in range(5):
+            xs = [ex[j, k, t] for j in range(n)]
+            m = sum(xs) / n
+            v = sum((x.real - m.real) ** 2 for x in xs) / (n - 1) / n
+            assert abs(mean[k, t] - m) < 1e-14
+            assert abs(se[k, t] - v ** 0.5) < 1e-14
+    m1, s1 = oracle.ensemble_stats(ex[:1])
+    assert np.all(s1 == 0) and np.allclose(m1, ex[0])
