@@ -174,7 +174,7 @@ qt_status qt_me_plan_time_rhs(qt_me_plan *plan, int32_t reps, double *ms_per_lau
  *                   of the rows; 0: the hardware's round-robin order;
  *   cached_matrix   1: the matrix is read through the caches (temporal loads), so a matrix that
  *                   fits the L2s can stay there across launches; 0: it is streamed past them.
- * xcd_order and cached_matrix apply to plans with one CSR problem (a plan with several uses 0, 0).
+ * xcd_order applies to plans with one CSR problem (a plan with several uses 0).
  * The dense kernel takes 1 or 2 waves per 16-row tile row.  qt_me_plan_autotune times the fused
  * SpMV-stage kernel of the plan's CSR problems for every candidate shape over `reps` launches (20
  * if reps <= 0), and each dense size bucket for its allowed waves-per-row choices over a budget of

@@ -452,17 +452,16 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
 // table (bi: problem, br: first row) of the logical block selects the problem.
 // ---------------------------------------------------------------------------------------------
 // Logical block -> (descriptor, control record, first row, partial slot), then the body.
-// FORM 0: several problems, block table.  FORM 1: one problem, descriptor by value.  FORM 2: as 1,
-// with the matrix read through the caches (temporal loads) instead of streamed past them, so that
-// with the XCD-contiguous order each XCD's slice of a matrix that fits the L2s stays there across
-// launches.
+// FORM 0: several problems, block table.  FORM 1: one problem, descriptor by value.  FORM 2 / 3: as
+// 1 / 0, with the matrix read through the caches (temporal loads) instead of streamed past them, so
+// that what of the matrices fits the L2s and the MALL is still there at the next launch.
 #define QT_CSR_DISPATCH(BODY, ...)                                                                   \
     const int lb = csr_block(xcd);                                                                   \
-    if constexpr (FORM > 0) {                                                                        \
+    if constexpr (FORM == 1 || FORM == 2) {                                                          \
         BODY<__VA_ARGS__, FORM == 2>(one, ctls, lb * CsrGeom<LPR, RG>::RPB, lb);                     \
     } else {                                                                                         \
         const int ii = bi[lb], row0 = br[lb];                                                        \
-        BODY<__VA_ARGS__, false>(insts[ii], ctls + ii, row0, row0 / CsrGeom<LPR, RG>::RPB);         \
+        BODY<__VA_ARGS__, FORM == 3>(insts[ii], ctls + ii, row0, row0 / CsrGeom<LPR, RG>::RPB);     \
     }
 
 template <typename T, int LPR, int RG, int FORM>
@@ -701,7 +700,7 @@ struct CsrArgs {
     const CsrInst *insts;
     CsrInst one;  // used when ninst == 1 and the host descriptor was given
     bool use_one;
-    int form;  // kernel FORM: 0 block table, 1 one problem, 2 one problem with temporal matrix loads
+    int form;  // kernel FORM: 0 block table, 1 one problem; 2 / 3: as 1 / 0 with temporal matrix loads
     CsrCtl *ctls;
     const int32_t *bi, *br, *ilist;
     int nblk, ninst, xcd;
@@ -715,7 +714,7 @@ static CsrArgs make_args(const CsrLaunch &L, hipStream_t s)
     a.use_one = L.ninst == 1 && L.one_host != nullptr;
     if (a.use_one) a.one = *L.one_host;
     else std::memset(&a.one, 0, sizeof(a.one));
-    a.form = a.use_one ? (L.keep ? 2 : 1) : 0;
+    a.form = a.use_one ? (L.keep ? 2 : 1) : (L.keep ? 3 : 0);
     a.ctls = L.ctls;
     a.bi = L.bi;
     a.br = L.br;
@@ -740,7 +739,10 @@ static void launch_control(const CsrArgs &a, int step_mode)
 
 #define QT_LAUNCH(KERNEL, a)                                                                                  \
     do {                                                                                                      \
-        if ((a).form == 2)                                                                                    \
+        if ((a).form == 3)                                                                                    \
+            hipLaunchKernelGGL((KERNEL<T, LPR, RG, 3>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+        else if ((a).form == 2)                                                                               \
             hipLaunchKernelGGL((KERNEL<T, LPR, RG, 2>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
                                (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
         else if ((a).form == 1)                                                                               \
@@ -753,7 +755,10 @@ static void launch_control(const CsrArgs &a, int step_mode)
 
 #define QT_LAUNCH_STAGE(SV, a)                                                                                \
     do {                                                                                                      \
-        if ((a).form == 2)                                                                                    \
+        if ((a).form == 3)                                                                                    \
+            hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 3, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+        else if ((a).form == 2)                                                                               \
             hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 2, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
                                (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
         else if ((a).form == 1)                                                                               \

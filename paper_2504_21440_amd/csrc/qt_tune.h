@@ -13,7 +13,7 @@ struct CsrShape {
     int lpr = 8;  // lanes per row group
     int rg = 1;   // rows per lane group
     int xcd = 0;   // 1: XCD-contiguous block order
-    int keep = 0;  // 1 (single-problem plans): temporal matrix loads, the matrix may stay in L2
+    int keep = 0;  // 1: temporal matrix loads, the matrix may stay in L2 / MALL across launches
 };
 
 // size bucket of a CSR right-hand side: log2 of the rows, rounded mean row length
@@ -29,10 +29,10 @@ void tune_store_dense(const std::string &key, int wpr);
 CsrShape csr_default_shape(int64_t rows, double mean_row);
 int dense_default_wpr(int np, int32_t prec);
 
-// Candidate CSR shapes the autotuner measures.  single: include the XCD-contiguous block order
-// and the temporal matrix loads.  Only single-problem plans use them: with several problems of
+// Candidate CSR shapes the autotuner measures (both matrix load kinds).  single: include the
+// XCD-contiguous block order, which only single-problem plans use: with several problems of
 // unequal step counts, an XCD whose problems have finished would sit idle while the others still
-// work through theirs (and the several matrices rarely fit the caches together).
+// work through theirs.
 int csr_candidates(CsrShape *out, int max, bool single);
 
 }  // namespace qt

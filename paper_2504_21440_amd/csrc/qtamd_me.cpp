@@ -349,7 +349,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         P->tune_key = csr_tune_key(P->prec, rows_tot, mean_row);
         CsrShape sh;
         if (!tune_lookup_csr(P->tune_key, &sh)) sh = csr_default_shape(rows_tot, mean_row);
-        if (P->ncsr > 1) sh.xcd = sh.keep = 0;  // see csr_candidates: single-problem options only
+        if (P->ncsr > 1) sh.xcd = 0;  // see csr_candidates: a single-problem option
         st = apply_shape(P, sh);
         if (!st) {
             hipError_t e = hipHostMalloc((void **)&P->h_cctl, sizeof(CsrCtl) * P->ncsr, hipHostMallocDefault);
@@ -699,7 +699,7 @@ qt_status qt_me_plan_set_shape(qt_me_plan *plan, const qt_csr_shape *shape)
     if (!plan->ncsr) return QT_OK;
     QT_HIP(hipSetDevice(plan->ctx->device));
     CsrShape sh{shape->lanes_per_row, shape->rows_per_group, shape->xcd_order, shape->cached_matrix};
-    if (plan->ncsr > 1) sh.xcd = sh.keep = 0;
+    if (plan->ncsr > 1) sh.xcd = 0;
     return apply_shape(plan, sh);
 }
 

@@ -84,7 +84,7 @@ int csr_candidates(CsrShape *out, int max, bool single)
 {
     static const int lprs[] = {4, 8, 16}, rgs[] = {1, 2, 4};
     int n = 0;
-    for (int k = 0; k < (single ? 2 : 1); ++k)
+    for (int k = 0; k < 2; ++k)
         for (int x = 0; x < (single ? 2 : 1); ++x)
             for (int l : lprs)
                 for (int r : rgs)

@@ -236,10 +236,10 @@ def test_csr_every_tile_shape_vs_oracle(ctx):
             probs[prec].append((qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec), om.all_up_ket(Lc), tl, e_ops))
     for prec, tol in [(qt.F64, 1e-6), (qt.MIXED, 1e-4)]:
         plan = qt.MePlan(ctx, probs[prec], qt.opts(precision=prec))
-        for (lpr, rg), xcd in [(sh, x) for x in (0, 1) for sh in SHAPES]:
-            print(f"[gpu] CSR shape lpr={lpr} rg={rg} xcd={xcd} prec={prec}", flush=True)
-            plan.set_shape(lpr, rg, xcd)
-            assert plan.shape()[:4] == (lpr, rg, 0, 0)  # two problems: the round-robin, streamed form
+        for (lpr, rg), xcd, keep in [(sh, x, k) for k in (0, 1) for x in (0, 1) for sh in SHAPES]:
+            print(f"[gpu] CSR shape lpr={lpr} rg={rg} xcd={xcd} keep={keep} prec={prec}", flush=True)
+            plan.set_shape(lpr, rg, xcd, keep)
+            assert plan.shape()[:4] == (lpr, rg, 0, keep)  # two problems: round-robin order
             plan.run()
             for i, ref in enumerate(refs):
                 ex, st, _ = plan.result(i)
