@@ -8,7 +8,7 @@ Conventions (arXiv:2504.21440, Sec. 2 and the constructor table of App. C):
     index 1 = "down"; sigma_- = |down><up| lowers up to down.
   * ``tensor`` is the Kronecker product with the first factor most significant.
 
-Model Hamiltonians follow the workloads this build measures:
+Model Hamiltonians of the benchmark workloads:
   * driven Kerr cavity (Sec. 6): H = Delta a^dag a + (U/2) a^dag a^dag a a + F (a + a^dag),
     C = sqrt(kappa) a;
   * open transverse-field Ising chain (Secs. 4 and 6):
