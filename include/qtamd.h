@@ -240,8 +240,9 @@ qt_status qt_mc_plan_destroy(qt_mc_plan *plan);
  * together, epoch by epoch, with requests that arrived earlier.  submit returns QT_EBUSY when the
  * request does not fit now (QT_ENOMEM if it can never fit).  step runs one epoch and retires
  * finished requests; poll reports completion and copies results.  Requests of every size share
- * the CSR launches, which use 8 lanes per row and one row per lane group; a request's results are
- * bitwise those of a plan with that shape (lanes_per_row 8, rows_per_group 1). */
+ * the CSR launches, which use 8 lanes per row and one row per lane group and read the matrices
+ * through the caches; a request's results are bitwise those of a plan with that shape
+ * (lanes_per_row 8, rows_per_group 1). */
 typedef struct {
     int64_t pool_bytes;      /* device memory budget for resident requests */
     int32_t max_slots;       /* resident requests at most */

@@ -40,7 +40,7 @@
 namespace qt {
 
 constexpr int CSR_THREADS = 256;
-constexpr int CTL_THREADS = 256;
+constexpr int CTL_THREADS = 512;  // 8 waves: one expectation operator per wave for up to 8 e_ops
 constexpr int CTL_MAX_EOPS = 64;  // operators whose sums the control kernel holds in LDS
 enum : int32_t { PH_STEP = 0, PH_INIT1 = 1, PH_INIT0 = 2 };
 

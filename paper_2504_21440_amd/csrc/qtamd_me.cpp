@@ -48,12 +48,27 @@ struct qt_me_plan {
     std::vector<qt::CsrInst> h_ci;  // host copy of the descriptors (block ranges change with the shape)
     std::vector<double> csr_tend;   // last save time of each CSR problem
     size_t o_cinst = 0, o_cctl = 0, o_bi = 0, o_br = 0, o_ilist = 0;
-    bool compacted = false;  // block table holds only the problems still running
-    int32_t nctl = 0;        // problems the control launch visits when compacted
     qt::CsrCtl *h_cctl = nullptr;  // pinned
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
     int32_t graph_steps = 16;
+    // Lanes: the CSR problems run as one or more groups, each with its own segment of the block
+    // table and of the control list, its own captured graph and its own stream.  A run starts with
+    // one lane holding every problem; finished problems are dropped and far-behind ones split off
+    // into a lane of their own as the run goes (see me_plan_run).
+    struct Lane {
+        std::vector<int32_t> members;  // CSR problem slots
+        int32_t boff = 0, nblk = 0;    // block-table segment
+        int32_t ioff = 0;              // control-list segment
+        bool listed = false;           // false: the control launch visits problems 0 .. ncsr-1
+        hipStream_t stream = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        int replays = 1;               // graph replays per round
+        bool done = false;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+    };
+    std::vector<Lane> lanes;
+    std::vector<hipStream_t> lane_streams;  // created on demand, destroyed with the plan
+    bool split = false;                     // lanes differ from the single full lane
     // dense group
     int32_t ndense = 0;
     size_t o_dinst = 0, o_dctl = 0, o_dorder = 0;
@@ -67,6 +82,8 @@ struct qt_me_plan {
 };
 
 namespace qt {
+
+constexpr int MAX_EXTRA_LANES = 3;  // lanes split off a plan's CSR problems, each on its own stream
 
 static size_t state_es(int32_t prec) { return prec == QT_F64 ? sizeof(double2) : sizeof(float2); }
 
@@ -151,71 +168,71 @@ static qt_status upload(void *dst, const void *src, size_t bytes, hipStream_t s)
     return QT_OK;
 }
 
+static void drop_graph(qt_me_plan::Lane &l)
+{
+    if (l.gexec) (void)hipGraphExecDestroy(l.gexec);
+    if (l.graph) (void)hipGraphDestroy(l.graph);
+    l.gexec = nullptr;
+    l.graph = nullptr;
+}
+
+// Write the block table and control list of every live lane, back to back, and upload them.  A
+// lane's blocks are those of its members at the plan's shape.  Graphs are recaptured on next use.
+static qt_status layout_lanes(qt_me_plan *P)
+{
+    const int rpb = csr_rows_per_block(P->shape.lpr, P->shape.rg);
+    std::vector<int32_t> bi, br, il;
+    for (auto &l : P->lanes) {
+        drop_graph(l);
+        if (l.done) continue;
+        l.boff = (int32_t)bi.size();
+        l.ioff = (int32_t)il.size();
+        for (int32_t i : l.members) {
+            CsrInst &c = P->h_ci[i];
+            c.block0 = (int32_t)bi.size();
+            for (int32_t b = 0; b < c.nblocks; ++b) {
+                bi.push_back(i);
+                br.push_back(b * rpb);
+            }
+            il.push_back(i);
+        }
+        l.nblk = (int32_t)bi.size() - l.boff;
+    }
+    hipStream_t s = P->ctx->stream;
+    qt_status st;
+    if ((st = upload(P->arena.at(P->o_cinst), P->h_ci.data(), sizeof(CsrInst) * P->ncsr, s))) return st;
+    if ((st = upload(P->arena.at(P->o_bi), bi.data(), 4 * bi.size(), s))) return st;
+    if ((st = upload(P->arena.at(P->o_br), br.data(), 4 * br.size(), s))) return st;
+    if ((st = upload(P->arena.at(P->o_ilist), il.data(), 4 * il.size(), s))) return st;
+    QT_HIP(hipStreamSynchronize(s));
+    P->nblk = (int32_t)bi.size();
+    return QT_OK;
+}
+
+// One lane with every CSR problem, on the context's stream, control launch over all problems.
+static qt_status reset_lanes(qt_me_plan *P)
+{
+    for (auto &l : P->lanes) drop_graph(l);
+    P->lanes.assign(1, qt_me_plan::Lane{});
+    auto &l = P->lanes[0];
+    for (int32_t i = 0; i < P->ncsr; ++i) l.members.push_back(i);
+    l.stream = P->ctx->stream;
+    P->split = false;
+    return layout_lanes(P);
+}
+
 // Lay the CSR problems out over the launch grid for a tile shape and upload the block tables.
 static qt_status apply_shape(qt_me_plan *P, CsrShape sh)
 {
     if (!csr_shape_supported(sh.lpr, sh.rg)) return set_error(QT_EINVAL, "unsupported CSR tile shape");
     const int rpb = csr_rows_per_block(sh.lpr, sh.rg);
-    std::vector<int32_t> bi, br;
-    for (int32_t i = 0; i < P->ncsr; ++i) {
-        CsrInst &c = P->h_ci[i];
-        c.nblocks = (c.n + rpb - 1) / rpb;
-        c.block0 = (int32_t)bi.size();
-        for (int32_t b = 0; b < c.nblocks; ++b) {
-            bi.push_back(i);
-            br.push_back(b * rpb);
-        }
-    }
-    hipStream_t s = P->ctx->stream;
-    qt_status st;
-    if ((st = upload(P->arena.at(P->o_cinst), P->h_ci.data(), sizeof(CsrInst) * P->ncsr, s))) return st;
-    if ((st = upload(P->arena.at(P->o_bi), bi.data(), 4 * bi.size(), s))) return st;
-    if ((st = upload(P->arena.at(P->o_br), br.data(), 4 * br.size(), s))) return st;
-    QT_HIP(hipStreamSynchronize(s));
-    P->nblk = (int32_t)bi.size();
+    for (int32_t i = 0; i < P->ncsr; ++i) P->h_ci[i].nblocks = (P->h_ci[i].n + rpb - 1) / rpb;
     P->shape = sh;
-    P->compacted = false;
-    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
-    if (P->graph) (void)hipGraphDestroy(P->graph);
-    P->gexec = nullptr;
-    P->graph = nullptr;
-    return QT_OK;
+    return reset_lanes(P);
 }
 
-// Rebuild the block table with only the problems in `live` (same shape): launches stop paying for
-// the workgroups of finished problems, which matters when step counts differ widely.  The graph
-// is recaptured at its next use.
-static qt_status compact(qt_me_plan *P, const std::vector<int32_t> &live)
-{
-    const int rpb = csr_rows_per_block(P->shape.lpr, P->shape.rg);
-    std::vector<int32_t> bi, br;
-    for (int32_t i : live) {
-        CsrInst &c = P->h_ci[i];
-        c.block0 = (int32_t)bi.size();
-        for (int32_t b = 0; b < c.nblocks; ++b) {
-            bi.push_back(i);
-            br.push_back(b * rpb);
-        }
-    }
-    hipStream_t s = P->ctx->stream;
-    qt_status st;
-    if ((st = upload(P->arena.at(P->o_cinst), P->h_ci.data(), sizeof(CsrInst) * P->ncsr, s))) return st;
-    if ((st = upload(P->arena.at(P->o_bi), bi.data(), 4 * bi.size(), s))) return st;
-    if ((st = upload(P->arena.at(P->o_br), br.data(), 4 * br.size(), s))) return st;
-    if ((st = upload(P->arena.at(P->o_ilist), live.data(), 4 * live.size(), s))) return st;
-    QT_HIP(hipStreamSynchronize(s));
-    P->nblk = (int32_t)bi.size();
-    P->nctl = (int32_t)live.size();
-    P->compacted = true;
-    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
-    if (P->graph) (void)hipGraphDestroy(P->graph);
-    P->gexec = nullptr;
-    P->graph = nullptr;
-    return QT_OK;
-}
-
-// Back to the full block table (every problem) if a run left it compacted.
-static qt_status restore_full(qt_me_plan *P) { return P->compacted ? apply_shape(P, P->shape) : QT_OK; }
+// Back to the single full lane if a run left the problems split or dropped.
+static qt_status restore_full(qt_me_plan *P) { return P->split ? reset_lanes(P) : QT_OK; }
 
 qt_status me_plan_autotune(qt_me_plan *P, int32_t reps);
 
@@ -402,36 +419,37 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
     return QT_OK;
 }
 
-// Launch configuration of the plan's CSR group at its current shape.
-static CsrLaunch csr_args(const qt_me_plan *P)
+// Launch configuration of lane `k` of the plan's CSR problems at the current shape.
+static CsrLaunch csr_args(const qt_me_plan *P, int k = 0)
 {
+    const auto &l = P->lanes[k];
     CsrLaunch L;
     L.f64 = P->prec == QT_F64;
     L.lpr = P->shape.lpr;
     L.rg = P->shape.rg;
     L.xcd = P->shape.xcd;
     L.keep = P->shape.keep;
-    L.nblk = P->nblk;
-    L.ninst = P->compacted ? P->nctl : P->ncsr;
-    L.ilist = P->compacted ? (const int32_t *)P->arena.at(P->o_ilist) : nullptr;
+    L.nblk = l.nblk;
+    L.ninst = l.listed ? (int)l.members.size() : P->ncsr;
+    L.ilist = l.listed ? (const int32_t *)P->arena.at(P->o_ilist) + l.ioff : nullptr;
     L.insts = (const CsrInst *)P->arena.at(P->o_cinst);
     L.ctls = (CsrCtl *)P->arena.at(P->o_cctl);
-    L.bi = (const int32_t *)P->arena.at(P->o_bi);
-    L.br = (const int32_t *)P->arena.at(P->o_br);
+    L.bi = (const int32_t *)P->arena.at(P->o_bi) + l.boff;
+    L.br = (const int32_t *)P->arena.at(P->o_br) + l.boff;
     L.one_host = P->ncsr == 1 ? &P->h_ci[0] : nullptr;
     return L;
 }
 
-static qt_status capture_graph(qt_me_plan *P)
+static qt_status capture_graph(qt_me_plan *P, int k = 0)
 {
-    if (P->gexec) return QT_OK;
-    hipStream_t s = P->ctx->stream;
-    const CsrLaunch L = csr_args(P);
-    QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < P->graph_steps; ++k) csr_launch_step(L, s);
-    hipError_t e = hipStreamEndCapture(s, &P->graph);
+    auto &l = P->lanes[k];
+    if (l.gexec) return QT_OK;
+    const CsrLaunch L = csr_args(P, k);
+    QT_HIP(hipStreamBeginCapture(l.stream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < P->graph_steps; ++j) csr_launch_step(L, l.stream);
+    hipError_t e = hipStreamEndCapture(l.stream, &l.graph);
     if (e) return set_error(QT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    QT_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+    QT_HIP(hipGraphInstantiate(&l.gexec, l.graph, nullptr, nullptr, 0));
     return QT_OK;
 }
 
@@ -466,41 +484,114 @@ qt_status me_plan_run(qt_me_plan *P)
     qt_status st = QT_OK;
     if (P->ncsr) {
         if ((st = restore_full(P))) return st;
-        const CsrLaunch L = csr_args(P);
+        const CsrLaunch L = csr_args(P, 0);
         auto *cc = L.ctls;
         csr_launch_reset(L.insts, L.ctls, P->ncsr, s);
         csr_launch_init(0, L, s);
         csr_launch_init(1, L, s);
         QT_HIP(hipGetLastError());
-        if ((st = capture_graph(P))) return st;
-        int replays = 1;
+        if ((st = capture_graph(P, 0))) return st;
         int64_t last_steps = -1;
+        std::vector<double> rem(P->ncsr, 0.0);  // steps still needed, from the current step size
         for (;;) {
-            for (int r = 0; r < replays; ++r) QT_HIP(hipGraphLaunch(P->gexec, s));
+            // one round: every live lane replays its graph on its own stream
+            for (auto &l : P->lanes) {
+                if (l.done) continue;
+                if (!l.e0) QT_HIP(hipEventCreate(&l.e0));
+                if (!l.e1) QT_HIP(hipEventCreate(&l.e1));
+                QT_HIP(hipEventRecord(l.e0, l.stream));
+                for (int r = 0; r < l.replays; ++r) QT_HIP(hipGraphLaunch(l.gexec, l.stream));
+                QT_HIP(hipEventRecord(l.e1, l.stream));
+            }
+            for (auto &l : P->lanes)
+                if (!l.done) QT_HIP(hipStreamSynchronize(l.stream));
             QT_HIP(hipMemcpyAsync(P->h_cctl, cc, sizeof(CsrCtl) * P->ncsr, hipMemcpyDeviceToHost, s));
             QT_HIP(hipStreamSynchronize(s));
-            // estimate the steps still needed from the slowest running problem
-            double need = 0.0;
-            int64_t steps = 0, live_blocks = 0;
-            std::vector<int32_t> live;
+            int64_t steps = 0;
             for (int32_t i = 0; i < P->ncsr; ++i) steps += P->h_cctl[i].n_steps;
             if (steps == last_steps) return set_error(QT_EDEVICE, "CSR solver made no progress in a graph replay");
             last_steps = steps;
             for (int32_t i = 0; i < P->ncsr; ++i) {
                 const CsrCtl &c = P->h_cctl[i];
-                if (c.status != ST_RUNNING) continue;
-                live.push_back(i);
-                live_blocks += P->h_ci[i].nblocks;
-                const double h = c.h > 0 ? c.h : 1e-6;
-                need = std::max(need, (P->csr_tend[i] - c.t) / h);
+                rem[i] = c.status == ST_RUNNING ? (P->csr_tend[i] - c.t) / (c.h > 0 ? c.h : 1e-6) : -1.0;
             }
-            if (live.empty()) break;
-            // drop finished problems from the launches once they hold half of the workgroups
-            if (P->ncsr > 1 && 2 * live_blocks <= P->nblk) {
-                if ((st = compact(P, live))) return st;
-                if ((st = capture_graph(P))) return st;
+            bool relayout = false, any = false;
+            const size_t nl = P->lanes.size();
+            for (size_t k = 0; k < nl; ++k) {
+                auto &l = P->lanes[k];
+                if (l.done) continue;
+                std::vector<int32_t> live;
+                int64_t live_blocks = 0;
+                for (int32_t i : l.members)
+                    if (rem[i] >= 0.0) {
+                        live.push_back(i);
+                        live_blocks += P->h_ci[i].nblocks;
+                    }
+                if (live.empty()) {
+                    l.done = true;
+                    relayout = true;
+                    continue;
+                }
+                any = true;
+                // Drop finished problems once they hold half of the lane's workgroups; at that point
+                // problems far behind the others (4x the median remaining steps) move to a lane of
+                // their own, so they no longer wait on the larger group's launches every step.
+                if (P->ncsr > 1 && 2 * live_blocks <= l.nblk) {
+                    std::vector<double> r;
+                    for (int32_t i : live) r.push_back(rem[i]);
+                    std::nth_element(r.begin(), r.begin() + r.size() / 2, r.end());
+                    const double med = r[r.size() / 2];
+                    std::vector<int32_t> slow, rest;
+                    for (int32_t i : live) (rem[i] >= 4.0 * med ? slow : rest).push_back(i);
+                    if (!slow.empty() && !rest.empty() && P->lanes.size() < 1 + MAX_EXTRA_LANES) {
+                        const size_t j = P->lanes.size() - 1;  // streams already made
+                        if (j >= P->lane_streams.size()) {
+                            hipStream_t ns;
+                            QT_HIP(hipStreamCreateWithFlags(&ns, hipStreamNonBlocking));
+                            P->lane_streams.push_back(ns);
+                        }
+                        qt_me_plan::Lane nlane;
+                        nlane.members = slow;
+                        nlane.listed = true;
+                        nlane.stream = P->lane_streams[j];
+                        P->lanes[k].members = rest;  // (reference l may move with the push_back)
+                        P->lanes[k].listed = true;
+                        P->lanes.push_back(nlane);
+                    } else {
+                        l.members = live;
+                        l.listed = true;
+                    }
+                    relayout = true;
+                }
             }
-            replays = (int)std::min(8.0, std::max(1.0, std::floor(need / P->graph_steps)));
+            if (!any) break;
+            if (relayout) {
+                P->split = true;
+                if ((st = layout_lanes(P))) return st;
+            }
+            // replays for the next round: each lane at most what it still needs; the slowest lane
+            // (by measured time per replay) up to 8, the others as many as fit in that round's time
+            std::vector<double> want(P->lanes.size(), 1.0), per(P->lanes.size(), 0.0);
+            double round_ms = 0.0;
+            for (size_t k = 0; k < P->lanes.size(); ++k) {
+                auto &l = P->lanes[k];
+                if (l.done) continue;
+                double need = 0.0;
+                for (int32_t i : l.members) need = std::max(need, rem[i]);
+                want[k] = std::max(1.0, std::floor(need / P->graph_steps));
+                float ms = 0.f;
+                if (l.e0 && l.e1 && hipEventElapsedTime(&ms, l.e0, l.e1) == hipSuccess && ms > 0.f)
+                    per[k] = (double)ms / std::max(1, l.replays);
+                if (per[k] > 0.0) round_ms = std::max(round_ms, std::min(8.0, want[k]) * per[k]);
+            }
+            for (size_t k = 0; k < P->lanes.size(); ++k) {
+                auto &l = P->lanes[k];
+                if (l.done) continue;
+                double r = std::min(8.0, want[k]);
+                if (per[k] > 0.0 && round_ms > 0.0) r = std::min({std::floor(round_ms / per[k]), want[k], 64.0});
+                l.replays = (int)std::max(1.0, r);
+                if ((st = capture_graph(P, (int)k))) return st;
+            }
         }
     }
     if (P->ndense) {
@@ -744,8 +835,12 @@ qt_status qt_me_plan_destroy(qt_me_plan *P)
 {
     if (!P) return QT_OK;
     (void)hipSetDevice(P->ctx->device);
-    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
-    if (P->graph) (void)hipGraphDestroy(P->graph);
+    for (auto &l : P->lanes) {
+        drop_graph(l);
+        if (l.e0) (void)hipEventDestroy(l.e0);
+        if (l.e1) (void)hipEventDestroy(l.e1);
+    }
+    for (hipStream_t ls : P->lane_streams) (void)hipStreamDestroy(ls);
     if (P->h_cctl) (void)hipHostFree(P->h_cctl);
     if (P->h_dctl) (void)hipHostFree(P->h_dctl);
     P->arena.release();

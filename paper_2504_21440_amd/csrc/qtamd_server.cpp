@@ -349,6 +349,7 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
         L.lpr = S->shape.lpr;
         L.rg = S->shape.rg;
         L.xcd = S->shape.xcd;
+        L.keep = S->shape.keep;
         QT_HIP(hipMemcpyAsync(S->d_ilist, csr_slots.data(), csr_slots.size() * 4, hipMemcpyHostToDevice, s));
         L.nblk = (int)bi.size();
         L.ninst = (int)csr_slots.size();  // the control launch visits the resident CSR slots only
@@ -485,6 +486,7 @@ qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **ou
     for (int i = ns - 1; i >= 0; --i) S->free_slots.push_back(i);
     // requests of many sizes share one grid: the shape for small spin and oscillator Liouvillians
     S->shape = csr_default_shape(0, 19.0);
+    S->shape.keep = 1;  // matrices read through the caches: many small resident ones fit the L2s / MALL
     ctx->refs++;
     S->counted = true;
     *out = S;
