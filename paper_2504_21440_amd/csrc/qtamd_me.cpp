@@ -231,8 +231,13 @@ static qt_status apply_shape(qt_me_plan *P, CsrShape sh)
     return reset_lanes(P);
 }
 
-// Back to the single full lane if a run left the problems split or dropped.
-static qt_status restore_full(qt_me_plan *P) { return P->split ? reset_lanes(P) : QT_OK; }
+// Back to the single full lane if a run left the problems split, dropped or finished.
+static qt_status restore_full(qt_me_plan *P)
+{
+    bool dirty = P->split;
+    for (const auto &l : P->lanes) dirty = dirty || l.done;
+    return dirty ? reset_lanes(P) : QT_OK;
+}
 
 qt_status me_plan_autotune(qt_me_plan *P, int32_t reps);
 
