@@ -235,6 +235,13 @@ qt_status qt_mc_plan_result(qt_mc_plan *plan, double *mean_out, double *se_out, 
                             double *jump_times, int32_t *jump_channels, qt_stats *stats);
 qt_status qt_mc_plan_destroy(qt_mc_plan *plan);
 
+/* Schrodinger equation (Sec. 3.1, sesolve): d psi/dt = -i H psi with the same adaptive
+ * Dormand-Prince 5(4) integrator, save-time landing and precision modes; expect_out [n_e][n_t]
+ * complex (host) holds <psi|O|psi> / <psi|psi> at every point of tlist.  psi0 (length d, host) is
+ * normalised before use.  Runs as a single trajectory without collapse operators, so d <= 4096. */
+qt_status qt_sesolve(qt_ctx *ctx, const qt_csr *H, const double *psi0, int32_t n_t, const double *tlist, int32_t n_e,
+                     const qt_csr *e_ops, const qt_opts *opts, double *expect_out, qt_stats *stats);
+
 /* Continuous-batching server.  Requests are admitted while their device footprint fits in the
  * pool and a slot is free; admitted requests keep rho and solver state resident and are advanced
  * together, epoch by epoch, with requests that arrived earlier.  submit returns QT_EBUSY when the

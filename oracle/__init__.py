@@ -249,6 +249,14 @@ def mcsolve(H, c_ops, psi0, tlist, e_ops, ntraj, seed, traj0=0, abstol=1e-8, rel
     return out
 
 
+def sesolve(H, psi0, tlist, e_ops, abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0):
+    """Schrodinger equation (Sec. 3.1, sesolve): d psi/dt = -i H psi, integrated by the same DP5
+    stepping as mcsolve; with no collapse operators no jump can happen, so one trajectory is the
+    solution.  Returns (expect [ne][nt], status)."""
+    out = mcsolve(H, [], psi0, tlist, e_ops, 1, 0, abstol=abstol, reltol=reltol, max_steps=max_steps, h0=h0)
+    return out["expect_tr"][0], int(out["status"][0])
+
+
 def ensemble_stats(expect_tr):
     lib = _load()
     ex = np.ascontiguousarray(expect_tr, dtype=np.complex128)

@@ -25,7 +25,7 @@ EXPORTED = [
     "qt_liouv_destroy", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
     "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_me_plan_autotune",
     "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
-    "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_server_create", "qt_server_submit", "qt_server_step",
+    "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_sesolve", "qt_server_create", "qt_server_submit", "qt_server_step",
     "qt_server_poll", "qt_server_footprint", "qt_server_destroy",
 ]
 
@@ -383,6 +383,19 @@ def mcsolve(ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, want_t
     _check(lib().qt_mcsolve(ctx.h, ctypes.byref(p.s), ctypes.byref(o), _p(mean), _p(se), _p(tr), _p(nj), mj,
                             _p(jt), _p(jc), ctypes.byref(st)))
     return _mc_pack(p, mean, se, tr, nj, mj, jt, jc, st)
+
+
+def sesolve(ctx, H, psi0, tlist, e_ops, options=None):
+    """qt_sesolve: (expect [n_e][n_t], stats) of the Schrodinger evolution of psi0 under H."""
+    p = _McProblem(H, [], psi0, tlist, e_ops, 1, 0)
+    ne, nt = len(e_ops), len(tlist)
+    ex = np.zeros((max(ne, 1), nt), np.complex128)
+    st = Stats()
+    o = options or opts(precision=F64)
+    vp = ctypes.c_void_p
+    _check(lib().qt_sesolve(ctx.h, vp(p.s.H), vp(p.s.psi0), ctypes.c_int32(p.s.n_t), vp(p.s.tlist),
+                            ctypes.c_int32(p.s.n_e), vp(p.s.e_ops), ctypes.byref(o), _p(ex), ctypes.byref(st)))
+    return ex[:ne], st.as_dict()
 
 
 class McPlan:

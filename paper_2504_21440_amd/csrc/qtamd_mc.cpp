@@ -319,4 +319,23 @@ qt_status qt_mcsolve(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts
     return st;
 }
 
+qt_status qt_sesolve(qt_ctx *ctx, const qt_csr *H, const double *psi0, int32_t n_t, const double *tlist, int32_t n_e,
+                     const qt_csr *e_ops, const qt_opts *opts, double *expect_out, qt_stats *stats)
+{
+    // the Schrodinger equation is the no-collapse case of the trajectory integrator: H_eff = H,
+    // the norm never falls below a threshold, one trajectory is the solution
+    qt_mc_problem p;
+    p.H = H;
+    p.n_c = 0;
+    p.c_ops = nullptr;
+    p.psi0 = psi0;
+    p.n_t = n_t;
+    p.tlist = tlist;
+    p.n_e = n_e;
+    p.e_ops = e_ops;
+    p.ntraj = 1;
+    p.seed = 0;
+    return qt_mcsolve(ctx, &p, opts, expect_out, nullptr, nullptr, nullptr, 0, nullptr, nullptr, stats);
+}
+
 }  // extern "C"

@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "qt_csr.h"
@@ -83,7 +85,25 @@ struct qt_me_plan {
 
 namespace qt {
 
-constexpr int MAX_EXTRA_LANES = 3;  // lanes split off a plan's CSR problems, each on its own stream
+// Lanes split off a plan's CSR problems, each on its own stream: QTAMD_MAX_LANES - 1 of them (at
+// most 7).  The default is no splitting: on the 512-cavity sweep a split at the first compaction
+// ran 15% slower than one compacted lane, because the remaining-step estimate (t_end - t) / h
+// misjudged which problems would finish last and the concurrent lanes slowed each other down.
+// Finished problems are dropped either way.  QTAMD_TRACE_LANES prints each round's lanes to stderr.
+static int max_extra_lanes()
+{
+    static const int v = [] {
+        const char *e = std::getenv("QTAMD_MAX_LANES");
+        const int n = e ? std::atoi(e) : 1;
+        return std::max(0, std::min(8, n) - 1);
+    }();
+    return v;
+}
+static bool trace_lanes()
+{
+    static const bool v = std::getenv("QTAMD_TRACE_LANES") != nullptr;
+    return v;
+}
 
 static size_t state_es(int32_t prec) { return prec == QT_F64 ? sizeof(double2) : sizeof(float2); }
 
@@ -231,12 +251,13 @@ static qt_status apply_shape(qt_me_plan *P, CsrShape sh)
     return reset_lanes(P);
 }
 
-// Back to the single full lane if a run left the problems split, dropped or finished.
+// Back to the single full lane if a run left the problems split or dropped; a lane that only
+// finished keeps its layout and graph.
 static qt_status restore_full(qt_me_plan *P)
 {
-    bool dirty = P->split;
-    for (const auto &l : P->lanes) dirty = dirty || l.done;
-    return dirty ? reset_lanes(P) : QT_OK;
+    if (P->split) return reset_lanes(P);
+    for (auto &l : P->lanes) l.done = false;
+    return QT_OK;
 }
 
 qt_status me_plan_autotune(qt_me_plan *P, int32_t reps);
@@ -512,6 +533,15 @@ qt_status me_plan_run(qt_me_plan *P)
                 if (!l.done) QT_HIP(hipStreamSynchronize(l.stream));
             QT_HIP(hipMemcpyAsync(P->h_cctl, cc, sizeof(CsrCtl) * P->ncsr, hipMemcpyDeviceToHost, s));
             QT_HIP(hipStreamSynchronize(s));
+            if (trace_lanes()) {
+                for (size_t k = 0; k < P->lanes.size(); ++k) {
+                    const auto &l = P->lanes[k];
+                    float ms = 0.f;
+                    if (!l.done) (void)hipEventElapsedTime(&ms, l.e0, l.e1);
+                    std::fprintf(stderr, "[lanes] lane %zu: %zu problems, %d blocks, %d replays, %.3f ms%s\n", k,
+                                 l.members.size(), l.nblk, l.replays, ms, l.done ? " (done)" : "");
+                }
+            }
             int64_t steps = 0;
             for (int32_t i = 0; i < P->ncsr; ++i) steps += P->h_cctl[i].n_steps;
             if (steps == last_steps) return set_error(QT_EDEVICE, "CSR solver made no progress in a graph replay");
@@ -548,7 +578,7 @@ qt_status me_plan_run(qt_me_plan *P)
                     const double med = r[r.size() / 2];
                     std::vector<int32_t> slow, rest;
                     for (int32_t i : live) (rem[i] >= 4.0 * med ? slow : rest).push_back(i);
-                    if (!slow.empty() && !rest.empty() && P->lanes.size() < 1 + MAX_EXTRA_LANES) {
+                    if (!slow.empty() && !rest.empty() && (int)P->lanes.size() < 1 + max_extra_lanes()) {
                         const size_t j = P->lanes.size() - 1;  // streams already made
                         if (j >= P->lane_streams.size()) {
                             hipStream_t ns;

@@ -129,3 +129,23 @@ def test_mc_error_paths(ctx):
     # single time point: the initial expectation only, no integration
     res = qt.mcsolve(ctx, H, cs, 3 * om.all_up_ket(3), np.array([0.5]), [_sz_sum(3)], 5, 1)
     assert np.allclose(res["mean"], 3.0) and (res["njumps"] == 0).all()
+
+
+@pytest.mark.parametrize("prec,tol", [(qt.F64, 1e-6), (qt.MIXED, 1e-4)])
+def test_sesolve_vs_oracle(ctx, prec, tol):
+    """Schrodinger evolution (no collapse operators) against the oracle's sesolve: an L=6 chain and
+    the L=10 chain of the trajectory workload (d = 1024), plus a random dense Hamiltonian."""
+    print(f"[gpu] sesolve prec={prec}", flush=True)
+    g = np.random.default_rng(31)
+    X = g.normal(size=(20, 20)) + 1j * g.normal(size=(20, 20))
+    cases = [(qt.model_ising(6, 1.0, 0.7, 0.2)[0], om.all_up_ket(6), [om.site_op(6, 2, om.sigmaz())]),
+             (qt.model_ising(10, 1.0, 1.0, 0.1)[0], om.all_up_ket(10), [om.site_op(10, 0, om.sigmaz())]),
+             (sp.csr_matrix(X + X.conj().T), g.normal(size=20) + 1j * g.normal(size=20),
+              [sp.csr_matrix(np.diag(np.arange(20.0)))])]
+    tl = np.linspace(0, 2, 11)
+    for H, psi0, e_ops in cases:
+        ref, status = oracle.sesolve(H, psi0, tl, e_ops)
+        assert status == 0
+        ex, st = qt.sesolve(ctx, H, psi0, tl, e_ops, options=qt.opts(precision=prec))
+        assert st["status"] == 0 and st["n_jumps"] == 0
+        assert np.abs(ex - ref).max() <= tol, np.abs(ex - ref).max()

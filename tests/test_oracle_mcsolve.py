@@ -1,5 +1,6 @@
 """Pins of the oracle's Monte-Carlo wave-function solver (Sec. 3.3) and of its Philox generator."""
 import numpy as np
+import pytest
 import scipy.sparse as sp
 import scipy.stats as ss
 
@@ -160,3 +161,47 @@ def test_ensemble_stats_definition():
             assert abs(se[k, t] - v ** 0.5) < 1e-14
     m1, s1 = oracle.ensemble_stats(ex[:1])
     assert np.all(s1 == 0) and np.allclose(m1, ex[0])
+
+
+def _expm_expect(H, psi0, tlist, e_ops):
+    import scipy.linalg as sl
+    Hd = H.toarray() if sp.issparse(H) else np.asarray(H)
+    psi0 = np.asarray(psi0, complex) / np.linalg.norm(psi0)
+    out = np.zeros((len(e_ops), len(tlist)), complex)
+    for n, t in enumerate(tlist):
+        psi = sl.expm(-1j * Hd * t) @ psi0
+        for k, O in enumerate(e_ops):
+            Od = O.toarray() if sp.issparse(O) else np.asarray(O)
+            out[k, n] = np.vdot(psi, Od @ psi)
+    return out
+
+
+@pytest.mark.parametrize("case", ["random6", "ising3"])
+def test_sesolve_matches_matrix_exponential(case):
+    """sesolve against psi(t) = expm(-i H t) psi0 (scipy), at tight tolerances."""
+    g = np.random.default_rng(23)
+    if case == "random6":
+        X = g.normal(size=(6, 6)) + 1j * g.normal(size=(6, 6))
+        H = sp.csr_matrix(X + X.conj().T)
+        psi0 = g.normal(size=6) + 1j * g.normal(size=6)
+        e_ops = [sp.csr_matrix(np.diag(np.arange(6.0))), sp.csr_matrix(g.normal(size=(6, 6)))]
+    else:
+        H, _ = om.ising(3, 1.0, 0.7, 0.2)
+        psi0 = om.all_up_ket(3)
+        e_ops = [om.site_op(3, 0, om.sigmaz()), om.site_op(3, 1, om.sigmax())]
+    tl = np.linspace(0, 3, 16)
+    ex, status = oracle.sesolve(H, psi0, tl, e_ops, abstol=1e-12, reltol=1e-10)
+    assert status == 0
+    assert np.abs(ex - _expm_expect(H, psi0, tl, e_ops)).max() < 1e-8
+
+
+def test_sesolve_conserves_energy_and_norm_of_expectations():
+    """<H> is a constant of the motion; an unnormalised psi0 gives the same expectations."""
+    H, _ = om.ising(4, 1.0, 0.9, 0.2)
+    g = np.random.default_rng(3)
+    psi0 = g.normal(size=16) + 1j * g.normal(size=16)
+    tl = np.linspace(0, 4, 9)
+    ex, _ = oracle.sesolve(H, psi0, tl, [H], abstol=1e-12, reltol=1e-10)
+    assert np.abs(ex[0] - ex[0, 0]).max() < 1e-8
+    ex2, _ = oracle.sesolve(H, 3.0 * psi0, tl, [H], abstol=1e-12, reltol=1e-10)
+    assert np.abs(ex2 - ex).max() < 1e-9
