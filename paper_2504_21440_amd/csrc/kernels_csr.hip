@@ -460,6 +460,7 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
     if constexpr (FORM == 1 || FORM == 2) {                                                          \
         BODY<__VA_ARGS__, FORM == 2>(one, ctls, lb * CsrGeom<LPR, RG>::RPB, lb);                     \
     } else {                                                                                         \
+        if (bound && lb >= bound[0]) return; /* grid sized for a capacity, table filled less */     \
         const int ii = bi[lb], row0 = br[lb];                                                        \
         BODY<__VA_ARGS__, FORM == 3>(insts[ii], ctls + ii, row0, row0 / CsrGeom<LPR, RG>::RPB);     \
     }
@@ -468,7 +469,8 @@ template <typename T, int LPR, int RG, int FORM>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init0(const CsrInst *__restrict__ insts, const CsrInst one,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ bi,
-                                                           const int32_t *__restrict__ br, int xcd)
+                                                           const int32_t *__restrict__ br, int xcd,
+                                                           const int32_t *__restrict__ bound)
 {
     QT_CSR_DISPATCH(init0_body, T, LPR, RG)
 }
@@ -477,7 +479,8 @@ template <typename T, int LPR, int RG, int FORM>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_init1(const CsrInst *__restrict__ insts, const CsrInst one,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ bi,
-                                                           const int32_t *__restrict__ br, int xcd)
+                                                           const int32_t *__restrict__ br, int xcd,
+                                                           const int32_t *__restrict__ bound)
 {
     QT_CSR_DISPATCH(init1_body, T, LPR, RG)
 }
@@ -486,7 +489,8 @@ template <typename T, int LPR, int RG, int FORM, int S>
 __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__restrict__ insts, const CsrInst one,
                                                            const CsrCtl *__restrict__ ctls,
                                                            const int32_t *__restrict__ bi,
-                                                           const int32_t *__restrict__ br, int xcd)
+                                                           const int32_t *__restrict__ br, int xcd,
+                                                           const int32_t *__restrict__ bound)
 {
     QT_CSR_DISPATCH(stage_body, T, LPR, RG, S)
 }
@@ -620,15 +624,18 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
     }
 }
 
-// ilist: the problems to visit (one workgroup each), or null for problems 0 .. gridDim.x - 1.
+// ilist: the problems to visit (one workgroup each), or null for problems 0 .. gridDim.x - 1;
+// ibound: when given, only the first ibound[0] entries of ilist are live.
 template <typename T, bool ONE>
 __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__restrict__ insts, const CsrInst one,
                                                              CsrCtl *__restrict__ ctls, int step_mode,
-                                                             const int32_t *__restrict__ ilist)
+                                                             const int32_t *__restrict__ ilist,
+                                                             const int32_t *__restrict__ ibound)
 {
     if constexpr (ONE) {
         control_body<T>(one, ctls, step_mode);
     } else {
+        if (ibound && (int)blockIdx.x >= ibound[0]) return;
         const int ii = ilist ? ilist[blockIdx.x] : (int)blockIdx.x;
         control_body<T>(insts[ii], ctls + ii, step_mode);
     }
@@ -702,7 +709,7 @@ struct CsrArgs {
     bool use_one;
     int form;  // kernel FORM: 0 block table, 1 one problem; 2 / 3: as 1 / 0 with temporal matrix loads
     CsrCtl *ctls;
-    const int32_t *bi, *br, *ilist;
+    const int32_t *bi, *br, *ilist, *bound, *ibound;
     int nblk, ninst, xcd;
     hipStream_t s;
 };
@@ -719,6 +726,8 @@ static CsrArgs make_args(const CsrLaunch &L, hipStream_t s)
     a.bi = L.bi;
     a.br = L.br;
     a.ilist = L.ilist;
+    a.bound = L.bound;
+    a.ibound = L.ibound;
     a.nblk = L.nblk;
     a.ninst = L.ninst;
     a.xcd = L.xcd;
@@ -731,42 +740,42 @@ static void launch_control(const CsrArgs &a, int step_mode)
 {
     if (a.use_one)
         hipLaunchKernelGGL((k_csr_control<T, true>), dim3(1), dim3(CTL_THREADS), 0, a.s, a.insts, a.one, a.ctls,
-                           step_mode, (const int32_t *)nullptr);
+                           step_mode, (const int32_t *)nullptr, (const int32_t *)nullptr);
     else
         hipLaunchKernelGGL((k_csr_control<T, false>), dim3(a.ninst), dim3(CTL_THREADS), 0, a.s, a.insts, a.one,
-                           a.ctls, step_mode, a.ilist);
+                           a.ctls, step_mode, a.ilist, a.ibound);
 }
 
 #define QT_LAUNCH(KERNEL, a)                                                                                  \
     do {                                                                                                      \
         if ((a).form == 3)                                                                                    \
             hipLaunchKernelGGL((KERNEL<T, LPR, RG, 3>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
-                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                       \
         else if ((a).form == 2)                                                                               \
             hipLaunchKernelGGL((KERNEL<T, LPR, RG, 2>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
-                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                       \
         else if ((a).form == 1)                                                                               \
             hipLaunchKernelGGL((KERNEL<T, LPR, RG, 1>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
-                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                       \
         else                                                                                                  \
             hipLaunchKernelGGL((KERNEL<T, LPR, RG, 0>), dim3((a).nblk), dim3(CSR_THREADS), 0, (a).s,         \
-                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                       \
+                               (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                       \
     } while (0)
 
 #define QT_LAUNCH_STAGE(SV, a)                                                                                \
     do {                                                                                                      \
         if ((a).form == 3)                                                                                    \
             hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 3, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
-                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                \
         else if ((a).form == 2)                                                                               \
             hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 2, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
-                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                \
         else if ((a).form == 1)                                                                               \
             hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 1, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
-                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                \
         else                                                                                                  \
             hipLaunchKernelGGL((k_csr_stage<T, LPR, RG, 0, SV>), dim3((a).nblk), dim3(CSR_THREADS), 0,       \
-                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd);                \
+                               (a).s, (a).insts, (a).one, (a).ctls, (a).bi, (a).br, (a).xcd, (a).bound);                \
     } while (0)
 
 template <typename T, int LPR, int RG>

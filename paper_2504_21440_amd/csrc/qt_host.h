@@ -99,6 +99,10 @@ struct CsrLaunch {
     CsrCtl *ctls = nullptr;
     const int32_t *bi = nullptr, *br = nullptr;  // block table: problem, first row
     const int32_t *ilist = nullptr;              // problems the control launch visits (null: 0..ninst-1)
+    // Device-side fill of a table sized for a capacity (null: nblk / ninst are exact): blocks at or
+    // past bound[0] and control workgroups at or past ibound[0] return at once, so a graph captured
+    // for the capacity stays valid while the table contents change.
+    const int32_t *bound = nullptr, *ibound = nullptr;
     const CsrInst *one_host = nullptr;           // host copy of the descriptor when ninst == 1
 };
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s);

@@ -100,7 +100,13 @@ struct qt_server {
     qt::DenseInst *d_dinst = nullptr;
     qt::DenseCtl *d_dctl = nullptr;
     int32_t *d_bi = nullptr, *d_br = nullptr, *d_order = nullptr, *d_ilist = nullptr;
+    int32_t *d_counts = nullptr;    // [0] live blocks of the table, [1] live entries of the control list
+    int32_t h_counts[2] = {0, 0};
     size_t blk_cap = 0;
+    // The CSR part of an epoch (starting-step evaluations, then steps_per_epoch steps) is one graph
+    // captured for the table's capacity; the table contents and their counts change every epoch.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     qt::CsrCtl *h_cctl = nullptr;   // pinned
     qt::DenseCtl *h_dctl = nullptr; // pinned
     std::vector<int32_t> free_slots;
@@ -336,31 +342,47 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
     }
     if (!bi.empty()) {
         if (bi.size() > S->blk_cap) {
+            if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+            if (S->graph) (void)hipGraphDestroy(S->graph);
+            S->gexec = nullptr;
+            S->graph = nullptr;
             if (S->d_bi) (void)hipFree(S->d_bi);
             if (S->d_br) (void)hipFree(S->d_br);
             S->blk_cap = bi.size() * 2;
             QT_HIP(hipMalloc(&S->d_bi, S->blk_cap * 4));
             QT_HIP(hipMalloc(&S->d_br, S->blk_cap * 4));
         }
+        S->h_counts[0] = (int32_t)bi.size();
+        S->h_counts[1] = (int32_t)csr_slots.size();
         QT_HIP(hipMemcpyAsync(S->d_bi, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
         QT_HIP(hipMemcpyAsync(S->d_br, br.data(), br.size() * 4, hipMemcpyHostToDevice, s));
-        CsrLaunch L;
-        L.f64 = f64;
-        L.lpr = S->shape.lpr;
-        L.rg = S->shape.rg;
-        L.xcd = S->shape.xcd;
-        L.keep = S->shape.keep;
         QT_HIP(hipMemcpyAsync(S->d_ilist, csr_slots.data(), csr_slots.size() * 4, hipMemcpyHostToDevice, s));
-        L.nblk = (int)bi.size();
-        L.ninst = (int)csr_slots.size();  // the control launch visits the resident CSR slots only
-        L.ilist = S->d_ilist;
-        L.insts = S->d_cinst;
-        L.ctls = S->d_cctl;
-        L.bi = S->d_bi;
-        L.br = S->d_br;
-        csr_launch_init(0, L, s);
-        csr_launch_init(1, L, s);
-        for (int k = 0; k < K; ++k) csr_launch_step(L, s);
+        QT_HIP(hipMemcpyAsync(S->d_counts, S->h_counts, sizeof(S->h_counts), hipMemcpyHostToDevice, s));
+        if (!S->gexec) {
+            CsrLaunch L;
+            L.f64 = f64;
+            L.lpr = S->shape.lpr;
+            L.rg = S->shape.rg;
+            L.xcd = 0;
+            L.keep = S->shape.keep;
+            L.nblk = (int)S->blk_cap;         // capacity; blocks past the live count return at once
+            L.ninst = S->cfg.max_slots;       // likewise for the control list
+            L.ilist = S->d_ilist;
+            L.bound = S->d_counts;
+            L.ibound = S->d_counts + 1;
+            L.insts = S->d_cinst;
+            L.ctls = S->d_cctl;
+            L.bi = S->d_bi;
+            L.br = S->d_br;
+            QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            csr_launch_init(0, L, s);
+            csr_launch_init(1, L, s);
+            for (int k = 0; k < K; ++k) csr_launch_step(L, s);
+            hipError_t ce = hipStreamEndCapture(s, &S->graph);
+            if (ce) return set_error(QT_EDEVICE, std::string("server graph capture: ") + hipGetErrorString(ce));
+            QT_HIP(hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0));
+        }
+        QT_HIP(hipGraphLaunch(S->gexec, s));
         QT_HIP(hipGetLastError());
     }
     // ---- dense slots: one budgeted launch per padded size, on the auxiliary streams ----
@@ -464,6 +486,7 @@ qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **ou
     if (e == hipSuccess) e = hipMalloc(&S->d_dctl, sizeof(DenseCtl) * ns);
     if (e == hipSuccess) e = hipMalloc(&S->d_order, sizeof(int32_t) * ns);
     if (e == hipSuccess) e = hipMalloc(&S->d_ilist, sizeof(int32_t) * ns);
+    if (e == hipSuccess) e = hipMalloc(&S->d_counts, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_cctl, sizeof(CsrCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_dctl, sizeof(DenseCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) {
@@ -546,6 +569,9 @@ qt_status qt_server_destroy(qt_server *S)
     if (S->d_dctl) (void)hipFree(S->d_dctl);
     if (S->d_order) (void)hipFree(S->d_order);
     if (S->d_ilist) (void)hipFree(S->d_ilist);
+    if (S->d_counts) (void)hipFree(S->d_counts);
+    if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+    if (S->graph) (void)hipGraphDestroy(S->graph);
     if (S->d_bi) (void)hipFree(S->d_bi);
     if (S->d_br) (void)hipFree(S->d_br);
     if (S->h_cctl) (void)hipHostFree(S->h_cctl);
