@@ -197,10 +197,10 @@ def section_sweep(ctx, n=512, nmax_dense=80):
         rho0[0, 0] = 1
         num = np.diag(np.arange(p["N"], dtype=float)).astype(complex)
         probs.append((Lo, rho0, workloads.tlist(p["t_end"], p["nt"]), [num]))
-    # untimed set-up: the autotuner picks the waves per tile row for each padded size
+    # untimed set-up: the autotuner picks the waves per workgroup for each padded size
     o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED, autotune=True)
     plan = qt.MePlan(ctx, probs, o)
-    wpr = plan.shape()[4]
+    waves = plan.shape()[4]
     plan.run()
     t0 = time.perf_counter()
     plan.run()
@@ -220,7 +220,7 @@ def section_sweep(ctx, n=512, nmax_dense=80):
         kern_ms = plan.time_rhs(reps=1)  # every dense bucket, one after another on one stream
         out.update({"dense_kernel_ms": kern_ms, "algorithmic_TFLOPs": flops / (kern_ms * 1e-3) / 1e12,
                     "frac_of_fp32_matrix_peak": flops / (kern_ms * 1e-3) / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
-                    "dense_waves_per_row_largest_bucket": wpr})
+                    "dense_waves_largest_bucket": waves})
     else:
         out["csr_shape"] = list(plan.shape()[:4])
     plan.close()

@@ -175,17 +175,20 @@ qt_status qt_me_plan_time_rhs(qt_me_plan *plan, int32_t reps, double *ms_per_lau
  *   cached_matrix   1: the matrix is read through the caches (temporal loads), so a matrix that
  *                   fits the L2s can stay there across launches; 0: it is streamed past them.
  * xcd_order applies to plans with one CSR problem (a plan with several uses 0).
- * The dense kernel takes 1 or 2 waves per 16-row tile row.  qt_me_plan_autotune times the fused
- * SpMV-stage kernel of the plan's CSR problems for every candidate shape over `reps` launches (20
- * if reps <= 0), and each dense size bucket for its allowed waves-per-row choices over a budget of
- * 8 steps; the fastest are kept for the plan and stored in a process-wide table keyed by precision
+ * The dense kernel is built with a few wave counts per workgroup for each padded size (for FP32:
+ * 1-2 at 16, 2 or 4 at 32, 3, 4, 6 or 8 at 48, 4 or 8 at 64, 4, 5 or 8 at 80; for FP64: 1 at 16,
+ * 2 or 4 at 32, 3 or 4 at 48); the waves split the output tiles into near-equal contiguous runs.
+ * qt_me_plan_autotune times the fused SpMV-stage kernel of the plan's CSR problems for every
+ * candidate shape over `reps` launches (20 if reps <= 0), and each dense size bucket for each of
+ * its wave counts over a budget of 8 steps; the fastest are kept for the plan and stored in a process-wide table keyed by precision
  * and size bucket (log2 of the rows and mean row length for CSR, padded dimension for dense),
  * which every later plan consults.  The plan's results are unspecified afterwards until the next
  * qt_me_plan_run.  qt_me_plan_shape reports the shape in use (zeros for a group the plan does not
  * have); qt_me_plan_set_shape imposes a CSR shape (QT_EINVAL if the kernels do not support it).
  * One shape serves every CSR problem of a plan; the row-sum and norm reduction orders follow
  * lanes_per_row and rows_per_group only, so a problem's results are bitwise the same alone and in
- * a batch, and with either xcd_order or cached_matrix, when those two are the same. */
+ * a batch, and with either xcd_order or cached_matrix, when those two are the same.  The dense
+ * kernel's norms are block reductions whose order follows the wave count. */
 typedef struct {
     int32_t lanes_per_row;
     int32_t rows_per_group;
@@ -194,7 +197,8 @@ typedef struct {
 } qt_csr_shape;
 qt_status qt_me_plan_autotune(qt_me_plan *plan, int32_t reps);
 qt_status qt_me_plan_set_shape(qt_me_plan *plan, const qt_csr_shape *shape);
-qt_status qt_me_plan_shape(const qt_me_plan *plan, qt_csr_shape *csr, int32_t *dense_waves_per_row);
+/* dense_waves: the wave count of the largest dense size bucket (0 without dense problems) */
+qt_status qt_me_plan_shape(const qt_me_plan *plan, qt_csr_shape *csr, int32_t *dense_waves);
 /* Persist the tuning table as a small JSON object {"key": [shape...], ...}.  load merges the
  * entries of a file written by save, ignoring any shape the kernels do not support. */
 qt_status qt_tune_save(const char *path);

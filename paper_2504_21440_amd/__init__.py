@@ -294,8 +294,8 @@ class MePlan:
         _check(lib().qt_me_plan_set_shape(self.h, ctypes.byref(sh)))
 
     def shape(self):
-        """(lanes per row, rows per lane group, XCD block order, cached matrix, dense waves per row)
-        in use (qt_me_plan_shape)."""
+        """(lanes per row, rows per lane group, XCD block order, cached matrix, dense waves per
+        workgroup of the largest padded size) in use (qt_me_plan_shape)."""
         sh, w = CsrShape(), ctypes.c_int32()
         _check(lib().qt_me_plan_shape(self.h, ctypes.byref(sh), ctypes.byref(w)))
         return sh.lanes_per_row, sh.rows_per_group, sh.xcd_order, sh.cached_matrix, w.value

@@ -8,9 +8,9 @@
 // (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64): Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
 //
 // One workgroup owns one problem for the whole launch and runs the adaptive Dormand-Prince 5(4)
-// loop itself.  Wave w owns output tile row I = w / WPR (16 rows) and every WPR-th tile of it; it
-// loads its 16 operator rows from L2 once per product into registers (all loads in flight at
-// once), so the inner MFMA loop reads only LDS.  LDS holds two NP x (NP+1) planar (re, im)
+// loop itself.  Wave w owns a contiguous run of output tiles (row-major tile order, near-equal runs
+// per wave); for each tile row its run touches it loads the 16 operator rows from L2 into
+// registers (all loads in flight at once), so the inner MFMA loop reads only LDS.  LDS holds two NP x (NP+1) planar (re, im)
 // matrices: B0 = the stage input rho_s, B1 = scratch for X_k and then M.  The odd row stride keeps
 // the transposed walks conflict-free.  Runge-Kutta stages of the elements a lane owns live in a
 // per-problem global buffer in tile order (contiguous per-lane accesses); the epilogue of each
@@ -52,14 +52,21 @@ template <typename T> __device__ __forceinline__ int mrow(int k4, int v)
     return sizeof(T) == 8 ? k4 + 4 * v : 4 * k4 + v;
 }
 
-template <typename T, int NP, int WPR> struct DenseGeom {
+// Work split: the NT x NT output tiles, in row-major order, are cut into WV contiguous chunks of
+// near-equal size, one per wave, so the matrix-core work spreads evenly over the 4 SIMDs of the CU
+// (with one wave per 16-row tile row, NP = 80 would put 2 of its 5 waves, 40% of the work, on one
+// SIMD).  A wave reloads its operator fragments only when its chunk crosses into the next tile row.
+template <typename T, int NP, int WV> struct DenseGeom {
     static constexpr int S = NP + 1;                   // LDS row stride
     static constexpr int NT = NP / 16;                 // tiles per side
-    static constexpr int WAVES = NT * WPR;             // wave w owns tile row w / WPR
-    static constexpr int MAXJ = (NT + WPR - 1) / WPR;  // tiles per wave (upper bound)
-    static constexpr int KF = NP / 4;                  // operator fragments per lane
+    static constexpr int TILES = NT * NT;
+    static constexpr int WAVES = WV;
+    static constexpr int MAXJ = (TILES + WV - 1) / WV;  // tiles per wave (upper bound)
+    static constexpr int KF = NP / 4;                   // operator fragments per lane
     static constexpr int PLANE = NP * S;
     static constexpr size_t LDS_BYTES = (size_t)6 * PLANE * sizeof(T);  // B0, B1, B2 (re, im)
+    // first tile of wave w's chunk (the chunk of w ends where that of w + 1 starts)
+    static __device__ __forceinline__ int chunk0(int w) { return (w * TILES) / WV; }
 };
 
 // acc += a * b on the matrix cores, complex a = (ar, ai), b = (br, bi).
@@ -82,8 +89,8 @@ __device__ __forceinline__ void load_frag(const typename vec2<T>::type *__restri
     for (int f = 0; f < NP / 4; ++f) frag[f] = row[4 * f];
 }
 
-template <typename T, int NP, int WPR> struct DenseRhs {
-    using G = DenseGeom<T, NP, WPR>;
+template <typename T, int NP, int WV> struct DenseRhs {
+    using G = DenseGeom<T, NP, WV>;
     using V = typename vec2<T>::type;
     using Acc = typename Mfma<T>::acc;
     static constexpr int S = G::S;
@@ -123,14 +130,14 @@ template <typename T, int NP, int WPR> struct DenseRhs {
     }
 
     // Evaluates L(B0) and calls epi(q, v, value) for every element this lane owns (tile q of the
-    // wave's tile row, accumulator slot v).  B1 holds C_k B0, B2 holds A B0.  With several collapse
+    // wave's chunk, accumulator slot v).  B1 holds C_k B0, B2 holds A B0.  With several collapse
     // channels the running sum Z is kept per element in zbuf (tile order, global).
     template <typename Epi>
     static __device__ __forceinline__ void eval(const V *__restrict__ ops, int nc, T *lds, V *__restrict__ zbuf,
                                                 Epi &&epi)
     {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int I = w / WPR, j0 = w % WPR;
+        const int t0 = G::chunk0(w), nq = G::chunk0(w + 1) - t0;
         const int r16 = lane & 15, k4 = lane >> 4;
         T *B0re = lds, *B0im = lds + G::PLANE, *B1re = lds + 2 * G::PLANE, *B1im = lds + 3 * G::PLANE;
         T *B2re = lds + 4 * G::PLANE, *B2im = lds + 5 * G::PLANE;
@@ -154,24 +161,34 @@ template <typename T, int NP, int WPR> struct DenseRhs {
             }
         }
         __syncthreads();
+        V frag[G::KF];
         for (int k = 0; k < kmax; ++k) {
             if (k == 0) {
                 // M = A B0 -> B2
-                V frag[G::KF];
-                load_frag<T, NP>(ops, I, lane, frag);
+                int Icur = -1;
 #pragma unroll 1
-                for (int J = j0; J < G::NT; J += WPR) {
+                for (int q = 0; q < nq; ++q) {
+                    const int t = t0 + q, I = t / G::NT, J = t % G::NT;
+                    if (I != Icur) {
+                        load_frag<T, NP>(ops, I, lane, frag);
+                        Icur = I;
+                    }
                     Acc mR = {0, 0, 0, 0}, mI = {0, 0, 0, 0};
                     tile_mm(frag, B0re, B0im, J, lane, mR, mI);
                     tile_store(B2re, B2im, I, J, lane, mR, mI);
                 }
             }
-            V frag[G::KF];
+            const V *Ck = ops + (1 + k) * mat;
+            int Icur = -1;
             if (nc > 0) {
                 // X = C_k B0 -> B1
-                load_frag<T, NP>(ops + (1 + k) * mat, I, lane, frag);
 #pragma unroll 1
-                for (int J = j0; J < G::NT; J += WPR) {
+                for (int q = 0; q < nq; ++q) {
+                    const int t = t0 + q, I = t / G::NT, J = t % G::NT;
+                    if (I != Icur) {
+                        load_frag<T, NP>(Ck, I, lane, frag);
+                        Icur = I;
+                    }
                     Acc xR = {0, 0, 0, 0}, xI = {0, 0, 0, 0};
                     tile_mm(frag, B0re, B0im, J, lane, xR, xI);
                     tile_store(B1re, B1im, I, J, lane, xR, xI);
@@ -179,10 +196,17 @@ template <typename T, int NP, int WPR> struct DenseRhs {
             }
             __syncthreads();
 #pragma unroll 1
-            for (int J = j0, q = 0; J < G::NT; J += WPR, ++q) {
+            for (int q = 0; q < nq; ++q) {
+                const int t = t0 + q, I = t / G::NT, J = t % G::NT;
                 Acc zR = {0, 0, 0, 0}, zI = {0, 0, 0, 0};
-                if (nc > 0) tile_mm_dag(frag, B1re, B1im, J, lane, zR, zI);  // Z_k = C_k X_k^dag
-                const size_t zb = ((size_t)(I * G::NT + J) * 64 + lane) * 4;
+                if (nc > 0) {
+                    if (I != Icur) {
+                        load_frag<T, NP>(Ck, I, lane, frag);
+                        Icur = I;
+                    }
+                    tile_mm_dag(frag, B1re, B1im, J, lane, zR, zI);  // Z_k = C_k X_k^dag
+                }
+                const size_t zb = ((size_t)t * 64 + lane) * 4;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     V z;
@@ -208,15 +232,15 @@ template <typename T, int NP, int WPR> struct DenseRhs {
 // Element index of (tile t, lane, v) in the tile-ordered global vectors.
 __device__ __forceinline__ size_t tix(int t, int lane, int v) { return ((size_t)t * 64 + lane) * 4 + v; }
 
-template <typename T, int NP, int WPR>
-__global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const DenseInst *__restrict__ insts,
+template <typename T, int NP, int WV>
+__global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__restrict__ insts,
                                                                       DenseCtl *__restrict__ ctls,
                                                                       const int32_t *__restrict__ order,
                                                                       int max_steps_launch, int reset)
 {
-    using G = DenseGeom<T, NP, WPR>;
+    using G = DenseGeom<T, NP, WV>;
     using V = typename vec2<T>::type;
-    using R = DenseRhs<T, NP, WPR>;
+    using R = DenseRhs<T, NP, WV>;
     constexpr int S = G::S;
     extern __shared__ char smem[];
     T *lds = (T *)smem;
@@ -228,7 +252,7 @@ __global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const Dens
     DenseCtl *C = ctls + ii;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r16 = lane & 15, k4 = lane >> 4;
-    const int Iw = w / WPR, j0 = w % WPR;  // this wave's tile row and first tile column
+    const int t0 = G::chunk0(w), nq = G::chunk0(w + 1) - t0;  // this wave's tiles: t0 .. t0 + nq - 1
     const int d = I.d;
     const size_t nvec = (size_t)NP * NP;
     V *vec = (V *)I.vec;
@@ -240,9 +264,9 @@ __global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const Dens
     const double nd = (double)d * d;
 
     // element (q, v) of this lane: tile-order index and (row, column)
-    auto eidx = [&](int q, int v) { return tix(Iw * G::NT + j0 + q * WPR, lane, v); };
-    auto erow = [&](int v) { return Iw * 16 + mrow<T>(k4, v); };
-    auto ecol = [&](int q) { return (j0 + q * WPR) * 16 + r16; };
+    auto eidx = [&](int q, int v) { return tix(t0 + q, lane, v); };
+    auto erow = [&](int q, int v) { return ((t0 + q) / G::NT) * 16 + mrow<T>(k4, v); };
+    auto ecol = [&](int q) { return ((t0 + q) % G::NT) * 16 + r16; };
     auto record_expect = [&](int idx, double sc) {
         for (int k = 0; k < I.ne; ++k) {
             const int32_t *ep = I.eptr + (size_t)k * (d + 1);
@@ -274,9 +298,9 @@ __global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const Dens
         // ---- initial state into B0 (planar, zero padded) and Y[0] (tile order) ----
         const V *r0 = (const V *)I.rho0;
         for (int q = 0; q < G::MAXJ; ++q) {
-            if (j0 + q * WPR >= G::NT) break;
+            if (q >= nq) break;
             for (int v = 0; v < 4; ++v) {
-                const int i = erow(v), j = ecol(q);
+                const int i = erow(q, v), j = ecol(q);
                 V y;
                 y.x = 0;
                 y.y = 0;
@@ -320,10 +344,10 @@ __global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const Dens
             } else {
                 const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
                 for (int q = 0; q < G::MAXJ; ++q) {
-                    if (j0 + q * WPR >= G::NT) break;
+                    if (q >= nq) break;
                     for (int v = 0; v < 4; ++v) {
                         const size_t e = eidx(q, v);
-                        const int i = erow(v), j = ecol(q);
+                        const int i = erow(q, v), j = ecol(q);
                         V y = Yb[0][e];
                         caxpy(y, (T)h0, Kb[0][e]);
                         B0re[i * S + j] = y.x;
@@ -373,10 +397,10 @@ __global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const Dens
         // stage-2 input: y + h a21 k1
         __syncthreads();
         for (int q = 0; q < G::MAXJ; ++q) {
-            if (j0 + q * WPR >= G::NT) break;
+            if (q >= nq) break;
             for (int v = 0; v < 4; ++v) {
                 const size_t e = eidx(q, v);
-                const int i = erow(v), j = ecol(q);
+                const int i = erow(q, v), j = ecol(q);
                 V x = cscale(y[e], sc);
                 caxpy(x, (T)(ht * DP5::a21), cscale(k1[e], sc));
                 B0re[i * S + j] = x.x;
@@ -433,7 +457,7 @@ __global__ __launch_bounds__((NP / 16) * WPR * 64) void k_dense_solve(const Dens
                     e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
                 }
                 if (s < 7) {
-                    const int i = erow(v), j = ecol(q);
+                    const int i = erow(q, v), j = ecol(q);
                     B0re[i * S + j] = o.x;
                     B0im[i * S + j] = o.y;
                 }
@@ -522,18 +546,51 @@ void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *op
     g->expect = expect;
 }
 
-int dense_choose_config(int d, int prec)
+// Wave counts built per padded size.  With one wave per tile row a size whose tile-row count is not
+// a multiple of 4 loads the SIMDs unevenly; the other counts split the tiles evenly (np = 48: 9
+// tiles; np = 80: 25 tiles) at one or two waves per SIMD.  FP64 keeps to the small counts (its
+// fragments take twice the registers).
+static int waves_built(int np, int prec, const int **list)
 {
-    // waves per 16-row tile row of the output: the autotuner's measured choice for this padded
-    // size, else two where the registers allow it (more waves in flight per CU) and one for the
-    // largest padded sizes and for FP64
-    const int np = dense_np(d);
-    int wpr;
-    if (tune_lookup_dense(dense_tune_key(prec, np), &wpr) && dense_wpr_allowed(np, prec, wpr)) return wpr;
-    return dense_default_wpr(np, prec);
+    static const int f16[] = {1, 2}, f32[] = {2, 4}, f48[] = {3, 4, 6, 8}, f64s[] = {4, 8}, f80[] = {4, 5, 8};
+    static const int d16[] = {1}, d32[] = {2, 4}, d48[] = {3, 4};
+    const bool dbl = prec == QT_F64;
+    switch (np) {
+    case 16: *list = dbl ? d16 : f16; return dbl ? 1 : 2;
+    case 32: *list = dbl ? d32 : f32; return 2;
+    case 48: *list = dbl ? d48 : f48; return dbl ? 2 : 4;
+    case 64: *list = f64s; return dbl ? 0 : 2;
+    case 80: *list = f80; return dbl ? 0 : 3;
+    default: *list = nullptr; return 0;
+    }
 }
 
-bool dense_wpr_allowed(int np, int prec, int wpr) { return wpr == 1 || (wpr == 2 && prec != QT_F64 && np <= 64); }
+int dense_waves_candidates(int np, int prec, int *out, int max)
+{
+    const int *l;
+    const int n = waves_built(np, prec, &l);
+    int k = 0;
+    for (int i = 0; i < n && k < max; ++i) out[k++] = l[i];
+    return k;
+}
+
+bool dense_waves_allowed(int np, int prec, int waves)
+{
+    const int *l;
+    const int n = waves_built(np, prec, &l);
+    for (int i = 0; i < n; ++i)
+        if (l[i] == waves) return true;
+    return false;
+}
+
+int dense_choose_config(int d, int prec)
+{
+    // waves per workgroup: the autotuner's measured choice for this padded size, else the default
+    const int np = dense_np(d);
+    int waves;
+    if (tune_lookup_dense(dense_tune_key(prec, np), &waves) && dense_waves_allowed(np, prec, waves)) return waves;
+    return dense_default_waves(np, prec);
+}
 
 const void *dense_state_ptr(const void *vec, int d, int prec)
 {
@@ -542,51 +599,54 @@ const void *dense_state_ptr(const void *vec, int d, int prec)
     return vec;
 }
 
-template <typename T, int NP, int WPR>
+template <typename T, int NP, int WV>
 static void launch_np(const DenseInst *insts, DenseCtl *ctls, const int32_t *order, int count, int msl, int reset,
                       hipStream_t s)
 {
-    using G = DenseGeom<T, NP, WPR>;
+    using G = DenseGeom<T, NP, WV>;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_dense_solve<T, NP, WPR>,
+        (void)hipFuncSetAttribute((const void *)k_dense_solve<T, NP, WV>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::LDS_BYTES);
         attr = true;
     }
-    hipLaunchKernelGGL((k_dense_solve<T, NP, WPR>), dim3(count), dim3(G::WAVES * 64), G::LDS_BYTES, s, insts, ctls,
+    hipLaunchKernelGGL((k_dense_solve<T, NP, WV>), dim3(count), dim3(G::WAVES * 64), G::LDS_BYTES, s, insts, ctls,
                        order, msl, reset);
 }
 
-template <typename T, int WPR>
-static void launch_bucket(int np, const DenseInst *insts, DenseCtl *ctls, const int32_t *order, int count, int msl,
-                          int reset, hipStream_t s)
-{
-    switch (np) {
-    case 16: launch_np<T, 16, WPR>(insts, ctls, order, count, msl, reset, s); break;
-    case 32: launch_np<T, 32, WPR>(insts, ctls, order, count, msl, reset, s); break;
-    case 48: launch_np<T, 48, WPR>(insts, ctls, order, count, msl, reset, s); break;
-    case 64:
-        if constexpr (sizeof(T) == 4) launch_np<T, 64, WPR>(insts, ctls, order, count, msl, reset, s);
-        break;
-    case 80:
-        if constexpr (sizeof(T) == 4) launch_np<T, 80, WPR>(insts, ctls, order, count, msl, reset, s);
-        break;
-    default: break;
-    }
-}
-
-// wpr: waves per 16-row tile row of the output (1 or 2); the workgroup has (np/16)*wpr waves.
-void dense_launch_bucket(int np, bool f64, int wpr, const DenseInst *insts, DenseCtl *ctls, const int32_t *order,
+// waves: waves per workgroup, one of the counts waves_built lists for (np, precision); the caller
+// checks it with dense_waves_allowed.
+void dense_launch_bucket(int np, bool f64, int waves, const DenseInst *insts, DenseCtl *ctls, const int32_t *order,
                          int count, int msl, int reset, hipStream_t s)
 {
     if (count <= 0) return;
-    if (f64) {
-        if (wpr == 2) launch_bucket<double, 2>(np, insts, ctls, order, count, msl, reset, s);
-        else launch_bucket<double, 1>(np, insts, ctls, order, count, msl, reset, s);
-    } else {
-        if (wpr == 2) launch_bucket<float, 2>(np, insts, ctls, order, count, msl, reset, s);
-        else launch_bucket<float, 1>(np, insts, ctls, order, count, msl, reset, s);
+#define QT_DW(T, NP, W)                                                                                           \
+    if (np == NP && waves == W) {                                                                                  \
+        launch_np<T, NP, W>(insts, ctls, order, count, msl, reset, s);                                            \
+        return;                                                                                                    \
     }
+    if (f64) {
+        QT_DW(double, 16, 1)
+        QT_DW(double, 32, 2)
+        QT_DW(double, 32, 4)
+        QT_DW(double, 48, 3)
+        QT_DW(double, 48, 4)
+    } else {
+        QT_DW(float, 16, 1)
+        QT_DW(float, 16, 2)
+        QT_DW(float, 32, 2)
+        QT_DW(float, 32, 4)
+        QT_DW(float, 48, 3)
+        QT_DW(float, 48, 4)
+        QT_DW(float, 48, 6)
+        QT_DW(float, 48, 8)
+        QT_DW(float, 64, 4)
+        QT_DW(float, 64, 8)
+        QT_DW(float, 80, 4)
+        QT_DW(float, 80, 5)
+        QT_DW(float, 80, 8)
+    }
+#undef QT_DW
 }
 
 void dense_unpack(const void *host_vec, int d, int prec, double scale, double *out)

@@ -48,10 +48,12 @@ inline int dense_state_vectors() { return 10; }
 void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *ops, const void *rho0, void *vec,
                      const double *tlist, const int32_t *eptr, const int32_t *ecol, const double2 *eval,
                      double2 *expect, const qt_opts &opts, int prec);
-// waves per 16-row tile row for a dimension: the autotuner's choice if it has one, else a default
+// waves per workgroup for a dimension: the autotuner's choice if it has one, else a default
 int dense_choose_config(int d, int prec);
-// whether a waves-per-row choice has a register budget that fits (np: padded size)
-bool dense_wpr_allowed(int np, int prec, int wpr);
+// whether the solver is built with this many waves per workgroup for padded size np
+bool dense_waves_allowed(int np, int prec, int waves);
+// the wave counts built for padded size np (at most max of them into out); returns their number
+int dense_waves_candidates(int np, int prec, int *out, int max);
 // pointer to the current state vector (tile order) of an instance, for diagnostics
 const void *dense_state_ptr(const void *vec, int d, int prec);
 // Launch the persistent solver for `count` instances of padded size np (order[] lists them).

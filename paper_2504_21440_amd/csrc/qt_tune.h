@@ -22,12 +22,12 @@ std::string dense_tune_key(int32_t prec, int np);
 
 bool tune_lookup_csr(const std::string &key, CsrShape *out);
 void tune_store_csr(const std::string &key, CsrShape s);
-bool tune_lookup_dense(const std::string &key, int *wpr);
-void tune_store_dense(const std::string &key, int wpr);
+bool tune_lookup_dense(const std::string &key, int *waves);
+void tune_store_dense(const std::string &key, int waves);
 
 // heuristic shapes used when the table has no entry
 CsrShape csr_default_shape(int64_t rows, double mean_row);
-int dense_default_wpr(int np, int32_t prec);
+int dense_default_waves(int np, int32_t prec);
 
 // Candidate CSR shapes the autotuner measures (both matrix load kinds).  single: include the
 // XCD-contiguous block order, which only single-problem plans use: with several problems of

@@ -102,11 +102,17 @@ struct qt_server {
     int32_t *d_bi = nullptr, *d_br = nullptr, *d_order = nullptr, *d_ilist = nullptr;
     int32_t *d_counts = nullptr;    // [0] live blocks of the table, [1] live entries of the control list
     int32_t h_counts[2] = {0, 0};
-    size_t blk_cap = 0;
-    // The CSR part of an epoch (starting-step evaluations, then steps_per_epoch steps) is one graph
-    // captured for the table's capacity; the table contents and their counts change every epoch.
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    size_t blk_cap = 0;             // allocated entries of d_bi / d_br
+    // The CSR part of an epoch (starting-step evaluations, then steps_per_epoch steps) is one graph,
+    // captured once per grid size: the live block count rounded up to a power of two, so the
+    // workgroups past the live count that return at once never outnumber the live ones.  The table
+    // contents and their counts change every epoch; the graphs stay valid until the table is
+    // reallocated.
+    struct EpochGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::map<int, EpochGraph> graphs;
     qt::CsrCtl *h_cctl = nullptr;   // pinned
     qt::DenseCtl *h_dctl = nullptr; // pinned
     std::vector<int32_t> free_slots;
@@ -321,6 +327,15 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
     return QT_OK;
 }
 
+static void drop_graphs(qt_server *S)
+{
+    for (auto &g : S->graphs) {
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+        if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+    }
+    S->graphs.clear();
+}
+
 static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finished)
 {
     Ctx *ctx = S->ctx;
@@ -341,16 +356,17 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
         csr_slots.push_back(R.slot);
     }
     if (!bi.empty()) {
-        if (bi.size() > S->blk_cap) {
-            if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
-            if (S->graph) (void)hipGraphDestroy(S->graph);
-            S->gexec = nullptr;
-            S->graph = nullptr;
+        int grid = 256;
+        while ((size_t)grid < bi.size()) grid *= 2;
+        if ((size_t)grid > S->blk_cap) {
+            drop_graphs(S);
             if (S->d_bi) (void)hipFree(S->d_bi);
             if (S->d_br) (void)hipFree(S->d_br);
-            S->blk_cap = bi.size() * 2;
-            QT_HIP(hipMalloc(&S->d_bi, S->blk_cap * 4));
-            QT_HIP(hipMalloc(&S->d_br, S->blk_cap * 4));
+            S->d_bi = S->d_br = nullptr;
+            S->blk_cap = 0;
+            QT_HIP(hipMalloc(&S->d_bi, (size_t)grid * 4));
+            QT_HIP(hipMalloc(&S->d_br, (size_t)grid * 4));
+            S->blk_cap = (size_t)grid;
         }
         S->h_counts[0] = (int32_t)bi.size();
         S->h_counts[1] = (int32_t)csr_slots.size();
@@ -358,14 +374,15 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
         QT_HIP(hipMemcpyAsync(S->d_br, br.data(), br.size() * 4, hipMemcpyHostToDevice, s));
         QT_HIP(hipMemcpyAsync(S->d_ilist, csr_slots.data(), csr_slots.size() * 4, hipMemcpyHostToDevice, s));
         QT_HIP(hipMemcpyAsync(S->d_counts, S->h_counts, sizeof(S->h_counts), hipMemcpyHostToDevice, s));
-        if (!S->gexec) {
+        qt_server::EpochGraph &G = S->graphs[grid];
+        if (!G.exec) {
             CsrLaunch L;
             L.f64 = f64;
             L.lpr = S->shape.lpr;
             L.rg = S->shape.rg;
             L.xcd = 0;
             L.keep = S->shape.keep;
-            L.nblk = (int)S->blk_cap;         // capacity; blocks past the live count return at once
+            L.nblk = grid;                    // blocks past the live count return at once
             L.ninst = S->cfg.max_slots;       // likewise for the control list
             L.ilist = S->d_ilist;
             L.bound = S->d_counts;
@@ -378,11 +395,19 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
             csr_launch_init(0, L, s);
             csr_launch_init(1, L, s);
             for (int k = 0; k < K; ++k) csr_launch_step(L, s);
-            hipError_t ce = hipStreamEndCapture(s, &S->graph);
-            if (ce) return set_error(QT_EDEVICE, std::string("server graph capture: ") + hipGetErrorString(ce));
-            QT_HIP(hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0));
+            hipError_t ce = hipStreamEndCapture(s, &G.graph);
+            if (ce) {
+                S->graphs.erase(grid);
+                return set_error(QT_EDEVICE, std::string("server graph capture: ") + hipGetErrorString(ce));
+            }
+            ce = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
+            if (ce) {
+                (void)hipGraphDestroy(G.graph);
+                S->graphs.erase(grid);
+                return set_error(QT_EDEVICE, std::string("server graph instantiate: ") + hipGetErrorString(ce));
+            }
         }
-        QT_HIP(hipGraphLaunch(S->gexec, s));
+        QT_HIP(hipGraphLaunch(G.exec, s));
         QT_HIP(hipGetLastError());
     }
     // ---- dense slots: one budgeted launch per padded size, on the auxiliary streams ----
@@ -570,8 +595,7 @@ qt_status qt_server_destroy(qt_server *S)
     if (S->d_order) (void)hipFree(S->d_order);
     if (S->d_ilist) (void)hipFree(S->d_ilist);
     if (S->d_counts) (void)hipFree(S->d_counts);
-    if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
-    if (S->graph) (void)hipGraphDestroy(S->graph);
+    drop_graphs(S);
     if (S->d_bi) (void)hipFree(S->d_bi);
     if (S->d_br) (void)hipFree(S->d_br);
     if (S->h_cctl) (void)hipHostFree(S->h_cctl);

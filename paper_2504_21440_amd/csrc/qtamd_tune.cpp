@@ -2,7 +2,7 @@
 //
 // The measuring itself happens where the kernels are (qt_me_plan_autotune times the fused
 // SpMV-stage kernel of a plan for every candidate shape; the dense kernel is timed over a short
-// step budget for each waves-per-row choice).  This file keeps the decisions: per size bucket, the
+// step budget for each built wave count).  This file keeps the decisions: per size bucket, the
 // fastest shape measured so far, consulted by every plan and server created afterwards.
 #include <cmath>
 #include <cstdio>
@@ -34,7 +34,7 @@ std::string csr_tune_key(int32_t prec, int64_t rows, double mean_row)
 std::string dense_tune_key(int32_t prec, int np)
 {
     char b[64];
-    std::snprintf(b, sizeof b, "dense:%s:np%d", prec == QT_F64 ? "f64" : "mixed", np);
+    std::snprintf(b, sizeof b, "dense:%s:np%d:waves", prec == QT_F64 ? "f64" : "mixed", np);
     return b;
 }
 
@@ -53,19 +53,19 @@ void tune_store_csr(const std::string &key, CsrShape s)
     g_csr[key] = s;
 }
 
-bool tune_lookup_dense(const std::string &key, int *wpr)
+bool tune_lookup_dense(const std::string &key, int *waves)
 {
     std::lock_guard<std::mutex> g(g_mu);
     auto it = g_dense.find(key);
     if (it == g_dense.end()) return false;
-    *wpr = it->second;
+    *waves = it->second;
     return true;
 }
 
-void tune_store_dense(const std::string &key, int wpr)
+void tune_store_dense(const std::string &key, int waves)
 {
     std::lock_guard<std::mutex> g(g_mu);
-    g_dense[key] = wpr;
+    g_dense[key] = waves;
 }
 
 CsrShape csr_default_shape(int64_t rows, double mean_row)
@@ -78,7 +78,13 @@ CsrShape csr_default_shape(int64_t rows, double mean_row)
     return s;
 }
 
-int dense_default_wpr(int np, int32_t prec) { return (prec == QT_F64 || np > 64) ? 1 : 2; }
+// FP64: one wave per tile row; FP32: two waves per SIMD where the padded size has more than 4 tiles
+int dense_default_waves(int np, int32_t prec)
+{
+    const int nt = np / 16;
+    if (prec == QT_F64) return nt;
+    return nt * nt > 4 ? 8 : nt * nt <= 1 ? 2 : 4;
+}
 
 int csr_candidates(CsrShape *out, int max, bool single)
 {
@@ -92,13 +98,14 @@ int csr_candidates(CsrShape *out, int max, bool single)
     return n;
 }
 
-// a stored waves-per-row choice is taken only where the kernel's register budget allows it
-static bool dense_key_accepts(const char *key, int wpr)
+// a stored wave count is taken only for a key of the current form and a count the solver is built with
+static bool dense_key_accepts(const char *key, int waves)
 {
-    int np = 0;
+    int np = 0, end = 0;
     char prec[16];
-    if (std::sscanf(key, "dense:%15[^:]:np%d", prec, &np) != 2) return false;
-    return dense_wpr_allowed(np, std::strcmp(prec, "f64") == 0 ? QT_F64 : QT_MIXED, wpr);
+    if (std::sscanf(key, "dense:%15[^:]:np%d:waves%n", prec, &np, &end) != 2 || end == 0 || key[end] != 0)
+        return false;
+    return dense_waves_allowed(np, std::strcmp(prec, "f64") == 0 ? QT_F64 : QT_MIXED, waves);
 }
 
 }  // namespace qt

@@ -381,8 +381,8 @@ def test_autotune_chooses_a_kernel_shape_and_keeps_parity(ctx, tmp_path):
     probs = [(qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED), om.all_up_ket(6), tl, e_ops),
              (qt.Liouvillian(ctx, Hk, ck, qt.FORM_DENSE, qt.MIXED), om.fock_dm(20, 0), tl, [om.number(20)])]
     plan = qt.MePlan(ctx, probs, o)
-    lpr, rg, xcd, keep, wpr = plan.shape()
-    assert (lpr, rg) in SHAPES and xcd in (0, 1) and keep in (0, 1) and wpr in (1, 2)
+    lpr, rg, xcd, keep, waves = plan.shape()
+    assert (lpr, rg) in SHAPES and xcd in (0, 1) and keep in (0, 1) and waves in (1, 2, 4)
     plan.run()
     assert np.abs(plan.result(0)[0] - ref).max() <= 1e-4
     assert np.abs(plan.result(1)[0] - refk).max() <= 1e-4
@@ -390,5 +390,5 @@ def test_autotune_chooses_a_kernel_shape_and_keeps_parity(ctx, tmp_path):
     qt.tune_save(str(path))
     table = json.loads(path.read_text())
     assert [lpr, rg, xcd, keep] in table.values()
-    assert table.get("dense:mixed:np32") == [wpr]
+    assert table.get("dense:mixed:np32:waves") == [waves]
     plan.close()

@@ -72,8 +72,10 @@ def test_tuning_table_roundtrip(tmp_path):
         '  "csr:f64:n12:r7": [4, 4],\n'
         '  "csr:f64:n13:r7": [4, 8],\n'      # rows per group above the lanes: not a kernel shape
         '  "csr:f64:n14:r7": [32, 1],\n'     # 32 lanes per row: not a kernel shape
-        '  "dense:mixed:np32": [2],\n'
-        '  "dense:f64:np48": [2]\n'          # two waves per row are not built for FP64
+        '  "dense:mixed:np32:waves": [4],\n'
+        '  "dense:mixed:np48": [2],\n'       # the older waves-per-row form of the key
+        '  "dense:mixed:np80:waves": [3],\n'  # 3 waves are not built for this size
+        '  "dense:f64:np48:waves": [8]\n'    # 8 waves are not built for FP64
         '}\n')
     qt.tune_load(str(src))
     out = tmp_path / "out.json"
@@ -82,8 +84,9 @@ def test_tuning_table_roundtrip(tmp_path):
     table = json.loads(out.read_text())
     assert table["csr:mixed:n20:r19"] == [16, 2, 1, 1]
     assert table["csr:f64:n12:r7"] == [4, 4, 0, 0]  # a two-number entry reads as round-robin, streamed
-    assert table["dense:mixed:np32"] == [2]
-    for bad in ("csr:f64:n13:r7", "csr:f64:n14:r7", "dense:f64:np48"):
+    assert table["dense:mixed:np32:waves"] == [4]
+    for bad in ("csr:f64:n13:r7", "csr:f64:n14:r7", "dense:mixed:np48", "dense:mixed:np80:waves",
+                "dense:f64:np48:waves"):
         assert bad not in table
     with pytest.raises(qt.QtError):
         qt.tune_load(str(tmp_path / "missing.json"))
