@@ -90,6 +90,10 @@ def _load():
         _lib.or_uniform_from_words.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         _lib.or_traj_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, P, P]
         _lib.or_ensemble_stats.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P]
+        _lib.or_mesolve_td.restype = ctypes.c_int32
+        _lib.or_mesolve_td.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
+                                       ctypes.c_int32, P, P, P, P, P]
+        _lib.or_coef_eval.argtypes = [P, ctypes.c_double, P]
     return _lib
 
 
@@ -115,6 +119,92 @@ class _OpPack:
     @property
     def ptr(self):
         return ctypes.cast(self.arr, ctypes.c_void_p)
+
+
+class _Coef(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("n_table", ctypes.c_int32),
+        ("a_re", ctypes.c_double),
+        ("a_im", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("phi", ctypes.c_double),
+        ("t0", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("table_t0", ctypes.c_double),
+        ("table_dt", ctypes.c_double),
+        ("table", ctypes.c_void_p),
+    ]
+
+
+_COEF_KINDS = {None: -1, "const": 0, "cos": 1, "exp": 2, "gauss": 3, "table": 4}
+
+
+class _CoefPack:
+    """Coefficient specifications (dicts: kind, a, omega, phi, t0, sigma, table, table_t0, table_dt;
+    None = no coefficient) as the C structs, with their sample tables kept alive."""
+
+    def __init__(self, specs):
+        self.keep = []
+        self.arr = (_Coef * max(1, len(specs)))()
+        for k, c in enumerate(specs):
+            if c is None:
+                self.arr[k] = _Coef(kind=-1)
+                continue
+            a = complex(c.get("a", 1.0))
+            tab, n = None, 0
+            if c["kind"] == "table":
+                t = np.ascontiguousarray(np.asarray(c["table"], dtype=np.complex128))
+                self.keep.append(t)
+                tab, n = t.ctypes.data, len(t)
+            self.arr[k] = _Coef(_COEF_KINDS[c["kind"]], n, a.real, a.imag, float(c.get("omega", 0.0)),
+                                float(c.get("phi", 0.0)), float(c.get("t0", 0.0)), float(c.get("sigma", 1.0)),
+                                float(c.get("table_t0", 0.0)), float(c.get("table_dt", 1.0)), tab)
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.arr, ctypes.c_void_p)
+
+
+def coef_eval(spec, t):
+    """The oracle's value of one time-dependent coefficient (Sec. 2, QobjEvo) at time t."""
+    lib = _load()
+    pk = _CoefPack([spec])
+    out = np.zeros(2)
+    lib.or_coef_eval(pk.ptr, float(t), _ptr(out))
+    return complex(out[0], out[1])
+
+
+def mesolve_td(H0, h_terms, c_ops, rho0, tlist, e_ops, abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0,
+               want_final=False):
+    """Time-dependent Lindblad master equation (Sec. 3.2 with H(t) = H_0 + sum_i f_i(t) H_i as in the
+    QobjEvo of Sec. 2 and the driven example of Sec. 3.5).
+
+    h_terms: list of (H_i, coefficient spec); c_ops: list of C_k or (C_k, spec) for a collapse
+    operator g_k(t) C_k (weight |g_k(t)|^2 on its dissipator).  Returns as ``mesolve``."""
+    lib = _load()
+    rho0 = np.asarray(rho0, dtype=np.complex128)
+    if rho0.ndim == 1:
+        rho0 = np.outer(rho0, rho0.conj())
+    rho0 = np.ascontiguousarray(rho0)
+    d = rho0.shape[0]
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    cs = [c[0] if isinstance(c, tuple) else c for c in c_ops]
+    gs = [c[1] if isinstance(c, tuple) else None for c in c_ops]
+    Hp = _OpPack([H0])
+    Tp = _OpPack([h for h, _ in h_terms])
+    Fp = _CoefPack([f for _, f in h_terms])
+    Cp = _OpPack(cs)
+    Gp = _CoefPack(gs)
+    Ep = _OpPack(e_ops)
+    ex = np.zeros((len(e_ops), len(tl)), dtype=np.complex128)
+    fin = np.zeros((d, d), dtype=np.complex128) if want_final else None
+    st = Stats()
+    o = opts(abstol, reltol, max_steps, h0)
+    rc = lib.or_mesolve_td(Hp.ptr, len(h_terms), Tp.ptr, Fp.ptr, len(cs), Cp.ptr, Gp.ptr, _ptr(rho0), len(tl),
+                           _ptr(tl), len(e_ops), Ep.ptr, ctypes.byref(o), _ptr(ex),
+                           _ptr(fin) if want_final else None, ctypes.byref(st))
+    return ex, st.as_dict(), rc, fin
 
 
 def tableau():

@@ -12,7 +12,10 @@ Model Hamiltonians of the benchmark workloads:
   * driven Kerr cavity (Sec. 6): H = Delta a^dag a + (U/2) a^dag a^dag a a + F (a + a^dag),
     C = sqrt(kappa) a;
   * open transverse-field Ising chain (Secs. 4 and 6):
-    H = J sum_i sz_i sz_{i+1} + h sum_i sx_i, C_i = sqrt(gamma) sm_i.
+    H = J sum_i sz_i sz_{i+1} + h sum_i sx_i, C_i = sqrt(gamma) sm_i;
+  * driven optomechanical system (Sec. 3.5, time-dependent example), cavity a (cutoff Nc) first:
+    H_0 = wc a^dag a + wm b^dag b + (g/2)(a + a^dag)^2 (b + b^dag), drive term (a + a^dag) with
+    coefficient F cos(wd t), C = sqrt(kappa) a and sqrt(gamma) b.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -65,6 +68,17 @@ def ising(L, J, h, gamma):
         H = H + h * site_op(L, i, sigmax())
     c_ops = [sp.csr_matrix(np.sqrt(gamma) * site_op(L, i, sigmam())) for i in range(L)]
     return sp.csr_matrix(H), c_ops
+
+
+def optomech(Nc, Nm, wc, wm, g, kappa, gamma):
+    """(H_0, drive operator a + a^dag, c_ops, cavity photon number) of the optomechanical system."""
+    a = tensor(destroy(Nc), qeye(Nm))
+    b = tensor(qeye(Nc), destroy(Nm))
+    ad, bd = a.conj().T, b.conj().T
+    xa = a + ad
+    H = wc * (ad @ a) + wm * (bd @ b) + 0.5 * g * (xa @ xa) @ (b + bd)
+    c_ops = [sp.csr_matrix(np.sqrt(kappa) * a), sp.csr_matrix(np.sqrt(gamma) * b)]
+    return sp.csr_matrix(H), sp.csr_matrix(xa), c_ops, sp.csr_matrix(ad @ a)
 
 
 def number(N):

@@ -16,6 +16,13 @@ chain of the performance section, the decaying oscillator of the GPU section):
     kappa ~ U[0.5, 2], vacuum start, t in [0, 20], 100 saves of <a^dag a>.
   * ``serving_trace``: Poisson arrivals; 70% Kerr (as the sweep), 30% Ising chains with L ~ U{4..9},
     J = 1, h ~ U[0.3, 1.5], gamma ~ U[0.05, 0.5].
+  * ``driven_cavity_td``: a lossy cavity omega0 a^dag a driven by F (e^{-i omega t} a^dag + h.c.),
+    omega0 = 4, omega = 3 (detuning 1), F = 0.8, kappa = 1, N = 15, t in [0, 5], 51 saves.
+  * ``optomech_td``: the driven optomechanical system of the time-dependent example (cavity
+    cutoff 10, mechanical cutoff 7, omega_c = 1, omega_m = 2, g = 0.05, kappa = gamma = 0.01,
+    drive F cos(omega_d t) (a + a^dag) with F = 10 kappa and omega_d = omega_c), vacuum start,
+    t in [0, 5 / kappa], 5000 saves of <a^dag a>; ``optomech_sweep`` draws omega_d values around
+    omega_c for a batch of such problems over a shorter window.
 """
 import numpy as np
 
@@ -72,6 +79,29 @@ def serving_trace(n=2000, qps=100.0, seed=5, kerr_frac=0.7):
                  "gamma": float(g.uniform(0.05, 0.5)), "t_end": 10.0, "nt": 100}
         p["arrival"] = t
         p["id"] = i
+        out.append(p)
+    return out
+
+
+def driven_cavity_td():
+    return {"kind": "cavity_td", "N": 15, "omega0": 4.0, "omega": 3.0, "F": 0.8, "kappa": 1.0, "t_end": 5.0,
+            "nt": 51}
+
+
+def optomech_td(t_end=None, nt=5000):
+    kappa = 0.01
+    return {"kind": "optomech", "Nc": 10, "Nm": 7, "wc": 1.0, "wm": 2.0, "g": 0.05, "kappa": kappa,
+            "gamma": 0.01, "F": 10 * kappa, "wd": 1.0, "t_end": (5.0 / kappa) if t_end is None else float(t_end),
+            "nt": int(nt)}
+
+
+def optomech_sweep(n=64, seed=7, t_end=100.0, nt=200, Nc=10, Nm=7):
+    """n optomechanical problems whose drive frequency omega_d ~ U[0.8, 1.2] omega_c."""
+    g = _rng(seed)
+    out = []
+    for _ in range(n):
+        p = optomech_td(t_end=t_end, nt=nt)
+        p.update({"wd": float(g.uniform(0.8, 1.2)), "Nc": int(Nc), "Nm": int(Nm)})
         out.append(p)
     return out
 
