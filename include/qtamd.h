@@ -124,6 +124,45 @@ void qt_csr_free(qt_csr *A);
  * Errors: QT_EINVAL for mismatched sizes, malformed CSR, or a dense d above the limit. */
 qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const qt_csr *c_ops, int32_t form,
                                int32_t precision, qt_liouv **out);
+/* Time-dependent Liouvillian (Sec. 2, QobjEvo; Sec. 3.2 with time-dependent operators, the driven
+ * example of Sec. 3.5):
+ *     H(t) = H0 + sum_i f_i(t) H_i,   collapse operators g_k(t) C_k,
+ *     L(t) rho = -i[H0, rho] - i sum_i f_i(t) (H_i rho - rho H_i) + sum_k w_k(t) D[C_k] rho,
+ * with w_k = |g_k(t)|^2 where c_coefs[k] has a kind other than QT_COEF_NONE and w_k = 1 otherwise.
+ * H0 is Hermitian; the H_i need not be (a complex drive f a^dag + conj(f) a is two terms) and the
+ * f_i may be complex.  Coefficient kinds (a = (a[0], a[1]) complex):
+ *     QT_COEF_CONST   a
+ *     QT_COEF_COS     a cos(omega t + phi)
+ *     QT_COEF_EXP     a exp(i (omega t + phi))
+ *     QT_COEF_GAUSS   a exp(-(t - t0)^2 / (2 sigma^2)) cos(omega t + phi)   (sigma > 0)
+ *     QT_COEF_TABLE   a times the linear interpolation of the n_table complex samples `table`
+ *                     (interleaved re/im, host) taken at table_t0 + k table_dt, held at the end
+ *                     values outside [table_t0, table_t0 + (n_table - 1) table_dt]  (table_dt > 0)
+ * The device evaluates each coefficient in FP64 at the time of every right-hand-side evaluation.
+ * The library copies the tables; the caller's arrays may be released after the call.
+ * CSR form only; at most 31 time-dependent terms (H_i plus weighted collapse operators) and
+ * d*d < 2^26.  Plans mix time-dependent and constant problems freely.  Errors: QT_EINVAL for the
+ * dense form, too many terms, a bad kind or table, mismatched sizes. */
+#define QT_COEF_NONE (-1)
+#define QT_COEF_CONST 0
+#define QT_COEF_COS 1
+#define QT_COEF_EXP 2
+#define QT_COEF_GAUSS 3
+#define QT_COEF_TABLE 4
+typedef struct {
+    int32_t kind;
+    int32_t n_table;
+    double a[2];
+    double omega, phi;
+    double t0, sigma;
+    double table_t0, table_dt;
+    const double *table;
+} qt_coef;
+qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, const qt_csr *h_terms,
+                                  const qt_coef *h_coefs, int32_t n_c, const qt_csr *c_ops, const qt_coef *c_coefs,
+                                  int32_t form, int32_t precision, qt_liouv **out);
+/* Number of time-dependent terms of a Liouvillian (0 for a constant one). */
+qt_status qt_liouv_terms(const qt_liouv *L, int32_t *n_terms);
 /* d, stored non-zeros (CSR form; 0 for dense), device bytes held. */
 qt_status qt_liouv_info(const qt_liouv *L, int32_t *d, int64_t *nnz, int64_t *bytes);
 /* Copies the assembled CSR back to the host (values widened to complex128).  indptr: d*d + 1,

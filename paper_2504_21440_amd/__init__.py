@@ -22,7 +22,7 @@ FORM_CSR, FORM_DENSE = 0, 1
 EXPORTED = [
     "qt_opts_default", "qt_last_error", "qt_version", "qt_ctx_create", "qt_ctx_destroy", "qt_model_kerr",
     "qt_model_ising", "qt_csr_free", "qt_liouvillian_build", "qt_liouv_info", "qt_liouv_export",
-    "qt_liouv_destroy", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
+    "qt_liouv_destroy", "qt_liouvillian_build_td", "qt_liouv_terms", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
     "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_me_plan_autotune",
     "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
     "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_sesolve", "qt_server_create", "qt_server_submit", "qt_server_step",
@@ -184,16 +184,79 @@ class Context:
             pass
 
 
-class Liouvillian:
-    """qt_liouvillian_build: device Liouvillian (CSR superoperator or dense operator form)."""
+COEF_NONE, COEF_CONST, COEF_COS, COEF_EXP, COEF_GAUSS, COEF_TABLE = -1, 0, 1, 2, 3, 4
+_COEF_KIND = {None: COEF_NONE, "const": COEF_CONST, "cos": COEF_COS, "exp": COEF_EXP, "gauss": COEF_GAUSS,
+              "table": COEF_TABLE}
 
-    def __init__(self, ctx, H, c_ops, form=FORM_CSR, precision=F64):
+
+class Coef(ctypes.Structure):
+    """qt_coef: a time-dependent coefficient (see qtamd.h for the kinds)."""
+    _fields_ = [("kind", ctypes.c_int32), ("n_table", ctypes.c_int32), ("a", ctypes.c_double * 2),
+                ("omega", ctypes.c_double), ("phi", ctypes.c_double), ("t0", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("table_t0", ctypes.c_double), ("table_dt", ctypes.c_double),
+                ("table", ctypes.c_void_p)]
+
+
+class _Coefs:
+    """Coefficient specifications (dicts with kind, a, omega, phi, t0, sigma, table, table_t0,
+    table_dt; None = no coefficient) as qt_coef structs, sample tables kept alive."""
+
+    def __init__(self, specs):
+        self.keep = []
+        self.arr = (Coef * max(1, len(specs)))()
+        for k, c in enumerate(specs):
+            if c is None:
+                self.arr[k].kind = COEF_NONE
+                continue
+            a = complex(c.get("a", 1.0))
+            e = self.arr[k]
+            e.kind = _COEF_KIND[c["kind"]]
+            e.a[0], e.a[1] = a.real, a.imag
+            e.omega, e.phi = float(c.get("omega", 0.0)), float(c.get("phi", 0.0))
+            e.t0, e.sigma = float(c.get("t0", 0.0)), float(c.get("sigma", 1.0))
+            e.table_t0, e.table_dt = float(c.get("table_t0", 0.0)), float(c.get("table_dt", 1.0))
+            if c["kind"] == "table":
+                t = np.ascontiguousarray(np.asarray(c["table"], dtype=np.complex128))
+                self.keep.append(t)
+                e.n_table, e.table = len(t), t.ctypes.data
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.arr, ctypes.c_void_p)
+
+
+class Liouvillian:
+    """qt_liouvillian_build: device Liouvillian (CSR superoperator or dense operator form).
+
+    With h_terms = [(H_i, coef), ...] and / or c_ops entries (C_k, coef), qt_liouvillian_build_td
+    builds the time-dependent generator of H(t) = H + sum_i f_i(t) H_i with collapse operators
+    g_k(t) C_k; coef is a dict {"kind": "const" | "cos" | "exp" | "gauss" | "table", "a": complex,
+    "omega", "phi", "t0", "sigma", "table", "table_t0", "table_dt"}."""
+
+    def __init__(self, ctx, H, c_ops, form=FORM_CSR, precision=F64, h_terms=None):
         self.ctx = ctx
         Hs = _Ops([H])
-        Cs = _Ops(c_ops)
+        cs = [c[0] if isinstance(c, tuple) else c for c in c_ops]
+        gs = [c[1] if isinstance(c, tuple) else None for c in c_ops]
+        Cs = _Ops(cs)
         self.h = ctypes.c_void_p()
-        _check(lib().qt_liouvillian_build(ctx.h, Hs.ptr, len(c_ops), Cs.ptr, form, precision, ctypes.byref(self.h)))
+        if h_terms or any(g is not None for g in gs):
+            h_terms = h_terms or []
+            Ts = _Ops([h for h, _ in h_terms])
+            Fs = _Coefs([f for _, f in h_terms])
+            Gs = _Coefs(gs)
+            _check(lib().qt_liouvillian_build_td(ctx.h, Hs.ptr, len(h_terms), Ts.ptr, Fs.ptr, len(cs), Cs.ptr,
+                                                 Gs.ptr, form, precision, ctypes.byref(self.h)))
+        else:
+            _check(lib().qt_liouvillian_build(ctx.h, Hs.ptr, len(cs), Cs.ptr, form, precision,
+                                              ctypes.byref(self.h)))
         self.form, self.precision = form, precision
+
+    def terms(self):
+        """Number of time-dependent terms (qt_liouv_terms)."""
+        n = ctypes.c_int32()
+        _check(lib().qt_liouv_terms(self.h, ctypes.byref(n)))
+        return n.value
 
     def info(self):
         d, nnz, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqtamd.so")
-SOURCES = ["kernels_csr.hip", "kernels_assembly.hip", "kernels_dense.hip", "kernels_mc.hip",
+SOURCES = ["kernels_csr.hip", "kernels_csr_td.hip", "kernels_assembly.hip", "kernels_dense.hip", "kernels_mc.hip",
            "qtamd_runtime.cpp", "qtamd_me.cpp", "qtamd_mc.cpp", "qtamd_server.cpp", "qtamd_tune.cpp"]
 ARCH = "gfx950"
 

@@ -5,11 +5,14 @@
 //     L = A kron I + I kron conj(A) + sum_k C_k kron conj(C_k),   A = -i H - 1/2 sum_k C_k^dag C_k.
 // Row (i, j) of L therefore collects
 //     A_ik at column (k, j),  conj(A_jl) at column (i, l),  C_ip conj(C_jq) at column (p, q).
+// (A Hamiltonian term of a time-dependent problem uses a second operator B in the place of the
+// right-hand A; see qt_asm.h.)
 // Each thread builds one row: it gathers these candidates, sorts them by column, sums duplicates
 // and drops exact zeros.  A count pass, a three-kernel scan and a fill pass produce CSR directly
 // in device memory, values computed in FP64 and stored in the solve precision.
 #include "qt_common.h"
 #include "qt_asm.h"
+#include "qt_csr.h"
 
 namespace qt {
 
@@ -45,9 +48,11 @@ __device__ int build_row(const AsmOps &op, int64_t r, int *cols, double2 *vals, 
     const int i = (int)(r / d), j = (int)(r % d);
     int n = 0;
     for (int p = op.arp[i]; p < op.arp[i + 1]; ++p) cand_insert(cols, vals, n, op.aci[p] * d + j, op.av[p], overflow);
-    for (int p = op.arp[j]; p < op.arp[j + 1]; ++p) {
-        const double2 a = op.av[p];
-        cand_insert(cols, vals, n, i * d + op.aci[p], make_double2(a.x, -a.y), overflow);
+    const int32_t *brp = op.brp ? op.brp : op.arp, *bci = op.brp ? op.bci : op.aci;
+    const double2 *bv = op.brp ? op.bv : op.av;
+    for (int p = brp[j]; p < brp[j + 1]; ++p) {
+        const double2 b = bv[p];
+        cand_insert(cols, vals, n, i * d + bci[p], make_double2(b.x, -b.y), overflow);
     }
     for (int k = 0; k < op.nc; ++k) {
         const int32_t *rp = op.crp + (size_t)k * (d + 1);
@@ -96,6 +101,37 @@ __global__ __launch_bounds__(128) void k_asm_fill(AsmOps op, const int32_t *rowp
         val[o] = from_d2<V>(vals[k]);
         ++o;
     }
+}
+
+// ---- time-dependent terms: one CSR with the term number in the column's high bits ----
+template <typename V>
+__global__ __launch_bounds__(128) void k_td_merge(const TdTerm *__restrict__ terms, int nt, int64_t n,
+                                                  int32_t *__restrict__ rowptr, int32_t *__restrict__ col,
+                                                  V *__restrict__ val)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    int32_t o = 0;
+    for (int k = 0; k < nt; ++k) o += terms[k].rp[r];
+    rowptr[r] = o;
+    if (r == n) return;
+    for (int k = 0; k < nt; ++k) {
+        const TdTerm t = terms[k];
+        const V *tv = (const V *)t.v;
+        for (int32_t p = t.rp[r]; p < t.rp[r + 1]; ++p) {
+            col[o] = t.ci[p] | (k << TD_TAG_SHIFT);
+            val[o] = tv[p];
+            ++o;
+        }
+    }
+}
+
+void asm_launch_td_merge(const TdTerm *terms, int nt, int64_t n, int32_t *rowptr, int32_t *col, void *val,
+                         bool f64, hipStream_t s)
+{
+    const dim3 g((unsigned)((n + 1 + 127) / 128)), t(128);
+    if (f64) hipLaunchKernelGGL(k_td_merge<double2>, g, t, 0, s, terms, nt, n, rowptr, col, (double2 *)val);
+    else hipLaunchKernelGGL(k_td_merge<float2>, g, t, 0, s, terms, nt, n, rowptr, col, (float2 *)val);
 }
 
 // ---- exclusive scan of int32 counts into int32 row pointers (total checked against 2^31) ----

@@ -11,6 +11,16 @@
 
 namespace qt {
 
+// Time-dependent Liouvillians: L(t) = sum_k w_k(t) L_k is stored as one CSR whose rows list the
+// entries of every term in turn; an entry's column index carries its term k above TD_TAG_SHIFT
+// (term 0 is the constant part, w_0 = 1).
+constexpr int TD_TAG_SHIFT = 26;
+constexpr int32_t TD_COL_MASK = (1 << TD_TAG_SHIFT) - 1;
+constexpr int TD_MAX_TERMS = 31;  // time-dependent terms (tags 1..31)
+constexpr int TD_SLOTS = 8;       // coefficient rows: two starting-step evaluations, stages 2..7
+
+struct CoefDev;
+
 // Solve status kept in device control records (errors use the public QT_E* codes 1..7).
 enum : int32_t {
     ST_RUNNING = 0,
@@ -43,6 +53,11 @@ struct CsrInst {
     const int32_t *evidx; // per e_op entry (i, j): index j*d + i of rho_ji in vec(rho)
     double2 *expect;      // [ne][nt]
     double *partials;     // 2 * nblocks doubles
+    // time dependence (nterms = 0: none)
+    int32_t nterms;          // time-dependent terms (column tags 1..nterms)
+    int32_t pad_td;
+    const CoefDev *coefs;    // [nterms]
+    void *cstage;            // [TD_SLOTS][nterms + 1] coefficient values (state precision), column 0 = 1
 };
 
 struct CsrCtl {

@@ -81,6 +81,9 @@ struct Liouv {
     void *val = nullptr;
     // dense form: A then C_k, each d x d row-major, in the solve precision
     void *dense = nullptr;
+    // time dependence (CSR form): column tags 1..nterms select the coefficient of each entry
+    int32_t nterms = 0;
+    void *coefs = nullptr;  // device: CoefDev[nterms] followed by their sample tables
     // host copies needed by the Monte-Carlo path and by the server footprint estimate
 };
 
@@ -104,8 +107,10 @@ struct CsrLaunch {
     // for the capacity stays valid while the table contents change.
     const int32_t *bound = nullptr, *ibound = nullptr;
     const CsrInst *one_host = nullptr;           // host copy of the descriptor when ninst == 1
+    bool td = false;  // some problem has a time-dependent Liouvillian: the SpMV kernels weight its terms
 };
-void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, hipStream_t s);
+// Resets the control records (and the coefficient rows of problems that have them).
+void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, bool f64, hipStream_t s);
 void csr_launch_init(int which, const CsrLaunch &L, hipStream_t s);
 void csr_launch_step(const CsrLaunch &L, hipStream_t s);
 void csr_launch_stage3(const CsrLaunch &L, hipStream_t s);

@@ -18,6 +18,7 @@
 #include "qt_dense.h"
 #include "qt_host.h"
 #include "qt_tune.h"
+#include "qt_coef.h"
 
 namespace qt {
 
@@ -29,6 +30,7 @@ struct MeProb {
     size_t o_rho0 = 0, o_tlist = 0, o_eptr = 0, o_ecol = 0, o_eval = 0, o_evidx = 0, o_expect = 0;
     size_t o_vec = 0;  // state vectors
     size_t o_part = 0;
+    size_t o_cstage = 0;  // coefficient rows (plans with a time-dependent problem)
     std::vector<char> rho0;  // host copy in state precision
     std::vector<double> tlist;
     std::vector<int32_t> eptr, ecol, evidx;
@@ -45,6 +47,7 @@ struct qt_me_plan {
     qt::Arena arena;
     // CSR group
     int32_t ncsr = 0, nblk = 0;
+    bool td = false;  // some CSR problem is time dependent: every CSR launch weights its terms
     qt::CsrShape shape;
     std::string tune_key;
     std::vector<qt::CsrInst> h_ci;  // host copy of the descriptors (block ranges change with the shape)
@@ -293,9 +296,16 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             m.slot = P->ncsr++;
             nnz_tot += m.L->nnz;
             rows_tot += (int64_t)m.d * m.d;
+            P->td = P->td || m.L->nterms > 0;
         } else {
             m.slot = P->ndense++;
         }
+    if (P->td)
+        for (auto &m : P->probs)
+            if (!m.dense && (int64_t)m.d * m.d > (int64_t)TD_COL_MASK) {
+                delete P;
+                return set_error(QT_EINVAL, "a plan with a time-dependent problem holds CSR problems with d*d < 2^26");
+            }
     for (auto &m : P->probs) {
         const size_t nvec = (size_t)m.d * m.d;
         m.o_rho0 = A.reserve(nvec * es);
@@ -310,6 +320,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             max_blocks += nb;
             m.o_vec = A.reserve(11 * nvec * es);  // Y[2], K[2], k2..k6, ys[2]
             m.o_part = A.reserve((size_t)nb * 16);
+            if (P->td) m.o_cstage = A.reserve((size_t)TD_SLOTS * (m.L->nterms + 1) * es);
         } else {
             const size_t np = (size_t)dense_np(m.d);
             m.o_vec = A.reserve(dense_state_vectors() * np * np * es);
@@ -379,6 +390,13 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             c.evidx = (const int32_t *)A.at(m.o_evidx);
             c.expect = (double2 *)A.at(m.o_expect);
             c.partials = (double *)A.at(m.o_part);
+            if (P->td) {
+                // every CSR problem of the plan takes the weighted kernels; a constant one has only
+                // the column of ones
+                c.nterms = m.L->nterms;
+                c.coefs = (const CoefDev *)m.L->coefs;
+                c.cstage = A.at(m.o_cstage);
+            }
         } else {
             DenseInst &g = di[m.slot];
             dense_fill_inst(&g, m.d, m.L->nc, m.nt, m.ne, m.L->dense, A.at(m.o_rho0), A.at(m.o_vec),
@@ -463,6 +481,7 @@ static CsrLaunch csr_args(const qt_me_plan *P, int k = 0)
     L.bi = (const int32_t *)P->arena.at(P->o_bi) + l.boff;
     L.br = (const int32_t *)P->arena.at(P->o_br) + l.boff;
     L.one_host = P->ncsr == 1 ? &P->h_ci[0] : nullptr;
+    L.td = P->td;
     return L;
 }
 
@@ -512,7 +531,7 @@ qt_status me_plan_run(qt_me_plan *P)
         if ((st = restore_full(P))) return st;
         const CsrLaunch L = csr_args(P, 0);
         auto *cc = L.ctls;
-        csr_launch_reset(L.insts, L.ctls, P->ncsr, s);
+        csr_launch_reset(L.insts, L.ctls, P->ncsr, L.f64, s);
         csr_launch_init(0, L, s);
         csr_launch_init(1, L, s);
         QT_HIP(hipGetLastError());
@@ -648,7 +667,7 @@ static qt_status time_stage(qt_me_plan *P, int32_t reps, double *ms)
     hipEvent_t e0, e1;
     QT_HIP(hipEventCreate(&e0));
     QT_HIP(hipEventCreate(&e1));
-    csr_launch_reset(L.insts, L.ctls, P->ncsr, s);
+    csr_launch_reset(L.insts, L.ctls, P->ncsr, L.f64, s);
     csr_launch_init(0, L, s);
     csr_launch_init(1, L, s);
     csr_launch_stage3(L, s);  // warm

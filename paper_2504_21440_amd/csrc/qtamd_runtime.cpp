@@ -6,6 +6,8 @@
 #include <map>
 
 #include "qt_asm.h"
+#include "qt_coef.h"
+#include "qt_csr.h"
 #include "qt_dense.h"
 #include "qt_host.h"
 
@@ -371,6 +373,114 @@ static qt_status upload_csr32(const HCsr &A, std::vector<int32_t> &rp, std::vect
     return QT_OK;
 }
 
+// Device assembly of  L = A (x) I + I (x) conj(B) + sum_k C_k (x) conj(C_k)  (B null: B = A) into
+// CSR with int32 indices, values in the solve precision.  On success the caller owns the three
+// device arrays.
+static qt_status assemble_csr(Ctx *ctx, const HCsr &A, const HCsr *B, const std::vector<HCsr> &cs, bool f64,
+                              int32_t **rowptr_out, int32_t **col_out, void **val_out, int64_t *nnz_out)
+{
+    const int32_t d = A.d, n_c = (int32_t)cs.size();
+    const size_t es = f64 ? sizeof(double2) : sizeof(float2);
+    qt_status st;
+    std::vector<int32_t> arp, aci, brp, bci;
+    std::vector<double2> av, bv;
+    if ((st = upload_csr32(A, arp, aci, av))) return st;
+    if (B && (st = upload_csr32(*B, brp, bci, bv))) return st;
+    std::vector<int32_t> crp((size_t)n_c * (d + 1)), cci;
+    std::vector<double2> cv;
+    for (int k = 0; k < n_c; ++k) {
+        const int32_t base = (int32_t)cci.size();
+        for (int32_t i = 0; i <= d; ++i) crp[(size_t)k * (d + 1) + i] = base + (int32_t)cs[k].ptr[i];
+        for (int64_t p = 0; p < cs[k].nnz(); ++p) {
+            cci.push_back(cs[k].idx[p]);
+            cv.push_back(make_double2(cs[k].val[p].real(), cs[k].val[p].imag()));
+        }
+    }
+    const int64_t n = (int64_t)d * d;
+    if (n >= 2147483647LL) return set_error(QT_EINVAL, "Liouvillian too large for int32 indexing");
+    Arena tmp;
+    const size_t o_arp = tmp.reserve(arp.size() * 4), o_aci = tmp.reserve(std::max<size_t>(1, aci.size()) * 4),
+                 o_av = tmp.reserve(std::max<size_t>(1, av.size()) * 16),
+                 o_brp = tmp.reserve(std::max<size_t>(1, brp.size()) * 4),
+                 o_bci = tmp.reserve(std::max<size_t>(1, bci.size()) * 4),
+                 o_bv = tmp.reserve(std::max<size_t>(1, bv.size()) * 16),
+                 o_crp = tmp.reserve(std::max<size_t>(1, crp.size()) * 4),
+                 o_cci = tmp.reserve(std::max<size_t>(1, cci.size()) * 4),
+                 o_cv = tmp.reserve(std::max<size_t>(1, cv.size()) * 16), o_cnt = tmp.reserve((size_t)n * 4),
+                 o_bs = tmp.reserve(((size_t)(n + 1023) / 1024 + 1) * 8), o_fl = tmp.reserve(64);
+    if ((st = tmp.alloc())) return st;
+    hipStream_t s = ctx->stream;
+    auto cp = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(tmp.at(off), src, bytes, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e = hipSuccess;
+    e = e ? e : cp(o_arp, arp.data(), arp.size() * 4);
+    e = e ? e : cp(o_aci, aci.data(), aci.size() * 4);
+    e = e ? e : cp(o_av, av.data(), av.size() * 16);
+    e = e ? e : cp(o_brp, brp.data(), brp.size() * 4);
+    e = e ? e : cp(o_bci, bci.data(), bci.size() * 4);
+    e = e ? e : cp(o_bv, bv.data(), bv.size() * 16);
+    e = e ? e : cp(o_crp, crp.data(), crp.size() * 4);
+    e = e ? e : cp(o_cci, cci.data(), cci.size() * 4);
+    e = e ? e : cp(o_cv, cv.data(), cv.size() * 16);
+    e = e ? e : hipMemsetAsync(tmp.at(o_fl), 0, 64, s);
+    AsmOps op{d,
+              n_c,
+              (const int32_t *)tmp.at(o_arp),
+              (const int32_t *)tmp.at(o_aci),
+              (const double2 *)tmp.at(o_av),
+              (const int32_t *)tmp.at(o_crp),
+              (const int32_t *)tmp.at(o_cci),
+              (const double2 *)tmp.at(o_cv),
+              B ? (const int32_t *)tmp.at(o_brp) : nullptr,
+              B ? (const int32_t *)tmp.at(o_bci) : nullptr,
+              B ? (const double2 *)tmp.at(o_bv) : nullptr};
+    int32_t *counts = (int32_t *)tmp.at(o_cnt);
+    int *flags = (int *)tmp.at(o_fl);
+    int32_t *rowptr = nullptr, *col = nullptr;
+    void *val = nullptr;
+    e = e ? e : hipMalloc(&rowptr, (size_t)(n + 1) * 4);
+    if (e == hipSuccess) {
+        asm_launch_count(op, counts, flags, s);
+        asm_launch_scan(counts, n, (int64_t *)tmp.at(o_bs), rowptr, flags, s);
+        e = hipGetLastError();
+    }
+    int hflags[2] = {0, 0};
+    int32_t total = 0;
+    e = e ? e : hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s);
+    e = e ? e : hipMemcpyAsync(&total, rowptr + n, 4, hipMemcpyDeviceToHost, s);
+    e = e ? e : hipStreamSynchronize(s);
+    if (e == hipSuccess && (hflags[0] || hflags[1])) {
+        tmp.release();
+        (void)hipFree(rowptr);
+        return set_error(QT_EINVAL, hflags[0] ? "Liouvillian row has too many candidate entries for CSR assembly "
+                                                "(use the dense form)"
+                                              : "Liouvillian has more than 2^31 non-zeros");
+    }
+    if (e == hipSuccess) {
+        e = hipMalloc(&col, std::max<size_t>(1, (size_t)total) * 4);
+        if (e == hipSuccess) e = hipMalloc(&val, std::max<size_t>(1, (size_t)total) * es);
+        if (e == hipSuccess) {
+            asm_launch_fill(op, rowptr, col, val, f64, s);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    tmp.release();
+    if (e != hipSuccess) {
+        if (rowptr) (void)hipFree(rowptr);
+        if (col) (void)hipFree(col);
+        if (val) (void)hipFree(val);
+        return set_error(QT_EDEVICE, std::string("Liouvillian assembly: ") + hipGetErrorString(e));
+    }
+    *rowptr_out = rowptr;
+    *col_out = col;
+    *val_out = val;
+    *nnz_out = total;
+    return QT_OK;
+}
+
 qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const qt_csr *c_ops, int32_t form,
                                int32_t precision, qt_liouv **out)
 {
@@ -437,100 +547,191 @@ qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const 
     }
 
     // CSR form: device assembly
-    std::vector<int32_t> arp, aci;
-    std::vector<double2> av;
-    if ((st = upload_csr32(A, arp, aci, av))) {
+    if ((st = assemble_csr(ctx, A, nullptr, cs, precision == QT_F64, &L->rowptr, &L->col, &L->val, &L->nnz))) {
         delete L;
         return st;
-    }
-    std::vector<int32_t> crp((size_t)n_c * (d + 1)), cci;
-    std::vector<double2> cv;
-    for (int k = 0; k < n_c; ++k) {
-        const int32_t base = (int32_t)cci.size();
-        for (int32_t i = 0; i <= d; ++i) crp[(size_t)k * (d + 1) + i] = base + (int32_t)cs[k].ptr[i];
-        for (int64_t p = 0; p < cs[k].nnz(); ++p) {
-            cci.push_back(cs[k].idx[p]);
-            cv.push_back(make_double2(cs[k].val[p].real(), cs[k].val[p].imag()));
-        }
     }
     const int64_t n = (int64_t)d * d;
-    if (n >= 2147483647LL) {
-        delete L;
-        return set_error(QT_EINVAL, "Liouvillian too large for int32 indexing");
+    L->bytes = (int64_t)((n + 1) * 4 + L->nnz * (4 + (int64_t)es));
+    ctx->refs++, *out = L;
+    return QT_OK;
+}
+
+static qt_status check_coef(const qt_coef &c, bool allow_none, const char *what)
+{
+    if (allow_none && c.kind == QT_COEF_NONE) return QT_OK;
+    if (c.kind < QT_COEF_CONST || c.kind > QT_COEF_TABLE)
+        return set_error(QT_EINVAL, std::string(what) + ": unknown coefficient kind");
+    if (c.kind == QT_COEF_GAUSS && !(c.sigma > 0.0))
+        return set_error(QT_EINVAL, std::string(what) + ": Gaussian coefficient needs sigma > 0");
+    if (c.kind == QT_COEF_TABLE && (c.n_table < 1 || !c.table || !(c.table_dt > 0.0)))
+        return set_error(QT_EINVAL, std::string(what) + ": table coefficient needs samples and table_dt > 0");
+    return QT_OK;
+}
+
+qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, const qt_csr *h_terms,
+                                  const qt_coef *h_coefs, int32_t n_c, const qt_csr *c_ops, const qt_coef *c_coefs,
+                                  int32_t form, int32_t precision, qt_liouv **out)
+{
+    if (!ctx || !H0 || !out || n_h < 0 || n_c < 0 || (n_h > 0 && (!h_terms || !h_coefs)) || (n_c > 0 && !c_ops))
+        return set_error(QT_EINVAL, "qt_liouvillian_build_td: null argument");
+    if (precision != QT_F64 && precision != QT_MIXED) return set_error(QT_EINVAL, "bad precision");
+    qt_status st;
+    for (int i = 0; i < n_h; ++i)
+        if ((st = check_coef(h_coefs[i], false, "h_coefs"))) return st;
+    int n_w = 0;  // weighted collapse operators
+    for (int k = 0; k < n_c && c_coefs; ++k) {
+        if ((st = check_coef(c_coefs[k], true, "c_coefs"))) return st;
+        n_w += c_coefs[k].kind != QT_COEF_NONE;
     }
-    Arena tmp;
-    const size_t o_arp = tmp.reserve(arp.size() * 4), o_aci = tmp.reserve(std::max<size_t>(1, aci.size()) * 4),
-                 o_av = tmp.reserve(std::max<size_t>(1, av.size()) * 16),
-                 o_crp = tmp.reserve(std::max<size_t>(1, crp.size()) * 4),
-                 o_cci = tmp.reserve(std::max<size_t>(1, cci.size()) * 4),
-                 o_cv = tmp.reserve(std::max<size_t>(1, cv.size()) * 16), o_cnt = tmp.reserve((size_t)n * 4),
-                 o_bs = tmp.reserve(((size_t)(n + 1023) / 1024 + 1) * 8), o_fl = tmp.reserve(64);
-    if ((st = tmp.alloc())) {
-        delete L;
+    const int nterms = n_h + n_w;
+    if (nterms == 0) return qt_liouvillian_build(ctx, H0, n_c, c_ops, form, precision, out);
+    if (form != QT_FORM_CSR) return set_error(QT_EINVAL, "time-dependent Liouvillians need the CSR form");
+    if (nterms > TD_MAX_TERMS) return set_error(QT_EINVAL, "at most 31 time-dependent terms");
+    HCsr h0;
+    if ((st = csr_from_abi(H0, 0, &h0, "H0"))) return st;
+    const int32_t d = h0.d;
+    const int64_t n = (int64_t)d * d;
+    if (n > (int64_t)TD_COL_MASK) return set_error(QT_EINVAL, "time-dependent Liouvillian needs d*d < 2^26");
+    std::vector<HCsr> hs(n_h), cs(n_c);
+    for (int i = 0; i < n_h; ++i)
+        if ((st = csr_from_abi(&h_terms[i], d, &hs[i], "h_terms"))) return st;
+    for (int k = 0; k < n_c; ++k)
+        if ((st = csr_from_abi(&c_ops[k], d, &cs[k], "c_ops"))) return st;
+    QT_HIP(hipSetDevice(ctx->device));
+    const bool f64 = precision == QT_F64;
+    const size_t es = f64 ? sizeof(double2) : sizeof(float2);
+    auto weighted = [&](int k) { return c_coefs && c_coefs[k].kind != QT_COEF_NONE; };
+
+    // term 0: H0 with the constant collapse operators; then each H_i; then each weighted C_k
+    struct Part {
+        int32_t *rp = nullptr, *ci = nullptr;
+        void *v = nullptr;
+        int64_t nnz = 0;
+    };
+    std::vector<Part> parts(1 + nterms);
+    auto free_parts = [&]() {
+        for (auto &q : parts) {
+            if (q.rp) (void)hipFree(q.rp);
+            if (q.ci) (void)hipFree(q.ci);
+            if (q.v) (void)hipFree(q.v);
+            q = Part();
+        }
+    };
+    {
+        std::vector<HCsr> c0;
+        HCsr A = csr_axpby(cd(0.0, -1.0), h0, cd(0.0, 0.0), csr_zero(d));
+        for (int k = 0; k < n_c; ++k)
+            if (!weighted(k)) {
+                A = csr_axpby(cd(1.0, 0.0), A, cd(-0.5, 0.0), csr_matmul(csr_adjoint(cs[k]), cs[k]));
+                c0.push_back(cs[k]);
+            }
+        st = assemble_csr(ctx, A, nullptr, c0, f64, &parts[0].rp, &parts[0].ci, &parts[0].v, &parts[0].nnz);
+    }
+    std::vector<CoefDev> cd_host(nterms);
+    std::vector<const qt_coef *> src(nterms);
+    int t = 1;
+    for (int i = 0; i < n_h && !st; ++i, ++t) {
+        // -i (H rho - rho H):  A = -i H,  B = -i H^dag  (rho B^dag = i rho H)
+        const HCsr A = csr_axpby(cd(0.0, -1.0), hs[i], cd(0.0, 0.0), csr_zero(d));
+        const HCsr B = csr_axpby(cd(0.0, -1.0), csr_adjoint(hs[i]), cd(0.0, 0.0), csr_zero(d));
+        st = assemble_csr(ctx, A, &B, {}, f64, &parts[t].rp, &parts[t].ci, &parts[t].v, &parts[t].nnz);
+        src[t - 1] = &h_coefs[i];
+        cd_host[t - 1].modsq = 0;
+    }
+    for (int k = 0; k < n_c && !st; ++k) {
+        if (!weighted(k)) continue;
+        // D[C]:  A = -1/2 C^dag C,  C (x) conj(C)
+        const HCsr A = csr_axpby(cd(-0.5, 0.0), csr_matmul(csr_adjoint(cs[k]), cs[k]), cd(0.0, 0.0), csr_zero(d));
+        st = assemble_csr(ctx, A, nullptr, {cs[k]}, f64, &parts[t].rp, &parts[t].ci, &parts[t].v, &parts[t].nnz);
+        src[t - 1] = &c_coefs[k];
+        cd_host[t - 1].modsq = 1;
+        ++t;
+    }
+    if (st) {
+        free_parts();
         return st;
     }
-    hipStream_t s = ctx->stream;
-    auto cp = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
-        if (!bytes) return hipSuccess;
-        return hipMemcpyAsync(tmp.at(off), src, bytes, hipMemcpyHostToDevice, s);
-    };
-    hipError_t e = hipSuccess;
-    e = e ? e : cp(o_arp, arp.data(), arp.size() * 4);
-    e = e ? e : cp(o_aci, aci.data(), aci.size() * 4);
-    e = e ? e : cp(o_av, av.data(), av.size() * 16);
-    e = e ? e : cp(o_crp, crp.data(), crp.size() * 4);
-    e = e ? e : cp(o_cci, cci.data(), cci.size() * 4);
-    e = e ? e : cp(o_cv, cv.data(), cv.size() * 16);
-    e = e ? e : hipMemsetAsync(tmp.at(o_fl), 0, 64, s);
-    AsmOps op{d,
-              n_c,
-              (const int32_t *)tmp.at(o_arp),
-              (const int32_t *)tmp.at(o_aci),
-              (const double2 *)tmp.at(o_av),
-              (const int32_t *)tmp.at(o_crp),
-              (const int32_t *)tmp.at(o_cci),
-              (const double2 *)tmp.at(o_cv)};
-    int32_t *counts = (int32_t *)tmp.at(o_cnt);
-    int *flags = (int *)tmp.at(o_fl);
-    e = e ? e : hipMalloc(&L->rowptr, (size_t)(n + 1) * 4);
+    int64_t total = 0;
+    for (auto &q : parts) total += q.nnz;
+    if (total >= 2147483647LL) {
+        free_parts();
+        return set_error(QT_EINVAL, "Liouvillian has more than 2^31 non-zeros");
+    }
+    // coefficient descriptors and their tables, one device buffer
+    size_t tab_bytes = 0;
+    for (int k = 0; k < nterms; ++k)
+        if (src[k]->kind == QT_COEF_TABLE) tab_bytes += (size_t)src[k]->n_table * sizeof(double2);
+    const size_t head = ((sizeof(CoefDev) * nterms + 255) / 256) * 256;
+    qt_liouv *L = new qt_liouv();
+    L->ctx = ctx;
+    L->form = form;
+    L->precision = precision;
+    L->d = d;
+    L->nc = n_c;
+    L->nterms = nterms;
+    L->nnz = total;
+    hipError_t e = hipMalloc(&L->coefs, head + std::max<size_t>(tab_bytes, 16));
+    std::vector<char> hostbuf(head + tab_bytes, 0);
+    size_t toff = head;
+    for (int k = 0; k < nterms && e == hipSuccess; ++k) {
+        const qt_coef &c = *src[k];
+        CoefDev &g = cd_host[k];
+        g.kind = c.kind;
+        g.n_table = c.kind == QT_COEF_TABLE ? c.n_table : 0;
+        g.pad = 0;
+        g.a_re = c.a[0];
+        g.a_im = c.a[1];
+        g.omega = c.omega;
+        g.phi = c.phi;
+        g.t0 = c.t0;
+        g.sigma = c.sigma;
+        g.table_t0 = c.table_t0;
+        g.table_dt = c.table_dt;
+        g.table = nullptr;
+        if (c.kind == QT_COEF_TABLE) {
+            std::memcpy(hostbuf.data() + toff, c.table, (size_t)c.n_table * sizeof(double2));
+            g.table = (const double2 *)((char *)L->coefs + toff);
+            toff += (size_t)c.n_table * sizeof(double2);
+        }
+    }
     if (e == hipSuccess) {
-        asm_launch_count(op, counts, flags, s);
-        asm_launch_scan(counts, n, (int64_t *)tmp.at(o_bs), L->rowptr, flags, s);
+        std::memcpy(hostbuf.data(), cd_host.data(), sizeof(CoefDev) * nterms);
+        e = hipMemcpy(L->coefs, hostbuf.data(), hostbuf.size(), hipMemcpyHostToDevice);
+    }
+    // merged CSR
+    std::vector<TdTerm> th(parts.size());
+    for (size_t k = 0; k < parts.size(); ++k) th[k] = TdTerm{parts[k].rp, parts[k].ci, parts[k].v};
+    TdTerm *dterms = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&dterms, sizeof(TdTerm) * th.size());
+    if (e == hipSuccess) e = hipMemcpy(dterms, th.data(), sizeof(TdTerm) * th.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&L->rowptr, (size_t)(n + 1) * 4);
+    if (e == hipSuccess) e = hipMalloc(&L->col, std::max<size_t>(1, (size_t)total) * 4);
+    if (e == hipSuccess) e = hipMalloc(&L->val, std::max<size_t>(1, (size_t)total) * es);
+    if (e == hipSuccess) {
+        asm_launch_td_merge(dterms, (int)th.size(), n, L->rowptr, L->col, L->val, f64, ctx->stream);
         e = hipGetLastError();
     }
-    int hflags[2] = {0, 0};
-    int32_t total = 0;
-    e = e ? e : hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s);
-    e = e ? e : hipMemcpyAsync(&total, L->rowptr + n, 4, hipMemcpyDeviceToHost, s);
-    e = e ? e : hipStreamSynchronize(s);
-    if (e == hipSuccess && (hflags[0] || hflags[1])) {
-        tmp.release();
-        (void)hipFree(L->rowptr);
-        delete L;
-        return set_error(QT_EINVAL, hflags[0] ? "Liouvillian row has too many candidate entries for CSR assembly "
-                                                "(use the dense form)"
-                                              : "Liouvillian has more than 2^31 non-zeros");
-    }
-    if (e == hipSuccess) {
-        L->nnz = total;
-        e = hipMalloc(&L->col, std::max<size_t>(1, (size_t)total) * 4);
-        if (e == hipSuccess) e = hipMalloc(&L->val, std::max<size_t>(1, (size_t)total) * es);
-        if (e == hipSuccess) {
-            asm_launch_fill(op, L->rowptr, L->col, L->val, precision == QT_F64, s);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-    }
-    tmp.release();
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (dterms) (void)hipFree(dterms);
+    free_parts();
     if (e != hipSuccess) {
         if (L->rowptr) (void)hipFree(L->rowptr);
         if (L->col) (void)hipFree(L->col);
         if (L->val) (void)hipFree(L->val);
+        if (L->coefs) (void)hipFree(L->coefs);
         delete L;
-        return set_error(QT_EDEVICE, std::string("Liouvillian assembly: ") + hipGetErrorString(e));
+        return set_error(QT_EDEVICE, std::string("time-dependent Liouvillian: ") + hipGetErrorString(e));
     }
-    L->bytes = (int64_t)((n + 1) * 4 + L->nnz * (4 + (int64_t)es));
+    L->bytes = (int64_t)((n + 1) * 4 + total * (4 + (int64_t)es) + head + tab_bytes);
     ctx->refs++, *out = L;
+    return QT_OK;
+}
+
+qt_status qt_liouv_terms(const qt_liouv *L, int32_t *n_terms)
+{
+    if (!L || !n_terms) return set_error(QT_EINVAL, "qt_liouv_terms: null argument");
+    *n_terms = L->nterms;
     return QT_OK;
 }
 
@@ -574,6 +775,7 @@ qt_status qt_liouv_destroy(qt_liouv *L)
     if (L->col) (void)hipFree(L->col);
     if (L->val) (void)hipFree(L->val);
     if (L->dense) (void)hipFree(L->dense);
+    if (L->coefs) (void)hipFree(L->coefs);
     L->ctx->refs--;
     delete L;
     return QT_OK;

@@ -177,6 +177,7 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
 {
     if (!p || !p->L || !ticket) return set_error(QT_EINVAL, "qt_server_submit: null argument");
     if (p->L->precision != S->prec) return set_error(QT_EINVAL, "request precision differs from the server's");
+    if (p->L->nterms > 0) return set_error(QT_EINVAL, "time-dependent Liouvillians are solved through plans");
     if (p->n_t < 1 || !p->tlist || !p->rho0 || p->n_e < 0 || (p->n_e > 0 && !p->e_ops))
         return set_error(QT_EINVAL, "malformed request");
     for (int32_t i = 0; i < p->n_t; ++i)
