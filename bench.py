@@ -335,6 +335,73 @@ def section_serving(ctx, n=240, qps=40.0, n_fifo=24):
     return out
 
 
+def _optomech_ops(p):
+    """Operators of the driven optomechanical system (cavity first), built with scipy."""
+    import scipy.sparse as sp
+
+    def destroy(N):
+        return sp.diags(np.sqrt(np.arange(1, N, dtype=float)), 1, shape=(N, N), format="csr").astype(complex)
+
+    a = sp.kron(destroy(p["Nc"]), sp.identity(p["Nm"]), format="csr")
+    b = sp.kron(sp.identity(p["Nc"]), destroy(p["Nm"]), format="csr")
+    ad, bd = a.conj().T, b.conj().T
+    xa = (a + ad).tocsr()
+    H0 = (p["wc"] * (ad @ a) + p["wm"] * (bd @ b) + 0.5 * p["g"] * (xa @ xa) @ (b + bd)).tocsr()
+    c_ops = [np.sqrt(p["kappa"]) * a, np.sqrt(p["gamma"]) * b]
+    return H0, xa, c_ops, (ad @ a).tocsr()
+
+
+def section_td(ctx, n_sweep=64):
+    """Time-dependent master equation: the driven optomechanical system (drive F cos(w_d t) on
+    a + a^dag), one full solve over t in [0, 5/kappa] with 5000 saves in FP64 and mixed precision,
+    then n_sweep drive frequencies over t in [0, 100] in one plan (mixed)."""
+    p = workloads.optomech_td()
+    H0, xa, c_ops, n_op = _optomech_ops(p)
+    d = p["Nc"] * p["Nm"]
+    rho0 = np.zeros((d, d), complex)
+    rho0[0, 0] = 1.0
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    coef = {"kind": "cos", "a": p["F"], "omega": p["wd"]}
+    out = {"Nc": p["Nc"], "Nm": p["Nm"], "n": d * d, "t_end": p["t_end"], "n_t": p["nt"]}
+    res = {}
+    for name, prec in [("fp64", qt.F64), ("mixed", qt.MIXED)]:
+        L = qt.Liouvillian(ctx, H0, c_ops, qt.FORM_CSR, prec, h_terms=[(xa, coef)])
+        plan = qt.MePlan(ctx, [(L, rho0, tl, [n_op])], qt.opts(precision=prec, autotune=True))
+        plan.run()
+        t0 = time.perf_counter()
+        plan.run()
+        dt = time.perf_counter() - t0
+        ex, st, _ = plan.result(0)
+        res[name] = ex[0]
+        out[name] = {"seconds": dt, "n_accept": st["n_accept"], "n_reject": st["n_reject"], "n_rhs": st["n_rhs"],
+                     "rhs_per_s": st["n_rhs"] / dt, "nnz": L.info()[1], "csr_shape": list(plan.shape()[:4]),
+                     "n_final": float(ex[0, -1].real)}
+        plan.close()
+        L.close()
+    out["mixed_vs_fp64_max_abs"] = float(np.abs(res["mixed"] - res["fp64"]).max())
+    sweep = workloads.optomech_sweep(n=n_sweep)
+    probs, Ls = [], []
+    for q in sweep:
+        Hq, xq, cq, nq = _optomech_ops(q)
+        Lq = qt.Liouvillian(ctx, Hq, cq, qt.FORM_CSR, qt.MIXED,
+                            h_terms=[(xq, {"kind": "cos", "a": q["F"], "omega": q["wd"]})])
+        Ls.append(Lq)
+        probs.append((Lq, rho0, workloads.tlist(q["t_end"], q["nt"]), [nq]))
+    plan = qt.MePlan(ctx, probs, qt.opts(precision=qt.MIXED, autotune=True))
+    plan.run()
+    t0 = time.perf_counter()
+    plan.run()
+    dt = time.perf_counter() - t0
+    rhs = sum(plan.result(i)[1]["n_rhs"] for i in range(len(probs)))
+    out["sweep"] = {"instances": len(probs), "t_end": sweep[0]["t_end"], "seconds": dt,
+                    "solves_per_s": len(probs) / dt, "rhs_per_s": rhs / dt, "csr_shape": list(plan.shape()[:4])}
+    plan.close()
+    for Lq in Ls:
+        Lq.close()
+    log(f"td: {out}")
+    return out
+
+
 def copy_calibration(mbytes):
     """One device-to-device copy of a known size (the HIP runtime's copy kernel), so that hardware
     traffic counters collected on this run can be scaled to bytes."""
@@ -356,7 +423,7 @@ def kernel_source_digest():
     import hashlib
     src = os.path.join(ROOT, "paper_2504_21440_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("kernels_csr.hip", "qt_csr.h", "qt_common.h"):
+    for f in ("kernels_csr.hip", "csr_kernels.h", "qt_coef.h", "qt_csr.h", "qt_common.h"):
         with open(os.path.join(src, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -408,7 +475,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-extra", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving")
+    ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving,td")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweep-splits", default="80,48,32",
                     help="largest cutoff N solved in the dense form, one sweep per value (80: all dense)")
@@ -433,7 +500,7 @@ def main():
     log("ising batch")
     batch = section_ising_batch(ctx, mixed["rtol"], max(1, args.steps // 2), 1)
     extra = {}
-    only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving"}
+    only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving", "td"}
     if args.skip_extra:
         only = set()
     if "hbm" in only:
@@ -450,7 +517,10 @@ def main():
     if "serving" in only:
         log("serving")
         extra["serving"] = section_serving(ctx)
-    kname = "k_csr_stage<float,%d,%d,%d,3>" % (mixed["csr_shape"][0], mixed["csr_shape"][1],
+    if "td" in only:
+        log("time-dependent")
+        extra["td_optomechanics"] = section_td(ctx)
+    kname = "k_csr_stage<float,%d,%d,%d,3,false>" % (mixed["csr_shape"][0], mixed["csr_shape"][1],
                                                2 if mixed["csr_shape"][3] else 1)
     rl = {"bound": "hbm", "achieved": mixed["stage_kernel_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": mixed["stage_kernel_GBs"] / HBM_PEAK_GBS, "traffic": profiled_traffic(kname),
