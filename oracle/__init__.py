@@ -94,6 +94,10 @@ def _load():
         _lib.or_mesolve_td.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
                                        ctypes.c_int32, P, P, P, P, P]
         _lib.or_coef_eval.argtypes = [P, ctypes.c_double, P]
+        _lib.or_mcsolve_td.restype = ctypes.c_int32
+        _lib.or_mcsolve_td.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
+                                       ctypes.c_int32, P, P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P, P,
+                                       ctypes.c_int32, P, P, P, P]
     return _lib
 
 
@@ -310,11 +314,26 @@ def mcsolve(H, c_ops, psi0, tlist, e_ops, ntraj, seed, traj0=0, abstol=1e-8, rel
     Returns a dict with per-trajectory expectations ``expect_tr`` [ntraj][ne][nt], ensemble ``mean``
     [ne][nt] (complex), ``se`` [ne][nt] (standard error of the real part), ``njumps``, ``status``,
     and optionally the first ``max_jump_record`` jump times and channels."""
+    return mcsolve_td(H, [], c_ops, psi0, tlist, e_ops, ntraj, seed, traj0, abstol, reltol, max_steps, h0,
+                      max_jump_record)
+
+
+def mcsolve_td(H, h_terms, c_ops, psi0, tlist, e_ops, ntraj, seed, traj0=0, abstol=1e-8, reltol=1e-6,
+               max_steps=1_000_000, h0=0.0, max_jump_record=0):
+    """Monte-Carlo wave function (Sec. 3.3) with the time-dependent operators of Sec. 2 (QobjEvo):
+    H(t) = H + sum_i f_i(t) H_i with h_terms = [(H_i, spec)], and c_ops entries C_k or (C_k, spec)
+    for a collapse operator g_k(t) C_k: H_eff(t) = H(t) - (i/2) sum_k |g_k(t)|^2 C_k^dag C_k and a jump
+    at t* picks channel k with weight |g_k(t*)|^2 |C_k psi|^2.  Returns as ``mcsolve``."""
     lib = _load()
     psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
     tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    cs = [c[0] if isinstance(c, tuple) else c for c in c_ops]
+    gs = [c[1] if isinstance(c, tuple) else None for c in c_ops]
     Hp = _OpPack([H])
-    Cp = _OpPack(c_ops)
+    Tp = _OpPack([h for h, _ in h_terms])
+    Fp = _CoefPack([f for _, f in h_terms])
+    Cp = _OpPack(cs)
+    Gp = _CoefPack(gs)
     Ep = _OpPack(e_ops)
     ne, nt = len(e_ops), len(tl)
     ex = np.zeros((ntraj, ne, nt), dtype=np.complex128)
@@ -325,9 +344,11 @@ def mcsolve(H, c_ops, psi0, tlist, e_ops, ntraj, seed, traj0=0, abstol=1e-8, rel
     jc = np.zeros((ntraj, max(mj, 1)), dtype=np.int32)
     nrhs = ctypes.c_int64(0)
     o = opts(abstol, reltol, max_steps, h0)
-    rc = lib.or_mcsolve(Hp.ptr, len(c_ops), Cp.ptr, _ptr(psi0), nt, _ptr(tl), ne, Ep.ptr, ctypes.byref(o),
-                        ctypes.c_uint64(seed), ctypes.c_uint64(traj0), ctypes.c_int64(ntraj), _ptr(ex), _ptr(nj), mj,
-                        _ptr(jt), _ptr(jc), _ptr(stt), ctypes.byref(nrhs))
+    rc = lib.or_mcsolve_td(Hp.ptr, len(h_terms), Tp.ptr, Fp.ptr, len(cs), Cp.ptr,
+                           Gp.ptr if any(g is not None for g in gs) else None, _ptr(psi0), nt, _ptr(tl), ne,
+                           Ep.ptr, ctypes.byref(o), ctypes.c_uint64(seed), ctypes.c_uint64(traj0),
+                           ctypes.c_int64(ntraj), _ptr(ex), _ptr(nj), mj, _ptr(jt), _ptr(jc), _ptr(stt),
+                           ctypes.byref(nrhs))
     mean = np.zeros((ne, nt), dtype=np.complex128)
     se = np.zeros((ne, nt))
     lib.or_ensemble_stats(ntraj, ne, nt, _ptr(ex), _ptr(mean), _ptr(se))
@@ -344,6 +365,14 @@ def sesolve(H, psi0, tlist, e_ops, abstol=1e-8, reltol=1e-6, max_steps=1_000_000
     stepping as mcsolve; with no collapse operators no jump can happen, so one trajectory is the
     solution.  Returns (expect [ne][nt], status)."""
     out = mcsolve(H, [], psi0, tlist, e_ops, 1, 0, abstol=abstol, reltol=reltol, max_steps=max_steps, h0=h0)
+    return out["expect_tr"][0], int(out["status"][0])
+
+
+def sesolve_td(H, h_terms, psi0, tlist, e_ops, abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0):
+    """Schrodinger equation with H(t) = H + sum_i f_i(t) H_i: the no-collapse trajectory.
+    Returns (expect [ne][nt], status)."""
+    out = mcsolve_td(H, h_terms, [], psi0, tlist, e_ops, 1, 0, abstol=abstol, reltol=reltol, max_steps=max_steps,
+                     h0=h0)
     return out["expect_tr"][0], int(out["status"][0])
 
 

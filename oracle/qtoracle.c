@@ -13,6 +13,8 @@
  *     (the paper prints the dissipator with a minus inside the bracket; the
  *      anticommutator is the only trace-preserving reading and is the one used
  *      here -- the trace-invariant tests pin it);
+ *   - the time-dependent master equation and trajectories (H(t) = H_0 + sum_i
+ *     f_i(t) H_i, collapse operators g_k(t) C_k; Sec. 2 QobjEvo, Sec. 3.5);
  *   - the Monte-Carlo wave-function method, Sec. 3.3: evolution under
  *       H_eff = H - (i/2) sum_k C_k^dag C_k,
  *     a jump when the (squared) norm of the unnormalised state falls to a
@@ -818,7 +820,21 @@ typedef struct {
     const or_csr *C;
     own_csr *Cd;
     cplx *tmp; /* per-trajectory scratch, length d */
+    /* time-dependent terms: H(t) = H + sum_i f_i(t) H_i, collapse operators g_k(t) C_k */
+    int32_t nh;
+    const or_csr *Hk;
+    const or_coef *fh;
+    const or_coef *gc; /* NULL, or per operator (kind ORC_NONE: weight 1) */
 } mc_ctx;
+
+/* |g_k(t)|^2, the weight of collapse operator k at time t (1 without a coefficient) */
+static double mc_weight(const mc_ctx *m, int32_t k, double t)
+{
+    if (!m->gc || m->gc[k].kind == ORC_NONE)
+        return 1.0;
+    const cplx g = coef_at(&m->gc[k], t);
+    return creal(g) * creal(g) + cimag(g) * cimag(g);
+}
 
 static void csr_mv(const or_csr *A, const cplx *x, cplx *y)
 {
@@ -840,17 +856,22 @@ static void own_mv_acc(const own_csr *A, const cplx *x, cplx alpha, cplx *y)
     }
 }
 
-/* dpsi = -i H_eff psi = -i H psi - 1/2 sum_k C_k^dag (C_k psi) */
+/* dpsi = -i H_eff(t) psi = -i H(t) psi - 1/2 sum_k |g_k(t)|^2 C_k^dag (C_k psi) */
 static void mc_rhs(void *ctx, double t, const cplx *psi, cplx *dpsi)
 {
-    (void)t;
     mc_ctx *m = ctx;
     csr_mv(m->H, psi, dpsi);
     for (int32_t i = 0; i < m->d; ++i)
         dpsi[i] *= -I;
+    for (int32_t q = 0; q < m->nh; ++q) {
+        const cplx f = coef_at(&m->fh[q], t);
+        csr_mv(&m->Hk[q], psi, m->tmp);
+        for (int32_t i = 0; i < m->d; ++i)
+            dpsi[i] += -I * f * m->tmp[i];
+    }
     for (int32_t k = 0; k < m->nc; ++k) {
         csr_mv(&m->C[k], psi, m->tmp);
-        own_mv_acc(&m->Cd[k], m->tmp, -0.5, dpsi);
+        own_mv_acc(&m->Cd[k], m->tmp, -0.5 * mc_weight(m, k, t), dpsi);
     }
 }
 
@@ -975,20 +996,20 @@ static int32_t mc_trajectory(mc_ctx *m, const cplx *psi0, int32_t nt, const doub
                 }
             }
             double tj = s.t + th * ht;
-            /* channel probabilities p_k = |C_k psi|^2 */
+            /* channel probabilities p_k = |g_k(t*)|^2 |C_k psi|^2 */
             double u, rnext;
             or_traj_draw(seed, traj, event, &u, &rnext);
             ++event;
             double tot = 0.0;
             for (int32_t k = 0; k < m->nc; ++k) {
                 csr_mv(&m->C[k], ybest, cpsi);
-                tot += norm2(cpsi, d);
+                tot += mc_weight(m, k, tj) * norm2(cpsi, d);
             }
             double target = u * tot, cum = 0.0;
             int32_t ch = m->nc - 1;
             for (int32_t k = 0; k < m->nc; ++k) {
                 csr_mv(&m->C[k], ybest, cpsi);
-                cum += norm2(cpsi, d);
+                cum += mc_weight(m, k, tj) * norm2(cpsi, d);
                 if (cum >= target) {
                     ch = k;
                     break;
@@ -1029,10 +1050,11 @@ static int32_t mc_trajectory(mc_ctx *m, const cplx *psi0, int32_t nt, const doub
  *   njumps:    [ntraj]
  *   jt, jc:    [ntraj][maxj] first jump times / channels (nullable when maxj == 0)
  *   status:    [ntraj] */
-int32_t or_mcsolve(const or_csr *H, int32_t nc, const or_csr *c_ops, const double *psi0, int32_t nt,
-                   const double *tlist, int32_t ne, const or_csr *e_ops, const or_opts *o, uint64_t seed,
-                   uint64_t traj0, int64_t ntraj, double *expect_tr, int64_t *njumps, int32_t maxj, double *jt,
-                   int32_t *jc, int32_t *status, int64_t *n_rhs_total)
+int32_t or_mcsolve_td(const or_csr *H, int32_t nh, const or_csr *h_terms, const or_coef *h_coefs, int32_t nc,
+                      const or_csr *c_ops, const or_coef *c_coefs, const double *psi0, int32_t nt,
+                      const double *tlist, int32_t ne, const or_csr *e_ops, const or_opts *o, uint64_t seed,
+                      uint64_t traj0, int64_t ntraj, double *expect_tr, int64_t *njumps, int32_t maxj, double *jt,
+                      int32_t *jc, int32_t *status, int64_t *n_rhs_total)
 {
     if (check_tlist(nt, tlist))
         return OR_EINVAL;
@@ -1044,7 +1066,7 @@ int32_t or_mcsolve(const or_csr *H, int32_t nc, const or_csr *c_ops, const doubl
     int64_t tot_rhs = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : tot_rhs)
     for (int64_t j = 0; j < ntraj; ++j) {
-        mc_ctx m = {d, H, nc, c_ops, Cd, calloc(d, sizeof(cplx))};
+        mc_ctx m = {d, H, nc, c_ops, Cd, calloc(d, sizeof(cplx)), nh, h_terms, h_coefs, c_coefs};
         or_stats st;
         memset(&st, 0, sizeof(st));
         int32_t rc = mc_trajectory(&m, (const cplx *)psi0, nt, tlist, ne, e_ops, o, seed, traj0 + (uint64_t)j,
@@ -1065,6 +1087,15 @@ int32_t or_mcsolve(const or_csr *H, int32_t nc, const or_csr *c_ops, const doubl
     if (n_rhs_total)
         *n_rhs_total = tot_rhs;
     return worst;
+}
+
+int32_t or_mcsolve(const or_csr *H, int32_t nc, const or_csr *c_ops, const double *psi0, int32_t nt,
+                   const double *tlist, int32_t ne, const or_csr *e_ops, const or_opts *o, uint64_t seed,
+                   uint64_t traj0, int64_t ntraj, double *expect_tr, int64_t *njumps, int32_t maxj, double *jt,
+                   int32_t *jc, int32_t *status, int64_t *n_rhs_total)
+{
+    return or_mcsolve_td(H, 0, NULL, NULL, nc, c_ops, NULL, psi0, nt, tlist, ne, e_ops, o, seed, traj0, ntraj,
+                         expect_tr, njumps, maxj, jt, jc, status, n_rhs_total);
 }
 
 /* Ensemble mean and standard error (unbiased variance of the real part). */

@@ -15,6 +15,7 @@ Each coefficient kind is checked against exact mathematics the oracle does not c
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 import scipy.special as ssp
 
 import oracle
@@ -170,3 +171,93 @@ def test_optomechanics_invariants_short_window():
     assert np.all(ex[0].real >= -1e-9) and np.all(ex[0].real <= p["Nc"] - 1)
     assert np.abs(ex[0].imag).max() < 1e-9
     assert ex[0, -1].real > 1e-3  # the drive has populated the cavity
+
+
+# --------------------------------------------------------------------------------------------
+# Time-dependent trajectories (Sec. 3.3 with the time-dependent operators of Sec. 2)
+# --------------------------------------------------------------------------------------------
+def test_td_sesolve_rotating_qubit_rabi_closed_form():
+    """No dissipation: in the frame rotating with the drive the qubit precesses about
+    (W, 0, w0 - w), so <sz>(t) = 1 - 2 (W/WR)^2 sin^2(WR t / 2) from up, WR^2 = W^2 + (w0 - w)^2."""
+    w0, w, W = 4.0, 4.4, 1.3
+    sz, sm = om.sigmaz(), om.sigmam()
+    terms = [(_sigma_plus(), {"kind": "exp", "a": 0.5 * W, "omega": -w}),
+             (sm, {"kind": "exp", "a": 0.5 * W, "omega": w})]
+    tl = np.linspace(0.0, 8.0, 41)
+    ex, st = oracle.sesolve_td(0.5 * w0 * sz, terms, np.array([1, 0], complex), tl, [sz], **TIGHT)
+    assert st == 0
+    WR = np.hypot(W, w0 - w)
+    np.testing.assert_allclose(ex[0].real, 1 - 2 * (W / WR) ** 2 * np.sin(WR * tl / 2) ** 2, atol=1e-8)
+
+
+def _weighted_decay(g0, om_):
+    """Decay rate |g(t)|^2 = g0 cos^2(om t): the no-jump norm is exp(-Lambda(t)) with
+    Lambda(t) = g0 (t/2 + sin(2 om t) / (4 om))."""
+    return lambda t: g0 * (0.5 * t + np.sin(2 * om_ * t) / (4 * om_))
+
+
+def test_td_weighted_collapse_jump_time_is_exact():
+    """H = 0, one collapse operator sqrt(g0) cos(om t) sigma_-: trajectory j jumps when
+    Lambda(t*) = -ln r0, with r0 its Philox threshold."""
+    import scipy.optimize as so
+    g0, om_ = 0.4, 1.7
+    Lam = _weighted_decay(g0, om_)
+    tl = np.linspace(0, 10, 21)
+    seed = 31
+    res = oracle.mcsolve_td(0.0 * om.sigmaz(), [], [(om.sigmam(), {"kind": "cos", "a": np.sqrt(g0), "omega": om_})],
+                            np.array([1, 0], complex), tl, [om.sigmaz()], 48, seed, max_jump_record=2, **TIGHT)
+    assert (res["status"] == 0).all()
+    seen = 0
+    for j in range(48):
+        r0, _ = oracle.traj_draw(seed, j, 0)
+        target = -np.log(r0)
+        if Lam(tl[-1]) > target:
+            tstar = so.brentq(lambda t: Lam(t) - target, 0.0, tl[-1], xtol=1e-14)
+            assert res["njumps"][j] == 1
+            assert abs(res["jump_times"][j, 0] - tstar) < 1e-7, (j, res["jump_times"][j, 0], tstar)
+            seen += 1
+        else:
+            assert res["njumps"][j] == 0
+    assert seen > 10
+
+
+def test_td_channel_choice_uses_weights_at_the_jump_time():
+    """Two channels out of one level, C_0 = sqrt(a) |1><0| (constant) and C_1 = sqrt(b) cos(om t)
+    |2><0|: the first jump picks channel 0 exactly when u (a + b cos^2(om t*)) <= a, with u the
+    trajectory's Philox channel uniform."""
+    a_, b_, om_ = 0.5, 0.8, 2.3
+    C0 = sp.csr_matrix(([np.sqrt(a_)], ([1], [0])), shape=(3, 3), dtype=complex)
+    C1 = sp.csr_matrix(([1.0], ([2], [0])), shape=(3, 3), dtype=complex)
+    H = sp.csr_matrix((3, 3), dtype=complex)
+    seed, n = 41, 200
+    res = oracle.mcsolve_td(H, [], [C0, (C1, {"kind": "cos", "a": np.sqrt(b_), "omega": om_})],
+                            np.array([1, 0, 0], complex), np.linspace(0, 40, 3), [C0], n, seed, max_jump_record=1,
+                            **TIGHT)
+    jumped = np.nonzero(res["njumps"] >= 1)[0]
+    assert len(jumped) > 0.95 * n
+    for j in jumped:
+        ts = res["jump_times"][j, 0]
+        u, _ = oracle.traj_draw(seed, j, 1)
+        w1 = b_ * np.cos(om_ * ts) ** 2
+        want = 0 if u * (a_ + w1) <= a_ else 1
+        assert res["jump_channels"][j, 0] == want, (j, u, ts)
+
+
+def test_td_mc_matches_td_me():
+    """Sec. 3.3: the trajectory average reproduces the time-dependent master equation (a driven Kerr
+    cavity with a rotating drive and a Gaussian-weighted extra loss channel; the nonlinearity makes
+    the jumps matter).  Both at tight tolerances, so the statistics dominate the difference."""
+    N = 8
+    a = om.destroy(N)
+    ad = a.conj().T
+    H0 = (2.0 * om.number(N) + 0.5 * (ad @ ad @ a @ a)).tocsr()
+    terms = [(a.conj().T.tocsr(), {"kind": "exp", "a": 0.6, "omega": -1.5}), (a, {"kind": "exp", "a": 0.6, "omega": 1.5})]
+    c_ops = [np.sqrt(0.3) * a, (a, {"kind": "gauss", "a": 0.8, "t0": 2.0, "sigma": 1.0})]
+    tl = np.linspace(0, 5, 11)
+    me = oracle.mesolve_td(H0, terms, c_ops, om.fock_dm(N, 0), tl, [om.number(N)], **TIGHT)[0][0].real
+    n = 3000
+    mc = oracle.mcsolve_td(H0, terms, c_ops, np.eye(N, dtype=complex)[0], tl, [om.number(N)], n, 3, **TIGHT)
+    dev = np.abs(mc["mean"][0].real - me)
+    se = mc["se"][0]
+    assert se[-1] > 1e-3  # the trajectories differ
+    assert (dev[1:] <= 4 * se[1:] + 1e-7).all(), (dev, se)
