@@ -278,12 +278,35 @@ qt_status qt_mc_plan_result(qt_mc_plan *plan, double *mean_out, double *se_out, 
                             double *jump_times, int32_t *jump_channels, qt_stats *stats);
 qt_status qt_mc_plan_destroy(qt_mc_plan *plan);
 
+/* Time-dependent trajectories (Sec. 3.3 with the time-dependent operators of Sec. 2, QobjEvo):
+ *     H(t) = H + sum_i f_i(t) H_i,   collapse operator k is g_k(t) C_k where c_coefs[k] has a kind
+ *     other than QT_COEF_NONE (c_coefs nullable: every C_k constant),
+ * so H_eff(t) = H(t) - (i/2) sum_k |g_k(t)|^2 C_k^dag C_k, and a jump at t* picks channel k with
+ * probability proportional to |g_k(t*)|^2 |C_k psi|^2 and applies C_k psi / |C_k psi| (the phase of
+ * g_k drops out of every expectation value).  Coefficients as for qt_liouvillian_build_td; at most
+ * 31 terms (H_i plus weighted collapse operators).  With td NULL or empty these are the plain calls. */
+typedef struct {
+    int32_t n_h;
+    const qt_csr *h_terms;
+    const qt_coef *h_coefs;
+    const qt_coef *c_coefs;
+} qt_td_terms;
+qt_status qt_mc_plan_create_td(qt_ctx *ctx, const qt_mc_problem *prob, const qt_td_terms *td, const qt_opts *opts,
+                               int32_t max_jump_record, qt_mc_plan **out);
+qt_status qt_mcsolve_td(qt_ctx *ctx, const qt_mc_problem *prob, const qt_td_terms *td, const qt_opts *opts,
+                        double *mean_out, double *se_out, double *expect_tr, int64_t *njumps, int32_t max_jump_record,
+                        double *jump_times, int32_t *jump_channels, qt_stats *stats);
+
 /* Schrodinger equation (Sec. 3.1, sesolve): d psi/dt = -i H psi with the same adaptive
  * Dormand-Prince 5(4) integrator, save-time landing and precision modes; expect_out [n_e][n_t]
  * complex (host) holds <psi|O|psi> / <psi|psi> at every point of tlist.  psi0 (length d, host) is
  * normalised before use.  Runs as a single trajectory without collapse operators, so d <= 4096. */
 qt_status qt_sesolve(qt_ctx *ctx, const qt_csr *H, const double *psi0, int32_t n_t, const double *tlist, int32_t n_e,
                      const qt_csr *e_ops, const qt_opts *opts, double *expect_out, qt_stats *stats);
+/* The same with H(t) = H + sum_i f_i(t) H_i (td->c_coefs ignored). */
+qt_status qt_sesolve_td(qt_ctx *ctx, const qt_csr *H, const qt_td_terms *td, const double *psi0, int32_t n_t,
+                        const double *tlist, int32_t n_e, const qt_csr *e_ops, const qt_opts *opts, double *expect_out,
+                        qt_stats *stats);
 
 /* Continuous-batching server.  Requests are admitted while their device footprint fits in the
  * pool and a slot is free; admitted requests keep rho and solver state resident and are advanced

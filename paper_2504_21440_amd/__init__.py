@@ -25,7 +25,8 @@ EXPORTED = [
     "qt_liouv_destroy", "qt_liouvillian_build_td", "qt_liouv_terms", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
     "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_me_plan_autotune",
     "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
-    "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_sesolve", "qt_server_create", "qt_server_submit", "qt_server_step",
+    "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_sesolve", "qt_mc_plan_create_td", "qt_mcsolve_td",
+    "qt_sesolve_td", "qt_server_create", "qt_server_submit", "qt_server_step",
     "qt_server_poll", "qt_server_footprint", "qt_server_destroy",
 ]
 
@@ -404,16 +405,31 @@ def expect(ctx, O, dev_state_ptr, d, is_ket=False, precision=F64):
     return complex(out[0], out[1])
 
 
+class TdTerms(ctypes.Structure):
+    _fields_ = [("n_h", ctypes.c_int32), ("h_terms", ctypes.c_void_p), ("h_coefs", ctypes.c_void_p),
+                ("c_coefs", ctypes.c_void_p)]
+
+
 class _McProblem:
-    def __init__(self, H, c_ops, psi0, tlist, e_ops, ntraj, seed):
+    """c_ops entries are C_k or (C_k, coefficient spec); h_terms = [(H_i, spec)] (qt_td_terms)."""
+
+    def __init__(self, H, c_ops, psi0, tlist, e_ops, ntraj, seed, h_terms=None):
+        cs = [c[0] if isinstance(c, tuple) else c for c in c_ops]
+        gs = [c[1] if isinstance(c, tuple) else None for c in c_ops]
+        h_terms = h_terms or []
         self.H = _Ops([H])
-        self.C = _Ops(c_ops)
+        self.C = _Ops(cs)
         self.E = _Ops(e_ops)
         self.psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
         self.tl = np.ascontiguousarray(tlist, dtype=np.float64)
-        self.s = McProblem(self.H.ptr.value, len(c_ops), self.C.ptr.value, self.psi0.ctypes.data, len(self.tl),
+        self.s = McProblem(self.H.ptr.value, len(cs), self.C.ptr.value, self.psi0.ctypes.data, len(self.tl),
                            self.tl.ctypes.data, len(e_ops), self.E.ptr.value, int(ntraj), int(seed))
         self.ne, self.nt, self.ntraj = len(e_ops), len(self.tl), int(ntraj)
+        self.T = _Ops([h for h, _ in h_terms])
+        self.F = _Coefs([f for _, f in h_terms])
+        self.G = _Coefs(gs)
+        self.td = TdTerms(len(h_terms), self.T.ptr.value, self.F.ptr.value,
+                          self.G.ptr.value if any(g is not None for g in gs) else None)
 
 
 def _mc_outputs(p, want_traj, max_jump_record):
@@ -437,41 +453,54 @@ def _mc_pack(p, mean, se, tr, nj, mj, jt, jc, st):
     return out
 
 
-def mcsolve(ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, want_traj=False, max_jump_record=0):
-    """qt_mcsolve: dict with mean, se, njumps, stats and optionally per-trajectory data."""
-    p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed)
+def mcsolve(ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, want_traj=False, max_jump_record=0,
+            h_terms=None):
+    """qt_mcsolve (qt_mcsolve_td with h_terms or weighted c_ops): dict with mean, se, njumps, stats
+    and optionally per-trajectory data."""
+    p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed, h_terms)
     mean, se, tr, nj, mj, jt, jc = _mc_outputs(p, want_traj, max_jump_record)
     st = Stats()
     o = options or opts(precision=MIXED)
-    _check(lib().qt_mcsolve(ctx.h, ctypes.byref(p.s), ctypes.byref(o), _p(mean), _p(se), _p(tr), _p(nj), mj,
-                            _p(jt), _p(jc), ctypes.byref(st)))
+    if p.td.n_h or p.td.c_coefs:
+        _check(lib().qt_mcsolve_td(ctx.h, ctypes.byref(p.s), ctypes.byref(p.td), ctypes.byref(o), _p(mean), _p(se),
+                                   _p(tr), _p(nj), mj, _p(jt), _p(jc), ctypes.byref(st)))
+    else:
+        _check(lib().qt_mcsolve(ctx.h, ctypes.byref(p.s), ctypes.byref(o), _p(mean), _p(se), _p(tr), _p(nj), mj,
+                                _p(jt), _p(jc), ctypes.byref(st)))
     return _mc_pack(p, mean, se, tr, nj, mj, jt, jc, st)
 
 
-def sesolve(ctx, H, psi0, tlist, e_ops, options=None):
-    """qt_sesolve: (expect [n_e][n_t], stats) of the Schrodinger evolution of psi0 under H."""
-    p = _McProblem(H, [], psi0, tlist, e_ops, 1, 0)
+def sesolve(ctx, H, psi0, tlist, e_ops, options=None, h_terms=None):
+    """qt_sesolve (qt_sesolve_td with h_terms): (expect [n_e][n_t], stats) of the Schrodinger
+    evolution of psi0 under H (+ sum_i f_i(t) H_i)."""
+    p = _McProblem(H, [], psi0, tlist, e_ops, 1, 0, h_terms)
     ne, nt = len(e_ops), len(tlist)
     ex = np.zeros((max(ne, 1), nt), np.complex128)
     st = Stats()
     o = options or opts(precision=F64)
     vp = ctypes.c_void_p
-    _check(lib().qt_sesolve(ctx.h, vp(p.s.H), vp(p.s.psi0), ctypes.c_int32(p.s.n_t), vp(p.s.tlist),
-                            ctypes.c_int32(p.s.n_e), vp(p.s.e_ops), ctypes.byref(o), _p(ex), ctypes.byref(st)))
+    if h_terms:
+        _check(lib().qt_sesolve_td(ctx.h, vp(p.s.H), ctypes.byref(p.td), vp(p.s.psi0), ctypes.c_int32(p.s.n_t),
+                                   vp(p.s.tlist), ctypes.c_int32(p.s.n_e), vp(p.s.e_ops), ctypes.byref(o), _p(ex),
+                                   ctypes.byref(st)))
+    else:
+        _check(lib().qt_sesolve(ctx.h, vp(p.s.H), vp(p.s.psi0), ctypes.c_int32(p.s.n_t), vp(p.s.tlist),
+                                ctypes.c_int32(p.s.n_e), vp(p.s.e_ops), ctypes.byref(o), _p(ex), ctypes.byref(st)))
     return ex[:ne], st.as_dict()
 
 
 class McPlan:
     """qt_mc_plan_*: device-resident trajectory ensemble."""
 
-    def __init__(self, ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, max_jump_record=0):
+    def __init__(self, ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, max_jump_record=0,
+                 h_terms=None):
         self.ctx = ctx
-        self.p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed)
+        self.p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed, h_terms)
         o = options or opts(precision=MIXED)
         self.mj = int(max_jump_record)
         self.h = ctypes.c_void_p()
-        _check(lib().qt_mc_plan_create(ctx.h, ctypes.byref(self.p.s), ctypes.byref(o), self.mj,
-                                       ctypes.byref(self.h)))
+        _check(lib().qt_mc_plan_create_td(ctx.h, ctypes.byref(self.p.s), ctypes.byref(self.p.td), ctypes.byref(o),
+                                          self.mj, ctypes.byref(self.h)))
 
     def run(self):
         _check(lib().qt_mc_plan_run(self.h))

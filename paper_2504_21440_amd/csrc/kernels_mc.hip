@@ -14,8 +14,14 @@
 // reaches u * sum_k |C_k psi|^2; psi <- C_k psi / |C_k psi|; a new threshold is drawn.  Draws come
 // from Philox-4x32-10 keyed by the seed with counter (trajectory, event): event 0 gives the first
 // threshold, event m >= 1 the channel uniform and the next threshold of jump m.
+//
+// Time-dependent problems (TD): A(t) = A_0 + sum_i f_i(t) (-i H_i) + sum_k |g_k(t)|^2 (-1/2 C_k^dag C_k)
+// is one ELL whose entries carry their term in the high column bits; before each right-hand side
+// the workgroup evaluates the coefficients at the stage time (its own trajectory's t + c_s h) into
+// LDS, and a jump weights channel k by |g_k(t*)|^2.
 #include <algorithm>
 
+#include "qt_coef.h"
 #include "qt_common.h"
 #include "qt_mc.h"
 
@@ -74,7 +80,7 @@ __device__ __forceinline__ void block_sum_n(double *v, int n, double *scr)
     __syncthreads();
 }
 
-template <typename T, int R>
+template <typename T, int R, bool TD>
 __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ Pp)
 {
     using V = typename vec2<T>::type;
@@ -86,14 +92,24 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
     __shared__ double scr[48];
     __shared__ double pk[MC_MAXC];
     __shared__ unsigned long long jsh;
+    __shared__ V cwsh[MC_MAX_TERMS + 1];  // coefficients of the current right-hand side (TD)
     const int tid = threadIdx.x;
     const V *__restrict__ ev = (const V *)P.ell_val;
     const int32_t *__restrict__ ec = P.ell_col;
     const V *__restrict__ cv = (const V *)P.cval;
 
     auto row = [&](int m) { return tid + m * MC_THREADS; };
-    // out = A x for own rows
-    auto rhs = [&](const V *x, V(&out)[R]) {
+    // out = A(ts) x for own rows.  Every call site is preceded by a barrier after the previous
+    // call, so the coefficient row may be rewritten here.
+    auto rhs = [&](const V *x, V(&out)[R], double ts) {
+        if constexpr (TD) {
+            if (tid <= P.nterms) {
+                double2 w = make_double2(1.0, 0.0);
+                if (tid > 0) w = coef_value(P.coefs[tid - 1], ts);
+                cwsh[tid] = from_d2<V>(w);
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const int r = row(m);
@@ -101,9 +117,24 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
             acc.x = 0;
             acc.y = 0;
             if (r < d)
-                for (int k = 0; k < P.W; ++k) cfma(acc, ev[(size_t)k * d + r], x[ec[(size_t)k * d + r]]);
+                for (int k = 0; k < P.W; ++k) {
+                    const int32_t c = ec[(size_t)k * d + r];
+                    if constexpr (TD)
+                        cfma(acc, cmul(ev[(size_t)k * d + r], cwsh[c >> MC_TAG_SHIFT]),
+                             x[c & ((1 << MC_TAG_SHIFT) - 1)]);
+                    else
+                        cfma(acc, ev[(size_t)k * d + r], x[c]);
+                }
             out[m] = acc;
         }
+    };
+    // weight |g_k(t)|^2 of collapse channel k (1 when constant)
+    auto cweight = [&](int k, double tt) {
+        if constexpr (TD) {
+            const int q = P.cweight[k];
+            if (q >= 0) return coef_value(P.coefs[q], tt).x;  // stored with modsq: the squared modulus
+        }
+        return 1.0;
     };
     // <x|O_q|x> / <x|x> for every e_op, into expect_tr[j][q][idx]
     auto record = [&](const V *x, uint64_t j, int idx) {
@@ -173,7 +204,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                 }
             }
             __syncthreads();
-            rhs(xs0, k[1]);
+            rhs(xs0, k[1], t + DP5::c2 * hh);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const int r = row(m);
@@ -185,7 +216,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                 }
             }
             __syncthreads();
-            rhs(xs1, k[2]);
+            rhs(xs1, k[2], t + DP5::c3 * hh);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const int r = row(m);
@@ -198,7 +229,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                 }
             }
             __syncthreads();
-            rhs(xs0, k[3]);
+            rhs(xs0, k[3], t + DP5::c4 * hh);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const int r = row(m);
@@ -212,7 +243,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                 }
             }
             __syncthreads();
-            rhs(xs1, k[4]);
+            rhs(xs1, k[4], t + DP5::c5 * hh);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const int r = row(m);
@@ -227,7 +258,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                 }
             }
             __syncthreads();
-            rhs(xs0, k[5]);
+            rhs(xs0, k[5], t + hh);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const int r = row(m);
@@ -241,7 +272,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                 if (r < d) xs1[r] = x;
             }
             __syncthreads();
-            rhs(xs1, k[6]);
+            rhs(xs1, k[6], t + hh);
             nrhs += 6;
             double v[2] = {0.0, 0.0};
 #pragma unroll
@@ -265,7 +296,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
 
         double h = 0.0;
         if (P.nt > 1) {
-            rhs(xs0, k[0]);
+            rhs(xs0, k[0], t);
             nrhs += 1;
             if (P.use_h0) {
                 h = P.h0;
@@ -292,7 +323,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                     }
                 }
                 __syncthreads();
-                rhs(xs1, k[1]);
+                rhs(xs1, k[1], t + h0);
                 nrhs += 1;
                 double w2 = 0.0;
 #pragma unroll
@@ -399,7 +430,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                     v[0] += abs2d(acc);
                 }
                 block_sum_n(v, 1, scr);
-                if (tid == 0) pk[c] = v[0];
+                if (tid == 0) pk[c] = v[0] * cweight(c, tj);
             }
             __syncthreads();
             double tot = 0.0;
@@ -439,7 +470,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
             for (int m = 0; m < R; ++m)
                 if (row(m) < d) xs0[row(m)] = y[m];
             __syncthreads();
-            rhs(xs0, k[0]);
+            rhs(xs0, k[0], t);
             nrhs += 1;
             h = hn;
             if (at_stop) record(xs0, j, idx++);
@@ -485,30 +516,32 @@ __global__ __launch_bounds__(256) void k_mc_stats(const double2 *__restrict__ tr
 
 __global__ void k_mc_queue_reset(unsigned long long *q) { *q = 0ull; }
 
-template <typename T, int R> static const void *mc_fn() { return (const void *)k_mc<T, R>; }
+template <typename T, int R, bool TD> static const void *mc_fn() { return (const void *)k_mc<T, R, TD>; }
 
-template <typename T> static const void *mc_pick(int rows)
+template <typename T, bool TD> static const void *mc_pick(int rows)
 {
     switch (rows) {
-    case 1: return mc_fn<T, 1>();
-    case 2: return mc_fn<T, 2>();
-    case 4: return mc_fn<T, 4>();
-    case 8: return mc_fn<T, 8>();
-    default: return mc_fn<T, 16>();
+    case 1: return mc_fn<T, 1, TD>();
+    case 2: return mc_fn<T, 2, TD>();
+    case 4: return mc_fn<T, 4, TD>();
+    case 8: return mc_fn<T, 8, TD>();
+    default: return mc_fn<T, 16, TD>();
     }
 }
 
 template <typename T, int R>
-static void mc_launch_t(const McParams *dev_p, int grid, size_t lds, hipStream_t s)
+static void mc_launch_t(const McParams *dev_p, bool td, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_mc<T, R>), dim3(grid), dim3(MC_THREADS), lds, s, dev_p);
+    if (td) hipLaunchKernelGGL((k_mc<T, R, true>), dim3(grid), dim3(MC_THREADS), lds, s, dev_p);
+    else hipLaunchKernelGGL((k_mc<T, R, false>), dim3(grid), dim3(MC_THREADS), lds, s, dev_p);
 }
 
 static size_t mc_lds(const McParams &p, bool f64) { return (size_t)2 * p.d * (f64 ? 16 : 8); }
 
-int mc_grid(const McParams &p, bool f64, int device)
+int mc_grid(const McParams &p, bool f64, bool td, int device)
 {
-    const void *fn = f64 ? mc_pick<double>(p.rows) : mc_pick<float>(p.rows);
+    const void *fn = f64 ? (td ? mc_pick<double, true>(p.rows) : mc_pick<double, false>(p.rows))
+                         : (td ? mc_pick<float, true>(p.rows) : mc_pick<float, false>(p.rows));
     const size_t lds = mc_lds(p, f64);
     if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
@@ -520,24 +553,24 @@ int mc_grid(const McParams &p, bool f64, int device)
     return (int)std::max<int64_t>(1, g);
 }
 
-void mc_launch(const McParams &p, const McParams *dev_p, bool f64, int grid, hipStream_t s)
+void mc_launch(const McParams &p, const McParams *dev_p, bool f64, bool td, int grid, hipStream_t s)
 {
     const size_t lds = mc_lds(p, f64);
     if (f64) {
         switch (p.rows) {
-        case 1: mc_launch_t<double, 1>(dev_p, grid, lds, s); break;
-        case 2: mc_launch_t<double, 2>(dev_p, grid, lds, s); break;
-        case 4: mc_launch_t<double, 4>(dev_p, grid, lds, s); break;
-        case 8: mc_launch_t<double, 8>(dev_p, grid, lds, s); break;
-        default: mc_launch_t<double, 16>(dev_p, grid, lds, s); break;
+        case 1: mc_launch_t<double, 1>(dev_p, td, grid, lds, s); break;
+        case 2: mc_launch_t<double, 2>(dev_p, td, grid, lds, s); break;
+        case 4: mc_launch_t<double, 4>(dev_p, td, grid, lds, s); break;
+        case 8: mc_launch_t<double, 8>(dev_p, td, grid, lds, s); break;
+        default: mc_launch_t<double, 16>(dev_p, td, grid, lds, s); break;
         }
     } else {
         switch (p.rows) {
-        case 1: mc_launch_t<float, 1>(dev_p, grid, lds, s); break;
-        case 2: mc_launch_t<float, 2>(dev_p, grid, lds, s); break;
-        case 4: mc_launch_t<float, 4>(dev_p, grid, lds, s); break;
-        case 8: mc_launch_t<float, 8>(dev_p, grid, lds, s); break;
-        default: mc_launch_t<float, 16>(dev_p, grid, lds, s); break;
+        case 1: mc_launch_t<float, 1>(dev_p, td, grid, lds, s); break;
+        case 2: mc_launch_t<float, 2>(dev_p, td, grid, lds, s); break;
+        case 4: mc_launch_t<float, 4>(dev_p, td, grid, lds, s); break;
+        case 8: mc_launch_t<float, 8>(dev_p, td, grid, lds, s); break;
+        default: mc_launch_t<float, 16>(dev_p, td, grid, lds, s); break;
         }
     }
 }

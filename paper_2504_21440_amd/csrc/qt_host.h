@@ -87,6 +87,12 @@ struct Liouv {
     // host copies needed by the Monte-Carlo path and by the server footprint estimate
 };
 
+// Time-dependent coefficients: validation of a qt_coef (QT_COEF_NONE accepted when allow_none) and
+// its device descriptor (table pointer left null for the caller to place).
+struct CoefDev;
+qt_status check_coef(const qt_coef &c, bool allow_none, const char *what);
+CoefDev coef_from_abi(const qt_coef &c, int modsq);
+
 // Kernel launchers (defined in the .hip files)
 struct CsrInst;
 struct CsrCtl;

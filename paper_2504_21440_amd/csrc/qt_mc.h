@@ -12,6 +12,10 @@ namespace qt {
 
 constexpr int MC_THREADS = 256;
 constexpr int MC_MAX_ROWS = 16;  // rows of the state per thread: d <= 4096
+constexpr int MC_TAG_SHIFT = 26;
+constexpr int MC_MAX_TERMS = 31;
+
+struct CoefDev;
 
 struct McParams {
     int32_t d, W, nc, ne, nt, rows;  // rows = rows per thread (power of two)
@@ -39,10 +43,17 @@ struct McParams {
     int64_t *naccept;        // [ntraj]
     int64_t *nreject;        // [ntraj]
     unsigned long long *queue;  // next trajectory to start
+    // time dependence (nterms = 0: none): A(t) = A_0 + sum_i f_i(t) (-i H_i) + sum_k |g_k(t)|^2 (-1/2 C_k^dag C_k);
+    // an ELL entry's column carries its term (0 = constant part) above MC_TAG_SHIFT
+    int32_t nterms;
+    int32_t pad_td;
+    const CoefDev *coefs;     // [nterms]
+    const int32_t *cweight;   // [nc]: coefficient (index into coefs) of collapse channel k, -1 for constant
 };
 
-void mc_launch(const McParams &p, const McParams *dev_p, bool f64, int grid, hipStream_t s);
-int mc_grid(const McParams &p, bool f64, int device);
+// td: the plan has time-dependent terms (the weighted kernel)
+void mc_launch(const McParams &p, const McParams *dev_p, bool f64, bool td, int grid, hipStream_t s);
+int mc_grid(const McParams &p, bool f64, bool td, int device);
 void mc_launch_stats(const double2 *expect_tr, int64_t ntraj, int ne, int nt, double2 *mean, double *se,
                      hipStream_t s);
 void mc_launch_queue_reset(unsigned long long *q, hipStream_t s);

@@ -1,7 +1,8 @@
 // qtamd_mc.cpp -- Monte-Carlo wave-function plans (arXiv:2504.21440, Sec. 3.3).
 //
 // The plan builds A = -i H_eff = -i H - 1/2 sum_k C_k^dag C_k on the host (sparse, FP64), stores it
-// in ELL column-major order in the solve precision, uploads the jump operators, e_ops and the
+// in ELL column-major order in the solve precision (with time-dependent terms: every term's entries
+// in turn, each column tagged with its term), uploads the jump operators, e_ops and the
 // normalised initial state, and lays out the per-trajectory outputs.  Running it launches the
 // persistent trajectory kernel and the FP64 ensemble reduction; nothing returns to the host until
 // every trajectory has finished.
@@ -10,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "qt_coef.h"
 #include "qt_csr.h"
 #include "qt_host.h"
 #include "qt_mc.h"
@@ -21,13 +23,14 @@ struct qt_mc_plan {
     qt::Arena arena;
     size_t o_params = 0, o_mean = 0, o_se = 0;
     int grid = 1;
+    bool td = false;
     double last_ms = 0.0;
 };
 
 namespace qt {
 
-static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_opts *opts_in, int32_t maxj,
-                                qt_mc_plan **out)
+static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_td_terms *td, const qt_opts *opts_in,
+                                int32_t maxj, qt_mc_plan **out)
 {
     if (!ctx || !pr || !out || !pr->H) return set_error(QT_EINVAL, "qt_mc_plan_create: null argument");
     qt_opts o;
@@ -64,24 +67,76 @@ static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_opts
     }
     if (!(nrm > 0)) return set_error(QT_EINVAL, "psi0 is zero");
     nrm = std::sqrt(nrm);
+    // time-dependent terms
+    const int32_t n_h = td ? td->n_h : 0;
+    if (n_h < 0 || (n_h > 0 && (!td->h_terms || !td->h_coefs))) return set_error(QT_EINVAL, "bad time-dependent terms");
+    const qt_coef *c_coefs = td ? td->c_coefs : nullptr;
+    std::vector<HCsr> hs(n_h);
+    for (int i = 0; i < n_h; ++i) {
+        if ((st = check_coef(td->h_coefs[i], false, "h_coefs"))) return st;
+        if ((st = csr_from_abi(&td->h_terms[i], d, &hs[i], "h_terms"))) return st;
+    }
+    auto weighted = [&](int k) { return c_coefs && c_coefs[k].kind != QT_COEF_NONE; };
+    int n_w = 0;
+    for (int k = 0; k < pr->n_c; ++k)
+        if (c_coefs) {
+            if ((st = check_coef(c_coefs[k], true, "c_coefs"))) return st;
+            n_w += weighted(k);
+        }
+    const int nterms = n_h + n_w;
+    if (nterms > MC_MAX_TERMS) return set_error(QT_EINVAL, "at most 31 time-dependent terms");
 
-    // A = -i H - 1/2 sum_k C_k^dag C_k, stored in ELL (column-major)
-    HCsr A = csr_axpby(cd(0.0, -1.0), H, cd(0.0, 0.0), csr_zero(d));
-    for (auto &c : cs) A = csr_axpby(cd(1.0, 0.0), A, cd(-0.5, 0.0), csr_matmul(csr_adjoint(c), c));
+    // A = -i H - 1/2 sum_k C_k^dag C_k (constant channels), then -i H_i, then -1/2 C_k^dag C_k of each
+    // weighted channel, stored in ELL (column-major) with each entry's term above MC_TAG_SHIFT
+    std::vector<HCsr> terms;
+    std::vector<const qt_coef *> tsrc;  // coefficient of term t (t >= 1)
+    std::vector<int32_t> cweight(std::max(1, pr->n_c), -1);
+    {
+        HCsr A = csr_axpby(cd(0.0, -1.0), H, cd(0.0, 0.0), csr_zero(d));
+        for (int k = 0; k < pr->n_c; ++k)
+            if (!weighted(k))
+                A = csr_axpby(cd(1.0, 0.0), A, cd(-0.5, 0.0), csr_matmul(csr_adjoint(cs[k]), cs[k]));
+        terms.push_back(A);
+        for (int i = 0; i < n_h; ++i) {
+            terms.push_back(csr_axpby(cd(0.0, -1.0), hs[i], cd(0.0, 0.0), csr_zero(d)));
+            tsrc.push_back(&td->h_coefs[i]);
+        }
+        for (int k = 0; k < pr->n_c; ++k)
+            if (weighted(k)) {
+                terms.push_back(
+                    csr_axpby(cd(-0.5, 0.0), csr_matmul(csr_adjoint(cs[k]), cs[k]), cd(0.0, 0.0), csr_zero(d)));
+                cweight[k] = (int32_t)tsrc.size();
+                tsrc.push_back(&c_coefs[k]);
+            }
+    }
     int32_t W = 1;
-    for (int32_t i = 0; i < d; ++i) W = std::max<int32_t>(W, (int32_t)(A.ptr[i + 1] - A.ptr[i]));
+    for (int32_t i = 0; i < d; ++i) {
+        int32_t w = 0;
+        for (auto &T : terms) w += (int32_t)(T.ptr[i + 1] - T.ptr[i]);
+        W = std::max(W, w);
+    }
     const bool f64 = o.precision == QT_F64;
     const size_t es_b = f64 ? 16 : 8;
     std::vector<int32_t> ell_col((size_t)W * d);
     std::vector<double> ell_val((size_t)W * d * 2, 0.0);
     for (int32_t r = 0; r < d; ++r) {
         int32_t k = 0;
-        for (int64_t p = A.ptr[r]; p < A.ptr[r + 1]; ++p, ++k) {
-            ell_col[(size_t)k * d + r] = A.idx[p];
-            ell_val[2 * ((size_t)k * d + r)] = A.val[p].real();
-            ell_val[2 * ((size_t)k * d + r) + 1] = A.val[p].imag();
+        for (size_t t = 0; t < terms.size(); ++t) {
+            const HCsr &T = terms[t];
+            for (int64_t p = T.ptr[r]; p < T.ptr[r + 1]; ++p, ++k) {
+                ell_col[(size_t)k * d + r] = T.idx[p] | ((int32_t)t << MC_TAG_SHIFT);
+                ell_val[2 * ((size_t)k * d + r)] = T.val[p].real();
+                ell_val[2 * ((size_t)k * d + r) + 1] = T.val[p].imag();
+            }
         }
         for (; k < W; ++k) ell_col[(size_t)k * d + r] = r;  // padding: zero value on the diagonal
+    }
+    // coefficient descriptors, their sample tables after them
+    std::vector<CoefDev> cdev(std::max(1, nterms));
+    size_t tab_bytes = 0;
+    for (int t = 0; t < nterms; ++t) {
+        cdev[t] = coef_from_abi(*tsrc[t], t >= n_h ? 1 : 0);
+        if (tsrc[t]->kind == QT_COEF_TABLE) tab_bytes += (size_t)tsrc[t]->n_table * sizeof(double2);
     }
     std::vector<int32_t> cptr((size_t)std::max(1, pr->n_c) * (d + 1), 0), ccol;
     std::vector<double> cval;
@@ -150,7 +205,8 @@ static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_opts
                  o_nj = a.reserve((size_t)nj * 8), o_jt = a.reserve(std::max<size_t>(1, (size_t)nj * maxj) * 8),
                  o_jc = a.reserve(std::max<size_t>(1, (size_t)nj * maxj) * 4), o_st = a.reserve((size_t)nj * 4),
                  o_nr = a.reserve((size_t)nj * 8), o_na = a.reserve((size_t)nj * 8), o_nx = a.reserve((size_t)nj * 8),
-                 o_q = a.reserve(64);
+                 o_q = a.reserve(64), o_cf = a.reserve(sizeof(CoefDev) * cdev.size()),
+                 o_tab = a.reserve(std::max<size_t>(16, tab_bytes)), o_cw = a.reserve(cweight.size() * 4);
     P->o_mean = a.reserve(std::max<size_t>(1, (size_t)pr->n_e * pr->n_t) * 16);
     P->o_se = a.reserve(std::max<size_t>(1, (size_t)pr->n_e * pr->n_t) * 8);
     P->o_params = a.reserve(sizeof(McParams));
@@ -177,6 +233,22 @@ static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_opts
     p.naccept = (int64_t *)a.at(o_na);
     p.nreject = (int64_t *)a.at(o_nx);
     p.queue = (unsigned long long *)a.at(o_q);
+    p.nterms = nterms;
+    p.pad_td = 0;
+    p.coefs = (const CoefDev *)a.at(o_cf);
+    p.cweight = (const int32_t *)a.at(o_cw);
+    P->td = nterms > 0;
+    std::vector<char> tabs(std::max<size_t>(16, tab_bytes));
+    {
+        size_t off = 0;
+        for (int t = 0; t < nterms; ++t)
+            if (tsrc[t]->kind == QT_COEF_TABLE) {
+                const size_t nb = (size_t)tsrc[t]->n_table * sizeof(double2);
+                std::memcpy(tabs.data() + off, tsrc[t]->table, nb);
+                cdev[t].table = (const double2 *)((char *)a.at(o_tab) + off);
+                off += nb;
+            }
+    }
     hipStream_t s = ctx->stream;
     hipError_t e = hipSuccess;
     auto up = [&](size_t off, const void *src, size_t n) {
@@ -192,6 +264,9 @@ static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_opts
     up(o_eval, eval.data(), eval.size() * 16);
     up(o_ps, ps_b.data(), ps_b.size());
     up(o_tl, pr->tlist, (size_t)pr->n_t * 8);
+    up(o_cf, cdev.data(), sizeof(CoefDev) * cdev.size());
+    up(o_tab, tabs.data(), tab_bytes);
+    up(o_cw, cweight.data(), cweight.size() * 4);
     up(P->o_params, &p, sizeof(McParams));
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -199,7 +274,7 @@ static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_opts
         delete P;
         return set_error(QT_EDEVICE, std::string("mc plan upload: ") + hipGetErrorString(e));
     }
-    P->grid = mc_grid(p, f64, ctx->device);
+    P->grid = mc_grid(p, f64, P->td, ctx->device);
     ctx->refs++;
     *out = P;
     return QT_OK;
@@ -215,7 +290,7 @@ static qt_status mc_plan_run(qt_mc_plan *P)
     QT_HIP(hipEventCreate(&e1));
     QT_HIP(hipEventRecord(e0, s));
     mc_launch_queue_reset(P->p.queue, s);
-    mc_launch(P->p, (const McParams *)P->arena.at(P->o_params), f64, P->grid, s);
+    mc_launch(P->p, (const McParams *)P->arena.at(P->o_params), f64, P->td, P->grid, s);
     mc_launch_stats(P->p.expect_tr, P->p.ntraj, P->p.ne, P->p.nt, (double2 *)P->arena.at(P->o_mean),
                     (double *)P->arena.at(P->o_se), s);
     QT_HIP(hipGetLastError());
@@ -277,7 +352,13 @@ extern "C" {
 qt_status qt_mc_plan_create(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, int32_t max_jump_record,
                             qt_mc_plan **out)
 {
-    return mc_plan_create(ctx, prob, opts, max_jump_record, out);
+    return mc_plan_create(ctx, prob, nullptr, opts, max_jump_record, out);
+}
+
+qt_status qt_mc_plan_create_td(qt_ctx *ctx, const qt_mc_problem *prob, const qt_td_terms *td, const qt_opts *opts,
+                               int32_t max_jump_record, qt_mc_plan **out)
+{
+    return mc_plan_create(ctx, prob, td, opts, max_jump_record, out);
 }
 
 qt_status qt_mc_plan_run(qt_mc_plan *plan)
@@ -303,12 +384,12 @@ qt_status qt_mc_plan_destroy(qt_mc_plan *plan)
     return QT_OK;
 }
 
-qt_status qt_mcsolve(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, double *mean_out, double *se_out,
-                     double *expect_tr, int64_t *njumps, int32_t max_jump_record, double *jump_times,
-                     int32_t *jump_channels, qt_stats *stats)
+qt_status qt_mcsolve_td(qt_ctx *ctx, const qt_mc_problem *prob, const qt_td_terms *td, const qt_opts *opts,
+                        double *mean_out, double *se_out, double *expect_tr, int64_t *njumps, int32_t max_jump_record,
+                        double *jump_times, int32_t *jump_channels, qt_stats *stats)
 {
     qt_mc_plan *P = nullptr;
-    qt_status st = qt_mc_plan_create(ctx, prob, opts, max_jump_record, &P);
+    qt_status st = qt_mc_plan_create_td(ctx, prob, td, opts, max_jump_record, &P);
     if (st) {
         if (stats) stats->status = st;
         return st;
@@ -317,6 +398,14 @@ qt_status qt_mcsolve(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts
     if (!st) st = qt_mc_plan_result(P, mean_out, se_out, expect_tr, njumps, jump_times, jump_channels, stats);
     qt_mc_plan_destroy(P);
     return st;
+}
+
+qt_status qt_mcsolve(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, double *mean_out, double *se_out,
+                     double *expect_tr, int64_t *njumps, int32_t max_jump_record, double *jump_times,
+                     int32_t *jump_channels, qt_stats *stats)
+{
+    return qt_mcsolve_td(ctx, prob, nullptr, opts, mean_out, se_out, expect_tr, njumps, max_jump_record, jump_times,
+                         jump_channels, stats);
 }
 
 qt_status qt_sesolve(qt_ctx *ctx, const qt_csr *H, const double *psi0, int32_t n_t, const double *tlist, int32_t n_e,
@@ -336,6 +425,29 @@ qt_status qt_sesolve(qt_ctx *ctx, const qt_csr *H, const double *psi0, int32_t n
     p.ntraj = 1;
     p.seed = 0;
     return qt_mcsolve(ctx, &p, opts, expect_out, nullptr, nullptr, nullptr, 0, nullptr, nullptr, stats);
+}
+
+qt_status qt_sesolve_td(qt_ctx *ctx, const qt_csr *H, const qt_td_terms *td, const double *psi0, int32_t n_t,
+                        const double *tlist, int32_t n_e, const qt_csr *e_ops, const qt_opts *opts, double *expect_out,
+                        qt_stats *stats)
+{
+    qt_mc_problem p;
+    p.H = H;
+    p.n_c = 0;
+    p.c_ops = nullptr;
+    p.psi0 = psi0;
+    p.n_t = n_t;
+    p.tlist = tlist;
+    p.n_e = n_e;
+    p.e_ops = e_ops;
+    p.ntraj = 1;
+    p.seed = 0;
+    qt_td_terms h;
+    h.n_h = td ? td->n_h : 0;
+    h.h_terms = td ? td->h_terms : nullptr;
+    h.h_coefs = td ? td->h_coefs : nullptr;
+    h.c_coefs = nullptr;
+    return qt_mcsolve_td(ctx, &p, &h, opts, expect_out, nullptr, nullptr, nullptr, 0, nullptr, nullptr, stats);
 }
 
 }  // extern "C"

@@ -557,7 +557,30 @@ qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const 
     return QT_OK;
 }
 
-static qt_status check_coef(const qt_coef &c, bool allow_none, const char *what)
+}  // extern "C"
+
+namespace qt {
+
+CoefDev coef_from_abi(const qt_coef &c, int modsq)
+{
+    CoefDev g;
+    g.kind = c.kind;
+    g.n_table = c.kind == QT_COEF_TABLE ? c.n_table : 0;
+    g.modsq = modsq;
+    g.pad = 0;
+    g.a_re = c.a[0];
+    g.a_im = c.a[1];
+    g.omega = c.omega;
+    g.phi = c.phi;
+    g.t0 = c.t0;
+    g.sigma = c.sigma;
+    g.table_t0 = c.table_t0;
+    g.table_dt = c.table_dt;
+    g.table = nullptr;  // the caller places the samples in device memory
+    return g;
+}
+
+qt_status check_coef(const qt_coef &c, bool allow_none, const char *what)
 {
     if (allow_none && c.kind == QT_COEF_NONE) return QT_OK;
     if (c.kind < QT_COEF_CONST || c.kind > QT_COEF_TABLE)
@@ -568,6 +591,10 @@ static qt_status check_coef(const qt_coef &c, bool allow_none, const char *what)
         return set_error(QT_EINVAL, std::string(what) + ": table coefficient needs samples and table_dt > 0");
     return QT_OK;
 }
+
+}  // namespace qt
+
+extern "C" {
 
 qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, const qt_csr *h_terms,
                                   const qt_coef *h_coefs, int32_t n_c, const qt_csr *c_ops, const qt_coef *c_coefs,
@@ -677,18 +704,7 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
     for (int k = 0; k < nterms && e == hipSuccess; ++k) {
         const qt_coef &c = *src[k];
         CoefDev &g = cd_host[k];
-        g.kind = c.kind;
-        g.n_table = c.kind == QT_COEF_TABLE ? c.n_table : 0;
-        g.pad = 0;
-        g.a_re = c.a[0];
-        g.a_im = c.a[1];
-        g.omega = c.omega;
-        g.phi = c.phi;
-        g.t0 = c.t0;
-        g.sigma = c.sigma;
-        g.table_t0 = c.table_t0;
-        g.table_dt = c.table_dt;
-        g.table = nullptr;
+        g = coef_from_abi(c, g.modsq);
         if (c.kind == QT_COEF_TABLE) {
             std::memcpy(hostbuf.data() + toff, c.table, (size_t)c.n_table * sizeof(double2));
             g.table = (const double2 *)((char *)L->coefs + toff);

@@ -220,3 +220,101 @@ def test_td_error_paths(ctx):
     assert e.value.code == qt.QT_EINVAL
     srv.close()
     L.close()
+
+
+# --------------------------------------------------------------------------------------------
+# Time-dependent trajectories and Schrodinger evolution
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [(qt.F64, 1e-6), (qt.MIXED, 1e-4)])
+def test_td_sesolve_rotating_qubit(ctx, prec, tol):
+    """Rabi oscillation under a rotating drive: the oracle and the closed form of the rotating frame."""
+    print(f"[gpu] TD sesolve rotating qubit prec={prec}", flush=True)
+    w0, w, W = 4.0, 4.4, 1.3
+    sz, sm = om.sigmaz(), om.sigmam()
+    terms = [(sm.conj().T.tocsr(), {"kind": "exp", "a": 0.5 * W, "omega": -w}),
+             (sm, {"kind": "exp", "a": 0.5 * W, "omega": w})]
+    tl = np.linspace(0.0, 8.0, 41)
+    psi0 = np.array([1, 0], complex)
+    ref = oracle.sesolve_td(0.5 * w0 * sz, terms, psi0, tl, [sz, sm])[0]
+    ex, st = qt.sesolve(ctx, 0.5 * w0 * sz, psi0, tl, [sz, sm], qt.opts(precision=prec), h_terms=terms)
+    assert st["status"] == 0
+    assert np.abs(ex - ref).max() <= tol, np.abs(ex - ref).max()
+    WR = np.hypot(W, w0 - w)
+    assert np.abs(ex[0].real - (1 - 2 * (W / WR) ** 2 * np.sin(WR * tl / 2) ** 2)).max() <= max(tol, 1e-5)
+
+
+def test_td_weighted_decay_jump_times_exact(ctx):
+    """One collapse operator sqrt(g0) cos(om t) sigma_-: trajectory j jumps where
+    g0 (t/2 + sin(2 om t) / (4 om)) = -ln r0 (FP64, tight tolerances), as the oracle does."""
+    import scipy.optimize as so
+    print("[gpu] TD weighted decay jump times", flush=True)
+    g0, om_ = 0.4, 1.7
+    Lam = lambda t: g0 * (0.5 * t + np.sin(2 * om_ * t) / (4 * om_))
+    tl = np.linspace(0, 10, 21)
+    seed = 31
+    H = sp.csr_matrix((2, 2), dtype=complex)
+    c = [(om.sigmam(), {"kind": "cos", "a": np.sqrt(g0), "omega": om_})]
+    res = qt.mcsolve(ctx, H, c, np.array([1, 0], complex), tl, [om.sigmaz()], 48, seed,
+                     options=qt.opts(abstol=1e-12, reltol=1e-10, precision=qt.F64), want_traj=True,
+                     max_jump_record=2)
+    seen = 0
+    for j in range(48):
+        r0, _ = oracle.traj_draw(seed, j, 0)
+        target = -np.log(r0)
+        if Lam(tl[-1]) > target:
+            tstar = so.brentq(lambda t: Lam(t) - target, 0.0, tl[-1], xtol=1e-14)
+            assert res["njumps"][j] == 1
+            assert abs(res["jump_times"][j, 0] - tstar) < 1e-7
+            seen += 1
+        else:
+            assert res["njumps"][j] == 0
+    assert seen > 10
+
+
+def _td_kerr():
+    N = 8
+    a = om.destroy(N)
+    ad = a.conj().T
+    H0 = (2.0 * om.number(N) + 0.5 * (ad @ ad @ a @ a)).tocsr()
+    terms = [(ad.tocsr(), {"kind": "exp", "a": 0.6, "omega": -1.5}), (a, {"kind": "exp", "a": 0.6, "omega": 1.5})]
+    c_ops = [np.sqrt(0.3) * a, (a, {"kind": "gauss", "a": 0.8, "t0": 2.0, "sigma": 1.0})]
+    return N, H0, terms, c_ops
+
+
+@pytest.mark.parametrize("prec", [qt.F64, qt.MIXED])
+def test_td_trajectory_parity_with_oracle(ctx, prec):
+    """Same seed, same time-dependent trajectories: jump counts, channels, times and expectations
+    equal the oracle's in FP64; in mixed precision nearly every trajectory jumps alike."""
+    print(f"[gpu] TD trajectory parity prec={prec}", flush=True)
+    N, H0, terms, c_ops = _td_kerr()
+    psi0 = np.eye(N, dtype=complex)[0]
+    tl = np.linspace(0, 5, 11)
+    n, seed = 48, 13
+    ref = oracle.mcsolve_td(H0, terms, c_ops, psi0, tl, [om.number(N)], n, seed, max_jump_record=8)
+    res = qt.mcsolve(ctx, H0, c_ops, psi0, tl, [om.number(N)], n, seed, options=qt.opts(precision=prec),
+                     want_traj=True, max_jump_record=8, h_terms=terms)
+    assert ref["njumps"].sum() > n  # the weighted channel and the drive make jumps happen
+    if prec == qt.F64:
+        np.testing.assert_array_equal(res["njumps"], ref["njumps"])
+        for j in range(n):
+            m = min(8, int(ref["njumps"][j]))
+            np.testing.assert_array_equal(res["jump_channels"][j, :m], ref["jump_channels"][j, :m])
+            assert np.abs(res["jump_times"][j, :m] - ref["jump_times"][j, :m]).max(initial=0) < 1e-8
+        assert np.abs(res["expect_tr"] - ref["expect_tr"]).max() < 1e-6
+    else:
+        assert (res["njumps"] == ref["njumps"]).mean() > 0.9
+
+
+def test_td_ensemble_matches_td_master_equation(ctx):
+    """Sec. 3.3 with time-dependent operators: 4,000 mixed-precision trajectories against the oracle's
+    time-dependent master equation, within 4 standard errors."""
+    print("[gpu] TD ensemble vs TD master equation", flush=True)
+    N, H0, terms, c_ops = _td_kerr()
+    tl = np.linspace(0, 5, 11)
+    me = oracle.mesolve_td(H0, terms, c_ops, om.fock_dm(N, 0), tl, [om.number(N)])[0][0].real
+    res = qt.mcsolve(ctx, H0, c_ops, np.eye(N, dtype=complex)[0], tl, [om.number(N)], 4000, 21,
+                     options=qt.opts(abstol=1e-8, reltol=1e-6, precision=qt.MIXED), h_terms=terms)
+    mean, se = res["mean"][0].real, res["se"][0]
+    z = np.abs(mean - me)[1:] / np.maximum(se[1:], 1e-12)
+    print(f"[gpu]   max z = {z.max():.2f}", flush=True)
+    assert (z > 3).sum() <= 1 and z.max() < 4.5
