@@ -90,7 +90,8 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
     V *xs0 = (V *)smem;
     V *xs1 = xs0 + d;
     __shared__ double scr[48];
-    __shared__ double pk[MC_MAXC];
+    __shared__ double pk[MC_MAXC];  // channel weights |g_k(t*)|^2 |C_k psi|^2
+    __shared__ double pn[MC_MAXC];  // |C_k psi|^2, for the post-jump normalisation
     __shared__ unsigned long long jsh;
     __shared__ V cwsh[MC_MAX_TERMS + 1];  // coefficients of the current right-hand side (TD)
     const int tid = threadIdx.x;
@@ -430,7 +431,10 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                     v[0] += abs2d(acc);
                 }
                 block_sum_n(v, 1, scr);
-                if (tid == 0) pk[c] = v[0] * cweight(c, tj);
+                if (tid == 0) {
+                    pn[c] = v[0];
+                    pk[c] = v[0] * cweight(c, tj);
+                }
             }
             __syncthreads();
             double tot = 0.0;
@@ -445,7 +449,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
                     break;
                 }
             }
-            const double inv = 1.0 / sqrt(pk[ch]);
+            const double inv = 1.0 / sqrt(pn[ch]);
             const int32_t *cp = P.cptr + (size_t)ch * (d + 1);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
@@ -465,7 +469,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
             r_th = rnext;
             const bool at_stop = land && th == 1.0;
             t = at_stop ? P.tlist[idx] : tj;
-            __syncthreads();  // every thread is done reading xs1 / pk
+            __syncthreads();  // every thread is done reading xs1 / pk / pn
 #pragma unroll
             for (int m = 0; m < R; ++m)
                 if (row(m) < d) xs0[row(m)] = y[m];
