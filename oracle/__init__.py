@@ -94,6 +94,11 @@ def _load():
         _lib.or_mesolve_td.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
                                        ctypes.c_int32, P, P, P, P, P]
         _lib.or_coef_eval.argtypes = [P, ctypes.c_double, P]
+        _lib.or_sdesolve.restype = ctypes.c_int32
+        _lib.or_sdesolve.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32, P, P, ctypes.c_int32, P,
+                                     ctypes.c_int32, P, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_int64, P, P]
+        _lib.or_wiener_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P]
         _lib.or_mcsolve_td.restype = ctypes.c_int32
         _lib.or_mcsolve_td.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P,
                                        ctypes.c_int32, P, P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P, P,
@@ -374,6 +379,49 @@ def sesolve_td(H, h_terms, psi0, tlist, e_ops, abstol=1e-8, reltol=1e-6, max_ste
     out = mcsolve_td(H, h_terms, [], psi0, tlist, e_ops, 1, 0, abstol=abstol, reltol=reltol, max_steps=max_steps,
                      h0=h0)
     return out["expect_tr"][0], int(out["status"][0])
+
+
+def _sdesolve(sme, H, c_ops, sc_ops, x0, tlist, e_ops, ntraj, seed, dt, traj0):
+    lib = _load()
+    x0 = np.ascontiguousarray(x0, dtype=np.complex128)
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    Hp, Cp, Sp, Ep = _OpPack([H]), _OpPack(c_ops), _OpPack(sc_ops), _OpPack(e_ops)
+    ne, nt, m = len(e_ops), len(tl), len(sc_ops)
+    ex = np.zeros((ntraj, ne, nt), dtype=np.complex128)
+    meas = np.zeros((ntraj, m, max(nt - 1, 0)))
+    rc = lib.or_sdesolve(int(sme), Hp.ptr, len(c_ops), Cp.ptr, m, Sp.ptr, _ptr(x0), nt, _ptr(tl), ne, Ep.ptr,
+                         float(dt), ctypes.c_uint64(seed), ctypes.c_uint64(traj0), ctypes.c_int64(ntraj), _ptr(ex),
+                         _ptr(meas))
+    mean = np.zeros((ne, nt), dtype=np.complex128)
+    se = np.zeros((ne, nt))
+    lib.or_ensemble_stats(ntraj, ne, nt, _ptr(ex), _ptr(mean), _ptr(se))
+    return {"expect_tr": ex, "mean": mean, "se": se, "measurement": meas, "measurement_mean": meas.mean(axis=0),
+            "rc": rc}
+
+
+def ssesolve(H, sc_ops, psi0, tlist, e_ops, ntraj, seed, dt, traj0=0):
+    """Stochastic Schrodinger equation under homodyne detection (Sec. 3.6, Ito form) with a fixed
+    step of at most dt.  Returns expect_tr [ntraj][ne][nt], mean, se, measurement [ntraj][nsc][nt-1]
+    (the current J_n = <S_n + S_n^dag> + dW_n/dt averaged over each tlist interval)."""
+    psi0 = np.asarray(psi0, dtype=np.complex128)
+    return _sdesolve(0, H, [], sc_ops, psi0, tlist, e_ops, ntraj, seed, dt, traj0)
+
+
+def smesolve(H, c_ops, sc_ops, rho0, tlist, e_ops, ntraj, seed, dt, traj0=0):
+    """Stochastic master equation under homodyne detection (Sec. 3.6, Ito form); rho0 a density
+    matrix or a ket.  Returns as ``ssesolve``."""
+    rho0 = np.asarray(rho0, dtype=np.complex128)
+    if rho0.ndim == 1:
+        rho0 = np.outer(rho0, rho0.conj())
+    return _sdesolve(1, H, c_ops, sc_ops, rho0, tlist, e_ops, ntraj, seed, dt, traj0)
+
+
+def wiener_normals(seed, traj, step, pair):
+    """The two standard normals behind Wiener increments 2*pair and 2*pair + 1 of a step."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _load().or_wiener_normals(ctypes.c_uint64(seed), ctypes.c_uint64(traj), ctypes.c_uint32(step),
+                              ctypes.c_uint32(pair), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def ensemble_stats(expect_tr):

@@ -1098,6 +1098,252 @@ int32_t or_mcsolve(const or_csr *H, int32_t nc, const or_csr *c_ops, const doubl
                          expect_tr, njumps, maxj, jt, jc, status, n_rhs_total);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Stochastic Schrodinger and master equations under homodyne detection      */
+/* (Sec. 3.6), Ito form:                                                      */
+/*   SSE  d psi = -i K psi dt + sum_n M_n psi dW_n,                           */
+/*        K = H + i sum_n (e_n/2 S_n - 1/2 S_n^dag S_n - e_n^2/8),            */
+/*        M_n = S_n - e_n/2,  e_n = <psi|S_n + S_n^dag|psi>;                  */
+/*   SME  d rho = L rho dt + sum_n H[S_n] rho dW_n,  L with c_ops and sc_ops, */
+/*        H[S] rho = S rho + rho S^dag - Tr(S rho + rho S^dag) rho;           */
+/*   measurement current J_n = <S_n + S_n^dag> + dW_n/dt.                     */
+/* Both share one form: x' = A(x) dt + sum_n (B_n x - c mu_n(x) x) dW_n, with */
+/* mu_n(x) = <S_n + S_n^dag> in the state x (c = 1/2 for the SSE, 1 for the   */
+/* SME); for the SSE the drift also carries sum_n (mu_n/2 S_n x - mu_n^2/8 x).*/
+/* The paper does not name its SDE scheme.  Here: fixed steps (each tlist     */
+/* interval cut into ceil(length / dt) equal steps), the derivative-free      */
+/* order-1.0 strong scheme of Platen (Kloeden & Platen, "Numerical Solution   */
+/* of Stochastic Differential Equations", Sec. 11.1) applied to each Wiener   */
+/* process with its own supporting value (the cross terms of several          */
+/* processes are left out), and the state renormalised after every step      */
+/* (unit norm, unit trace).  Wiener increments: dW = sqrt(dt) z, z standard   */
+/* normal by the Box-Muller transform of two Philox-4x32-10 uniforms, counter */
+/* (traj_lo, traj_hi, step, 1 + n/2), n even -> cos branch, n odd -> sin.     */
+/* ------------------------------------------------------------------------- */
+void or_wiener_normals(uint64_t seed, uint64_t traj, uint32_t step, uint32_t pair, double *z0, double *z1)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)traj, (uint32_t)(traj >> 32), step, 1u + pair};
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    double u1 = or_uniform_from_words(w[0], w[1]);
+    double u2 = or_uniform_from_words(w[2], w[3]);
+    double r = sqrt(-2.0 * log(u1));
+    const double two_pi = 6.283185307179586476925286766559;
+    *z0 = r * cos(two_pi * u2);
+    *z1 = r * sin(two_pi * u2);
+}
+
+typedef struct {
+    int32_t d, nsc, sme;
+    int64_t n;          /* state length: d (SSE) or d*d (SME) */
+    const or_csr *H;
+    const or_csr *S;    /* sc_ops */
+    own_csr *Sd;        /* S_n^dag */
+    me_ctx me;          /* SME: the Lindbladian with c_ops and sc_ops */
+    cplx *tmp;          /* length n */
+} sde_ctx;
+
+/* out = B_n x: S_n psi (SSE), S_n rho + rho S_n^dag (SME) */
+static void sde_noise_op(sde_ctx *c, int32_t k, const cplx *x, cplx *out)
+{
+    if (!c->sme) {
+        csr_mv(&c->S[k], x, out);
+        return;
+    }
+    own_csr Sk = own_copy(&c->S[k]);
+    memset(out, 0, sizeof(cplx) * c->n);
+    acc_AX(&Sk, x, 1.0, out);
+    acc_XA(x, &c->Sd[k], 1.0, out);
+    own_free(&Sk);
+}
+
+/* mu_n = <S_n + S_n^dag>: 2 Re<psi|S psi>/<psi|psi> (SSE), Re Tr(S rho + rho S^dag) (SME) */
+static double sde_mu(const sde_ctx *c, const cplx *x, const cplx *Bx)
+{
+    if (!c->sme) {
+        cplx num = 0.0;
+        double den = 0.0;
+        for (int64_t i = 0; i < c->n; ++i) {
+            num += conj(x[i]) * Bx[i];
+            den += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+        }
+        return 2.0 * creal(num) / den;
+    }
+    double tr = 0.0;
+    for (int32_t i = 0; i < c->d; ++i)
+        tr += creal(Bx[(int64_t)i * c->d + i]);
+    return tr;
+}
+
+/* drift a(x) given B_n x and mu_n already computed at x */
+static void sde_drift(sde_ctx *c, const cplx *x, cplx *const *Bx, const double *mu, cplx *a)
+{
+    if (c->sme) {
+        me_rhs(&c->me, 0.0, x, a);
+        return;
+    }
+    /* -i H psi - 1/2 sum S^dag S psi + sum (mu/2 S psi - mu^2/8 psi) */
+    csr_mv(c->H, x, a);
+    for (int64_t i = 0; i < c->n; ++i)
+        a[i] *= -I;
+    for (int32_t k = 0; k < c->nsc; ++k) {
+        own_mv_acc(&c->Sd[k], Bx[k], -0.5, a);
+        for (int64_t i = 0; i < c->n; ++i)
+            a[i] += 0.5 * mu[k] * Bx[k][i] - 0.125 * mu[k] * mu[k] * x[i];
+    }
+}
+
+static void sde_normalise(const sde_ctx *c, cplx *x)
+{
+    double s = 0.0;
+    if (c->sme) {
+        for (int32_t i = 0; i < c->d; ++i)
+            s += creal(x[(int64_t)i * c->d + i]);
+    } else {
+        s = sqrt(norm2(x, c->n));
+    }
+    for (int64_t i = 0; i < c->n; ++i)
+        x[i] /= s;
+}
+
+static void sde_record(const sde_ctx *c, const cplx *x, int32_t ne, const or_csr *e_ops, int32_t nt, int32_t idx,
+                       double *expect_tr)
+{
+    for (int32_t k = 0; k < ne; ++k) {
+        cplx v = c->sme ? trace_O_rho(&e_ops[k], x, c->d) : expect_ket(&e_ops[k], x, c->d);
+        expect_tr[2 * ((int64_t)k * nt + idx)] = creal(v);
+        expect_tr[2 * ((int64_t)k * nt + idx) + 1] = cimag(v);
+    }
+}
+
+/* One trajectory.  meas: [nsc][nt-1], the current averaged over each tlist interval. */
+static void sde_trajectory(sde_ctx *c, const cplx *x0, int32_t nt, const double *tlist, int32_t ne,
+                           const or_csr *e_ops, double dt, uint64_t seed, uint64_t traj, double *expect_tr,
+                           double *meas)
+{
+    const int64_t n = c->n;
+    const int32_t m = c->nsc;
+    const double cg = c->sme ? 1.0 : 0.5; /* mu multiple removed by the diffusion */
+    cplx *x = calloc(n, sizeof(cplx)), *a = calloc(n, sizeof(cplx)), *xs = calloc(n, sizeof(cplx));
+    cplx *xn = calloc(n, sizeof(cplx));
+    cplx **Bx = malloc(sizeof(cplx *) * (m ? m : 1)), **Bs = malloc(sizeof(cplx *) * (m ? m : 1));
+    for (int32_t k = 0; k < m; ++k) {
+        Bx[k] = calloc(n, sizeof(cplx));
+        Bs[k] = calloc(n, sizeof(cplx));
+    }
+    double *mu = calloc(m ? m : 1, sizeof(double)), *dW = calloc(m ? m : 1, sizeof(double));
+    double *acc = calloc(m ? m : 1, sizeof(double));
+    memcpy(x, x0, sizeof(cplx) * n);
+    sde_normalise(c, x);
+    sde_record(c, x, ne, e_ops, nt, 0, expect_tr);
+    uint32_t step = 0;
+    for (int32_t iv = 0; iv + 1 < nt; ++iv) {
+        const double len = tlist[iv + 1] - tlist[iv];
+        int64_t ns = (int64_t)ceil(len / dt * (1.0 - 1e-12));
+        if (ns < 1)
+            ns = 1;
+        const double h = len / (double)ns, sq = sqrt(h);
+        for (int32_t k = 0; k < m; ++k)
+            acc[k] = 0.0;
+        for (int64_t q = 0; q < ns; ++q, ++step) {
+            for (int32_t k = 0; k < m; k += 2) {
+                double z0, z1;
+                or_wiener_normals(seed, traj, step, (uint32_t)(k / 2), &z0, &z1);
+                dW[k] = sq * z0;
+                if (k + 1 < m)
+                    dW[k + 1] = sq * z1;
+            }
+            /* a(Y), b_n(Y) = B_n Y - cg mu_n Y */
+            for (int32_t k = 0; k < m; ++k) {
+                sde_noise_op(c, k, x, Bx[k]);
+                mu[k] = sde_mu(c, x, Bx[k]);
+                acc[k] += mu[k] * h + dW[k];
+            }
+            sde_drift(c, x, Bx, mu, a);
+            /* Y' = Y + a h + sum_n b_n dW_n + sum_n (b_n(Ups_n) - b_n(Y)) (dW_n^2 - h) / (2 sqrt h),
+             * Ups_n = Y + a h + b_n sqrt h */
+            for (int64_t i = 0; i < n; ++i)
+                xn[i] = x[i] + a[i] * h;
+            for (int32_t k = 0; k < m; ++k) {
+                const double w = (dW[k] * dW[k] - h) / (2.0 * sq);
+                for (int64_t i = 0; i < n; ++i) {
+                    const cplx b = Bx[k][i] - cg * mu[k] * x[i];
+                    xs[i] = x[i] + a[i] * h + b * sq;
+                }
+                sde_noise_op(c, k, xs, Bs[k]);
+                const double ms = sde_mu(c, xs, Bs[k]);
+                for (int64_t i = 0; i < n; ++i) {
+                    const cplx b = Bx[k][i] - cg * mu[k] * x[i];
+                    const cplx bs = Bs[k][i] - cg * ms * xs[i];
+                    xn[i] += b * dW[k] + (bs - b) * w;
+                }
+            }
+            memcpy(x, xn, sizeof(cplx) * n);
+            sde_normalise(c, x);
+        }
+        for (int32_t k = 0; k < m; ++k)
+            meas[(int64_t)k * (nt - 1) + iv] = acc[k] / len;
+        sde_record(c, x, ne, e_ops, nt, iv + 1, expect_tr);
+    }
+    for (int32_t k = 0; k < m; ++k) {
+        free(Bx[k]);
+        free(Bs[k]);
+    }
+    free(Bx);
+    free(Bs);
+    free(mu);
+    free(dW);
+    free(acc);
+    free(x);
+    free(a);
+    free(xs);
+    free(xn);
+}
+
+/* SSE (sme = 0, x0 = psi0 of length d, c_ops ignored) or SME (sme = 1, x0 = rho0 d x d);
+ * expect_tr [ntraj][ne][nt], meas [ntraj][nsc][nt-1]. */
+int32_t or_sdesolve(int32_t sme, const or_csr *H, int32_t nc, const or_csr *c_ops, int32_t nsc, const or_csr *sc_ops,
+                    const double *x0, int32_t nt, const double *tlist, int32_t ne, const or_csr *e_ops, double dt,
+                    uint64_t seed, uint64_t traj0, int64_t ntraj, double *expect_tr, double *meas)
+{
+    if (check_tlist(nt, tlist) || !(dt > 0.0))
+        return OR_EINVAL;
+    const int32_t d = H->d;
+    const int64_t n = sme ? (int64_t)d * d : d;
+    own_csr *Sd = malloc(sizeof(own_csr) * (nsc ? nsc : 1));
+    for (int32_t k = 0; k < nsc; ++k)
+        Sd[k] = own_adjoint(&sc_ops[k]);
+    or_csr *all = malloc(sizeof(or_csr) * (nc + nsc ? nc + nsc : 1));
+    for (int32_t k = 0; k < nc; ++k)
+        all[k] = c_ops[k];
+    for (int32_t k = 0; k < nsc; ++k)
+        all[nc + k] = sc_ops[k];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < ntraj; ++j) {
+        sde_ctx c;
+        c.d = d;
+        c.nsc = nsc;
+        c.sme = sme;
+        c.n = n;
+        c.H = H;
+        c.S = sc_ops;
+        c.Sd = Sd;
+        c.tmp = NULL;
+        if (sme)
+            me_ctx_init(&c.me, H, nc + nsc, all);
+        sde_trajectory(&c, (const cplx *)x0, nt, tlist, ne, e_ops, dt, seed, traj0 + (uint64_t)j,
+                       expect_tr + 2 * j * (int64_t)ne * nt, meas + j * (int64_t)nsc * (nt > 1 ? nt - 1 : 0));
+        if (sme)
+            me_ctx_free(&c.me);
+    }
+    for (int32_t k = 0; k < nsc; ++k)
+        own_free(&Sd[k]);
+    free(Sd);
+    free(all);
+    return OR_OK;
+}
+
 /* Ensemble mean and standard error (unbiased variance of the real part). */
 void or_ensemble_stats(int64_t ntraj, int32_t ne, int32_t nt, const double *expect_tr, double *mean,
                        double *se)
