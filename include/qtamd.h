@@ -308,6 +308,52 @@ qt_status qt_sesolve_td(qt_ctx *ctx, const qt_csr *H, const qt_td_terms *td, con
                         const double *tlist, int32_t n_e, const qt_csr *e_ops, const qt_opts *opts, double *expect_out,
                         qt_stats *stats);
 
+/* Stochastic Schrodinger (SSE) and master (SME) equations under homodyne detection (Sec. 3.6, Ito
+ * form): with measured operators S_n (sc_ops) and Wiener increments dW_n,
+ *   SSE  d psi = -i K psi dt + sum_n (S_n - e_n/2) psi dW_n,
+ *        K = H + i sum_n (e_n/2 S_n - 1/2 S_n^dag S_n - e_n^2/8),  e_n = <psi|S_n + S_n^dag|psi>;
+ *   SME  d rho = -i[H, rho] dt + sum_i D[C_i] rho dt + sum_n D[S_n] rho dt
+ *               + sum_n (S_n rho + rho S_n^dag - Tr(S_n rho + rho S_n^dag) rho) dW_n;
+ * measurement current J_n = <S_n + S_n^dag> + dW_n/dt (reported averaged over each tlist interval).
+ * Fixed steps: each tlist interval is cut into ceil(length / dt) equal steps; each step is the
+ * derivative-free order-1.0 strong scheme of Platen applied to each Wiener process (exact order 1
+ * for one measured operator), followed by renormalisation (unit norm / unit trace).  dW_n =
+ * sqrt(h) z, z standard normal from Philox-4x32-10 keyed by seed with counter (trajectory_lo,
+ * trajectory_hi, step, 1 + n/2) through the Box-Muller transform (n even: cos, odd: sin).
+ * SSE: state0 a ket (is_ket = 1), no c_ops.  SME: state0 a d x d density matrix or a ket.
+ * Limits: state length (d, or d*d for the SME) <= 4096, at most 8 measured operators.
+ * Outputs (host): mean_out [n_e][n_t] complex, se_out [n_e][n_t] standard error of the real part,
+ * expect_tr [ntraj][n_e][n_t] complex, meas_mean [n_sc][n_t - 1] and meas_tr
+ * [ntraj][n_sc][n_t - 1] currents; each nullable. */
+typedef struct qt_sde_plan qt_sde_plan;
+typedef struct {
+    const qt_csr *H;
+    int32_t n_c;
+    const qt_csr *c_ops;
+    int32_t n_sc;
+    const qt_csr *sc_ops;
+    const double *state0;
+    int32_t is_ket;
+    int32_t n_t;
+    const double *tlist;
+    int32_t n_e;
+    const qt_csr *e_ops;
+    int64_t ntraj;
+    uint64_t seed;
+    double dt;
+} qt_sde_problem;
+/* master: 0 SSE, 1 SME */
+qt_status qt_sde_plan_create(qt_ctx *ctx, const qt_sde_problem *prob, int32_t master, const qt_opts *opts,
+                             qt_sde_plan **out);
+qt_status qt_sde_plan_run(qt_sde_plan *plan);
+qt_status qt_sde_plan_result(qt_sde_plan *plan, double *mean_out, double *se_out, double *expect_tr,
+                             double *meas_mean, double *meas_tr, qt_stats *stats);
+qt_status qt_sde_plan_destroy(qt_sde_plan *plan);
+qt_status qt_ssesolve(qt_ctx *ctx, const qt_sde_problem *prob, const qt_opts *opts, double *mean_out, double *se_out,
+                      double *meas_mean, qt_stats *stats);
+qt_status qt_smesolve(qt_ctx *ctx, const qt_sde_problem *prob, const qt_opts *opts, double *mean_out, double *se_out,
+                      double *meas_mean, qt_stats *stats);
+
 /* Continuous-batching server.  Requests are admitted while their device footprint fits in the
  * pool and a slot is free; admitted requests keep rho and solver state resident and are advanced
  * together, epoch by epoch, with requests that arrived earlier.  submit returns QT_EBUSY when the

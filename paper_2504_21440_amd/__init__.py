@@ -26,7 +26,8 @@ EXPORTED = [
     "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_me_plan_autotune",
     "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
     "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_sesolve", "qt_mc_plan_create_td", "qt_mcsolve_td",
-    "qt_sesolve_td", "qt_server_create", "qt_server_submit", "qt_server_step",
+    "qt_sesolve_td", "qt_sde_plan_create", "qt_sde_plan_run", "qt_sde_plan_result", "qt_sde_plan_destroy",
+    "qt_ssesolve", "qt_smesolve", "qt_server_create", "qt_server_submit", "qt_server_step",
     "qt_server_poll", "qt_server_footprint", "qt_server_destroy",
 ]
 
@@ -68,6 +69,14 @@ class McProblem(ctypes.Structure):
                 ("psi0", ctypes.c_void_p), ("n_t", ctypes.c_int32), ("tlist", ctypes.c_void_p),
                 ("n_e", ctypes.c_int32), ("e_ops", ctypes.c_void_p), ("ntraj", ctypes.c_int64),
                 ("seed", ctypes.c_uint64)]
+
+
+class SdeProblem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_void_p), ("n_c", ctypes.c_int32), ("c_ops", ctypes.c_void_p),
+                ("n_sc", ctypes.c_int32), ("sc_ops", ctypes.c_void_p), ("state0", ctypes.c_void_p),
+                ("is_ket", ctypes.c_int32), ("n_t", ctypes.c_int32), ("tlist", ctypes.c_void_p),
+                ("n_e", ctypes.c_int32), ("e_ops", ctypes.c_void_p), ("ntraj", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("dt", ctypes.c_double)]
 
 
 class CsrShape(ctypes.Structure):
@@ -578,3 +587,73 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class SdePlan:
+    """qt_sde_plan_*: stochastic Schrodinger (master=False) or master (master=True) equation under
+    homodyne detection, ntraj trajectories with a fixed step of at most dt."""
+
+    def __init__(self, ctx, H, sc_ops, state0, tlist, e_ops, ntraj, seed, dt, c_ops=(), master=False, options=None):
+        self.ctx = ctx
+        self.H, self.C, self.S, self.E = _Ops([H]), _Ops(list(c_ops)), _Ops(list(sc_ops)), _Ops(list(e_ops))
+        self.x0 = np.ascontiguousarray(state0, dtype=np.complex128)
+        self.tl = np.ascontiguousarray(tlist, dtype=np.float64)
+        self.ne, self.nt, self.m, self.ntraj = len(e_ops), len(self.tl), len(sc_ops), int(ntraj)
+        self.s = SdeProblem(self.H.ptr.value, len(c_ops), self.C.ptr.value, len(sc_ops), self.S.ptr.value,
+                            self.x0.ctypes.data, 1 if self.x0.ndim == 1 else 0, self.nt, self.tl.ctypes.data,
+                            self.ne, self.E.ptr.value, self.ntraj, int(seed), float(dt))
+        o = options or opts(precision=MIXED)
+        self.h = ctypes.c_void_p()
+        _check(lib().qt_sde_plan_create(ctx.h, ctypes.byref(self.s), int(bool(master)), ctypes.byref(o),
+                                        ctypes.byref(self.h)))
+
+    def run(self):
+        _check(lib().qt_sde_plan_run(self.h))
+
+    def result(self, want_traj=False):
+        """dict: mean [n_e][n_t], se, measurement_mean [n_sc][n_t-1], stats, and with want_traj
+        expect_tr [ntraj][n_e][n_t] and measurement [ntraj][n_sc][n_t-1]."""
+        ne, nt, m, nj = self.ne, self.nt, self.m, self.ntraj
+        mean = np.zeros((max(ne, 1), nt), np.complex128)
+        se = np.zeros((max(ne, 1), nt))
+        tr = np.zeros((nj, max(ne, 1), nt), np.complex128) if want_traj else None
+        mm = np.zeros((max(m, 1), max(nt - 1, 1)))
+        mt = np.zeros((nj, max(m, 1), max(nt - 1, 1))) if want_traj else None
+        st = Stats()
+        _check(lib().qt_sde_plan_result(self.h, _p(mean), _p(se), _p(tr), _p(mm), _p(mt), ctypes.byref(st)))
+        out = {"mean": mean[:ne], "se": se[:ne], "measurement_mean": mm[:m, :nt - 1], "stats": st.as_dict()}
+        if want_traj:
+            out["expect_tr"] = tr[:, :ne]
+            out["measurement"] = mt[:, :m, :nt - 1]
+        return out
+
+    def close(self):
+        if self.h:
+            lib().qt_sde_plan_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ssesolve(ctx, H, sc_ops, psi0, tlist, e_ops, ntraj, seed, dt, options=None, want_traj=False):
+    """Stochastic Schrodinger equation under homodyne detection (qt_sde_plan_* with master = 0)."""
+    P = SdePlan(ctx, H, sc_ops, psi0, tlist, e_ops, ntraj, seed, dt, master=False, options=options)
+    try:
+        P.run()
+        return P.result(want_traj)
+    finally:
+        P.close()
+
+
+def smesolve(ctx, H, c_ops, sc_ops, rho0, tlist, e_ops, ntraj, seed, dt, options=None, want_traj=False):
+    """Stochastic master equation under homodyne detection (qt_sde_plan_* with master = 1)."""
+    P = SdePlan(ctx, H, sc_ops, rho0, tlist, e_ops, ntraj, seed, dt, c_ops=c_ops, master=True, options=options)
+    try:
+        P.run()
+        return P.result(want_traj)
+    finally:
+        P.close()

@@ -24,36 +24,11 @@
 #include "qt_coef.h"
 #include "qt_common.h"
 #include "qt_mc.h"
+#include "qt_rng.h"
 
 namespace qt {
 
 constexpr int MC_MAXC = 64;  // collapse channels handled by the jump kernel
-
-// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64 multiplies
-// (multipliers 0xD2511F53, 0xCD9E8D57) with the key bumped by the Weyl constants 0x9E3779B9,
-// 0xBB67AE85 between rounds.
-__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-        c[1] = (uint32_t)p1;
-        c[3] = (uint32_t)p0;
-        c[0] = n0;
-        c[2] = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-// Uniform double in (0, 1) from 27 + 26 bits of two words, offset by half a unit of 2^-53.
-__device__ __forceinline__ double u01(uint32_t hi, uint32_t lo)
-{
-    return ((double)(hi >> 5) * 67108864.0 + (double)(lo >> 6) + 0.5) * (1.0 / 9007199254740992.0);
-}
 
 __device__ __forceinline__ void traj_draw(uint64_t seed, uint64_t traj, uint32_t event, double *a, double *b)
 {

@@ -1,0 +1,117 @@
+"""GPU parity of the stochastic Schrodinger and master equations under homodyne detection (Sec. 3.6)
+against the FP64 oracle.  In FP64 the GPU draws the same Wiener increments and takes the same steps,
+so every trajectory's expectation values and currents agree to rounding (bar 1e-8 / 1e-6); in mixed
+precision the ensemble follows the master equation within a few standard errors."""
+from math import factorial
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from oracle import models as om
+import paper_2504_21440_amd as qt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating context", flush=True)
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+def _coherent(N, al):
+    return np.array([np.exp(-abs(al) ** 2 / 2) * al ** n / np.sqrt(float(factorial(n))) for n in range(N)],
+                    complex)
+
+
+def _jc(N=6, wc=5.0, wq=5.0, g=0.1):
+    """The Jaynes-Cummings system of the homodyne example (cavity first, qubit second)."""
+    a = sp.kron(om.destroy(N), om.qeye(2), format="csr")
+    sm = sp.kron(om.qeye(N), om.sigmam(), format="csr")
+    sz = sp.kron(om.qeye(N), om.sigmaz(), format="csr")
+    H = (wc * (a.conj().T @ a) + 0.5 * wq * sz + g * (a.conj().T @ sm + a @ sm.conj().T)).tocsr()
+    return a, sm, sz, H
+
+
+def test_sse_trajectories_match_oracle_fp64(ctx):
+    print("[gpu] SSE trajectories FP64 vs oracle", flush=True)
+    N = 6
+    a, sm, sz, H = _jc(N)
+    S = [np.sqrt(1.0) * a]
+    X = np.sqrt(1.0) * (a + a.conj().T)
+    psi0 = np.kron(_coherent(N, 1.0), np.array([1, 0], complex))
+    tl = np.linspace(0, 2 * np.pi / 5, 41)
+    ref = oracle.ssesolve(H, S, psi0, tl, [X, sz], 12, 17, 2e-3)
+    res = qt.ssesolve(ctx, H, S, psi0, tl, [X, sz], 12, 17, 2e-3, options=qt.opts(precision=qt.F64),
+                      want_traj=True)
+    assert np.abs(res["expect_tr"] - ref["expect_tr"]).max() < 1e-8
+    assert np.abs(res["measurement"] - ref["measurement"]).max() < 1e-6
+    assert res["stats"]["status"] == 0
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_sme_trajectories_match_oracle_fp64(ctx, m):
+    """SME with an extra loss channel and m measured operators (Wiener pairs and an odd one out)."""
+    print(f"[gpu] SME trajectories FP64 vs oracle, {m} measured operators", flush=True)
+    N = 4
+    a, sm, sz, H = _jc(N, 1.0, 1.0, 0.3)
+    S = [np.sqrt(0.8) * a, np.sqrt(0.5) * sm, np.sqrt(0.3) * sz][:m]
+    C = [np.sqrt(0.2) * sm]
+    psi0 = np.kron(_coherent(N, 0.7), np.array([1, 0], complex))
+    tl = np.linspace(0, 2, 11)
+    e = [sz, a.conj().T @ a]
+    ref = oracle.smesolve(H, C, S, psi0, tl, e, 8, 5, 4e-3)
+    res = qt.smesolve(ctx, H, C, S, psi0, tl, e, 8, 5, 4e-3, options=qt.opts(precision=qt.F64), want_traj=True)
+    assert np.abs(res["expect_tr"] - ref["expect_tr"]).max() < 1e-8
+    assert np.abs(res["measurement"] - ref["measurement"]).max() < 1e-6
+    np.testing.assert_allclose(res["mean"], ref["mean"], atol=1e-8)
+
+
+def test_sse_coherent_state_closed_form(ctx):
+    """Homodyne detection of a lossy cavity keeps a coherent state coherent with the deterministic
+    amplitude alpha e^{-(i w + kappa/2) t}, in FP64 and mixed precision."""
+    print("[gpu] SSE coherent state closed form", flush=True)
+    N, w, kap, al = 20, 1.0, 1.0, 1.0
+    a = om.destroy(N)
+    tl = np.linspace(0, 3, 31)
+    exact = al * np.exp(-(1j * w + kap / 2) * tl)
+    for prec, tol in [(qt.F64, 3e-3), (qt.MIXED, 3e-3)]:
+        res = qt.ssesolve(ctx, w * om.number(N), [np.sqrt(kap) * a], _coherent(N, al), tl, [a], 64, 1, 1e-3,
+                          options=qt.opts(precision=prec), want_traj=True)
+        assert np.abs(res["expect_tr"][:, 0, :] - exact).max() < tol
+
+
+@pytest.mark.parametrize("master", [False, True])
+def test_mixed_precision_ensemble_follows_master_equation(ctx, master):
+    print(f"[gpu] {'SME' if master else 'SSE'} mixed-precision ensemble vs master equation", flush=True)
+    H = 0.5 * om.sigmax()
+    S = [np.sqrt(0.5) * om.sigmam()]
+    C = [np.sqrt(0.2) * om.sigmaz()] if master else []
+    tl = np.linspace(0, 4, 21)
+    me = oracle.mesolve(H, S + C, np.array([1, 0], complex), tl, [om.sigmaz()])[0][0].real
+    fn = (lambda: qt.smesolve(ctx, H, C, S, np.array([1, 0], complex), tl, [om.sigmaz()], 4000, 3, 2e-3)) \
+        if master else (lambda: qt.ssesolve(ctx, H, S, np.array([1, 0], complex), tl, [om.sigmaz()], 4000, 3, 2e-3))
+    res = fn()
+    z = np.abs(res["mean"][0].real - me)[1:] / res["se"][0][1:]
+    print(f"[gpu]   max z = {z.max():.2f}", flush=True)
+    assert (z > 3).sum() <= 1 and z.max() < 4.5
+
+
+def test_sde_error_paths(ctx):
+    print("[gpu] SDE error paths", flush=True)
+    H = 0.5 * om.sigmax()
+    S = [om.sigmam()]
+    tl = np.linspace(0, 1, 3)
+    with pytest.raises(qt.QtError):
+        qt.SdePlan(ctx, H, S, np.array([1, 0], complex), tl, [], 4, 0, 1e-3, c_ops=[om.sigmaz()], master=False)
+    with pytest.raises(qt.QtError):
+        qt.SdePlan(ctx, H, S, np.array([1, 0], complex), tl, [], 4, 0, 0.0)
+    with pytest.raises(qt.QtError):
+        qt.SdePlan(ctx, H, S * 9, np.array([1, 0], complex), tl, [], 4, 0, 1e-3)
+    big = sp.identity(80, dtype=complex, format="csr")
+    with pytest.raises(qt.QtError):  # SME state of 6,400 entries
+        qt.SdePlan(ctx, big, [big], np.eye(80, dtype=complex)[0], tl, [], 4, 0, 1e-3, master=True)
