@@ -402,6 +402,46 @@ def section_td(ctx, n_sweep=64):
     return out
 
 
+def section_sde(ctx):
+    """Stochastic Schrodinger and master equations under homodyne detection: the Jaynes-Cummings
+    example (d = 40; SME n = 1,600), 500 trajectories, fixed step 1e-3 over t in [0, 2 pi]."""
+    import scipy.sparse as sp
+    from math import factorial
+    p = workloads.jc_homodyne()
+    N = p["N"]
+    dst = sp.diags(np.sqrt(np.arange(1, N, dtype=float)), 1, shape=(N, N), format="csr").astype(complex)
+    sm2 = sp.csr_matrix(np.array([[0, 0], [1, 0]], dtype=complex))
+    sz2 = sp.csr_matrix(np.array([[1, 0], [0, -1]], dtype=complex))
+    a = sp.kron(dst, sp.identity(2), format="csr")
+    sm = sp.kron(sp.identity(N), sm2, format="csr")
+    sz = sp.kron(sp.identity(N), sz2, format="csr")
+    ad = a.conj().T
+    H = (p["wc"] * (ad @ a) + 0.5 * p["wq"] * sz + p["g"] * (ad @ sm + a @ sm.conj().T)).tocsr()
+    S = [np.sqrt(p["kappa"]) * a]
+    X = (np.sqrt(p["kappa"]) * (a + ad)).tocsr()
+    coh = np.array([np.exp(-p["alpha"] ** 2 / 2) * p["alpha"] ** n / np.sqrt(float(factorial(n))) for n in range(N)])
+    psi0 = np.kron(coh, np.array([1.0, 0.0])).astype(complex)
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    out = {"d": 2 * N, "ntraj": p["ntraj"], "dt": p["dt"], "t_end": p["t_end"], "n_t": p["nt"]}
+    C = [np.sqrt(p["gamma"]) * sm, (np.sqrt(p["kappa_phi"]) * (ad @ a)).tocsr()]
+    for name, master, cops in [("sse", False, []), ("sme", True, C)]:
+        for pname, prec in [("mixed", qt.MIXED), ("fp64", qt.F64)]:
+            P = qt.SdePlan(ctx, H, S, psi0, tl, [X], p["ntraj"], p["seed"], p["dt"], c_ops=cops, master=master,
+                           options=qt.opts(precision=prec))
+            P.run()
+            t0 = time.perf_counter()
+            P.run()
+            dt_ = time.perf_counter() - t0
+            r = P.result()
+            out[f"{name}_{pname}"] = {"seconds": dt_, "trajectories_per_s": p["ntraj"] / dt_,
+                                      "steps_per_s": r["stats"]["n_accept"] / dt_,
+                                      "X_mean_final": float(r["mean"][0, -1].real),
+                                      "J_mean_last_interval": float(r["measurement_mean"][0, -1])}
+            P.close()
+    log(f"sde: {out}")
+    return out
+
+
 def copy_calibration(mbytes):
     """One device-to-device copy of a known size (the HIP runtime's copy kernel), so that hardware
     traffic counters collected on this run can be scaled to bytes."""
@@ -475,7 +515,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-extra", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving,td")
+    ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving,td,sde")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweep-splits", default="80,48,32",
                     help="largest cutoff N solved in the dense form, one sweep per value (80: all dense)")
@@ -500,7 +540,7 @@ def main():
     log("ising batch")
     batch = section_ising_batch(ctx, mixed["rtol"], max(1, args.steps // 2), 1)
     extra = {}
-    only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving", "td"}
+    only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving", "td", "sde"}
     if args.skip_extra:
         only = set()
     if "hbm" in only:
@@ -520,6 +560,9 @@ def main():
     if "td" in only:
         log("time-dependent")
         extra["td_optomechanics"] = section_td(ctx)
+    if "sde" in only:
+        log("stochastic")
+        extra["homodyne_jc"] = section_sde(ctx)
     kname = "k_csr_stage<float,%d,%d,%d,3,false>" % (mixed["csr_shape"][0], mixed["csr_shape"][1],
                                                2 if mixed["csr_shape"][3] else 1)
     rl = {"bound": "hbm", "achieved": mixed["stage_kernel_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -23,6 +23,10 @@ chain of the performance section, the decaying oscillator of the GPU section):
     drive F cos(omega_d t) (a + a^dag) with F = 10 kappa and omega_d = omega_c), vacuum start,
     t in [0, 5 / kappa], 5000 saves of <a^dag a>; ``optomech_sweep`` draws omega_d values around
     omega_c for a batch of such problems over a shorter window.
+  * ``jc_homodyne``: the homodyne example (cavity cutoff 20, omega_c = omega_q = 5, g = 0.1,
+    kappa = 1 measured through S = sqrt(kappa) a, qubit decay gamma = 2 and cavity dephasing
+    kappa_phi = 0.3 as extra losses of the master-equation variant), cavity in the coherent state
+    alpha = 2 and qubit excited, t in [0, 10 pi / omega_c] with 400 saves, 500 trajectories, step 1e-3.
 """
 import numpy as np
 
@@ -104,6 +108,11 @@ def optomech_sweep(n=64, seed=7, t_end=100.0, nt=200, Nc=10, Nm=7):
         p.update({"wd": float(g.uniform(0.8, 1.2)), "Nc": int(Nc), "Nm": int(Nm)})
         out.append(p)
     return out
+
+
+def jc_homodyne():
+    return {"kind": "jc", "N": 20, "wc": 5.0, "wq": 5.0, "g": 0.1, "kappa": 1.0, "gamma": 2.0, "kappa_phi": 0.3,
+            "alpha": 2.0, "t_end": 10 * np.pi / 5.0, "nt": 400, "ntraj": 500, "seed": 2025, "dt": 1e-3}
 
 
 def random_hermitian_dm(d, seed):
