@@ -424,6 +424,27 @@ def wiener_normals(seed, traj, step, pair):
     return a.value, b.value
 
 
+def steadystate(H, c_ops):
+    """Steady state of the Lindblad master equation (Sec. 3.2, steadystate): the density matrix with
+    L rho = 0 and Tr rho = 1, from its definition as a linear system -- the Kronecker Liouvillian of
+    ``liouvillian.py`` with the trace condition added as an extra equation -- solved by a sparse
+    direct factorisation (scipy's spsolve on the normal equations is avoided: the system is square
+    because the equation of rho_00 is replaced by the trace row, which is valid when the steady state
+    is unique).  Returns the d x d density matrix."""
+    import scipy.sparse.linalg as spl
+    from oracle import liouvillian as ol
+    L = ol.liouvillian(H, c_ops).tolil()
+    n = L.shape[0]
+    d = int(round(np.sqrt(n)))
+    L[0, :] = 0.0
+    for i in range(d):
+        L[0, i * d + i] = 1.0
+    b = np.zeros(n, dtype=complex)
+    b[0] = 1.0
+    x = spl.spsolve(L.tocsc(), b)
+    return x.reshape(d, d)
+
+
 def ensemble_stats(expect_tr):
     lib = _load()
     ex = np.ascontiguousarray(expect_tr, dtype=np.complex128)
