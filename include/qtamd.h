@@ -199,6 +199,23 @@ qt_status qt_me_plan_create(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, 
 qt_status qt_me_plan_run(qt_me_plan *plan);
 qt_status qt_me_plan_result(qt_me_plan *plan, int32_t i, double *expect_out, double *rho_final, qt_stats *stats);
 qt_status qt_me_plan_destroy(qt_me_plan *plan);
+/* Steady state (Sec. 3.2, steadystate): the density matrix with L rho_ss = 0 (and the trace of
+ * rho0), reached by integrating the master equation with the same adaptive integrator until
+ * |L rho|_2 <= tol after an accepted step (the Frobenius norm of d rho/dt, FP64).  Near the steady
+ * state the explicit steps are limited by stability, and the stiff components stay at the level the
+ * error control admits, so |L rho| levels off near |L| * abstol (measured: about 5e3 * abstol for a
+ * driven Kerr cavity of cutoff 20): take abstol at least 1e-4 * tol, and in mixed precision tol
+ * well above the FP32 rounding of L rho.  The distance to rho_ss is at most tol divided by the
+ * spectral gap of L.  A problem that converges stops, and
+ * every save time not yet reached receives the expectation values of the converged state; one that
+ * passes its last save time unconverged ends with QT_EMAXSTEPS.  Both forms (CSR, dense).
+ * qt_steadystate integrates one problem over [0, t_max]: expect_out [n_e] complex, rho_out d x d
+ * (nullable). */
+qt_status qt_me_plan_create_steady(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, double tol,
+                                   qt_me_plan **out);
+qt_status qt_steadystate(qt_ctx *ctx, const qt_liouv *L, const double *rho0, int32_t is_ket, double tol, double t_max,
+                         int32_t n_e, const qt_csr *e_ops, const qt_opts *opts, double *expect_out, double *rho_out,
+                         qt_stats *stats);
 /* Measurement: average device duration (HIP events on the plan's stream) of one right-hand-side
  * launch over `reps` back-to-back launches.  CSR problems: one fused SpMV-stage kernel (the stage
  * that forms the fourth stage input) over every CSR problem of the plan, from a freshly reset

@@ -24,7 +24,7 @@ EXPORTED = [
     "qt_model_ising", "qt_csr_free", "qt_liouvillian_build", "qt_liouv_info", "qt_liouv_export",
     "qt_liouv_destroy", "qt_liouvillian_build_td", "qt_liouv_terms", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
     "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_me_plan_autotune",
-    "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
+    "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_me_plan_create_steady", "qt_steadystate", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
     "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_sesolve", "qt_mc_plan_create_td", "qt_mcsolve_td",
     "qt_sesolve_td", "qt_sde_plan_create", "qt_sde_plan_run", "qt_sde_plan_result", "qt_sde_plan_destroy",
     "qt_ssesolve", "qt_smesolve", "qt_server_create", "qt_server_submit", "qt_server_step",
@@ -295,6 +295,21 @@ class Liouvillian:
             pass
 
 
+def steadystate(ctx, L, rho0, e_ops, tol=1e-9, t_max=1e4, options=None, want_rho=False):
+    """qt_steadystate: (expect [n_e] complex, stats dict, rho_ss or None) of the state the master
+    equation reaches from rho0 once |L rho|_2 <= tol."""
+    r, is_ket = _rho0_array(rho0)
+    E = _Ops(e_ops)
+    d = L.info()[0]
+    ex = np.zeros(max(1, len(e_ops)), np.complex128)
+    rho = np.zeros((d, d), np.complex128) if want_rho else None
+    st = Stats()
+    o = options or opts(precision=L.precision)
+    _check(lib().qt_steadystate(ctx.h, L.h, _p(r), is_ket, ctypes.c_double(tol), ctypes.c_double(t_max),
+                                len(e_ops), E.ptr, ctypes.byref(o), _p(ex), _p(rho), ctypes.byref(st)))
+    return ex[:len(e_ops)], st.as_dict(), rho
+
+
 def _rho0_array(rho0):
     r = np.ascontiguousarray(rho0, dtype=np.complex128)
     return r, (1 if r.ndim == 1 else 0)
@@ -328,14 +343,19 @@ def mesolve(ctx, L, rho0, tlist, e_ops, options=None, want_final=False):
 
 
 class MePlan:
-    """qt_me_plan_*: device-resident batch of master-equation problems."""
+    """qt_me_plan_*: device-resident batch of master-equation problems.  steady_tol > 0: steady-state
+    mode (qt_me_plan_create_steady)."""
 
-    def __init__(self, ctx, problems, options=None):
+    def __init__(self, ctx, problems, options=None, steady_tol=0.0):
         self.ctx = ctx  # the context must outlive the plan
         self.P = _MeProblems(problems)
         o = options or opts(precision=problems[0][0].precision)
         self.h = ctypes.c_void_p()
-        _check(lib().qt_me_plan_create(ctx.h, len(problems), self.P.arr, ctypes.byref(o), ctypes.byref(self.h)))
+        if steady_tol > 0:
+            _check(lib().qt_me_plan_create_steady(ctx.h, len(problems), self.P.arr, ctypes.byref(o),
+                                                  ctypes.c_double(steady_tol), ctypes.byref(self.h)))
+        else:
+            _check(lib().qt_me_plan_create(ctx.h, len(problems), self.P.arr, ctypes.byref(o), ctypes.byref(self.h)))
 
     def run(self):
         _check(lib().qt_me_plan_run(self.h))

@@ -353,7 +353,7 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
                                        cw);
     }
 
-    double e2 = 0.0;
+    double e2 = 0.0, l2 = 0.0;  // error norm part; |L y_new|^2 part (steady-state mode)
     if (rs.valid) {
         const int row = rs.row;
         const V a = pick(acc, rs.q);
@@ -409,11 +409,17 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
             const double my = sqrt(abs2d(yr)), mn = sqrt(abs2d(ynr));
             const double sc = I.atol + I.rtol * fmax(my, mn);
             e2 = (e.x * e.x + e.y * e.y) / (sc * sc);
+            l2 = abs2d(a);
         }
     }
     if (S == 7) {
         e2 = block_sum(e2, scr);
-        if (threadIdx.x == 0) I.partials[2 * part] = e2;
+        const bool steady = I.steady_tol2 > 0.0;  // the same in every thread of the block
+        if (steady) l2 = block_sum(l2, scr);
+        if (threadIdx.x == 0) {
+            I.partials[2 * part] = e2;
+            if (steady) I.partials[2 * part + 1] = l2;
+        }
     }
 }
 

@@ -169,6 +169,8 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
         }
     }
     const double part = partials_part(I, 0);
+    const bool steady = I.steady_tol2 > 0.0;
+    const double lpart = steady ? partials_part(I, 1) : 0.0;
     const double trp = I.renorm ? csr_trace_part(I, ynew) : 0.0;
     const double tot = block_sum(part, scr);  // its barriers also publish exs
     const double err = sqrt(tot / I.n);
@@ -179,7 +181,12 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
         const double tr = block_sum(trp, scr);
         if (accept) scale_new = C->tr0 / tr;
     }
-    if (accept && land) {
+    // steady-state mode: |L y_new|_2 (of the rescaled state) at or below the tolerance ends the solve
+    const bool conv = steady && accept && block_sum(lpart, scr) * scale_new * scale_new <= I.steady_tol2;
+    if (conv) {
+        // the state no longer changes: every remaining save time receives its expectation values
+        for (int idx = sidx; idx < I.nt; ++idx) csr_record_expect(I, ynew, scale_new, idx);
+    } else if (accept && land) {
         if (spec) {
             for (int k = threadIdx.x; k < I.ne; k += blockDim.x)
                 I.expect[(size_t)k * I.nt + sidx] = make_double2(exs[k].x * scale_new, exs[k].y * scale_new);
@@ -202,9 +209,13 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
             C->err_prev = fmax(err, 1e-4);
             C->last_rejected = 0;
             C->scale = scale_new;
-            if (land) {
+            if (conv) {
+                C->save_idx = I.nt;
+                C->status = ST_DONE;
+            } else if (land) {
                 C->save_idx = sidx + 1;
-                if (sidx + 1 >= I.nt) C->status = ST_DONE;
+                // in steady-state mode, passing the last save time unconverged is a failure
+                if (sidx + 1 >= I.nt) C->status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS
             }
         } else {
             C->n_reject += 1;

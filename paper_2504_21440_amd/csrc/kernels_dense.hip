@@ -408,7 +408,7 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
             }
         }
         __syncthreads();
-        double e2 = 0.0;
+        double e2 = 0.0, l2 = 0.0;  // error norm; |L y_new|^2 (steady-state mode)
         for (int s = 2; s <= 7; ++s) {
             R::eval(ops, I.nc, lds, zbuf, [&](int q, int v, V a) {
                 const size_t e = eidx(q, v);
@@ -455,6 +455,7 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
                     caxpy(er, ht * DP5::e7, to_d2(a));
                     const double scl = I.atol + I.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(ynew[e])));
                     e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
+                    l2 += abs2d(a);
                 }
                 if (s < 7) {
                     const int i = erow(q, v), j = ecol(q);
@@ -468,6 +469,8 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
         ++n_steps;
         // B0 now holds y_new (the stage-7 input)
         e2 = block_sum(e2, scr);
+        const bool steady = I.steady_tol2 > 0.0;
+        if (steady) l2 = block_sum(l2, scr);
         const double err = sqrt(e2 / nd);
         if (!isfinite(err)) {
             status = 6;  // QT_ENONFINITE
@@ -477,7 +480,14 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
             ++n_accept;
             double sc_new = 1.0;
             if (I.renorm) sc_new = tr0 / trace_b0();
-            if (land) record_expect(save_idx, sc_new);
+            // steady-state mode: |L y_new|_2 at or below the tolerance ends the solve, and every
+            // remaining save time receives the expectation values of the converged state
+            const bool conv = steady && l2 * sc_new * sc_new <= I.steady_tol2;
+            if (conv) {
+                for (int k = save_idx; k < I.nt; ++k) record_expect(k, sc_new);
+            } else if (land) {
+                record_expect(save_idx, sc_new);
+            }
             t = land ? I.tlist[save_idx] : t + ht;
             parity = 1 - parity;
             double hn = ht * pi_factor(err, err_prev);
@@ -486,9 +496,12 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
             err_prev = fmax(err, 1e-4);
             last_rejected = 0;
             scale = sc_new;
-            if (land) {
+            if (conv) {
+                save_idx = I.nt;
+                status = ST_DONE;
+            } else if (land) {
                 ++save_idx;
-                if (save_idx >= I.nt) status = ST_DONE;
+                if (save_idx >= I.nt) status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS: not converged
             }
         } else {
             ++n_reject;
@@ -544,6 +557,7 @@ void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *op
     g->ecol = ecol;
     g->eval = eval;
     g->expect = expect;
+    g->steady_tol2 = 0.0;
 }
 
 // Wave counts built per padded size.  With one wave per tile row a size whose tile-row count is not

@@ -58,6 +58,8 @@ struct CsrInst {
     int32_t pad_td;
     const CoefDev *coefs;    // [nterms]
     void *cstage;            // [TD_SLOTS][nterms + 1] coefficient values (state precision), column 0 = 1
+    // steady-state mode (0: off): stop once |L y|_2^2 <= steady_tol2 after an accepted step
+    double steady_tol2;
 };
 
 struct CsrCtl {

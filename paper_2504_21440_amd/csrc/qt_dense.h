@@ -32,6 +32,7 @@ struct DenseInst {
     const int32_t *ecol;
     const double2 *eval;
     double2 *expect;
+    double steady_tol2;  // steady-state mode (0: off): stop once |L y|_2^2 <= steady_tol2
 };
 
 enum : int32_t { DENSE_ST_INIT = 200 };

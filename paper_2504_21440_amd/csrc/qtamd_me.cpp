@@ -265,9 +265,11 @@ static qt_status restore_full(qt_me_plan *P)
 
 qt_status me_plan_autotune(qt_me_plan *P, int32_t reps);
 
-qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts_in, qt_me_plan **out)
+qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts_in, qt_me_plan **out,
+                         double steady_tol)
 {
     if (!ctx || n <= 0 || !probs || !out) return set_error(QT_EINVAL, "qt_me_plan_create: bad arguments");
+    if (!(steady_tol >= 0.0) || !std::isfinite(steady_tol)) return set_error(QT_EINVAL, "steady-state tolerance");
     qt_opts opts;
     if (opts_in) opts = *opts_in;
     else qt_opts_default(&opts);
@@ -390,6 +392,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             c.evidx = (const int32_t *)A.at(m.o_evidx);
             c.expect = (double2 *)A.at(m.o_expect);
             c.partials = (double *)A.at(m.o_part);
+            c.steady_tol2 = steady_tol * steady_tol;
             if (P->td) {
                 // every CSR problem of the plan takes the weighted kernels; a constant one has only
                 // the column of ones
@@ -403,6 +406,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
                             (const double *)A.at(m.o_tlist), (const int32_t *)A.at(m.o_eptr),
                             (const int32_t *)A.at(m.o_ecol), (const double2 *)A.at(m.o_eval),
                             (double2 *)A.at(m.o_expect), opts, P->prec);
+            g.steady_tol2 = steady_tol * steady_tol;
         }
     }
     if (!st && P->ncsr) {
@@ -819,7 +823,47 @@ extern "C" {
 
 qt_status qt_me_plan_create(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, qt_me_plan **out)
 {
-    return me_plan_create(ctx, n, probs, opts, out);
+    return me_plan_create(ctx, n, probs, opts, out, 0.0);
+}
+
+qt_status qt_me_plan_create_steady(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, double tol,
+                                   qt_me_plan **out)
+{
+    if (!(tol > 0.0)) return set_error(QT_EINVAL, "qt_me_plan_create_steady: tol must be positive");
+    return me_plan_create(ctx, n, probs, opts, out, tol);
+}
+
+qt_status qt_steadystate(qt_ctx *ctx, const qt_liouv *L, const double *rho0, int32_t is_ket, double tol, double t_max,
+                         int32_t n_e, const qt_csr *e_ops, const qt_opts *opts, double *expect_out, double *rho_out,
+                         qt_stats *stats)
+{
+    if (!L || !(t_max > 0.0) || !std::isfinite(t_max)) return set_error(QT_EINVAL, "qt_steadystate: bad arguments");
+    const double tl[2] = {0.0, t_max};
+    qt_me_problem p;
+    p.L = L;
+    p.rho0 = rho0;
+    p.is_ket = is_ket;
+    p.n_t = 2;
+    p.tlist = tl;
+    p.n_e = n_e;
+    p.e_ops = e_ops;
+    qt_me_plan *P = nullptr;
+    qt_status st = qt_me_plan_create_steady(ctx, 1, &p, opts, tol, &P);
+    if (st) {
+        if (stats) stats->status = st;
+        return st;
+    }
+    st = qt_me_plan_run(P);
+    std::vector<double> ex((size_t)2 * std::max(1, n_e) * 2);
+    if (!st) st = qt_me_plan_result(P, 0, ex.data(), rho_out, stats);
+    else if (stats) stats->status = st;
+    if (!st && expect_out)
+        for (int32_t k = 0; k < n_e; ++k) {  // the values at the second save time: the converged state
+            expect_out[2 * k] = ex[2 * ((size_t)k * 2 + 1)];
+            expect_out[2 * k + 1] = ex[2 * ((size_t)k * 2 + 1) + 1];
+        }
+    qt_me_plan_destroy(P);
+    return st;
 }
 
 qt_status qt_me_plan_run(qt_me_plan *plan)
