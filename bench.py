@@ -10,8 +10,9 @@ loosest tolerance whose result stays within 1e-4 of a tight FP64 oracle solution
 The same JSON line carries: the FP64 single-solve path on the same problem, the roofline of the
 fused SpMV-stage kernel (live, HIP events) at this size and at an HBM-sized Liouvillian (L = 10),
 the 512-cavity dense parameter sweep on the matrix cores (batched solves/s, TFLOP/s), the
-quantum-jump ensemble (trajectories/s), the served request stream (p50/p99 latency), and the FP64
-CPU oracle timed on this host.
+quantum-jump ensemble (trajectories/s), the served request stream (p50/p99 latency over a load
+sweep), the time-dependent, stochastic, Schrodinger and steady-state solvers, and the FP64 CPU
+oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--no-cpu]
 """
@@ -309,7 +310,8 @@ def section_serving(ctx, n=240, qps=40.0, n_fifo=24):
     1e-4 tolerances, served with continuous batching through the CSR form (the Kerr operators are
     tridiagonal: the CSR right-hand side does ~30x fewer flops than the dense form); the plain FP64
     single-solve path (CSR form, one request at a time, FIFO) runs the first n_fifo requests of the
-    same trace for comparison."""
+    same trace for comparison.  The load sweep offers 0.25, 0.5, 0.7 and 0.9 times the saturating
+    throughput X (X: the same requests all arriving at once)."""
     om_ = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED)
     # saturating throughput X: the same requests all arriving at once
     lat_s, span_s = _serve_mixed(ctx, workloads.serving_trace(n=n, qps=1e9), om_)
@@ -317,10 +319,13 @@ def section_serving(ctx, n=240, qps=40.0, n_fifo=24):
     out = {"requests": n, "mixed_rtol": om_.reltol,
            "saturated": {"solves_per_s": x_sat, "makespan_s": span_s, "p50_s": float(np.percentile(lat_s, 50)),
                          "p99_s": float(np.percentile(lat_s, 99))}}
-    for name, q in [("at_qps", qps), ("at_0.7x_saturation", 0.7 * x_sat)]:
+    def at(q):
         lat, span = _serve_mixed(ctx, workloads.serving_trace(n=n, qps=q), om_)
-        out[name] = {"qps": q, "solves_per_s": n / span, "p50_s": float(np.percentile(lat, 50)),
-                     "p99_s": float(np.percentile(lat, 99)), "makespan_s": span}
+        return {"qps": q, "solves_per_s": n / span, "p50_s": float(np.percentile(lat, 50)),
+                "p99_s": float(np.percentile(lat, 99)), "makespan_s": span}
+    out["at_qps"] = at(qps)
+    # offered load as a fraction of the saturating throughput
+    out["load_sweep"] = {f"{f}x": at(f * x_sat) for f in (0.25, 0.5, 0.7, 0.9)}
     trace = workloads.serving_trace(n=n, qps=qps)
     head = trace[:n_fifo]
     lat_m, span_m = _serve_mixed(ctx, head, om_)
@@ -442,6 +447,74 @@ def section_sde(ctx):
     return out
 
 
+def section_sesolve(ctx):
+    """Schrodinger evolution of the closed L = 10 transverse-field chain (d = 1,024, J = 1, h = 1,
+    all spins up, t in [0, 10], <sum sigma_z> at 100 times): one trajectory of the jump kernel with
+    no collapse operators, FP64 at the default tolerances and mixed at rtol 1e-5 / atol 1e-7."""
+    p = workloads.ising_mc()
+    H, _ = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    Sz = sum(sz_ops(p["L"]))
+    out = {"L": p["L"], "d": 2 ** p["L"], "n_t": p["nt"]}
+    res = {}
+    for name, o in [("fp64", qt.opts(precision=qt.F64)),
+                    ("mixed", qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED))]:
+        qt.sesolve(ctx, H, up_ket(p["L"]), tl, [Sz], options=o)
+        t0 = time.perf_counter()
+        ex, st = qt.sesolve(ctx, H, up_ket(p["L"]), tl, [Sz], options=o)
+        dt = time.perf_counter() - t0
+        res[name] = ex[0].real
+        out[name] = {"seconds": dt, "n_accept": st["n_accept"], "n_rhs": st["n_rhs"], "rhs_per_s": st["n_rhs"] / dt,
+                     "rtol": o.reltol, "atol": o.abstol, "sz_final": float(ex[0, -1].real)}
+    out["mixed_vs_fp64_max_abs"] = float(np.abs(res["mixed"] - res["fp64"]).max())
+    log(f"sesolve: {out}")
+    return out
+
+
+def section_steady(ctx, n_kerr=64):
+    """Steady states by relaxation (integrate until |L rho|_2 <= tol), FP64: the first n_kerr
+    cavities with N <= 48 (the FP64 dense form's limit) of the 512-cavity sweep as one dense-form
+    plan, and the L = 8 dissipative chain on the CSR form, both at tol 1e-6.  The residual of the
+    integrated state settles near |L|_2 * atol * sqrt(n) (n = d^2), so atol sits well below
+    tol / (|L|_2 sqrt(n)): |L|_2 is about 2.3e3 for the largest cavities and about 30 for the chain."""
+    out = {}
+    sweep = [p for p in workloads.kerr_sweep() if p["N"] <= 48][:n_kerr]
+    probs = []
+    for p in sweep:
+        H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
+        Lo = qt.Liouvillian(ctx, H, c, qt.FORM_DENSE, qt.F64)
+        rho0 = np.zeros((p["N"], p["N"]), complex)
+        rho0[0, 0] = 1
+        num = np.diag(np.arange(p["N"], dtype=float)).astype(complex)
+        probs.append((Lo, rho0, np.array([0.0, 1000.0]), [num]))
+    o = qt.opts(abstol=1e-13, reltol=1e-11, precision=qt.F64)
+    plan = qt.MePlan(ctx, probs, o, steady_tol=1e-6)
+    plan.run()
+    t0 = time.perf_counter()
+    plan.run()
+    dt = time.perf_counter() - t0
+    sts = [plan.result(i, check=False)[1] for i in range(n_kerr)]
+    out["kerr_dense"] = {"instances": n_kerr, "N_max": max(p["N"] for p in sweep), "tol": 1e-6, "atol": o.abstol, "rtol": o.reltol, "seconds": dt,
+                         "solves_per_s": n_kerr / dt, "rhs_per_s": sum(s["n_rhs"] for s in sts) / dt,
+                         "steps_max": max(s["n_accept"] + s["n_reject"] for s in sts),
+                         "converged": sum(1 for s in sts if s["status"] == 0)}
+    plan.close()
+    p = workloads.ising_single()
+    H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+    Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.F64)
+    o = qt.opts(abstol=1e-12, reltol=1e-10, precision=qt.F64)
+    qt.steadystate(ctx, Lo, up_ket(p["L"]), sz_ops(p["L"]), tol=1e-6, t_max=500.0, options=o)
+    t0 = time.perf_counter()
+    ex, st, _ = qt.steadystate(ctx, Lo, up_ket(p["L"]), sz_ops(p["L"]), tol=1e-6, t_max=500.0, options=o)
+    dt = time.perf_counter() - t0
+    out["ising_L8_csr"] = {"tol": 1e-6, "atol": o.abstol, "rtol": o.reltol, "seconds": dt, "n_accept": st["n_accept"],
+                           "n_rhs": st["n_rhs"], "rhs_per_s": st["n_rhs"] / dt,
+                           "sz_site1": float(ex[0].real)}
+    Lo.close()
+    log(f"steady: {out}")
+    return out
+
+
 def copy_calibration(mbytes):
     """One device-to-device copy of a known size (the HIP runtime's copy kernel), so that hardware
     traffic counters collected on this run can be scaled to bytes."""
@@ -515,7 +588,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-extra", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of extra sections: hbm,sweep,mc,serving,td,sde")
+    ap.add_argument("--only", default="",
+                    help="comma list of extra sections: hbm,sweep,mc,serving,td,sde,sesolve,steady")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweep-splits", default="80,48,32",
                     help="largest cutoff N solved in the dense form, one sweep per value (80: all dense)")
@@ -540,7 +614,7 @@ def main():
     log("ising batch")
     batch = section_ising_batch(ctx, mixed["rtol"], max(1, args.steps // 2), 1)
     extra = {}
-    only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving", "td", "sde"}
+    only = set(args.only.split(",")) if args.only else {"hbm", "sweep", "mc", "serving", "td", "sde", "sesolve", "steady"}
     if args.skip_extra:
         only = set()
     if "hbm" in only:
@@ -563,6 +637,12 @@ def main():
     if "sde" in only:
         log("stochastic")
         extra["homodyne_jc"] = section_sde(ctx)
+    if "sesolve" in only:
+        log("sesolve")
+        extra["sesolve_L10"] = section_sesolve(ctx)
+    if "steady" in only:
+        log("steady states")
+        extra["steadystate"] = section_steady(ctx)
     kname = "k_csr_stage<float,%d,%d,%d,3,false>" % (mixed["csr_shape"][0], mixed["csr_shape"][1],
                                                2 if mixed["csr_shape"][3] else 1)
     rl = {"bound": "hbm", "achieved": mixed["stage_kernel_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

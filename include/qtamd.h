@@ -203,9 +203,10 @@ qt_status qt_me_plan_destroy(qt_me_plan *plan);
  * rho0), reached by integrating the master equation with the same adaptive integrator until
  * |L rho|_2 <= tol after an accepted step (the Frobenius norm of d rho/dt, FP64).  Near the steady
  * state the explicit steps are limited by stability, and the stiff components stay at the level the
- * error control admits, so |L rho| levels off near |L| * abstol (measured: about 5e3 * abstol for a
- * driven Kerr cavity of cutoff 20): take abstol at least 1e-4 * tol, and in mixed precision tol
- * well above the FP32 rounding of L rho.  The distance to rho_ss is at most tol divided by the
+ * error control admits (about abstol per element), so |L rho|_2 levels off near
+ * |L|_2 * abstol * sqrt(d^2) (measured: about 5e3 * abstol for a driven Kerr cavity of cutoff 20):
+ * take abstol well below tol / (|L|_2 d), at least 1e-4 * tol, and in mixed precision tol well
+ * above the FP32 rounding of L rho.  The distance to rho_ss is at most tol divided by the
  * spectral gap of L.  A problem that converges stops, and
  * every save time not yet reached receives the expectation values of the converged state; one that
  * passes its last save time unconverged ends with QT_EMAXSTEPS.  Both forms (CSR, dense).
