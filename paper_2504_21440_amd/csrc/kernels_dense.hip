@@ -28,6 +28,100 @@ namespace qt {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// The problem buffers are global memory, but a pointer read out of a descriptor is generic to the
+// compiler, which then emits flat accesses.  A flat access may alias LDS, so it stays ordered
+// behind the LDS traffic of the matrix products and its completion is waited for together with
+// LDS reads.  Every buffer access of this file therefore goes through these global-only views.
+#define QT_GLOBAL __attribute__((address_space(1)))
+typedef float gf2 __attribute__((ext_vector_type(2)));
+typedef double gd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gld(const float2 *p)
+{
+    const gf2 v = *(const QT_GLOBAL gf2 *)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 gld(const double2 *p)
+{
+    const gd2 v = *(const QT_GLOBAL gd2 *)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double gld(const double *p) { return *(const QT_GLOBAL double *)p; }
+__device__ __forceinline__ int32_t gld(const int32_t *p) { return *(const QT_GLOBAL int32_t *)p; }
+__device__ __forceinline__ void gst(float2 *p, float2 a)
+{
+    gf2 v;
+    v.x = a.x;
+    v.y = a.y;
+    *(QT_GLOBAL gf2 *)p = v;
+}
+__device__ __forceinline__ void gst(double2 *p, double2 a)
+{
+    gd2 v;
+    v.x = a.x;
+    v.y = a.y;
+    *(QT_GLOBAL gd2 *)p = v;
+}
+// The 4 consecutive tile-order elements a lane owns in one output tile, with 16-byte accesses.
+typedef float gf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void gld4(const float2 *p, float2 (&r)[4])
+{
+    const gf4 a = *(const QT_GLOBAL gf4 *)p, b = *(const QT_GLOBAL gf4 *)(p + 2);
+    r[0] = make_float2(a.x, a.y);
+    r[1] = make_float2(a.z, a.w);
+    r[2] = make_float2(b.x, b.y);
+    r[3] = make_float2(b.z, b.w);
+}
+__device__ __forceinline__ void gld4(const double2 *p, double2 (&r)[4])
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r[v] = gld(p + v);
+}
+__device__ __forceinline__ void gst4(float2 *p, const float2 (&r)[4])
+{
+    gf4 a, b;
+    a.x = r[0].x;
+    a.y = r[0].y;
+    a.z = r[1].x;
+    a.w = r[1].y;
+    b.x = r[2].x;
+    b.y = r[2].y;
+    b.z = r[3].x;
+    b.w = r[3].y;
+    *(QT_GLOBAL gf4 *)p = a;
+    *(QT_GLOBAL gf4 *)(p + 2) = b;
+}
+__device__ __forceinline__ void gst4(double2 *p, const double2 (&r)[4])
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gst(p + v, r[v]);
+}
+// Two consecutive elements (16 or 32 bytes).
+__device__ __forceinline__ void gld2(const float2 *p, float2 (&r)[2])
+{
+    const gf4 a = *(const QT_GLOBAL gf4 *)p;
+    r[0] = make_float2(a.x, a.y);
+    r[1] = make_float2(a.z, a.w);
+}
+__device__ __forceinline__ void gld2(const double2 *p, double2 (&r)[2])
+{
+    r[0] = gld(p);
+    r[1] = gld(p + 1);
+}
+__device__ __forceinline__ void gst2(float2 *p, const float2 &r0, const float2 &r1)
+{
+    gf4 a;
+    a.x = r0.x;
+    a.y = r0.y;
+    a.z = r1.x;
+    a.w = r1.y;
+    *(QT_GLOBAL gf4 *)p = a;
+}
+__device__ __forceinline__ void gst2(double2 *p, const double2 &r0, const double2 &r1)
+{
+    gst(p, r0);
+    gst(p + 1, r1);
+}
+
 template <typename T> struct Mfma;
 template <> struct Mfma<float> {
     using acc = v4f;
@@ -69,6 +163,9 @@ template <typename T, int NP, int WV> struct DenseGeom {
     static __device__ __forceinline__ int chunk0(int w) { return (w * TILES) / WV; }
 };
 
+// Element index of (tile t, lane, v) in the tile-ordered global vectors.
+__device__ __forceinline__ size_t tix(int t, int lane, int v) { return ((size_t)t * 64 + lane) * 4 + v; }
+
 // acc += a * b on the matrix cores, complex a = (ar, ai), b = (br, bi).
 template <typename T>
 __device__ __forceinline__ void cmma(typename Mfma<T>::acc &aR, typename Mfma<T>::acc &aI, T ar, T ai, T br, T bi)
@@ -86,7 +183,7 @@ __device__ __forceinline__ void load_frag(const typename vec2<T>::type *__restri
 {
     const typename vec2<T>::type *row = op + (size_t)(I * 16 + (lane & 15)) * NP + (lane >> 4);
 #pragma unroll
-    for (int f = 0; f < NP / 4; ++f) frag[f] = row[4 * f];
+    for (int f = 0; f < NP / 4; ++f) frag[f] = gld(row + 4 * f);
 }
 
 template <typename T, int NP, int WV> struct DenseRhs {
@@ -129,9 +226,10 @@ template <typename T, int NP, int WV> struct DenseRhs {
         }
     }
 
-    // Evaluates L(B0) and calls epi(q, v, value) for every element this lane owns (tile q of the
-    // wave's chunk, accumulator slot v).  B1 holds C_k B0, B2 holds A B0.  With several collapse
-    // channels the running sum Z is kept per element in zbuf (tile order, global).
+    // Evaluates L(B0) and calls epi(q, value[4]) for the elements this lane owns in tile q of the
+    // wave's chunk (accumulator slots 0..3, consecutive in tile order).  B1 holds C_k B0, B2 holds
+    // A B0.  With several collapse channels the running sum Z is kept per element in zbuf (tile
+    // order, global).
     template <typename Epi>
     static __device__ __forceinline__ void eval(const V *__restrict__ ops, int nc, T *lds, V *__restrict__ zbuf,
                                                 Epi &&epi)
@@ -200,37 +298,42 @@ template <typename T, int NP, int WV> struct DenseRhs {
                 const int t = t0 + q, I = t / G::NT, J = t % G::NT;
                 Acc zR = {0, 0, 0, 0}, zI = {0, 0, 0, 0};
                 if (nc > 0) {
-                    if (I != Icur) {
-                        load_frag<T, NP>(Ck, I, lane, frag);
-                        Icur = I;
-                    }
-                    tile_mm_dag(frag, B1re, B1im, J, lane, zR, zI);  // Z_k = C_k X_k^dag
+                    // fragments reloaded per tile: keeping them across the epilogue would take
+                    // the registers its loads need to be in flight together
+                    V fz[G::KF];
+                    load_frag<T, NP>(Ck, I, lane, fz);
+                    tile_mm_dag(fz, B1re, B1im, J, lane, zR, zI);  // Z_k = C_k X_k^dag
                 }
-                const size_t zb = ((size_t)t * 64 + lane) * 4;
+                const size_t zb = tix(t, lane, 0);
+                V z[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    V z;
-                    z.x = zR[v];
-                    z.y = zI[v];
-                    if (k > 0) z = cadd(z, zbuf[zb + v]);
-                    if (k + 1 < kmax) {
-                        zbuf[zb + v] = z;
-                    } else {
+                    z[v].x = zR[v];
+                    z[v].y = zI[v];
+                }
+                if (k > 0) {
+                    V zp[4];
+                    gld4(zbuf + zb, zp);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) z[v] = cadd(z[v], zp[v]);
+                }
+                if (k + 1 < kmax) {
+                    gst4(zbuf + zb, z);
+                } else {
+                    V o[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
                         const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
-                        V o;
-                        o.x = z.x + B2re[i * S + j] + B2re[j * S + i];
-                        o.y = z.y + B2im[i * S + j] - B2im[j * S + i];
-                        epi(q, v, o);
+                        o[v].x = z[v].x + B2re[i * S + j] + B2re[j * S + i];
+                        o[v].y = z[v].y + B2im[i * S + j] - B2im[j * S + i];
                     }
+                    epi(q, o);
                 }
             }
             if (k + 1 < kmax) __syncthreads();  // B1 is rewritten by the next channel
         }
     }
 };
-
-// Element index of (tile t, lane, v) in the tile-ordered global vectors.
-__device__ __forceinline__ size_t tix(int t, int lane, int v) { return ((size_t)t * 64 + lane) * 4 + v; }
 
 template <typename T, int NP, int WV>
 __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__restrict__ insts,
@@ -272,16 +375,16 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
             const int32_t *ep = I.eptr + (size_t)k * (d + 1);
             double sr = 0.0, si = 0.0;
             for (int i = threadIdx.x; i < d; i += blockDim.x)
-                for (int p = ep[i]; p < ep[i + 1]; ++p) {
-                    const double2 o = I.eval[p];
-                    const int j = I.ecol[p];
+                for (int p = gld(ep + i), pe = gld(ep + i + 1); p < pe; ++p) {
+                    const double2 o = gld(I.eval + p);
+                    const int j = gld(I.ecol + p);
                     const double rr = (double)B0re[j * S + i], ri = (double)B0im[j * S + i];
                     sr += o.x * rr - o.y * ri;
                     si += o.x * ri + o.y * rr;
                 }
             sr = block_sum(sr, scr);
             si = block_sum(si, scr);
-            if (threadIdx.x == 0) I.expect[(size_t)k * I.nt + idx] = make_double2(sr * sc, si * sc);
+            if (threadIdx.x == 0) gst(I.expect + (size_t)k * I.nt + idx, make_double2(sr * sc, si * sc));
         }
     };
     auto trace_b0 = [&]() {
@@ -304,14 +407,14 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
                 V y;
                 y.x = 0;
                 y.y = 0;
-                if (i < d && j < d) y = r0[(size_t)i * d + j];
-                Yb[0][eidx(q, v)] = y;
+                if (i < d && j < d) y = gld(r0 + (size_t)i * d + j);
+                gst(Yb[0] + eidx(q, v), y);
                 B0re[i * S + j] = y.x;
                 B0im[i * S + j] = y.y;
             }
         }
         __syncthreads();
-        t = I.tlist[0];
+        t = gld(I.tlist);
         err_prev = 1e-4;
         scale = 1.0;
         save_idx = 1;
@@ -327,13 +430,18 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
         if (status == ST_RUNNING) {
             // k1 = L(y0); starting step from d0 = |y0|, d1 = |k1|, d2 = |f(y0 + h0 k1) - k1| / h0
             double s0 = 0.0, s1 = 0.0;
-            R::eval(ops, I.nc, lds, zbuf, [&](int q, int v, V a) {
-                const size_t e = eidx(q, v);
-                Kb[0][e] = a;
-                const double ya = sqrt(abs2d(Yb[0][e]));
-                const double sc = I.atol + I.rtol * ya;
-                s0 += ya * ya / (sc * sc);
-                s1 += abs2d(a) / (sc * sc);
+            R::eval(ops, I.nc, lds, zbuf, [&](int q, const V (&a)[4]) {
+                const size_t e = eidx(q, 0);
+                V y0[4];
+                gld4(Yb[0] + e, y0);
+                gst4(Kb[0] + e, a);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double ya = sqrt(abs2d(y0[v]));
+                    const double sc = I.atol + I.rtol * ya;
+                    s0 += ya * ya / (sc * sc);
+                    s1 += abs2d(a[v]) / (sc * sc);
+                }
             });
             n_rhs += 1;
             s0 = block_sum(s0, scr);
@@ -345,23 +453,31 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
                 const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
                 for (int q = 0; q < G::MAXJ; ++q) {
                     if (q >= nq) break;
+                    V y0[4], f0[4];
+                    gld4(Yb[0] + eidx(q, 0), y0);
+                    gld4(Kb[0] + eidx(q, 0), f0);
                     for (int v = 0; v < 4; ++v) {
-                        const size_t e = eidx(q, v);
                         const int i = erow(q, v), j = ecol(q);
-                        V y = Yb[0][e];
-                        caxpy(y, (T)h0, Kb[0][e]);
+                        V y = y0[v];
+                        caxpy(y, (T)h0, f0[v]);
                         B0re[i * S + j] = y.x;
                         B0im[i * S + j] = y.y;
                     }
                 }
                 __syncthreads();
                 double s2 = 0.0;
-                R::eval(ops, I.nc, lds, zbuf, [&](int q, int v, V a) {
-                    const size_t e = eidx(q, v);
-                    const double2 f1 = to_d2(a), f0 = to_d2(Kb[0][e]);
-                    const double sc = I.atol + I.rtol * sqrt(abs2d(Yb[0][e]));
-                    const double dx = (f1.x - f0.x) / h0, dy = (f1.y - f0.y) / h0;
-                    s2 += (dx * dx + dy * dy) / (sc * sc);
+                R::eval(ops, I.nc, lds, zbuf, [&](int q, const V (&a)[4]) {
+                    const size_t e = eidx(q, 0);
+                    V y0[4], k0[4];
+                    gld4(Kb[0] + e, k0);
+                    gld4(Yb[0] + e, y0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double2 f1 = to_d2(a[v]), f0 = to_d2(k0[v]);
+                        const double sc = I.atol + I.rtol * sqrt(abs2d(y0[v]));
+                        const double dx = (f1.x - f0.x) / h0, dy = (f1.y - f0.y) / h0;
+                        s2 += (dx * dx + dy * dy) / (sc * sc);
+                    }
                 });
                 n_rhs += 1;
                 s2 = block_sum(s2, scr);
@@ -391,18 +507,20 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
     while (status == ST_RUNNING && budget != 0) {
         if (budget > 0) --budget;
         int32_t land;
-        const double ht = clip_step(t, h, I.tlist[save_idx], &land);
+        const double ht = clip_step(t, h, gld(I.tlist + save_idx), &land);
         const T sc = (T)scale;
         V *y = Yb[parity], *ynew = Yb[1 - parity], *k1 = Kb[parity], *k7 = Kb[1 - parity];
         // stage-2 input: y + h a21 k1
         __syncthreads();
         for (int q = 0; q < G::MAXJ; ++q) {
             if (q >= nq) break;
+            V yv[4], kv[4];
+            gld4(y + eidx(q, 0), yv);
+            gld4(k1 + eidx(q, 0), kv);
             for (int v = 0; v < 4; ++v) {
-                const size_t e = eidx(q, v);
                 const int i = erow(q, v), j = ecol(q);
-                V x = cscale(y[e], sc);
-                caxpy(x, (T)(ht * DP5::a21), cscale(k1[e], sc));
+                V x = cscale(yv[v], sc);
+                caxpy(x, (T)(ht * DP5::a21), cscale(kv[v], sc));
                 B0re[i * S + j] = x.x;
                 B0im[i * S + j] = x.y;
             }
@@ -410,57 +528,77 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
         __syncthreads();
         double e2 = 0.0, l2 = 0.0;  // error norm; |L y_new|^2 (steady-state mode)
         for (int s = 2; s <= 7; ++s) {
-            R::eval(ops, I.nc, lds, zbuf, [&](int q, int v, V a) {
-                const size_t e = eidx(q, v);
-                const V yr = cscale(y[e], sc), k1r = cscale(k1[e], sc);
-                V o = yr;
-                if (s == 2) {
-                    ks[0][e] = a;
-                    caxpy(o, (T)(ht * DP5::a31), k1r);
-                    caxpy(o, (T)(ht * DP5::a32), a);
-                } else if (s == 3) {
-                    ks[1][e] = a;
-                    caxpy(o, (T)(ht * DP5::a41), k1r);
-                    caxpy(o, (T)(ht * DP5::a42), ks[0][e]);
-                    caxpy(o, (T)(ht * DP5::a43), a);
-                } else if (s == 4) {
-                    ks[2][e] = a;
-                    caxpy(o, (T)(ht * DP5::a51), k1r);
-                    caxpy(o, (T)(ht * DP5::a52), ks[0][e]);
-                    caxpy(o, (T)(ht * DP5::a53), ks[1][e]);
-                    caxpy(o, (T)(ht * DP5::a54), a);
-                } else if (s == 5) {
-                    ks[3][e] = a;
-                    caxpy(o, (T)(ht * DP5::a61), k1r);
-                    caxpy(o, (T)(ht * DP5::a62), ks[0][e]);
-                    caxpy(o, (T)(ht * DP5::a63), ks[1][e]);
-                    caxpy(o, (T)(ht * DP5::a64), ks[2][e]);
-                    caxpy(o, (T)(ht * DP5::a65), a);
-                } else if (s == 6) {
-                    ks[4][e] = a;
-                    caxpy(o, (T)(ht * DP5::b1), k1r);
-                    caxpy(o, (T)(ht * DP5::b3), ks[1][e]);
-                    caxpy(o, (T)(ht * DP5::b4), ks[2][e]);
-                    caxpy(o, (T)(ht * DP5::b5), ks[3][e]);
-                    caxpy(o, (T)(ht * DP5::b6), a);
-                    ynew[e] = o;
-                } else {
-                    k7[e] = a;
-                    double2 er = make_double2(0.0, 0.0);
-                    caxpy(er, ht * DP5::e1, to_d2(k1r));
-                    caxpy(er, ht * DP5::e3, to_d2(ks[1][e]));
-                    caxpy(er, ht * DP5::e4, to_d2(ks[2][e]));
-                    caxpy(er, ht * DP5::e5, to_d2(ks[3][e]));
-                    caxpy(er, ht * DP5::e6, to_d2(ks[4][e]));
-                    caxpy(er, ht * DP5::e7, to_d2(a));
-                    const double scl = I.atol + I.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(ynew[e])));
-                    e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
-                    l2 += abs2d(a);
-                }
-                if (s < 7) {
-                    const int i = erow(q, v), j = ecol(q);
-                    B0re[i * S + j] = o.x;
-                    B0im[i * S + j] = o.y;
+            R::eval(ops, I.nc, lds, zbuf, [&](int q, const V (&a)[4]) {
+                // Two elements at a time: every load of the pair first (the stores below go to
+                // other vectors, which the compiler cannot tell apart), then the combination, then
+                // the stores.  Pairs keep the loads in flight within the register budget.
+#pragma unroll 1
+                for (int p0 = 0; p0 < 4; p0 += 2) {
+                    const size_t e = eidx(q, p0);
+                    V yv[2], k1v[2], kv0[2], kv1[2], kv2[2], kv3[2], kv4[2], o[2];
+                    gld2(y + e, yv);
+                    gld2(k1 + e, k1v);
+                    if (s >= 3 && s <= 5) gld2(ks[0] + e, kv0);
+                    if (s >= 4) gld2(ks[1] + e, kv1);
+                    if (s >= 5) gld2(ks[2] + e, kv2);
+                    if (s >= 6) gld2(ks[3] + e, kv3);
+                    if (s == 7) {
+                        gld2(ks[4] + e, kv4);
+                        gld2(ynew + e, o);  // the candidate y_new, for the error weights
+                    }
+                    const V ap[2] = {p0 == 0 ? a[0] : a[2], p0 == 0 ? a[1] : a[3]};
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        const V yr = cscale(yv[v], sc), k1r = cscale(k1v[v], sc);
+                        if (s == 7) {
+                            double2 er = make_double2(0.0, 0.0);
+                            caxpy(er, ht * DP5::e1, to_d2(k1r));
+                            caxpy(er, ht * DP5::e3, to_d2(kv1[v]));
+                            caxpy(er, ht * DP5::e4, to_d2(kv2[v]));
+                            caxpy(er, ht * DP5::e5, to_d2(kv3[v]));
+                            caxpy(er, ht * DP5::e6, to_d2(kv4[v]));
+                            caxpy(er, ht * DP5::e7, to_d2(ap[v]));
+                            const double scl = I.atol + I.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(o[v])));
+                            e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
+                            l2 += abs2d(ap[v]);
+                            continue;
+                        }
+                        o[v] = yr;
+                        if (s == 2) {
+                            caxpy(o[v], (T)(ht * DP5::a31), k1r);
+                            caxpy(o[v], (T)(ht * DP5::a32), ap[v]);
+                        } else if (s == 3) {
+                            caxpy(o[v], (T)(ht * DP5::a41), k1r);
+                            caxpy(o[v], (T)(ht * DP5::a42), kv0[v]);
+                            caxpy(o[v], (T)(ht * DP5::a43), ap[v]);
+                        } else if (s == 4) {
+                            caxpy(o[v], (T)(ht * DP5::a51), k1r);
+                            caxpy(o[v], (T)(ht * DP5::a52), kv0[v]);
+                            caxpy(o[v], (T)(ht * DP5::a53), kv1[v]);
+                            caxpy(o[v], (T)(ht * DP5::a54), ap[v]);
+                        } else if (s == 5) {
+                            caxpy(o[v], (T)(ht * DP5::a61), k1r);
+                            caxpy(o[v], (T)(ht * DP5::a62), kv0[v]);
+                            caxpy(o[v], (T)(ht * DP5::a63), kv1[v]);
+                            caxpy(o[v], (T)(ht * DP5::a64), kv2[v]);
+                            caxpy(o[v], (T)(ht * DP5::a65), ap[v]);
+                        } else {
+                            caxpy(o[v], (T)(ht * DP5::b1), k1r);
+                            caxpy(o[v], (T)(ht * DP5::b3), kv1[v]);
+                            caxpy(o[v], (T)(ht * DP5::b4), kv2[v]);
+                            caxpy(o[v], (T)(ht * DP5::b5), kv3[v]);
+                            caxpy(o[v], (T)(ht * DP5::b6), ap[v]);
+                        }
+                        const int i = erow(q, p0 + v), j = ecol(q);
+                        B0re[i * S + j] = o[v].x;
+                        B0im[i * S + j] = o[v].y;
+                    }
+                    if (s == 7) {
+                        gst2(k7 + e, ap[0], ap[1]);
+                    } else {
+                        gst2(vec + (size_t)(2 + s) * nvec + e, ap[0], ap[1]);  // k_s (ks[s - 2])
+                        if (s == 6) gst2(ynew + e, o[0], o[1]);
+                    }
                 }
             });
             __syncthreads();
@@ -488,7 +626,7 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
             } else if (land) {
                 record_expect(save_idx, sc_new);
             }
-            t = land ? I.tlist[save_idx] : t + ht;
+            t = land ? gld(I.tlist + save_idx) : t + ht;
             parity = 1 - parity;
             double hn = ht * pi_factor(err, err_prev);
             if (last_rejected && hn > ht) hn = ht;
