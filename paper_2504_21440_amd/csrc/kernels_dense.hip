@@ -28,11 +28,8 @@ namespace qt {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// The problem buffers are global memory, but a pointer read out of a descriptor is generic to the
-// compiler, which then emits flat accesses.  A flat access may alias LDS, so it stays ordered
-// behind the LDS traffic of the matrix products and its completion is waited for together with
-// LDS reads.  Every buffer access of this file therefore goes through these global-only views.
-#define QT_GLOBAL __attribute__((address_space(1)))
+// Every buffer access of this file goes through these global-only views (QT_GLOBAL): the LDS
+// traffic of the matrix products then neither orders against nor waits for it.
 typedef float gf2 __attribute__((ext_vector_type(2)));
 typedef double gd2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float2 gld(const float2 *p)

@@ -10,8 +10,13 @@
 
 #include "qt_csr.h"
 
-namespace qt {
+// Global-memory (address space 1) qualifier for the pointers a kernel reads out of a descriptor in
+// memory.  Such pointers are generic to the compiler, which then emits flat accesses; a flat access
+// may alias LDS, so it stays ordered against the kernel's LDS traffic and is waited for together
+// with LDS reads.
+#define QT_GLOBAL __attribute__((address_space(1)))
 
+namespace qt {
 
 template <typename T> struct vec2;
 template <> struct vec2<float> { using type = float2; };
