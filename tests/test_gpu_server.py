@@ -82,6 +82,52 @@ def test_server_results_equal_alone_and_in_mix(ctx):
     srv.close()
 
 
+def test_server_large_and_small_lanes_match_alone(ctx):
+    """A large chain (L = 8: 65,536 Liouville rows, the large lane) served together with small CSR
+    cavities and chains (the small lane, which replays its epochs while the large one runs): every
+    result bitwise equal to the same problem solved alone in a plan, and the small ones within 1e-4
+    of the FP64 oracle."""
+    print("[gpu] server lanes vs alone", flush=True)
+    o = qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED)
+    probs = []
+    H, cs = qt.model_ising(8, 1.0, 0.7, 0.2)
+    L8 = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED)
+    probs.append(((L8, om.all_up_ket(8), workloads.tlist(1.0, 6), [om.site_op(8, 0, om.sigmaz())]), None))
+    for N, U in [(12, 0.3), (20, 0.5), (30, 0.2)]:
+        Hk, ck = qt.model_kerr(N, 1.0, U, 0.8, 1.0)
+        Lk = qt.Liouvillian(ctx, Hk, ck, qt.FORM_CSR, qt.MIXED)
+        probs.append(((Lk, om.fock_dm(N, 0), workloads.tlist(5.0, 11), [om.number(N)]), (Hk, ck)))
+    for Lc in (4, 5):
+        Hi, ci = qt.model_ising(Lc, 1.0, 0.9, 0.3)
+        Li = qt.Liouvillian(ctx, Hi, ci, qt.FORM_CSR, qt.MIXED)
+        probs.append(((Li, om.all_up_ket(Lc), workloads.tlist(3.0, 7), [om.site_op(Lc, 0, om.sigmaz())]),
+                      (Hi, ci)))
+    srv = qt.Server(ctx, pool_bytes=1 << 30, max_slots=16, steps_per_epoch=8, options=o)
+    tickets = {srv.submit(*pr): i for i, (pr, _) in enumerate(probs)}
+    assert None not in tickets
+    results, epochs = {}, 0
+    while tickets:
+        srv.step()
+        epochs += 1
+        for t in list(tickets):
+            r = srv.poll(t)
+            if r is not None:
+                results[tickets.pop(t)] = r
+        assert epochs < 100000
+    for i, (pr, ops) in enumerate(probs):
+        plan = qt.MePlan(ctx, [pr], o)
+        plan.set_shape(8, 1)  # the server's CSR launch shape
+        plan.run()
+        alone = plan.result(0)
+        plan.close()
+        np.testing.assert_array_equal(results[i][0], alone[0])
+        assert results[i][1]["n_accept"] == alone[1]["n_accept"]
+        if ops is not None:
+            ref, _, _, _ = oracle.mesolve(ops[0], ops[1], pr[1], pr[2], pr[3])
+            assert np.abs(results[i][0] - ref).max() < 1e-4
+    srv.close()
+
+
 def test_server_admission_by_footprint(ctx):
     print("[gpu] server admission", flush=True)
     o = qt.opts(precision=qt.MIXED)
