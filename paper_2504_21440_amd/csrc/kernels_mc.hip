@@ -70,10 +70,9 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
     __shared__ unsigned long long jsh;
     __shared__ V cwsh[MC_MAX_TERMS + 1];  // coefficients of the current right-hand side (TD)
     const int tid = threadIdx.x;
-    // the matrix streams through global-only pointers, apart from the LDS gathers of the state
-    const QT_GLOBAL V *__restrict__ ev = (const QT_GLOBAL V *)P.ell_val;
-    const QT_GLOBAL int32_t *__restrict__ ec = (const QT_GLOBAL int32_t *)P.ell_col;
-    const QT_GLOBAL V *__restrict__ cv = (const QT_GLOBAL V *)P.cval;
+    const V *__restrict__ ev = (const V *)P.ell_val;
+    const int32_t *__restrict__ ec = P.ell_col;
+    const V *__restrict__ cv = (const V *)P.cval;
 
     auto row = [&](int m) { return tid + m * MC_THREADS; };
     // out = A(ts) x for own rows.  Every call site is preceded by a barrier after the previous

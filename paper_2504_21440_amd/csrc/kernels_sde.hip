@@ -52,11 +52,8 @@ __global__ __launch_bounds__(SDE_THREADS) void k_sde(const SdeParams *__restrict
     __shared__ double scr[4 * (SDE_MAX_SC + 1)];
     __shared__ unsigned long long jsh;
     const int tid = threadIdx.x;
-    // the operators stream through global-only pointers, apart from the LDS gathers of the state
-    const QT_GLOBAL V *__restrict__ av = (const QT_GLOBAL V *)P.a_val;
-    const QT_GLOBAL V *__restrict__ bv = (const QT_GLOBAL V *)P.b_val;
-    const QT_GLOBAL int32_t *__restrict__ acol = (const QT_GLOBAL int32_t *)P.a_col;
-    const QT_GLOBAL int32_t *__restrict__ bcol = (const QT_GLOBAL int32_t *)P.b_col;
+    const V *__restrict__ av = (const V *)P.a_val;
+    const V *__restrict__ bv = (const V *)P.b_val;
     auto row = [&](int q) { return tid + q * SDE_THREADS; };
     auto is_diag = [&](int r) { return r % (P.d + 1) == 0; };
     // (A xs) at own row r
@@ -64,7 +61,7 @@ __global__ __launch_bounds__(SDE_THREADS) void k_sde(const SdeParams *__restrict
         V acc;
         acc.x = 0;
         acc.y = 0;
-        for (int k = 0; k < P.WA; ++k) cfma(acc, av[(size_t)k * n + r], xs[acol[(size_t)k * n + r]]);
+        for (int k = 0; k < P.WA; ++k) cfma(acc, av[(size_t)k * n + r], xs[P.a_col[(size_t)k * n + r]]);
         return acc;
     };
     // (B_j xs) at own row r
@@ -74,7 +71,7 @@ __global__ __launch_bounds__(SDE_THREADS) void k_sde(const SdeParams *__restrict
         acc.y = 0;
         const size_t base = (size_t)j * P.WB * n;
         for (int k = 0; k < P.WB; ++k)
-            cfma(acc, bv[base + (size_t)k * n + r], xs[bcol[base + (size_t)k * n + r]]);
+            cfma(acc, bv[base + (size_t)k * n + r], xs[P.b_col[base + (size_t)k * n + r]]);
         return acc;
     };
     // this thread's share of mu for the state u (its own rows) and its image Bu:
