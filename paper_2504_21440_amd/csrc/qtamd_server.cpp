@@ -10,6 +10,13 @@
 // their pool memory released -- so requests that arrived meanwhile join the next epoch: a request's
 // work overlaps on the device with whatever else is resident.  A request's arithmetic does not
 // depend on what else is resident: its blocks, reductions and step decisions are its own.
+//
+// CSR requests run in two lanes, each with its own block table, epoch graphs and stream: large
+// Liouvillians on the context's stream, small ones on its auxiliary stream.  A small problem's
+// step costs a few microseconds of launch latency, a large one's far more, so in one shared table
+// a stiff small request would advance only at the large ones' pace.  While the large lane's epoch
+// runs, the small lane replays its own epoch graph, until the large lane finishes or no small
+// request is left running.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -99,20 +106,24 @@ struct qt_server {
     qt::CsrCtl *d_cctl = nullptr;
     qt::DenseInst *d_dinst = nullptr;
     qt::DenseCtl *d_dctl = nullptr;
-    int32_t *d_bi = nullptr, *d_br = nullptr, *d_order = nullptr, *d_ilist = nullptr;
-    int32_t *d_counts = nullptr;    // [0] live blocks of the table, [1] live entries of the control list
-    int32_t h_counts[2] = {0, 0};
-    size_t blk_cap = 0;             // allocated entries of d_bi / d_br
-    // The CSR part of an epoch (starting-step evaluations, then steps_per_epoch steps) is one graph,
-    // captured once per grid size: the live block count rounded up to a power of two, so the
-    // workgroups past the live count that return at once never outnumber the live ones.  The table
-    // contents and their counts change every epoch; the graphs stay valid until the table is
+    int32_t *d_order = nullptr;
+    // The CSR part of an epoch (starting-step evaluations, then steps_per_epoch steps) is one graph
+    // per lane, captured once per grid size: the live block count rounded up to a power of two, so
+    // the workgroups past the live count that return at once never outnumber the live ones.  The
+    // table contents and their counts change every epoch; the graphs stay valid until the table is
     // reallocated.
     struct EpochGraph {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
     };
-    std::map<int, EpochGraph> graphs;
+    struct Lane {
+        int32_t *d_bi = nullptr, *d_br = nullptr, *d_ilist = nullptr;
+        int32_t *d_counts = nullptr;  // [0] live blocks of the table, [1] live entries of the control list
+        int32_t h_counts[2] = {0, 0};
+        size_t blk_cap = 0;           // allocated entries of d_bi / d_br
+        std::map<int, EpochGraph> graphs;
+    };
+    Lane lanes[2];  // 0: large Liouvillians (context stream), 1: small ones (auxiliary stream)
     qt::CsrCtl *h_cctl = nullptr;   // pinned
     qt::DenseCtl *h_dctl = nullptr; // pinned
     std::vector<int32_t> free_slots;
@@ -328,13 +339,78 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
     return QT_OK;
 }
 
-static void drop_graphs(qt_server *S)
+static void drop_graphs(qt_server::Lane &ln)
 {
-    for (auto &g : S->graphs) {
+    for (auto &g : ln.graphs) {
         if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
         if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
     }
-    S->graphs.clear();
+    ln.graphs.clear();
+}
+
+// Liouville rows up to which a CSR request runs in the small lane (d <= 128)
+constexpr int64_t SMALL_LANE_ROWS = 16384;
+
+// Uploads a lane's block table and control list and launches its epoch graph (capturing it on
+// first use of this grid size) on stream s.
+static qt_status launch_lane(qt_server *S, qt_server::Lane &ln, const std::vector<int32_t> &bi,
+                             const std::vector<int32_t> &br, const std::vector<int32_t> &slots, int K, hipStream_t s)
+{
+    int grid = 256;
+    while ((size_t)grid < bi.size()) grid *= 2;
+    if ((size_t)grid > ln.blk_cap) {
+        QT_HIP(hipStreamSynchronize(s));  // the old table may still be read by a launch in flight
+        drop_graphs(ln);
+        if (ln.d_bi) (void)hipFree(ln.d_bi);
+        if (ln.d_br) (void)hipFree(ln.d_br);
+        ln.d_bi = ln.d_br = nullptr;
+        ln.blk_cap = 0;
+        QT_HIP(hipMalloc(&ln.d_bi, (size_t)grid * 4));
+        QT_HIP(hipMalloc(&ln.d_br, (size_t)grid * 4));
+        ln.blk_cap = (size_t)grid;
+    }
+    ln.h_counts[0] = (int32_t)bi.size();
+    ln.h_counts[1] = (int32_t)slots.size();
+    QT_HIP(hipMemcpyAsync(ln.d_bi, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
+    QT_HIP(hipMemcpyAsync(ln.d_br, br.data(), br.size() * 4, hipMemcpyHostToDevice, s));
+    QT_HIP(hipMemcpyAsync(ln.d_ilist, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, s));
+    QT_HIP(hipMemcpyAsync(ln.d_counts, ln.h_counts, sizeof(ln.h_counts), hipMemcpyHostToDevice, s));
+    qt_server::EpochGraph &G = ln.graphs[grid];
+    if (!G.exec) {
+        CsrLaunch L;
+        L.f64 = S->prec == QT_F64;
+        L.lpr = S->shape.lpr;
+        L.rg = S->shape.rg;
+        L.xcd = 0;
+        L.keep = S->shape.keep;
+        L.nblk = grid;               // blocks past the live count return at once
+        L.ninst = S->cfg.max_slots;  // likewise for the control list
+        L.ilist = ln.d_ilist;
+        L.bound = ln.d_counts;
+        L.ibound = ln.d_counts + 1;
+        L.insts = S->d_cinst;
+        L.ctls = S->d_cctl;
+        L.bi = ln.d_bi;
+        L.br = ln.d_br;
+        QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        csr_launch_init(0, L, s);
+        csr_launch_init(1, L, s);
+        for (int k = 0; k < K; ++k) csr_launch_step(L, s);
+        hipError_t ce = hipStreamEndCapture(s, &G.graph);
+        if (ce) {
+            ln.graphs.erase(grid);
+            return set_error(QT_EDEVICE, std::string("server graph capture: ") + hipGetErrorString(ce));
+        }
+        ce = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
+        if (ce) {
+            (void)hipGraphDestroy(G.graph);
+            ln.graphs.erase(grid);
+            return set_error(QT_EDEVICE, std::string("server graph instantiate: ") + hipGetErrorString(ce));
+        }
+    }
+    QT_HIP(hipGraphLaunch(G.exec, s));
+    QT_HIP(hipGetLastError());
+    return QT_OK;
 }
 
 static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finished)
@@ -344,72 +420,18 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
     hipStream_t s = ctx->stream;
     const bool f64 = S->prec == QT_F64;
     const int K = std::max(1, S->cfg.steps_per_epoch);
-    // ---- CSR slots: block table of all active CSR requests ----
-    std::vector<int32_t> bi, br, csr_slots;
+    // ---- CSR slots: one block table per lane ----
+    std::vector<int32_t> bi[2], br[2], csr_slots[2];
     const int rpb = csr_rows_per_block(S->shape.lpr, S->shape.rg);
     for (uint64_t tk : S->active) {
         Request &R = S->reqs[tk];
         if (R.dense) continue;
+        const int l = (int64_t)R.d * R.d <= SMALL_LANE_ROWS ? 1 : 0;
         for (int32_t b = 0; b < R.nblocks; ++b) {
-            bi.push_back(R.slot);
-            br.push_back(b * rpb);
+            bi[l].push_back(R.slot);
+            br[l].push_back(b * rpb);
         }
-        csr_slots.push_back(R.slot);
-    }
-    if (!bi.empty()) {
-        int grid = 256;
-        while ((size_t)grid < bi.size()) grid *= 2;
-        if ((size_t)grid > S->blk_cap) {
-            drop_graphs(S);
-            if (S->d_bi) (void)hipFree(S->d_bi);
-            if (S->d_br) (void)hipFree(S->d_br);
-            S->d_bi = S->d_br = nullptr;
-            S->blk_cap = 0;
-            QT_HIP(hipMalloc(&S->d_bi, (size_t)grid * 4));
-            QT_HIP(hipMalloc(&S->d_br, (size_t)grid * 4));
-            S->blk_cap = (size_t)grid;
-        }
-        S->h_counts[0] = (int32_t)bi.size();
-        S->h_counts[1] = (int32_t)csr_slots.size();
-        QT_HIP(hipMemcpyAsync(S->d_bi, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
-        QT_HIP(hipMemcpyAsync(S->d_br, br.data(), br.size() * 4, hipMemcpyHostToDevice, s));
-        QT_HIP(hipMemcpyAsync(S->d_ilist, csr_slots.data(), csr_slots.size() * 4, hipMemcpyHostToDevice, s));
-        QT_HIP(hipMemcpyAsync(S->d_counts, S->h_counts, sizeof(S->h_counts), hipMemcpyHostToDevice, s));
-        qt_server::EpochGraph &G = S->graphs[grid];
-        if (!G.exec) {
-            CsrLaunch L;
-            L.f64 = f64;
-            L.lpr = S->shape.lpr;
-            L.rg = S->shape.rg;
-            L.xcd = 0;
-            L.keep = S->shape.keep;
-            L.nblk = grid;                    // blocks past the live count return at once
-            L.ninst = S->cfg.max_slots;       // likewise for the control list
-            L.ilist = S->d_ilist;
-            L.bound = S->d_counts;
-            L.ibound = S->d_counts + 1;
-            L.insts = S->d_cinst;
-            L.ctls = S->d_cctl;
-            L.bi = S->d_bi;
-            L.br = S->d_br;
-            QT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            csr_launch_init(0, L, s);
-            csr_launch_init(1, L, s);
-            for (int k = 0; k < K; ++k) csr_launch_step(L, s);
-            hipError_t ce = hipStreamEndCapture(s, &G.graph);
-            if (ce) {
-                S->graphs.erase(grid);
-                return set_error(QT_EDEVICE, std::string("server graph capture: ") + hipGetErrorString(ce));
-            }
-            ce = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
-            if (ce) {
-                (void)hipGraphDestroy(G.graph);
-                S->graphs.erase(grid);
-                return set_error(QT_EDEVICE, std::string("server graph instantiate: ") + hipGetErrorString(ce));
-            }
-        }
-        QT_HIP(hipGraphLaunch(G.exec, s));
-        QT_HIP(hipGetLastError());
+        csr_slots[l].push_back(R.slot);
     }
     // ---- dense slots: one budgeted launch per padded size, on the auxiliary streams ----
     std::map<int32_t, std::vector<int32_t>> buckets;
@@ -435,7 +457,39 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
         }
         QT_HIP(hipGetLastError());
     }
+    // ---- large CSR lane (after the dense launches' start event, so those run beside it) ----
+    hipEvent_t big_done = nullptr;
+    if (!bi[0].empty()) {
+        qt_status st = launch_lane(S, S->lanes[0], bi[0], br[0], csr_slots[0], K, s);
+        if (st) {
+            if (ev) (void)hipEventDestroy(ev);
+            return st;
+        }
+        QT_HIP(hipEventCreateWithFlags(&big_done, hipEventDisableTiming));
+        QT_HIP(hipEventRecord(big_done, s));
+    }
+    // ---- small CSR lane: replayed while the large lane runs and a small request still steps ----
+    if (!bi[1].empty()) {
+        hipStream_t sa = ctx->aux;
+        constexpr int MAX_REPLAYS = 64;  // bounds an epoch, so that new requests are admitted
+        for (int rep = 0; rep < MAX_REPLAYS; ++rep) {
+            qt_status st = launch_lane(S, S->lanes[1], bi[1], br[1], csr_slots[1], K, sa);
+            if (st) {
+                if (big_done) (void)hipEventDestroy(big_done);
+                if (ev) (void)hipEventDestroy(ev);
+                return st;
+            }
+            QT_HIP(hipMemcpyAsync(S->h_cctl, S->d_cctl, sizeof(CsrCtl) * S->cfg.max_slots, hipMemcpyDeviceToHost,
+                                  sa));
+            QT_HIP(hipStreamSynchronize(sa));
+            if (!big_done || hipEventQuery(big_done) != hipErrorNotReady) break;
+            bool running = false;
+            for (int32_t slot : csr_slots[1]) running = running || S->h_cctl[slot].status == ST_RUNNING;
+            if (!running) break;
+        }
+    }
     // ---- wait, then retire finished requests ----
+    if (big_done) (void)hipEventDestroy(big_done);
     QT_HIP(hipMemcpyAsync(S->h_cctl, S->d_cctl, sizeof(CsrCtl) * S->cfg.max_slots, hipMemcpyDeviceToHost, s));
     QT_HIP(hipStreamSynchronize(s));
     if (ev) {
@@ -511,8 +565,10 @@ qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **ou
     if (e == hipSuccess) e = hipMalloc(&S->d_dinst, sizeof(DenseInst) * ns);
     if (e == hipSuccess) e = hipMalloc(&S->d_dctl, sizeof(DenseCtl) * ns);
     if (e == hipSuccess) e = hipMalloc(&S->d_order, sizeof(int32_t) * ns);
-    if (e == hipSuccess) e = hipMalloc(&S->d_ilist, sizeof(int32_t) * ns);
-    if (e == hipSuccess) e = hipMalloc(&S->d_counts, sizeof(int32_t) * 2);
+    for (auto &ln : S->lanes) {
+        if (e == hipSuccess) e = hipMalloc(&ln.d_ilist, sizeof(int32_t) * ns);
+        if (e == hipSuccess) e = hipMalloc(&ln.d_counts, sizeof(int32_t) * 2);
+    }
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_cctl, sizeof(CsrCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_dctl, sizeof(DenseCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) {
@@ -594,11 +650,14 @@ qt_status qt_server_destroy(qt_server *S)
     if (S->d_dinst) (void)hipFree(S->d_dinst);
     if (S->d_dctl) (void)hipFree(S->d_dctl);
     if (S->d_order) (void)hipFree(S->d_order);
-    if (S->d_ilist) (void)hipFree(S->d_ilist);
-    if (S->d_counts) (void)hipFree(S->d_counts);
-    drop_graphs(S);
-    if (S->d_bi) (void)hipFree(S->d_bi);
-    if (S->d_br) (void)hipFree(S->d_br);
+    (void)hipStreamSynchronize(S->ctx->aux);
+    for (auto &ln : S->lanes) {
+        if (ln.d_ilist) (void)hipFree(ln.d_ilist);
+        if (ln.d_counts) (void)hipFree(ln.d_counts);
+        drop_graphs(ln);
+        if (ln.d_bi) (void)hipFree(ln.d_bi);
+        if (ln.d_br) (void)hipFree(ln.d_br);
+    }
     if (S->h_cctl) (void)hipHostFree(S->h_cctl);
     if (S->h_dctl) (void)hipHostFree(S->h_dctl);
     if (S->counted) S->ctx->refs--;
