@@ -28,36 +28,9 @@ namespace qt {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Every buffer access of this file goes through these global-only views (QT_GLOBAL): the LDS
-// traffic of the matrix products then neither orders against nor waits for it.
-typedef float gf2 __attribute__((ext_vector_type(2)));
-typedef double gd2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ float2 gld(const float2 *p)
-{
-    const gf2 v = *(const QT_GLOBAL gf2 *)p;
-    return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ double2 gld(const double2 *p)
-{
-    const gd2 v = *(const QT_GLOBAL gd2 *)p;
-    return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ double gld(const double *p) { return *(const QT_GLOBAL double *)p; }
-__device__ __forceinline__ int32_t gld(const int32_t *p) { return *(const QT_GLOBAL int32_t *)p; }
-__device__ __forceinline__ void gst(float2 *p, float2 a)
-{
-    gf2 v;
-    v.x = a.x;
-    v.y = a.y;
-    *(QT_GLOBAL gf2 *)p = v;
-}
-__device__ __forceinline__ void gst(double2 *p, double2 a)
-{
-    gd2 v;
-    v.x = a.x;
-    v.y = a.y;
-    *(QT_GLOBAL gd2 *)p = v;
-}
+// Every buffer access of this file goes through the global-only loads and stores of qt_common.h
+// (gld / gst and the wider ones below): the LDS traffic of the matrix products then neither
+// orders against nor waits for it.
 // The 4 consecutive tile-order elements a lane owns in one output tile, with 16-byte accesses.
 typedef float gf4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void gld4(const float2 *p, float2 (&r)[4])

@@ -94,12 +94,14 @@ __global__ __launch_bounds__(MC_THREADS) void k_mc(const McParams *__restrict__ 
             acc.y = 0;
             if (r < d)
                 for (int k = 0; k < P.W; ++k) {
-                    const int32_t c = ec[(size_t)k * d + r];
+                    // global-only loads of the matrix stream (generic ones would be ordered against,
+                    // and waited for with, the LDS gathers of the state)
+                    const int32_t c = gld(ec + (size_t)k * d + r);
                     if constexpr (TD)
-                        cfma(acc, cmul(ev[(size_t)k * d + r], cwsh[c >> MC_TAG_SHIFT]),
+                        cfma(acc, cmul(gld(ev + (size_t)k * d + r), cwsh[c >> MC_TAG_SHIFT]),
                              x[c & ((1 << MC_TAG_SHIFT) - 1)]);
                     else
-                        cfma(acc, ev[(size_t)k * d + r], x[c]);
+                        cfma(acc, gld(ev + (size_t)k * d + r), x[c]);
                 }
             out[m] = acc;
         }

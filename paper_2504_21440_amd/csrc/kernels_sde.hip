@@ -61,7 +61,8 @@ __global__ __launch_bounds__(SDE_THREADS) void k_sde(const SdeParams *__restrict
         V acc;
         acc.x = 0;
         acc.y = 0;
-        for (int k = 0; k < P.WA; ++k) cfma(acc, av[(size_t)k * n + r], xs[P.a_col[(size_t)k * n + r]]);
+        // global-only loads of the operator streams, apart from the LDS gathers of the state
+        for (int k = 0; k < P.WA; ++k) cfma(acc, gld(av + (size_t)k * n + r), xs[gld(P.a_col + (size_t)k * n + r)]);
         return acc;
     };
     // (B_j xs) at own row r
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(SDE_THREADS) void k_sde(const SdeParams *__restrict
         acc.y = 0;
         const size_t base = (size_t)j * P.WB * n;
         for (int k = 0; k < P.WB; ++k)
-            cfma(acc, bv[base + (size_t)k * n + r], xs[P.b_col[base + (size_t)k * n + r]]);
+            cfma(acc, gld(bv + base + (size_t)k * n + r), xs[gld(P.b_col + base + (size_t)k * n + r)]);
         return acc;
     };
     // this thread's share of mu for the state u (its own rows) and its image Bu:

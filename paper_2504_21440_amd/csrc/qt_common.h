@@ -18,6 +18,36 @@
 
 namespace qt {
 
+// Loads and stores through global-only views of generic pointers (see QT_GLOBAL).
+typedef float gf2 __attribute__((ext_vector_type(2)));
+typedef double gd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gld(const float2 *p)
+{
+    const gf2 v = *(const QT_GLOBAL gf2 *)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 gld(const double2 *p)
+{
+    const gd2 v = *(const QT_GLOBAL gd2 *)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double gld(const double *p) { return *(const QT_GLOBAL double *)p; }
+__device__ __forceinline__ int32_t gld(const int32_t *p) { return *(const QT_GLOBAL int32_t *)p; }
+__device__ __forceinline__ void gst(float2 *p, float2 a)
+{
+    gf2 v;
+    v.x = a.x;
+    v.y = a.y;
+    *(QT_GLOBAL gf2 *)p = v;
+}
+__device__ __forceinline__ void gst(double2 *p, double2 a)
+{
+    gd2 v;
+    v.x = a.x;
+    v.y = a.y;
+    *(QT_GLOBAL gd2 *)p = v;
+}
+
 template <typename T> struct vec2;
 template <> struct vec2<float> { using type = float2; };
 template <> struct vec2<double> { using type = double2; };
