@@ -503,19 +503,23 @@ __global__ void k_mc_queue_reset(unsigned long long *q) { *q = 0ull; }
 
 template <typename T, int R, bool TD, int OCC> static const void *mc_fn() { return (const void *)k_mc<T, R, TD, OCC>; }
 
-// Ensembles of at least this many trajectories with complex64 states of 4 rows per thread (d of
-// 513..1,024) take the variant held to 3 waves per SIMD (measured on the L = 10 ensemble: 45,500 ->
-// 56,900 trajectories/s; a lone trajectory runs 10-20% slower there because of the spills).
+// Ensembles of at least this many complex64 trajectories with 2, 4 or 8 rows per thread take the
+// variant held to 3 waves per SIMD (2 at 8 rows): more trajectories in flight outweigh the spilled
+// registers (measured on dissipative chains of L = 9, 10, 11: +34%, +20% and +61% trajectories/s
+// at 2,048 trajectories); a lone trajectory runs 10-20% slower there, so it keeps the other one.
 constexpr int64_t MC_DENSE_ENSEMBLE = 2048;
-static bool mc_occ3(const McParams &p, bool f64) { return !f64 && p.rows == 4 && p.ntraj >= MC_DENSE_ENSEMBLE; }
+static bool mc_occ3(const McParams &p, bool f64)
+{
+    return !f64 && (p.rows == 2 || p.rows == 4 || p.rows == 8) && p.ntraj >= MC_DENSE_ENSEMBLE;
+}
 
 template <typename T, bool TD> static const void *mc_pick(int rows, bool occ3)
 {
     switch (rows) {
     case 1: return mc_fn<T, 1, TD, 1>();
-    case 2: return mc_fn<T, 2, TD, 1>();
+    case 2: return occ3 ? mc_fn<T, 2, TD, 3>() : mc_fn<T, 2, TD, 1>();
     case 4: return occ3 ? mc_fn<T, 4, TD, 3>() : mc_fn<T, 4, TD, 1>();
-    case 8: return mc_fn<T, 8, TD, 1>();
+    case 8: return occ3 ? mc_fn<T, 8, TD, 2>() : mc_fn<T, 8, TD, 1>();
     default: return mc_fn<T, 16, TD, 1>();
     }
 }
@@ -559,12 +563,18 @@ void mc_launch(const McParams &p, const McParams *dev_p, bool f64, bool td, int 
     } else {
         switch (p.rows) {
         case 1: mc_launch_t<float, 1, 1>(dev_p, td, grid, lds, s); break;
-        case 2: mc_launch_t<float, 2, 1>(dev_p, td, grid, lds, s); break;
+        case 2:
+            if (mc_occ3(p, f64)) mc_launch_t<float, 2, 3>(dev_p, td, grid, lds, s);
+            else mc_launch_t<float, 2, 1>(dev_p, td, grid, lds, s);
+            break;
         case 4:
             if (mc_occ3(p, f64)) mc_launch_t<float, 4, 3>(dev_p, td, grid, lds, s);
             else mc_launch_t<float, 4, 1>(dev_p, td, grid, lds, s);
             break;
-        case 8: mc_launch_t<float, 8, 1>(dev_p, td, grid, lds, s); break;
+        case 8:
+            if (mc_occ3(p, f64)) mc_launch_t<float, 8, 2>(dev_p, td, grid, lds, s);
+            else mc_launch_t<float, 8, 1>(dev_p, td, grid, lds, s);
+            break;
         default: mc_launch_t<float, 16, 1>(dev_p, td, grid, lds, s); break;
         }
     }
