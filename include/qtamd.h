@@ -125,7 +125,7 @@ void qt_csr_free(qt_csr *A);
 qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const qt_csr *c_ops, int32_t form,
                                int32_t precision, qt_liouv **out);
 /* Time-dependent Liouvillian (Sec. 2, QobjEvo; Sec. 3.2 with time-dependent operators, the driven
- * example of Sec. 3.5):
+ * example of Sec. 3.4):
  *     H(t) = H0 + sum_i f_i(t) H_i,   collapse operators g_k(t) C_k,
  *     L(t) rho = -i[H0, rho] - i sum_i f_i(t) (H_i rho - rho H_i) + sum_k w_k(t) D[C_k] rho,
  * with w_k = |g_k(t)|^2 where c_coefs[k] has a kind other than QT_COEF_NONE and w_k = 1 otherwise.
@@ -326,7 +326,7 @@ qt_status qt_sesolve_td(qt_ctx *ctx, const qt_csr *H, const qt_td_terms *td, con
                         const double *tlist, int32_t n_e, const qt_csr *e_ops, const qt_opts *opts, double *expect_out,
                         qt_stats *stats);
 
-/* Stochastic Schrodinger (SSE) and master (SME) equations under homodyne detection (Sec. 3.6, Ito
+/* Stochastic Schrodinger (SSE) and master (SME) equations under homodyne detection (Sec. 3.5, Ito
  * form): with measured operators S_n (sc_ops) and Wiener increments dW_n,
  *   SSE  d psi = -i K psi dt + sum_n (S_n - e_n/2) psi dW_n,
  *        K = H + i sum_n (e_n/2 S_n - 1/2 S_n^dag S_n - e_n^2/8),  e_n = <psi|S_n + S_n^dag|psi>;

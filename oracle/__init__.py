@@ -187,7 +187,7 @@ def coef_eval(spec, t):
 def mesolve_td(H0, h_terms, c_ops, rho0, tlist, e_ops, abstol=1e-8, reltol=1e-6, max_steps=1_000_000, h0=0.0,
                want_final=False):
     """Time-dependent Lindblad master equation (Sec. 3.2 with H(t) = H_0 + sum_i f_i(t) H_i as in the
-    QobjEvo of Sec. 2 and the driven example of Sec. 3.5).
+    QobjEvo of Sec. 2 and the driven example of Sec. 3.4).
 
     h_terms: list of (H_i, coefficient spec); c_ops: list of C_k or (C_k, spec) for a collapse
     operator g_k(t) C_k (weight |g_k(t)|^2 on its dissipator).  Returns as ``mesolve``."""
@@ -400,7 +400,7 @@ def _sdesolve(sme, H, c_ops, sc_ops, x0, tlist, e_ops, ntraj, seed, dt, traj0):
 
 
 def ssesolve(H, sc_ops, psi0, tlist, e_ops, ntraj, seed, dt, traj0=0):
-    """Stochastic Schrodinger equation under homodyne detection (Sec. 3.6, Ito form) with a fixed
+    """Stochastic Schrodinger equation under homodyne detection (Sec. 3.5, Ito form) with a fixed
     step of at most dt.  Returns expect_tr [ntraj][ne][nt], mean, se, measurement [ntraj][nsc][nt-1]
     (the current J_n = <S_n + S_n^dag> + dW_n/dt averaged over each tlist interval)."""
     psi0 = np.asarray(psi0, dtype=np.complex128)
@@ -408,7 +408,7 @@ def ssesolve(H, sc_ops, psi0, tlist, e_ops, ntraj, seed, dt, traj0=0):
 
 
 def smesolve(H, c_ops, sc_ops, rho0, tlist, e_ops, ntraj, seed, dt, traj0=0):
-    """Stochastic master equation under homodyne detection (Sec. 3.6, Ito form); rho0 a density
+    """Stochastic master equation under homodyne detection (Sec. 3.5, Ito form); rho0 a density
     matrix or a ket.  Returns as ``ssesolve``."""
     rho0 = np.asarray(rho0, dtype=np.complex128)
     if rho0.ndim == 1:

@@ -13,7 +13,7 @@ Model Hamiltonians of the benchmark workloads:
     C = sqrt(kappa) a;
   * open transverse-field Ising chain (Secs. 4 and 6):
     H = J sum_i sz_i sz_{i+1} + h sum_i sx_i, C_i = sqrt(gamma) sm_i;
-  * driven optomechanical system (Sec. 3.5, time-dependent example), cavity a (cutoff Nc) first:
+  * driven optomechanical system (Sec. 3.4, time-dependent example), cavity a (cutoff Nc) first:
     H_0 = wc a^dag a + wm b^dag b + (g/2)(a + a^dag)^2 (b + b^dag), drive term (a + a^dag) with
     coefficient F cos(wd t), C = sqrt(kappa) a and sqrt(gamma) b.
 """

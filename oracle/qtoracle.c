@@ -14,7 +14,7 @@
  *      anticommutator is the only trace-preserving reading and is the one used
  *      here -- the trace-invariant tests pin it);
  *   - the time-dependent master equation and trajectories (H(t) = H_0 + sum_i
- *     f_i(t) H_i, collapse operators g_k(t) C_k; Sec. 2 QobjEvo, Sec. 3.5);
+ *     f_i(t) H_i, collapse operators g_k(t) C_k; Sec. 2 QobjEvo, Sec. 3.4);
  *   - the Monte-Carlo wave-function method, Sec. 3.3: evolution under
  *       H_eff = H - (i/2) sum_k C_k^dag C_k,
  *     a jump when the (squared) norm of the unnormalised state falls to a
@@ -628,7 +628,7 @@ int32_t or_mesolve(const or_csr *H, int32_t nc, const or_csr *c_ops, const doubl
 
 /* ------------------------------------------------------------------------- */
 /* Time-dependent master equation (Sec. 3.2 with time-dependent operators,    */
-/* the QobjEvo of Sec. 2 and the driven example of Sec. 3.5):                 */
+/* the QobjEvo of Sec. 2 and the driven example of Sec. 3.4):                 */
 /*   H(t) = H_0 + sum_i f_i(t) H_i,   collapse operators g_k(t) C_k,          */
 /*   d rho/dt = -i[H_0, rho] - i sum_i f_i(t) (H_i rho - rho H_i)             */
 /*              + sum_k |g_k(t)|^2 D[C_k] rho.                                */
@@ -1100,7 +1100,7 @@ int32_t or_mcsolve(const or_csr *H, int32_t nc, const or_csr *c_ops, const doubl
 
 /* ------------------------------------------------------------------------- */
 /* Stochastic Schrodinger and master equations under homodyne detection      */
-/* (Sec. 3.6), Ito form:                                                      */
+/* (Sec. 3.5), Ito form:                                                      */
 /*   SSE  d psi = -i K psi dt + sum_n M_n psi dW_n,                           */
 /*        K = H + i sum_n (e_n/2 S_n - 1/2 S_n^dag S_n - e_n^2/8),            */
 /*        M_n = S_n - e_n/2,  e_n = <psi|S_n + S_n^dag|psi>;                  */

@@ -3,7 +3,7 @@
 // Same kernels as kernels_csr.hip (csr_kernels.h), instantiated with TD = true: every stored entry
 // of the summed Liouvillian L(t) = L_0 + sum_k w_k(t) L_k carries its term number in the high bits
 // of its column index, and the row sum weights it with the term's coefficient at the time of the
-// evaluation (arXiv:2504.21440, Sec. 2, QobjEvo; Sec. 3.5).  The coefficient rows are written by
+// evaluation (arXiv:2504.21440, Sec. 2, QobjEvo; Sec. 3.4).  The coefficient rows are written by
 // the control and reset kernels.  A separate translation unit so the two kernel families compile
 // in parallel.
 #include "csr_kernels.h"

@@ -448,8 +448,9 @@ __global__ __launch_bounds__(MC_THREADS) __attribute__((amdgpu_waves_per_eu(OCC)
             }
             ++njump;
             r_th = rnext;
-            const bool at_stop = land && th == 1.0;
-            t = at_stop ? P.tlist[idx] : tj;
+            // the root search keeps th strictly inside (0, 1), so a jump always falls before the end
+            // of the step, and the save time it was aiming at (if any) is recorded by a later step
+            t = tj;
             __syncthreads();  // every thread is done reading xs1 / pk / pn
 #pragma unroll
             for (int m = 0; m < R; ++m)
@@ -458,7 +459,6 @@ __global__ __launch_bounds__(MC_THREADS) __attribute__((amdgpu_waves_per_eu(OCC)
             rhs(xs0, k[0], t);
             nrhs += 1;
             h = hn;
-            if (at_stop) record(xs0, j, idx++);
         }
         if (tid == 0) {
             P.njumps[j] = njump;

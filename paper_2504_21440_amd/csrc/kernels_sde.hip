@@ -1,6 +1,6 @@
 // kernels_sde.hip -- stochastic Schrodinger and master equations under homodyne detection on gfx950.
 //
-// arXiv:2504.21440, Sec. 3.6 (Ito form): one 256-thread workgroup integrates one trajectory at a
+// arXiv:2504.21440, Sec. 3.5 (Ito form): one 256-thread workgroup integrates one trajectory at a
 // time and claims the next from a device-wide queue.  Each thread owns R rows of the state vector x
 // (the ket, or vec(rho)); x, the drift and the new state stay in registers, the products B_n x of
 // the thread's rows in LDS, and the vector every gather reads (x, then each supporting value) in
@@ -298,12 +298,22 @@ template <typename T, int R, bool SME, int OCC> static const void *sde_fn()
     return (const void *)k_sde<T, R, SME, OCC>;
 }
 
-// Complex64 ensembles with 4 or 8 rows per thread and more trajectories than compute units take
-// the variant held to 2 waves per SIMD, so that two trajectories share a CU (measured on the
-// homodyne master equation: 512 trajectories at n = 1,024 / 1,600 run 77% / 64% faster than two
-// rounds of 256 in the unconstrained variant, bitwise the same; the FP64 kernel spills too much
-// there and keeps the unconstrained variant).
-constexpr int64_t SDE_SHARED_CU_ENSEMBLE = 256;
+// Complex64 ensembles with 4 or 8 rows per thread and more trajectories than the device has compute
+// units take the variant held to 2 waves per SIMD, so that two trajectories share a CU (measured on
+// the homodyne master equation on a 256-CU device: 512 trajectories at n = 1,024 / 1,600 run 77% /
+// 64% faster than two rounds of 256 in the unconstrained variant, bitwise the same; the FP64 kernel
+// spills too much there and keeps the unconstrained variant).
+static int device_cus(int device)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
+    return cus;
+}
+
+void sde_choose_variant(SdeParams &p, bool f64, int device)
+{
+    p.occ2 = (!f64 && (p.rows == 4 || p.rows == 8) && p.ntraj > (int64_t)device_cus(device)) ? 1 : 0;
+}
 
 template <typename T, bool SME> static const void *sde_pick(int rows, bool occ2)
 {
@@ -319,8 +329,7 @@ template <typename T, bool SME> static const void *sde_pick(int rows, bool occ2)
 static const void *sde_kernel(const SdeParams &p, bool f64)
 {
     if (f64) return p.sme ? sde_pick<double, true>(p.rows, false) : sde_pick<double, false>(p.rows, false);
-    const bool o2 = (p.rows == 4 || p.rows == 8) && p.ntraj > SDE_SHARED_CU_ENSEMBLE;
-    return p.sme ? sde_pick<float, true>(p.rows, o2) : sde_pick<float, false>(p.rows, o2);
+    return p.sme ? sde_pick<float, true>(p.rows, p.occ2 != 0) : sde_pick<float, false>(p.rows, p.occ2 != 0);
 }
 
 int sde_grid(const SdeParams &p, bool f64, int device)
@@ -331,9 +340,7 @@ int sde_grid(const SdeParams &p, bool f64, int device)
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, SDE_THREADS, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(p.ntraj, (int64_t)per_cu * cus));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(p.ntraj, (int64_t)per_cu * device_cus(device)));
 }
 
 void sde_launch(const SdeParams &p, const SdeParams *dev_p, bool f64, int grid, hipStream_t s)

@@ -1,6 +1,6 @@
 // qt_coef.h -- time-dependent coefficients of a Liouvillian term (host and device).
 //
-// A time-dependent problem (arXiv:2504.21440, Sec. 2, QobjEvo; Sec. 3.5) has
+// A time-dependent problem (arXiv:2504.21440, Sec. 2, QobjEvo; Sec. 3.4) has
 //     H(t) = H_0 + sum_i f_i(t) H_i   and collapse operators g_k(t) C_k,
 // so its generator is L(t) = L_0 + sum_i f_i(t) L[H_i] + sum_k |g_k(t)|^2 D[C_k] with
 // L[H](rho) = -i (H rho - rho H).  The coefficient kinds are closed forms the device evaluates in

@@ -1,5 +1,5 @@
 // qt_sde.h -- descriptors of the stochastic Schrodinger / master equation solver (homodyne
-// detection, arXiv:2504.21440, Sec. 3.6).
+// detection, arXiv:2504.21440, Sec. 3.5).
 //
 // Both equations are integrated as x' = a(x) dt + sum_n (B_n x - cg mu_n(x) x) dW_n for a state
 // vector x of length n: the ket (SSE, n = d) or vec(rho) (SME, n = d*d).  A is the linear part of
@@ -19,7 +19,8 @@ constexpr int SDE_MAX_ROWS = 16;  // n <= 4096
 constexpr int SDE_MAX_SC = 8;     // measured operators
 
 struct SdeParams {
-    int32_t n, d, m, ne, nt, rows, sme, pad;
+    int32_t n, d, m, ne, nt, rows, sme;
+    int32_t occ2;          // complex64 variant held to 2 waves per SIMD (set by sde_choose_variant)
     int32_t WA, WB;       // ELL widths of A and of each B_n
     double cg;
     uint64_t seed;
@@ -42,6 +43,8 @@ struct SdeParams {
 };
 
 size_t sde_lds_bytes(const SdeParams &p, bool f64);
+// Sets p.occ2 from the ensemble size and the device's compute-unit count.
+void sde_choose_variant(SdeParams &p, bool f64, int device);
 int sde_grid(const SdeParams &p, bool f64, int device);
 void sde_launch(const SdeParams &p, const SdeParams *dev_p, bool f64, int grid, hipStream_t s);
 

@@ -1,5 +1,5 @@
 // qtamd_sde.cpp -- stochastic Schrodinger / master equation plans under homodyne detection
-// (arXiv:2504.21440, Sec. 3.6).
+// (arXiv:2504.21440, Sec. 3.5).
 //
 // The plan builds, on the host in FP64, the linear drift A and the measured operators B_n of the
 // state space (SSE: A = -i H - 1/2 sum S^dag S, B_n = S_n on kets; SME: A = the Lindbladian with
@@ -236,7 +236,8 @@ static qt_status sde_plan_create(Ctx *ctx, const qt_sde_problem *pr, int32_t mas
     while (rows * SDE_THREADS < n) rows *= 2;
     p.rows = rows;
     p.sme = master ? 1 : 0;
-    p.pad = 0;
+    p.occ2 = 0;
+    sde_choose_variant(p, f64, ctx->device);
     p.WA = WA;
     p.WB = WB;
     p.cg = master ? 1.0 : 0.5;

@@ -1,4 +1,4 @@
-"""GPU parity of the stochastic Schrodinger and master equations under homodyne detection (Sec. 3.6)
+"""GPU parity of the stochastic Schrodinger and master equations under homodyne detection (Sec. 3.5)
 against the FP64 oracle.  In FP64 the GPU draws the same Wiener increments and takes the same steps,
 so every trajectory's expectation values and currents agree to rounding (bar 1e-8 / 1e-6); in mixed
 precision the ensemble follows the master equation within a few standard errors."""

@@ -1,5 +1,5 @@
 """GPU parity of the time-dependent master equation (H(t) = H_0 + sum_i f_i(t) H_i, collapse
-operators g_k(t) C_k; the QobjEvo of Sec. 2 and the driven example of Sec. 3.5) against the FP64
+operators g_k(t) C_k; the QobjEvo of Sec. 2 and the driven example of Sec. 3.4) against the FP64
 oracle.  Bars: max |d<O>| <= 1e-6 in FP64 mode, <= 1e-4 in mixed FP32/FP64 mode; the assembled
 terms against their Kronecker definitions to rounding; a constant problem bitwise the same inside a
 plan that takes the weighted kernels."""

@@ -1,5 +1,5 @@
 """Pins of the oracle's stochastic Schrodinger and master equations under homodyne detection
-(Sec. 3.6, Ito form, measurement current J = <S + S^dag> + dW/dt).
+(Sec. 3.5, Ito form, measurement current J = <S + S^dag> + dW/dt).
 
 Checked against what the mathematics fixes, not against the oracle itself:
   * the Wiener increments: standard normal statistics of the Box-Muller draws;

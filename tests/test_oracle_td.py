@@ -1,5 +1,5 @@
 """Pins of the oracle's time-dependent master equation (Sec. 3.2 with H(t) = H_0 + sum_i f_i(t) H_i,
-the QobjEvo of Sec. 2 and the driven example of Sec. 3.5).
+the QobjEvo of Sec. 2 and the driven example of Sec. 3.4).
 
 Each coefficient kind is checked against exact mathematics the oracle does not contain:
   * complex exponentials: a frame rotating with the drive makes the problem time independent, so
