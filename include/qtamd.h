@@ -165,6 +165,10 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
 qt_status qt_liouv_terms(const qt_liouv *L, int32_t *n_terms);
 /* d, stored non-zeros (CSR form; 0 for dense), device bytes held. */
 qt_status qt_liouv_info(const qt_liouv *L, int32_t *d, int64_t *nnz, int64_t *bytes);
+/* Device bytes the Liouvillian holds until qt_liouv_destroy: CSR row pointers, columns and values
+ * (and the coefficient tables of a time-dependent one), or the dense operators.  A served request
+ * is charged this plus its own state (qt_server_footprint). */
+qt_status qt_liouv_footprint(const qt_liouv *L, size_t *bytes);
 /* Copies the assembled CSR back to the host (values widened to complex128).  indptr: d*d + 1,
  * indices and values: nnz from qt_liouv_info.  CSR form only. */
 qt_status qt_liouv_export(const qt_liouv *L, int64_t *indptr, int32_t *indices, double *values);
@@ -186,6 +190,22 @@ typedef struct {
 /* One-shot solve: expect_out [n_e][n_t] complex (host), rho_final d x d complex (host, nullable). */
 qt_status qt_mesolve(qt_ctx *ctx, const qt_me_problem *prob, const qt_opts *opts, double *expect_out,
                      double *rho_final, qt_stats *stats);
+/* Caller-owned device workspace.  qt_me_plan_workspace reports the device bytes a plan of these
+ * problems needs (initial states, save times, e_ops, expectation values, Runge-Kutta stages, block
+ * tables, control records); qt_me_plan_create_ws lays the plan out in the caller's buffer dev_ws
+ * (device memory on the context's device, 256-byte aligned, at least that many bytes; a torch
+ * tensor's storage will do) instead of allocating, and qt_mesolve_ws is the one-shot solve in such
+ * a buffer.  The buffer must stay allocated and untouched by the caller until the plan is destroyed
+ * (for qt_mesolve_ws: until the call returns, which synchronises the context's stream).  Neither
+ * creation nor run nor result allocates device memory (the plan's small pinned host mirrors of its
+ * control records aside); results are bitwise those of the allocating calls.  Errors: QT_EINVAL for
+ * a null or misaligned buffer, QT_ENOMEM when ws_bytes is below the workspace size. */
+qt_status qt_me_plan_workspace(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts,
+                               size_t *bytes);
+qt_status qt_me_plan_create_ws(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, void *dev_ws,
+                               size_t ws_bytes, qt_me_plan **out);
+qt_status qt_mesolve_ws(qt_ctx *ctx, const qt_me_problem *prob, const qt_opts *opts, void *dev_ws, size_t ws_bytes,
+                        double *expect_out, double *rho_final, qt_stats *stats);
 /* Many problems advanced together in the same launches (each with its own step size, accept /
  * reject decisions and save times).  expect_out[i] is [n_e][n_t] of problem i. */
 qt_status qt_mesolve_batch(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts,
@@ -285,7 +305,9 @@ typedef struct {
 
 /* mean_out [n_e][n_t] complex; se_out [n_e][n_t] standard error of the real part (nullable);
  * expect_tr [ntraj][n_e][n_t] complex (nullable); njumps [ntraj] (nullable); jump_times and
- * jump_channels [ntraj][max_jump_record] (nullable when max_jump_record == 0). */
+ * jump_channels [ntraj][max_jump_record] (nullable when max_jump_record == 0); the first
+ * min(njumps[j], max_jump_record) entries of row j are trajectory j's jumps in order, the rest are
+ * unspecified. */
 qt_status qt_mcsolve(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, double *mean_out, double *se_out,
                      double *expect_tr, int64_t *njumps, int32_t max_jump_record, double *jump_times,
                      int32_t *jump_channels, qt_stats *stats);
@@ -295,6 +317,17 @@ qt_status qt_mc_plan_run(qt_mc_plan *plan);
 qt_status qt_mc_plan_result(qt_mc_plan *plan, double *mean_out, double *se_out, double *expect_tr, int64_t *njumps,
                             double *jump_times, int32_t *jump_channels, qt_stats *stats);
 qt_status qt_mc_plan_destroy(qt_mc_plan *plan);
+
+/* Trajectory plans in a caller-owned device workspace, as for qt_me_plan_create_ws: the bytes a
+ * plan of this problem needs (operators, per-trajectory expectation rows, jump records, counters,
+ * ensemble sums), the plan laid out in the caller's buffer, and the one-shot solve in it. */
+qt_status qt_mc_plan_workspace(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, int32_t max_jump_record,
+                               size_t *bytes);
+qt_status qt_mc_plan_create_ws(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, int32_t max_jump_record,
+                               void *dev_ws, size_t ws_bytes, qt_mc_plan **out);
+qt_status qt_mcsolve_ws(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, void *dev_ws, size_t ws_bytes,
+                        double *mean_out, double *se_out, double *expect_tr, int64_t *njumps, int32_t max_jump_record,
+                        double *jump_times, int32_t *jump_channels, qt_stats *stats);
 
 /* Time-dependent trajectories (Sec. 3.3 with the time-dependent operators of Sec. 2, QobjEvo):
  *     H(t) = H + sum_i f_i(t) H_i,   collapse operator k is g_k(t) C_k where c_coefs[k] has a kind
@@ -388,6 +421,13 @@ typedef struct {
 } qt_server_cfg;
 
 qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **out);
+/* The server's device memory is one region sized at creation: the request pool (pool_bytes), the
+ * slot-indexed descriptors and control records, and the block tables of both lanes at their largest
+ * admissible size, so submit, step and poll never allocate device memory.  qt_server_workspace
+ * reports its bytes; qt_server_create_ws places it in the caller's buffer (256-byte aligned device
+ * memory on the context's device, kept until qt_server_destroy) instead of allocating it. */
+qt_status qt_server_workspace(const qt_server_cfg *cfg, size_t *bytes);
+qt_status qt_server_create_ws(qt_ctx *ctx, const qt_server_cfg *cfg, void *dev_ws, size_t ws_bytes, qt_server **out);
 /* The problem's L must stay alive until the request completes. */
 qt_status qt_server_submit(qt_server *srv, const qt_me_problem *prob, uint64_t *ticket);
 qt_status qt_server_step(qt_server *srv, int32_t *n_active, int32_t *n_finished);

@@ -29,6 +29,8 @@ EXPORTED = [
     "qt_sesolve_td", "qt_sde_plan_create", "qt_sde_plan_run", "qt_sde_plan_result", "qt_sde_plan_destroy",
     "qt_ssesolve", "qt_smesolve", "qt_server_create", "qt_server_submit", "qt_server_step",
     "qt_server_poll", "qt_server_footprint", "qt_server_destroy",
+    "qt_liouv_footprint", "qt_me_plan_workspace", "qt_me_plan_create_ws", "qt_mesolve_ws", "qt_mc_plan_workspace",
+    "qt_mc_plan_create_ws", "qt_mcsolve_ws", "qt_server_workspace", "qt_server_create_ws",
 ]
 
 
@@ -273,6 +275,12 @@ class Liouvillian:
         _check(lib().qt_liouv_info(self.h, ctypes.byref(d), ctypes.byref(nnz), ctypes.byref(b)))
         return d.value, nnz.value, b.value
 
+    def footprint(self):
+        """Device bytes the Liouvillian holds (qt_liouv_footprint)."""
+        b = ctypes.c_size_t()
+        _check(lib().qt_liouv_footprint(self.h, ctypes.byref(b)))
+        return b.value
+
     def export(self):
         import scipy.sparse as sp
         d, nnz, _ = self.info()
@@ -330,28 +338,53 @@ class _MeProblems:
             self.meta.append((d, len(tl), len(e_ops)))
 
 
-def mesolve(ctx, L, rho0, tlist, e_ops, options=None, want_final=False):
-    """qt_mesolve: returns (expect [n_e][n_t] complex, stats dict, rho_final or None)."""
+def _ws(workspace):
+    """(device pointer, bytes) of a caller-owned workspace as ctypes arguments."""
+    ptr, nbytes = workspace
+    return ctypes.c_void_p(int(ptr)), ctypes.c_size_t(int(nbytes))
+
+
+def mesolve(ctx, L, rho0, tlist, e_ops, options=None, want_final=False, workspace=None):
+    """qt_mesolve (qt_mesolve_ws with workspace = (device pointer, bytes)): returns
+    (expect [n_e][n_t] complex, stats dict, rho_final or None)."""
     P = _MeProblems([(L, rho0, tlist, e_ops)])
     d, nt, ne = P.meta[0]
     ex = np.zeros((max(ne, 1), nt), np.complex128)
     fin = np.zeros((d, d), np.complex128) if want_final else None
     st = Stats()
     o = options or opts(precision=L.precision)
-    _check(lib().qt_mesolve(ctx.h, ctypes.byref(P.arr[0]), ctypes.byref(o), _p(ex), _p(fin), ctypes.byref(st)))
+    if workspace is not None:
+        _check(lib().qt_mesolve_ws(ctx.h, ctypes.byref(P.arr[0]), ctypes.byref(o), *_ws(workspace), _p(ex), _p(fin),
+                                   ctypes.byref(st)))
+    else:
+        _check(lib().qt_mesolve(ctx.h, ctypes.byref(P.arr[0]), ctypes.byref(o), _p(ex), _p(fin), ctypes.byref(st)))
     return ex[:ne], st.as_dict(), fin
+
+
+def me_plan_workspace(ctx, problems, options=None):
+    """Device bytes a plan of these problems needs in a caller-owned workspace (qt_me_plan_workspace)."""
+    P = _MeProblems(problems)
+    o = options or opts(precision=problems[0][0].precision)
+    b = ctypes.c_size_t()
+    _check(lib().qt_me_plan_workspace(ctx.h, len(problems), P.arr, ctypes.byref(o), ctypes.byref(b)))
+    return b.value
 
 
 class MePlan:
     """qt_me_plan_*: device-resident batch of master-equation problems.  steady_tol > 0: steady-state
     mode (qt_me_plan_create_steady)."""
 
-    def __init__(self, ctx, problems, options=None, steady_tol=0.0):
+    def __init__(self, ctx, problems, options=None, steady_tol=0.0, workspace=None):
         self.ctx = ctx  # the context must outlive the plan
         self.P = _MeProblems(problems)
         o = options or opts(precision=problems[0][0].precision)
         self.h = ctypes.c_void_p()
-        if steady_tol > 0:
+        if workspace is not None:  # (device pointer, bytes) owned by the caller: qt_me_plan_create_ws
+            if steady_tol > 0:
+                raise ValueError("steady-state plans allocate their own arena")
+            _check(lib().qt_me_plan_create_ws(ctx.h, len(problems), self.P.arr, ctypes.byref(o), *_ws(workspace),
+                                              ctypes.byref(self.h)))
+        elif steady_tol > 0:
             _check(lib().qt_me_plan_create_steady(ctx.h, len(problems), self.P.arr, ctypes.byref(o),
                                                   ctypes.c_double(steady_tol), ctypes.byref(self.h)))
         else:
@@ -518,16 +551,44 @@ def sesolve(ctx, H, psi0, tlist, e_ops, options=None, h_terms=None):
     return ex[:ne], st.as_dict()
 
 
+def mc_plan_workspace(ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, max_jump_record=0):
+    """Device bytes a trajectory plan needs in a caller-owned workspace (qt_mc_plan_workspace)."""
+    p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed, None)
+    o = options or opts(precision=MIXED)
+    b = ctypes.c_size_t()
+    _check(lib().qt_mc_plan_workspace(ctx.h, ctypes.byref(p.s), ctypes.byref(o), int(max_jump_record),
+                                      ctypes.byref(b)))
+    return b.value
+
+
+def mcsolve_ws(ctx, workspace, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, want_traj=False,
+               max_jump_record=0):
+    """qt_mcsolve_ws: mcsolve in a caller-owned device workspace (device pointer, bytes)."""
+    p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed, None)
+    mean, se, tr, nj, mj, jt, jc = _mc_outputs(p, want_traj, max_jump_record)
+    st = Stats()
+    o = options or opts(precision=MIXED)
+    _check(lib().qt_mcsolve_ws(ctx.h, ctypes.byref(p.s), ctypes.byref(o), *_ws(workspace), _p(mean), _p(se), _p(tr),
+                               _p(nj), mj, _p(jt), _p(jc), ctypes.byref(st)))
+    return _mc_pack(p, mean, se, tr, nj, mj, jt, jc, st)
+
+
 class McPlan:
     """qt_mc_plan_*: device-resident trajectory ensemble."""
 
     def __init__(self, ctx, H, c_ops, psi0, tlist, e_ops, ntraj, seed, options=None, max_jump_record=0,
-                 h_terms=None):
+                 h_terms=None, workspace=None):
         self.ctx = ctx
         self.p = _McProblem(H, c_ops, psi0, tlist, e_ops, ntraj, seed, h_terms)
         o = options or opts(precision=MIXED)
         self.mj = int(max_jump_record)
         self.h = ctypes.c_void_p()
+        if workspace is not None:  # (device pointer, bytes) owned by the caller: qt_mc_plan_create_ws
+            if self.p.td.n_h or self.p.td.c_coefs:
+                raise ValueError("time-dependent trajectory plans allocate their own arena")
+            _check(lib().qt_mc_plan_create_ws(ctx.h, ctypes.byref(self.p.s), ctypes.byref(o), self.mj,
+                                              *_ws(workspace), ctypes.byref(self.h)))
+            return
         _check(lib().qt_mc_plan_create_td(ctx.h, ctypes.byref(self.p.s), ctypes.byref(self.p.td), ctypes.byref(o),
                                           self.mj, ctypes.byref(self.h)))
 
@@ -553,15 +614,27 @@ class McPlan:
             pass
 
 
+def server_workspace(pool_bytes=16 << 30, max_slots=256, steps_per_epoch=32, options=None):
+    """Device bytes of a server's memory region (qt_server_workspace)."""
+    o = options or opts(precision=MIXED)
+    cfg = ServerCfg(int(pool_bytes), int(max_slots), int(steps_per_epoch), o)
+    b = ctypes.c_size_t()
+    _check(lib().qt_server_workspace(ctypes.byref(cfg), ctypes.byref(b)))
+    return b.value
+
+
 class Server:
     """qt_server_*: continuous-batching master-equation server."""
 
-    def __init__(self, ctx, pool_bytes=16 << 30, max_slots=256, steps_per_epoch=32, options=None):
+    def __init__(self, ctx, pool_bytes=16 << 30, max_slots=256, steps_per_epoch=32, options=None, workspace=None):
         o = options or opts(precision=MIXED)
         self.ctx = ctx
         self.cfg = ServerCfg(int(pool_bytes), int(max_slots), int(steps_per_epoch), o)
         self.h = ctypes.c_void_p()
-        _check(lib().qt_server_create(ctx.h, ctypes.byref(self.cfg), ctypes.byref(self.h)))
+        if workspace is not None:  # (device pointer, bytes) owned by the caller: qt_server_create_ws
+            _check(lib().qt_server_create_ws(ctx.h, ctypes.byref(self.cfg), *_ws(workspace), ctypes.byref(self.h)))
+        else:
+            _check(lib().qt_server_create(ctx.h, ctypes.byref(self.cfg), ctypes.byref(self.h)))
         self.pending = {}
 
     def footprint(self, L, rho0, tlist, e_ops):

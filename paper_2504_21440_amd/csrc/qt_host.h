@@ -41,10 +41,12 @@ HCsr csr_zero(int32_t d);
 std::vector<int32_t> expect_vec_index(const std::vector<int32_t> &eptr, const std::vector<int32_t> &ecol, int32_t d,
                                       int32_t ne);
 
-// A device arena: one hipMalloc carved into 256-byte aligned pieces.
+// A device arena: one hipMalloc carved into 256-byte aligned pieces, or a caller's device buffer
+// (adopt), which the arena never frees.
 struct Arena {
     void *base = nullptr;
     size_t size = 0, used = 0;
+    bool external = false;
     std::vector<std::pair<size_t, size_t>> plan;  // planned offsets
     size_t reserve(size_t bytes)
     {
@@ -53,6 +55,10 @@ struct Arena {
         return off;
     }
     qt_status alloc();
+    // Places the planned layout in the caller's buffer (256-byte aligned, at least `size` bytes).
+    qt_status adopt(void *ws, size_t ws_bytes, const char *who);
+    // alloc() without a caller buffer, adopt() with one.
+    qt_status place(void *ws, size_t ws_bytes, const char *who) { return ws ? adopt(ws, ws_bytes, who) : alloc(); }
     void *at(size_t off) const { return (char *)base + off; }
     void release();
 };

@@ -29,10 +29,13 @@ struct qt_mc_plan {
 
 namespace qt {
 
+// ws: the caller's device workspace (null: the plan allocates its arena); query: only report the
+// workspace bytes and create nothing.
 static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_td_terms *td, const qt_opts *opts_in,
-                                int32_t maxj, qt_mc_plan **out)
+                                int32_t maxj, qt_mc_plan **out, void *ws = nullptr, size_t ws_bytes = 0,
+                                size_t *query = nullptr)
 {
-    if (!ctx || !pr || !out || !pr->H) return set_error(QT_EINVAL, "qt_mc_plan_create: null argument");
+    if (!ctx || !pr || (!out && !query) || !pr->H) return set_error(QT_EINVAL, "qt_mc_plan_create: null argument");
     qt_opts o;
     if (opts_in) o = *opts_in;
     else qt_opts_default(&o);
@@ -210,7 +213,12 @@ static qt_status mc_plan_create(Ctx *ctx, const qt_mc_problem *pr, const qt_td_t
     P->o_mean = a.reserve(std::max<size_t>(1, (size_t)pr->n_e * pr->n_t) * 16);
     P->o_se = a.reserve(std::max<size_t>(1, (size_t)pr->n_e * pr->n_t) * 8);
     P->o_params = a.reserve(sizeof(McParams));
-    if ((st = a.alloc())) {
+    if (query) {
+        *query = a.size;
+        delete P;
+        return QT_OK;
+    }
+    if ((st = a.place(ws, ws_bytes, "qt_mc_plan_create_ws"))) {
         delete P;
         return st;
     }
@@ -359,6 +367,36 @@ qt_status qt_mc_plan_create_td(qt_ctx *ctx, const qt_mc_problem *prob, const qt_
                                int32_t max_jump_record, qt_mc_plan **out)
 {
     return mc_plan_create(ctx, prob, td, opts, max_jump_record, out);
+}
+
+qt_status qt_mc_plan_workspace(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, int32_t max_jump_record,
+                               size_t *bytes)
+{
+    if (!bytes) return set_error(QT_EINVAL, "qt_mc_plan_workspace: null bytes");
+    return mc_plan_create(ctx, prob, nullptr, opts, max_jump_record, nullptr, nullptr, 0, bytes);
+}
+
+qt_status qt_mc_plan_create_ws(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, int32_t max_jump_record,
+                               void *dev_ws, size_t ws_bytes, qt_mc_plan **out)
+{
+    if (!dev_ws) return set_error(QT_EINVAL, "qt_mc_plan_create_ws: null workspace");
+    return mc_plan_create(ctx, prob, nullptr, opts, max_jump_record, out, dev_ws, ws_bytes, nullptr);
+}
+
+qt_status qt_mcsolve_ws(qt_ctx *ctx, const qt_mc_problem *prob, const qt_opts *opts, void *dev_ws, size_t ws_bytes,
+                        double *mean_out, double *se_out, double *expect_tr, int64_t *njumps, int32_t max_jump_record,
+                        double *jump_times, int32_t *jump_channels, qt_stats *stats)
+{
+    qt_mc_plan *P = nullptr;
+    qt_status st = qt_mc_plan_create_ws(ctx, prob, opts, max_jump_record, dev_ws, ws_bytes, &P);
+    if (st) {
+        if (stats) stats->status = st;
+        return st;
+    }
+    st = qt_mc_plan_run(P);
+    if (!st) st = qt_mc_plan_result(P, mean_out, se_out, expect_tr, njumps, jump_times, jump_channels, stats);
+    qt_mc_plan_destroy(P);
+    return st;
 }
 
 qt_status qt_mc_plan_run(qt_mc_plan *plan)

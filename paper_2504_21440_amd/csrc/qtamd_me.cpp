@@ -265,10 +265,12 @@ static qt_status restore_full(qt_me_plan *P)
 
 qt_status me_plan_autotune(qt_me_plan *P, int32_t reps);
 
+// ws: the caller's device workspace (null: the plan allocates its arena); query: only report the
+// workspace bytes the problems need and create nothing.
 qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts_in, qt_me_plan **out,
-                         double steady_tol)
+                         double steady_tol, void *ws = nullptr, size_t ws_bytes = 0, size_t *query = nullptr)
 {
-    if (!ctx || n <= 0 || !probs || !out) return set_error(QT_EINVAL, "qt_me_plan_create: bad arguments");
+    if (!ctx || n <= 0 || !probs || (!out && !query)) return set_error(QT_EINVAL, "qt_me_plan_create: bad arguments");
     if (!(steady_tol >= 0.0) || !std::isfinite(steady_tol)) return set_error(QT_EINVAL, "steady-state tolerance");
     qt_opts opts;
     if (opts_in) opts = *opts_in;
@@ -340,7 +342,12 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
         P->o_dctl = A.reserve(sizeof(DenseCtl) * P->ndense);
         P->o_dorder = A.reserve(sizeof(int32_t) * P->ndense);
     }
-    qt_status st = A.alloc();
+    if (query) {
+        *query = A.size;
+        delete P;
+        return QT_OK;
+    }
+    qt_status st = A.place(ws, ws_bytes, "qt_me_plan_create_ws");
     if (st) {
         delete P;
         return st;
@@ -826,6 +833,20 @@ qt_status qt_me_plan_create(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, 
     return me_plan_create(ctx, n, probs, opts, out, 0.0);
 }
 
+qt_status qt_me_plan_workspace(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts,
+                               size_t *bytes)
+{
+    if (!bytes) return set_error(QT_EINVAL, "qt_me_plan_workspace: null bytes");
+    return me_plan_create(ctx, n, probs, opts, nullptr, 0.0, nullptr, 0, bytes);
+}
+
+qt_status qt_me_plan_create_ws(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, void *dev_ws,
+                               size_t ws_bytes, qt_me_plan **out)
+{
+    if (!dev_ws) return set_error(QT_EINVAL, "qt_me_plan_create_ws: null workspace");
+    return me_plan_create(ctx, n, probs, opts, out, 0.0, dev_ws, ws_bytes, nullptr);
+}
+
 qt_status qt_me_plan_create_steady(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, double tol,
                                    qt_me_plan **out)
 {
@@ -957,6 +978,22 @@ qt_status qt_mesolve(qt_ctx *ctx, const qt_me_problem *prob, const qt_opts *opts
 {
     qt_me_plan *P = nullptr;
     qt_status st = qt_me_plan_create(ctx, 1, prob, opts, &P);
+    if (st) {
+        if (stats) stats->status = st;
+        return st;
+    }
+    st = qt_me_plan_run(P);
+    if (!st) st = qt_me_plan_result(P, 0, expect_out, rho_final, stats);
+    else if (stats) stats->status = st;
+    qt_me_plan_destroy(P);
+    return st;
+}
+
+qt_status qt_mesolve_ws(qt_ctx *ctx, const qt_me_problem *prob, const qt_opts *opts, void *dev_ws, size_t ws_bytes,
+                        double *expect_out, double *rho_final, qt_stats *stats)
+{
+    qt_me_plan *P = nullptr;
+    qt_status st = qt_me_plan_create_ws(ctx, 1, prob, opts, dev_ws, ws_bytes, &P);
     if (st) {
         if (stats) stats->status = st;
         return st;

@@ -33,10 +33,23 @@ qt_status Arena::alloc()
     return QT_OK;
 }
 
+qt_status Arena::adopt(void *ws, size_t ws_bytes, const char *who)
+{
+    if (((uintptr_t)ws & 255) != 0)
+        return set_error(QT_EINVAL, std::string(who) + ": workspace must be 256-byte aligned");
+    if (ws_bytes < size)
+        return set_error(QT_ENOMEM, std::string(who) + ": workspace of " + std::to_string(ws_bytes) +
+                                        " bytes, " + std::to_string(size) + " needed");
+    base = ws;
+    external = true;
+    return QT_OK;
+}
+
 void Arena::release()
 {
-    if (base) (void)hipFree(base);
+    if (base && !external) (void)hipFree(base);
     base = nullptr;
+    external = false;
     size = used = 0;
 }
 
@@ -757,6 +770,13 @@ qt_status qt_liouv_info(const qt_liouv *L, int32_t *d, int64_t *nnz, int64_t *by
     if (d) *d = L->d;
     if (nnz) *nnz = L->nnz;
     if (bytes) *bytes = L->bytes;
+    return QT_OK;
+}
+
+qt_status qt_liouv_footprint(const qt_liouv *L, size_t *bytes)
+{
+    if (!L || !bytes) return set_error(QT_EINVAL, "qt_liouv_footprint: null argument");
+    *bytes = (size_t)L->bytes;
     return QT_OK;
 }
 

@@ -99,6 +99,7 @@ struct qt_server {
     qt::Ctx *ctx = nullptr;
     qt_server_cfg cfg{};
     int32_t prec = QT_MIXED;
+    qt::Arena arena;  // pool, slot arrays and block tables: one allocation, or the caller's workspace
     void *pool = nullptr;
     qt::PoolAlloc alloc;
     // slot-indexed device arrays
@@ -120,7 +121,7 @@ struct qt_server {
         int32_t *d_bi = nullptr, *d_br = nullptr, *d_ilist = nullptr;
         int32_t *d_counts = nullptr;  // [0] live blocks of the table, [1] live entries of the control list
         int32_t h_counts[2] = {0, 0};
-        size_t blk_cap = 0;           // allocated entries of d_bi / d_br
+        size_t blk_cap = 0;           // entries of d_bi / d_br (a power of two, fixed at creation)
         std::map<int, EpochGraph> graphs;
     };
     Lane lanes[2];  // 0: large Liouvillians (context stream), 1: small ones (auxiliary stream)
@@ -358,17 +359,8 @@ static qt_status launch_lane(qt_server *S, qt_server::Lane &ln, const std::vecto
 {
     int grid = 256;
     while ((size_t)grid < bi.size()) grid *= 2;
-    if ((size_t)grid > ln.blk_cap) {
-        QT_HIP(hipStreamSynchronize(s));  // the old table may still be read by a launch in flight
-        drop_graphs(ln);
-        if (ln.d_bi) (void)hipFree(ln.d_bi);
-        if (ln.d_br) (void)hipFree(ln.d_br);
-        ln.d_bi = ln.d_br = nullptr;
-        ln.blk_cap = 0;
-        QT_HIP(hipMalloc(&ln.d_bi, (size_t)grid * 4));
-        QT_HIP(hipMalloc(&ln.d_br, (size_t)grid * 4));
-        ln.blk_cap = (size_t)grid;
-    }
+    // the table capacity bounds every admissible mix of requests (server_table_capacity)
+    if ((size_t)grid > ln.blk_cap) return set_error(QT_EDEVICE, "server block table over its capacity");
     ln.h_counts[0] = (int32_t)bi.size();
     ln.h_counts[1] = (int32_t)slots.size();
     QT_HIP(hipMemcpyAsync(ln.d_bi, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, s));
@@ -540,36 +532,93 @@ static qt_status server_step(qt_server *S, int32_t *n_active, int32_t *n_finishe
     return QT_OK;
 }
 
-}  // namespace qt
-
-using namespace qt;
-
-extern "C" {
-
-qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **out)
+// Workgroup-table entries one lane can need: a resident CSR request of n Liouville rows has
+// ceil(n / rows_per_block) blocks and holds at least 11 n state values of the pool, so the blocks of
+// everything the pool admits number at most pool_bytes / (11 es rows_per_block) + max_slots.  Epoch
+// grids are powers of two of at least 256, so the capacity is the power of two at or above that.
+static size_t server_table_capacity(const qt_server_cfg *cfg, const CsrShape &sh)
 {
-    if (!ctx || !cfg || !out) return set_error(QT_EINVAL, "qt_server_create: null argument");
+    const size_t rpb = (size_t)csr_rows_per_block(sh.lpr, sh.rg);
+    const size_t bound = (size_t)cfg->pool_bytes / (11 * es_of(cfg->opts.precision) * rpb) + (size_t)cfg->max_slots;
+    size_t cap = 256;
+    while (cap < bound) cap *= 2;
+    return cap;
+}
+
+static CsrShape server_shape()
+{
+    // requests of many sizes share one grid: the shape for small spin and oscillator Liouvillians
+    CsrShape sh = csr_default_shape(0, 19.0);
+    sh.keep = 1;  // matrices read through the caches: many small resident ones fit the L2s / MALL
+    return sh;
+}
+
+static qt_status check_cfg(const qt_server_cfg *cfg)
+{
     if (cfg->pool_bytes <= 0 || cfg->max_slots <= 0 || cfg->steps_per_epoch <= 0)
         return set_error(QT_EINVAL, "server config: pool_bytes, max_slots and steps_per_epoch must be positive");
     if (cfg->opts.precision != QT_F64 && cfg->opts.precision != QT_MIXED)
         return set_error(QT_EINVAL, "server config: bad precision");
+    return QT_OK;
+}
+
+// Lays out the server's device memory in S->arena and returns the offsets through the members.
+struct ServerLayout {
+    size_t pool, cinst, cctl, dinst, dctl, order, ilist[2], counts[2], bi[2], br[2];
+};
+static ServerLayout server_layout(Arena &A, const qt_server_cfg *cfg, size_t cap)
+{
+    const size_t ns = (size_t)cfg->max_slots;
+    ServerLayout L;
+    L.pool = A.reserve((size_t)cfg->pool_bytes);
+    L.cinst = A.reserve(sizeof(CsrInst) * ns);
+    L.cctl = A.reserve(sizeof(CsrCtl) * ns);
+    L.dinst = A.reserve(sizeof(DenseInst) * ns);
+    L.dctl = A.reserve(sizeof(DenseCtl) * ns);
+    L.order = A.reserve(sizeof(int32_t) * ns);
+    for (int k = 0; k < 2; ++k) {
+        L.ilist[k] = A.reserve(sizeof(int32_t) * ns);
+        L.counts[k] = A.reserve(sizeof(int32_t) * 2);
+        L.bi[k] = A.reserve(4 * cap);
+        L.br[k] = A.reserve(4 * cap);
+    }
+    return L;
+}
+
+static qt_status server_create(Ctx *ctx, const qt_server_cfg *cfg, void *ws, size_t ws_bytes, qt_server **out)
+{
+    if (!ctx || !cfg || !out) return set_error(QT_EINVAL, "qt_server_create: null argument");
+    qt_status st = check_cfg(cfg);
+    if (st) return st;
     QT_HIP(hipSetDevice(ctx->device));
     qt_server *S = new qt_server();
     S->ctx = ctx;
     S->cfg = *cfg;
     S->prec = cfg->opts.precision;
+    S->shape = server_shape();
     const int ns = cfg->max_slots;
-    hipError_t e = hipMalloc(&S->pool, (size_t)cfg->pool_bytes);
-    if (e == hipSuccess) e = hipMalloc(&S->d_cinst, sizeof(CsrInst) * ns);
-    if (e == hipSuccess) e = hipMalloc(&S->d_cctl, sizeof(CsrCtl) * ns);
-    if (e == hipSuccess) e = hipMalloc(&S->d_dinst, sizeof(DenseInst) * ns);
-    if (e == hipSuccess) e = hipMalloc(&S->d_dctl, sizeof(DenseCtl) * ns);
-    if (e == hipSuccess) e = hipMalloc(&S->d_order, sizeof(int32_t) * ns);
-    for (auto &ln : S->lanes) {
-        if (e == hipSuccess) e = hipMalloc(&ln.d_ilist, sizeof(int32_t) * ns);
-        if (e == hipSuccess) e = hipMalloc(&ln.d_counts, sizeof(int32_t) * 2);
+    const size_t cap = server_table_capacity(cfg, S->shape);
+    const ServerLayout Ly = server_layout(S->arena, cfg, cap);
+    if ((st = S->arena.place(ws, ws_bytes, "qt_server_create_ws"))) {
+        delete S;
+        return st;
     }
-    if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_cctl, sizeof(CsrCtl) * ns, hipHostMallocDefault);
+    Arena &A = S->arena;
+    S->pool = A.at(Ly.pool);
+    S->d_cinst = (CsrInst *)A.at(Ly.cinst);
+    S->d_cctl = (CsrCtl *)A.at(Ly.cctl);
+    S->d_dinst = (DenseInst *)A.at(Ly.dinst);
+    S->d_dctl = (DenseCtl *)A.at(Ly.dctl);
+    S->d_order = (int32_t *)A.at(Ly.order);
+    for (int k = 0; k < 2; ++k) {
+        auto &ln = S->lanes[k];
+        ln.d_ilist = (int32_t *)A.at(Ly.ilist[k]);
+        ln.d_counts = (int32_t *)A.at(Ly.counts[k]);
+        ln.d_bi = (int32_t *)A.at(Ly.bi[k]);
+        ln.d_br = (int32_t *)A.at(Ly.br[k]);
+        ln.blk_cap = cap;
+    }
+    hipError_t e = hipHostMalloc((void **)&S->h_cctl, sizeof(CsrCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_dctl, sizeof(DenseCtl) * ns, hipHostMallocDefault);
     if (e == hipSuccess) {
         // every slot starts finished: the kernels skip it until a request is admitted into it
@@ -579,8 +628,10 @@ qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **ou
             std::memset(&S->h_dctl[i], 0, sizeof(DenseCtl));
             S->h_dctl[i].status = ST_DONE;
         }
-        e = hipMemcpy(S->d_cctl, S->h_cctl, sizeof(CsrCtl) * ns, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(S->d_dctl, S->h_dctl, sizeof(DenseCtl) * ns, hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(S->d_cctl, S->h_cctl, sizeof(CsrCtl) * ns, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S->d_dctl, S->h_dctl, sizeof(DenseCtl) * ns, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     }
     if (e != hipSuccess) {
         qt_server_destroy(S);
@@ -589,13 +640,38 @@ qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **ou
     }
     S->alloc.init((size_t)cfg->pool_bytes);
     for (int i = ns - 1; i >= 0; --i) S->free_slots.push_back(i);
-    // requests of many sizes share one grid: the shape for small spin and oscillator Liouvillians
-    S->shape = csr_default_shape(0, 19.0);
-    S->shape.keep = 1;  // matrices read through the caches: many small resident ones fit the L2s / MALL
     ctx->refs++;
     S->counted = true;
     *out = S;
     return QT_OK;
+}
+
+}  // namespace qt
+
+using namespace qt;
+
+extern "C" {
+
+qt_status qt_server_create(qt_ctx *ctx, const qt_server_cfg *cfg, qt_server **out)
+{
+    return server_create(ctx, cfg, nullptr, 0, out);
+}
+
+qt_status qt_server_workspace(const qt_server_cfg *cfg, size_t *bytes)
+{
+    if (!cfg || !bytes) return set_error(QT_EINVAL, "qt_server_workspace: null argument");
+    qt_status st = check_cfg(cfg);
+    if (st) return st;
+    Arena A;
+    (void)server_layout(A, cfg, server_table_capacity(cfg, server_shape()));
+    *bytes = A.size;
+    return QT_OK;
+}
+
+qt_status qt_server_create_ws(qt_ctx *ctx, const qt_server_cfg *cfg, void *dev_ws, size_t ws_bytes, qt_server **out)
+{
+    if (!dev_ws) return set_error(QT_EINVAL, "qt_server_create_ws: null workspace");
+    return server_create(ctx, cfg, dev_ws, ws_bytes, out);
 }
 
 qt_status qt_server_footprint(const qt_server *srv, const qt_me_problem *prob, int64_t *bytes)
@@ -644,20 +720,9 @@ qt_status qt_server_destroy(qt_server *S)
     (void)hipStreamSynchronize(S->ctx->stream);
     for (int b = 0; b < Ctx::NPOOL; ++b)
         if (S->ctx->pool[b]) (void)hipStreamSynchronize(S->ctx->pool[b]);
-    if (S->pool) (void)hipFree(S->pool);
-    if (S->d_cinst) (void)hipFree(S->d_cinst);
-    if (S->d_cctl) (void)hipFree(S->d_cctl);
-    if (S->d_dinst) (void)hipFree(S->d_dinst);
-    if (S->d_dctl) (void)hipFree(S->d_dctl);
-    if (S->d_order) (void)hipFree(S->d_order);
     (void)hipStreamSynchronize(S->ctx->aux);
-    for (auto &ln : S->lanes) {
-        if (ln.d_ilist) (void)hipFree(ln.d_ilist);
-        if (ln.d_counts) (void)hipFree(ln.d_counts);
-        drop_graphs(ln);
-        if (ln.d_bi) (void)hipFree(ln.d_bi);
-        if (ln.d_br) (void)hipFree(ln.d_br);
-    }
+    for (auto &ln : S->lanes) drop_graphs(ln);
+    S->arena.release();
     if (S->h_cctl) (void)hipHostFree(S->h_cctl);
     if (S->h_dctl) (void)hipHostFree(S->h_dctl);
     if (S->counted) S->ctx->refs--;
