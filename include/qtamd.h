@@ -286,6 +286,19 @@ qt_status qt_tune_load(const char *path);
  * (QT_F64) or complex64 (QT_MIXED), accumulated in FP64.  out: one complex (host). */
 qt_status qt_expect(qt_ctx *ctx, int32_t d, const qt_csr *O, const void *dev_state, int32_t is_ket,
                     int32_t precision, double *out);
+/* The same expectation value for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): it calls no hipMalloc, hipFree or
+ * other allocating routine.  The operator is staged, as the caller passes it, in a device array of
+ * QT_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the process ends;
+ * an operator that needs more (about 12 (d + 1) + 20 nnz bytes plus alignment) is rejected with
+ * QT_ENOMEM.  O is read in place: its entries are summed in the order given (duplicates are two
+ * terms; for a canonical CSR -- rows sorted, no duplicates or exact zeros -- the result is bitwise
+ * that of qt_expect).  Every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU (two threads, or two contexts whose streams run at the same time) race; the call returns
+ * after its stream is synchronised.  Errors as for qt_expect, plus QT_ENOMEM for the size limit. */
+#define QT_NOALLOC_SCRATCH_BYTES (8 << 20)
+qt_status qt_expect_noalloc(qt_ctx *ctx, int32_t d, const qt_csr *O, const void *dev_state, int32_t is_ket,
+                            int32_t precision, double *out);
 
 /* Monte-Carlo wave function (Sec. 3.3).  Trajectory j draws from Philox-4x32-10 keyed by seed
  * with counter (j_lo, j_hi, event, 0): event 0 gives the first threshold, event m >= 1 the channel

@@ -24,7 +24,7 @@ EXPORTED = [
     "qt_model_ising", "qt_csr_free", "qt_liouvillian_build", "qt_liouv_info", "qt_liouv_export",
     "qt_liouv_destroy", "qt_liouvillian_build_td", "qt_liouv_terms", "qt_mesolve", "qt_mesolve_batch", "qt_me_plan_create", "qt_me_plan_run",
     "qt_me_plan_result", "qt_me_plan_destroy", "qt_me_plan_time_rhs", "qt_me_plan_autotune",
-    "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_me_plan_create_steady", "qt_steadystate", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
+    "qt_me_plan_set_shape", "qt_me_plan_shape", "qt_me_plan_create_steady", "qt_steadystate", "qt_tune_save", "qt_tune_load", "qt_expect", "qt_expect_noalloc", "qt_mcsolve", "qt_mc_plan_create", "qt_mc_plan_run",
     "qt_mc_plan_result", "qt_mc_plan_destroy", "qt_sesolve", "qt_mc_plan_create_td", "qt_mcsolve_td",
     "qt_sesolve_td", "qt_sde_plan_create", "qt_sde_plan_run", "qt_sde_plan_result", "qt_sde_plan_destroy",
     "qt_ssesolve", "qt_smesolve", "qt_server_create", "qt_server_submit", "qt_server_step",
@@ -464,6 +464,16 @@ def expect(ctx, O, dev_state_ptr, d, is_ket=False, precision=F64):
     E = _Ops([O])
     out = np.zeros(2)
     _check(lib().qt_expect(ctx.h, d, E.ptr, ctypes.c_void_p(dev_state_ptr), int(is_ket), precision, _p(out)))
+    return complex(out[0], out[1])
+
+
+def expect_noalloc(ctx, O, dev_state_ptr, d, is_ket=False, precision=F64):
+    """qt_expect_noalloc: the same value as :func:`expect`, staged in the library's fixed device
+    scratch array instead of memory allocated per call."""
+    E = _Ops([O])
+    out = np.zeros(2)
+    _check(lib().qt_expect_noalloc(ctx.h, d, E.ptr, ctypes.c_void_p(dev_state_ptr), int(is_ket), precision,
+                                   _p(out)))
     return complex(out[0], out[1])
 
 

@@ -127,6 +127,8 @@ void csr_launch_init(int which, const CsrLaunch &L, hipStream_t s);
 void csr_launch_step(const CsrLaunch &L, hipStream_t s);
 void csr_launch_stage3(const CsrLaunch &L, hipStream_t s);
 constexpr int CSR_MIN_ROWS_PER_BLOCK = 16;  // smallest tile (16 lanes per row, one row per group)
+// Looks up the device address of the allocation-free scratch array on `device` (current).
+qt_status noalloc_init_device(int32_t device);
 void launch_expect(bool f64, int d, const int32_t *rp, const int32_t *ci, const double2 *v, const void *state,
                    int is_ket, double2 *out, hipStream_t s);
 

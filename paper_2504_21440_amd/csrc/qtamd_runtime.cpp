@@ -240,6 +240,11 @@ qt_status qt_ctx_create(int32_t device, void *hip_stream, qt_ctx **out)
         delete c;
         return set_error(QT_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     }
+    qt_status st = noalloc_init_device(device);
+    if (st) {
+        qt_ctx_destroy(c);
+        return st;
+    }
     *out = c;
     return QT_OK;
 }
