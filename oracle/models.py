@@ -81,6 +81,26 @@ def optomech(Nc, Nm, wc, wm, g, kappa, gamma):
     return sp.csr_matrix(H), sp.csr_matrix(xa), c_ops, sp.csr_matrix(ad @ a)
 
 
+def jc_homodyne(N, wc, wq, g, kappa, gamma, kappa_phi, alpha):
+    """The homodyne-detection example (Sec. 3.5): a cavity (cutoff N, first factor) coupled to a
+    qubit, H = wc a^dag a + (wq/2) sz + g (a^dag sm + a sm^dag); measured operator sqrt(kappa) a; extra
+    losses of the master-equation variant sqrt(gamma) sm and sqrt(kappa_phi) a^dag a; the observable
+    sqrt(kappa) (a + a^dag); initial state the coherent state alpha (real) times the excited qubit.
+    Returns (H, [S], c_ops, X, psi0)."""
+    from math import exp, factorial, sqrt
+    a = tensor(destroy(N), qeye(2))
+    sm = tensor(qeye(N), sigmam())
+    sz = tensor(qeye(N), sigmaz())
+    ad = a.conj().T
+    H = wc * (ad @ a) + 0.5 * wq * sz + g * (ad @ sm + a @ sm.conj().T)
+    S = [sp.csr_matrix(np.sqrt(kappa) * a)]
+    c_ops = [sp.csr_matrix(np.sqrt(gamma) * sm), sp.csr_matrix(np.sqrt(kappa_phi) * (ad @ a))]
+    X = sp.csr_matrix(np.sqrt(kappa) * (a + ad))
+    coh = np.array([exp(-alpha ** 2 / 2) * alpha ** n / sqrt(float(factorial(n))) for n in range(N)])
+    psi0 = np.kron(coh, np.array([1.0, 0.0])).astype(complex)
+    return sp.csr_matrix(H), S, c_ops, X, psi0
+
+
 def number(N):
     a = destroy(N)
     return sp.csr_matrix(a.conj().T @ a)
