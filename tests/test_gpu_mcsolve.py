@@ -149,3 +149,28 @@ def test_sesolve_vs_oracle(ctx, prec, tol):
         ex, st = qt.sesolve(ctx, H, psi0, tl, e_ops, options=qt.opts(precision=prec))
         assert st["status"] == 0 and st["n_jumps"] == 0
         assert np.abs(ex - ref).max() <= tol, np.abs(ex - ref).max()
+
+
+def test_sesolve_l10_full_horizon_as_benchmarked(ctx):
+    """The closed L = 10 chain exactly as benchmarked (d = 1,024, t in [0, 10], <sum sigma_z> at 100
+    times): FP64 at the default tolerances against the oracle at the same tolerances (same integrator,
+    <= 1e-6), and both FP64 and mixed precision at rtol 1e-6 / atol 1e-8 (the loosest tolerance of the
+    ladder that meets 1e-4 in mixed precision) within 1e-4 of the stored tight FP64 oracle solution."""
+    print("[gpu] sesolve L=10 full horizon", flush=True)
+    p = workloads.ising_mc()
+    H = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])[0]
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    e = [_sz_sum(p["L"])]
+    psi0 = om.all_up_ket(p["L"])
+    ref, status = oracle.sesolve(H, psi0, tl, e)
+    assert status == 0
+    ex, st = qt.sesolve(ctx, H, psi0, tl, e, options=qt.opts(precision=qt.F64))
+    assert st["status"] == 0 and np.abs(ex - ref).max() <= 1e-6, np.abs(ex - ref).max()
+    with open(os.path.join(GOLD, "sesolve_l10_tight.json")) as f:
+        g = json.load(f)
+    tight = np.array(g["expect_re"]) + 1j * np.array(g["expect_im"])
+    for prec in (qt.F64, qt.MIXED):
+        ex, st = qt.sesolve(ctx, H, psi0, tl, e, options=qt.opts(abstol=1e-8, reltol=1e-6, precision=prec))
+        err = np.abs(ex - tight).max()
+        print(f"[gpu]   prec={prec}: max |d<sum sz>| vs tight oracle = {err:.2e}", flush=True)
+        assert st["status"] == 0 and err <= 1e-4

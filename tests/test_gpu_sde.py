@@ -71,6 +71,34 @@ def test_sme_trajectories_match_oracle_fp64(ctx, m):
     np.testing.assert_allclose(res["mean"], ref["mean"], atol=1e-8)
 
 
+@pytest.mark.parametrize("master", [False, True])
+def test_homodyne_example_at_benched_size_matches_stored_oracle_trajectories(ctx, master):
+    """The homodyne example exactly as benchmarked (cavity cutoff 20, d = 40; SME n = 1,600; 500
+    FP64 trajectories, step 1e-3 over t in [0, 2 pi], 400 saves): its first trajectories equal the
+    stored FP64 oracle trajectories (same Wiener increments) within 1e-8 in <X> and 1e-6 in the
+    interval-averaged current."""
+    import json
+    import os
+    import workloads
+    print(f"[gpu] homodyne example {'SME' if master else 'SSE'} at benched size vs stored oracle", flush=True)
+    p = workloads.jc_homodyne()
+    H, S, C, X, psi0 = om.jc_homodyne(p["N"], p["wc"], p["wq"], p["g"], p["kappa"], p["gamma"], p["kappa_phi"],
+                                      p["alpha"])
+    tl = np.linspace(0.0, p["t_end"], p["nt"])
+    P = qt.SdePlan(ctx, H, S, psi0, tl, [X], p["ntraj"], p["seed"], p["dt"], c_ops=C if master else (),
+                   master=master, options=qt.opts(precision=qt.F64))
+    P.run()
+    r = P.result(want_traj=True)
+    P.close()
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "jc_homodyne_traj.json")) as f:
+        g = json.load(f)["sme" if master else "sse"]
+    ref = np.array(g["expect_re"]) + 1j * np.array(g["expect_im"])
+    k = ref.shape[0]
+    assert r["stats"]["status"] == 0
+    assert np.abs(r["expect_tr"][:k] - ref).max() < 1e-8
+    assert np.abs(r["measurement"][:k] - np.array(g["measurement"])).max() < 1e-6
+
+
 def test_sse_coherent_state_closed_form(ctx):
     """Homodyne detection of a lossy cavity keeps a coherent state coherent with the deterministic
     amplitude alpha e^{-(i w + kappa/2) t}, in FP64 and mixed precision."""

@@ -177,6 +177,37 @@ def test_td_optomechanics_every_launch_form_vs_oracle(ctx):
             plan.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(qt.F64, 1e-6), (qt.MIXED, 1e-4)])
+def test_td_optomechanics_example_at_benched_size(ctx, prec, tol):
+    """The optomechanical example exactly as benchmarked (cavity cutoff 10, mechanical cutoff 7:
+    n = 4,900; t in [0, 5 / kappa] = [0, 500], 5,000 saves; default tolerances; the shipped tuning
+    table and autotuner picking the launch shape) against the stored FP64 oracle solution."""
+    import json
+    import os
+    print(f"[gpu] TD optomech example at benched size prec={prec}", flush=True)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    qt.tune_load(os.path.join(root, "paper_2504_21440_amd", "tuning", "mi355x.json"))
+    p = workloads.optomech_td()
+    H0, xa, c, n_op = om.optomech(p["Nc"], p["Nm"], p["wc"], p["wm"], p["g"], p["kappa"], p["gamma"])
+    d = p["Nc"] * p["Nm"]
+    rho0 = np.zeros((d, d), complex)
+    rho0[0, 0] = 1.0
+    L = qt.Liouvillian(ctx, H0, c, qt.FORM_CSR, prec, h_terms=[(xa, {"kind": "cos", "a": p["F"], "omega": p["wd"]})])
+    plan = qt.MePlan(ctx, [(L, rho0, workloads.tlist(p["t_end"], p["nt"]), [n_op])],
+                     qt.opts(precision=prec, autotune=True))
+    plan.run()
+    ex, st, _ = plan.result(0)
+    plan.close()
+    L.close()
+    with open(os.path.join(root, "tests", "golden", "optomech_full.json")) as f:
+        g = json.load(f)
+    ref = np.array(g["expect_re"]) + 1j * np.array(g["expect_im"])
+    assert st["status"] == 0
+    err = np.abs(ex - ref).max()
+    print(f"[gpu]   max |d<a^dag a>| = {err:.2e} over {p['nt']} saves, {st['n_accept']} steps", flush=True)
+    assert err <= tol
+
+
 def test_td_plan_keeps_constant_problems_bitwise(ctx):
     """A constant problem in a plan that also holds a time-dependent one runs through the weighted
     kernels with the coefficient 1: its results equal those of the constant-only plan bit for bit."""
