@@ -138,11 +138,9 @@ template <typename V, int RG> __device__ __forceinline__ V pick(const V (&a)[RG]
 // Tr(O_k Y) for operator k, accumulated in FP64 by one wave: Tr(O rho) = sum_{(i,j) in nnz(O)}
 // O_ij rho_ji, one gather per entry through evidx, reduced with shuffles in a fixed order.
 template <typename V>
-__device__ __forceinline__ double2 csr_expect_one(const CsrInst &I, const V *__restrict__ Y, int k)
+__device__ __forceinline__ double2 csr_expect_range(const CsrInst &I, const V *__restrict__ Y, int b, int e)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t *ep = I.eptr + (size_t)k * (I.d + 1);
-    const int b = ep[0], e = ep[I.d];
     double sr = 0.0, si = 0.0;
 #pragma unroll 4
     for (int p = b + lane; p < e; p += 64) {
@@ -152,6 +150,13 @@ __device__ __forceinline__ double2 csr_expect_one(const CsrInst &I, const V *__r
         si += o.x * r.y + o.y * r.x;
     }
     return make_double2(wave_sum(sr), wave_sum(si));
+}
+
+template <typename V>
+__device__ __forceinline__ double2 csr_expect_one(const CsrInst &I, const V *__restrict__ Y, int k)
+{
+    const int32_t *ep = I.eptr + (size_t)k * (I.d + 1);
+    return csr_expect_range(I, Y, ep[0], ep[I.d]);
 }
 
 // Expectation values of the state Y (times `scale`) into expect[k][idx]: one wave per operator,
@@ -339,7 +344,13 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
     }
     V acc[RG];
     const V *__restrict__ cw = td_coefs<V, TD>(I, S);
-    if (S == 2) {
+    // For a constant L, k1 = L y (first same as last), so the second stage's right-hand side
+    // L (y + a21 h k1) = k1 + a21 h (L k1): one gather per entry instead of two.  A constant problem
+    // in a plan with time-dependent ones takes the same route through the weighted kernels.
+    const bool lin2 = S == 2 && (!TD || I.nterms == 0);
+    if (lin2) {
+        csr_rows<V, LPR, RG, KEEP, TD>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return k1[cc]; }, acc, cw);
+    } else if (S == 2) {
         const T c = (T)(h * DP5::a21);
         csr_rows<V, LPR, RG, KEEP, TD>(rb, I.col, (const V *)I.val, rs.q,
                                        [&](int cc) {
@@ -356,7 +367,13 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
     double e2 = 0.0, l2 = 0.0;  // error norm part; |L y_new|^2 part (steady-state mode)
     if (rs.valid) {
         const int row = rs.row;
-        const V a = pick(acc, rs.q);
+        V a = pick(acc, rs.q);
+        if (lin2) {
+            // the lazy trace scale s applies to y and k1 alike: L (s y + a21 h s k1) = s k1 + a21 h s (L k1)
+            const V lk1 = a;
+            a = k1r;
+            caxpy(a, (T)(h * DP5::a21) * s, lk1);
+        }
         if (S == 2) {
             ks[0][row] = a;
             V o = yr;

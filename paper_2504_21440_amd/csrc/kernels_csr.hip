@@ -91,12 +91,25 @@ template <typename T>
 __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int step_mode)
 {
     using V = typename vec2<T>::type;
-    __shared__ double scr[16];
+    __shared__ double scr[48];
     __shared__ double2 exs[CTL_MAX_EOPS];
     __shared__ double td_t, td_h;  // a time-dependent problem's next evaluations: rows td_first..td_last
     __shared__ int td_first, td_last;
-    if (C->status != ST_RUNNING) return;
+    // Requests that do not depend on the control record go out with it: this thread's share of the
+    // block partials (column 0; column 1 as well when a steady-state test needs it) and the bounds
+    // of the first expectation operator of this wave.
+    const int status = C->status;
     const int phase = C->phase;
+    const double part0 = partials_part(I, 0);
+    const double part1 = I.steady_tol2 > 0.0 ? partials_part(I, 1) : 0.0;
+    const int k0 = threadIdx.x >> 6;
+    int eb0 = 0, ee0 = 0;
+    if (k0 < I.ne) {
+        const int32_t *ep = I.eptr + (size_t)k0 * (I.d + 1);
+        eb0 = ep[0];
+        ee0 = ep[I.d];
+    }
+    if (status != ST_RUNNING) return;
     if ((phase == PH_STEP) != (step_mode != 0)) return;
     // after thread 0 has decided: the coefficient rows of the evaluations the next launches make
     auto td_next = [&]() {
@@ -106,7 +119,7 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
     };
     if (threadIdx.x == 0) td_first = 1, td_last = 0;
     if (phase == PH_INIT0) {
-        const double ta = sum_partials(I, 0, scr), tb = sum_partials(I, 1, scr);
+        const double ta = block_sum(part0, scr), tb = sum_partials(I, 1, scr);
         const V *x0 = (const V *)I.rho0;
         const double tr = csr_trace(I, x0, scr);
         csr_record_expect(I, x0, 1.0, 0);
@@ -136,7 +149,7 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
         return;
     }
     if (phase == PH_INIT1) {
-        const double ta = sum_partials(I, 0, scr);
+        const double ta = block_sum(part0, scr);
         if (threadIdx.x == 0) {
             const double h0 = C->h0;
             const double d2 = sqrt(ta / I.n), d1 = C->last_err;
@@ -160,29 +173,27 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
     const int sidx = C->save_idx;
     const V *ynew = (const V *)I.Y[1 - p];
     // Everything that only reads is issued before the decision: the error partials, the
-    // candidate's trace and, at a save time, the expectation sums (wasted on a rejection).
+    // candidate's trace and, at a save time, the expectation sums (wasted on a rejection); the
+    // first operator's bounds and the partials were already requested with the control record.
     const bool spec = land && I.ne <= CTL_MAX_EOPS;
     if (spec) {
         for (int k = threadIdx.x >> 6; k < I.ne; k += blockDim.x >> 6) {
-            const double2 sk = csr_expect_one(I, ynew, k);
+            const double2 sk = k == k0 ? csr_expect_range(I, ynew, eb0, ee0) : csr_expect_one(I, ynew, k);
             if ((threadIdx.x & 63) == 0) exs[k] = sk;
         }
     }
-    const double part = partials_part(I, 0);
     const bool steady = I.steady_tol2 > 0.0;
-    const double lpart = steady ? partials_part(I, 1) : 0.0;
-    const double trp = I.renorm ? csr_trace_part(I, ynew) : 0.0;
-    const double tot = block_sum(part, scr);  // its barriers also publish exs
-    const double err = sqrt(tot / I.n);
+    // one set of barriers for the error, trace and residual sums (each summed as block_sum would);
+    // the barriers also publish exs
+    double sums[3] = {part0, I.renorm ? csr_trace_part(I, ynew) : 0.0, part1};
+    block_sum_n<3>(sums, scr);
+    const double err = sqrt(sums[0] / I.n);
     const bool finite = isfinite(err);
     const bool accept = finite && err <= 1.0;
     double scale_new = 1.0;
-    if (I.renorm) {
-        const double tr = block_sum(trp, scr);
-        if (accept) scale_new = C->tr0 / tr;
-    }
+    if (I.renorm && accept) scale_new = C->tr0 / sums[1];
     // steady-state mode: |L y_new|_2 (of the rescaled state) at or below the tolerance ends the solve
-    const bool conv = steady && accept && block_sum(lpart, scr) * scale_new * scale_new <= I.steady_tol2;
+    const bool conv = steady && accept && sums[2] * scale_new * scale_new <= I.steady_tol2;
     if (conv) {
         // the state no longer changes: every remaining save time receives its expectation values
         for (int idx = sidx; idx < I.nt; ++idx) csr_record_expect(I, ynew, scale_new, idx);

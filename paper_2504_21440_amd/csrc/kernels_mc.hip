@@ -20,6 +20,7 @@
 // the workgroup evaluates the coefficients at the stage time (its own trajectory's t + c_s h) into
 // LDS, and a jump weights channel k by |g_k(t*)|^2.
 #include <algorithm>
+#include <cstdlib>
 
 #include "qt_coef.h"
 #include "qt_common.h"
@@ -57,8 +58,9 @@ __device__ __forceinline__ void block_sum_n(double *v, int n, double *scr)
 
 // OCC: the waves per SIMD the register allocation must allow (1: no constraint).  A large ensemble
 // gains from more resident trajectories even at the price of spilled registers; a single
-// trajectory does not.
-template <typename T, int R, bool TD, int OCC>
+// trajectory does not.  ELDS: the workgroup copies the ELL of A into LDS once and every right-hand
+// side of every trajectory it runs reads the matrix from there instead of from L2.
+template <typename T, int R, bool TD, int OCC, bool ELDS = false>
 __global__ __launch_bounds__(MC_THREADS) __attribute__((amdgpu_waves_per_eu(OCC))) void k_mc(
     const McParams *__restrict__ Pp)
 {
@@ -77,6 +79,15 @@ __global__ __launch_bounds__(MC_THREADS) __attribute__((amdgpu_waves_per_eu(OCC)
     const V *__restrict__ ev = (const V *)P.ell_val;
     const int32_t *__restrict__ ec = P.ell_col;
     const V *__restrict__ cv = (const V *)P.cval;
+    V *evs = xs1 + d;                             // ELDS: values, then columns, after the state buffers
+    int32_t *ecs = (int32_t *)(evs + (size_t)P.W * d);
+    if constexpr (ELDS) {
+        for (int i = threadIdx.x; i < P.W * d; i += MC_THREADS) {
+            evs[i] = gld(ev + i);
+            ecs[i] = gld(ec + i);
+        }
+        __syncthreads();
+    }
 
     auto row = [&](int m) { return tid + m * MC_THREADS; };
     // out = A(ts) x for own rows.  Every call site is preceded by a barrier after the previous
@@ -100,12 +111,13 @@ __global__ __launch_bounds__(MC_THREADS) __attribute__((amdgpu_waves_per_eu(OCC)
                 for (int k = 0; k < P.W; ++k) {
                     // global-only loads of the matrix stream (generic ones would be ordered against,
                     // and waited for with, the LDS gathers of the state)
-                    const int32_t c = gld(ec + (size_t)k * d + r);
+                    const size_t at = (size_t)k * d + r;
+                    const int32_t c = ELDS ? ecs[at] : gld(ec + at);
+                    const V a = ELDS ? evs[at] : gld(ev + at);
                     if constexpr (TD)
-                        cfma(acc, cmul(gld(ev + (size_t)k * d + r), cwsh[c >> MC_TAG_SHIFT]),
-                             x[c & ((1 << MC_TAG_SHIFT) - 1)]);
+                        cfma(acc, cmul(a, cwsh[c >> MC_TAG_SHIFT]), x[c & ((1 << MC_TAG_SHIFT) - 1)]);
                     else
-                        cfma(acc, gld(ev + (size_t)k * d + r), x[c]);
+                        cfma(acc, a, x[c]);
                 }
             out[m] = acc;
         }
@@ -501,7 +513,10 @@ __global__ __launch_bounds__(256) void k_mc_stats(const double2 *__restrict__ tr
 
 __global__ void k_mc_queue_reset(unsigned long long *q) { *q = 0ull; }
 
-template <typename T, int R, bool TD, int OCC> static const void *mc_fn() { return (const void *)k_mc<T, R, TD, OCC>; }
+template <typename T, int R, bool TD, int OCC, bool ELDS = false> static const void *mc_fn()
+{
+    return (const void *)k_mc<T, R, TD, OCC, ELDS>;
+}
 
 // Ensembles of at least this many complex64 trajectories with 2, 4 or 8 rows per thread take the
 // variant held to 3 waves per SIMD (2 at 8 rows): more trajectories in flight outweigh the spilled
@@ -511,6 +526,25 @@ constexpr int64_t MC_DENSE_ENSEMBLE = 2048;
 static bool mc_occ3(const McParams &p, bool f64)
 {
     return !f64 && (p.rows == 2 || p.rows == 4 || p.rows == 8) && p.ntraj >= MC_DENSE_ENSEMBLE;
+}
+
+// Bytes of LDS beyond the state buffers that the ELL of A takes (values and columns).
+static size_t mc_ell_lds(const McParams &p, bool f64) { return (size_t)p.W * p.d * ((f64 ? 16 : 8) + 4); }
+static size_t mc_lds_base(const McParams &p, bool f64) { return (size_t)2 * p.d * (f64 ? 16 : 8); }
+constexpr size_t MC_LDS_LIMIT = 160 * 1024 - 4096;  // gfx950 LDS per workgroup, less the static arrays
+
+// Ensembles whose complex64 ELL fits next to the state buffers in LDS (2 or 4 rows per thread,
+// constant A) read the matrix from LDS (QTAMD_MC_ELDS=0 turns this off, =1 forces it where it fits).
+static bool mc_elds(const McParams &p, bool f64, bool td)
+{
+    static const int mode = [] {
+        const char *e = std::getenv("QTAMD_MC_ELDS");
+        return e ? std::atoi(e) : -1;
+    }();
+    const bool fits = !f64 && !td && (p.rows == 2 || p.rows == 4) &&
+                      mc_lds_base(p, f64) + mc_ell_lds(p, f64) <= MC_LDS_LIMIT;
+    if (!fits || mode == 0) return false;
+    return mode == 1 || p.ntraj >= MC_DENSE_ENSEMBLE;
 }
 
 template <typename T, bool TD> static const void *mc_pick(int rows, bool occ3)
@@ -531,14 +565,18 @@ static void mc_launch_t(const McParams *dev_p, bool td, int grid, size_t lds, hi
     else hipLaunchKernelGGL((k_mc<T, R, false, OCC>), dim3(grid), dim3(MC_THREADS), lds, s, dev_p);
 }
 
-static size_t mc_lds(const McParams &p, bool f64) { return (size_t)2 * p.d * (f64 ? 16 : 8); }
+static size_t mc_lds(const McParams &p, bool f64, bool td)
+{
+    return mc_lds_base(p, f64) + (mc_elds(p, f64, td) ? mc_ell_lds(p, f64) : 0);
+}
 
 int mc_grid(const McParams &p, bool f64, bool td, int device)
 {
     const bool o3 = mc_occ3(p, f64);
     const void *fn = f64 ? (td ? mc_pick<double, true>(p.rows, o3) : mc_pick<double, false>(p.rows, o3))
                          : (td ? mc_pick<float, true>(p.rows, o3) : mc_pick<float, false>(p.rows, o3));
-    const size_t lds = mc_lds(p, f64);
+    if (mc_elds(p, f64, td)) fn = p.rows == 2 ? mc_fn<float, 2, false, 1, true>() : mc_fn<float, 4, false, 1, true>();
+    const size_t lds = mc_lds(p, f64, td);
     if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, MC_THREADS, lds) != hipSuccess || per_cu < 1)
@@ -551,7 +589,12 @@ int mc_grid(const McParams &p, bool f64, bool td, int device)
 
 void mc_launch(const McParams &p, const McParams *dev_p, bool f64, bool td, int grid, hipStream_t s)
 {
-    const size_t lds = mc_lds(p, f64);
+    const size_t lds = mc_lds(p, f64, td);
+    if (mc_elds(p, f64, td)) {
+        if (p.rows == 2) hipLaunchKernelGGL((k_mc<float, 2, false, 1, true>), dim3(grid), dim3(MC_THREADS), lds, s, dev_p);
+        else hipLaunchKernelGGL((k_mc<float, 4, false, 1, true>), dim3(grid), dim3(MC_THREADS), lds, s, dev_p);
+        return;
+    }
     if (f64) {
         switch (p.rows) {
         case 1: mc_launch_t<double, 1, 1>(dev_p, td, grid, lds, s); break;

@@ -175,4 +175,27 @@ __device__ __forceinline__ double block_sum(double v, double *scratch)
     return s;
 }
 
+// Block sums of N doubles per thread at once, each summed exactly as block_sum sums it (so the
+// results are bitwise those of N separate block_sum calls) with one set of barriers.
+// scratch: >= 16 * N doubles of LDS.
+template <int N> __device__ __forceinline__ void block_sum_n(double (&v)[N], double *scratch)
+{
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) scratch[16 * j + w] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += scratch[16 * j + i];
+        v[j] = s;
+    }
+    __syncthreads();
+}
+
 }  // namespace qt
