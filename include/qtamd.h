@@ -117,8 +117,9 @@ void qt_csr_free(qt_csr *A);
 /* Liouvillian (Sec. 3.2; the precomputed-superoperator use of Sec. 5).
  * form QT_FORM_CSR: assembles on the device, in FP64, the superoperator
  *     L = A (x) I + I (x) conj(A) + sum_k C_k (x) conj(C_k),   A = -i H - 1/2 sum_k C_k^dag C_k,
- * for the row-major vec, drops exact zeros, stores values as complex128 (QT_F64) or complex64
- * (QT_MIXED) with int32 indices (nnz < 2^31).
+ * for the row-major vec, drops entries that are zero in the storage precision, stores values as
+ * complex128 (QT_F64) or complex64 (QT_MIXED) with int32 indices (nnz < 2^31), and pads every row
+ * with explicit zeros to a multiple of 4 stored entries (so the SpMV can load aligned runs of 4).
  * form QT_FORM_DENSE: stores A and the C_k as dense matrices zero-padded to a multiple of 16 for
  * the batched MFMA right-hand side; d <= 80 (QT_MIXED) or d <= 48 (QT_F64).
  * Errors: QT_EINVAL for mismatched sizes, malformed CSR, or a dense d above the limit. */
@@ -163,14 +164,14 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
                                   int32_t form, int32_t precision, qt_liouv **out);
 /* Number of time-dependent terms of a Liouvillian (0 for a constant one). */
 qt_status qt_liouv_terms(const qt_liouv *L, int32_t *n_terms);
-/* d, stored non-zeros (CSR form; 0 for dense), device bytes held. */
+/* d, non-zeros of L (CSR form, padding not counted; 0 for dense), device bytes held. */
 qt_status qt_liouv_info(const qt_liouv *L, int32_t *d, int64_t *nnz, int64_t *bytes);
 /* Device bytes the Liouvillian holds until qt_liouv_destroy: CSR row pointers, columns and values
  * (and the coefficient tables of a time-dependent one), or the dense operators.  A served request
  * is charged this plus its own state (qt_server_footprint). */
 qt_status qt_liouv_footprint(const qt_liouv *L, size_t *bytes);
-/* Copies the assembled CSR back to the host (values widened to complex128).  indptr: d*d + 1,
- * indices and values: nnz from qt_liouv_info.  CSR form only. */
+/* Copies the assembled CSR back to the host (values widened to complex128, row padding left out).
+ * indptr: d*d + 1, indices and values: nnz from qt_liouv_info.  CSR form only. */
 qt_status qt_liouv_export(const qt_liouv *L, int64_t *indptr, int32_t *indices, double *values);
 qt_status qt_liouv_destroy(qt_liouv *L);
 
@@ -244,13 +245,21 @@ qt_status qt_steadystate(qt_ctx *ctx, const qt_liouv *L, const double *rho0, int
  * results are unspecified afterwards until the next qt_me_plan_run. */
 qt_status qt_me_plan_time_rhs(qt_me_plan *plan, int32_t reps, double *ms_per_launch);
 
+/* Measurement: the achievable HBM bandwidth of the context's device, bytes read plus bytes written
+ * per second of a streaming copy of `bytes` bytes (16-byte non-temporal loads and stores), repeated
+ * `reps` times and timed with HIP events on the context's stream; the reference point for the
+ * bandwidth-bound SpMV beside the published peak.  Allocates two buffers of `bytes` for the call. */
+qt_status qt_measure_copy_bandwidth(qt_ctx *ctx, int64_t bytes, int32_t reps, double *gbs);
+
 /* Autotuner.  The CSR stage kernels take a launch shape (qt_csr_shape):
  *   lanes_per_row   4, 8 or 16 lanes of a wavefront share a row;
  *   rows_per_group  1, 2 or 4 rows per lane group (at most lanes_per_row);
  *   xcd_order       1: each of the 8 XCDs (each with its own L2) works through one contiguous eighth
  *                   of the rows; 0: the hardware's round-robin order;
  *   cached_matrix   1: the matrix is read through the caches (temporal loads), so a matrix that
- *                   fits the L2s can stay there across launches; 0: it is streamed past them.
+ *                   fits the L2s can stay there across launches; 0: it is streamed past them;
+ *                   2: as 1, each lane loading runs of 4 stored entries with 16-byte loads (rows are
+ *                   stored padded to multiples of 4); built for 4x1, 8x1, 8x2 and 16x1.
  * xcd_order applies to plans with one CSR problem (a plan with several uses 0).
  * The dense kernel is built with a few wave counts per workgroup for each padded size (for FP32:
  * 1-2 at 16, 2 or 4 at 32, 3, 4, 6 or 8 at 48, 4 or 8 at 64, 4, 5 or 8 at 80; for FP64: 1 at 16,

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqtamd.so")
 SOURCES = ["kernels_csr.hip", "kernels_csr_td.hip", "kernels_assembly.hip", "kernels_dense.hip", "kernels_mc.hip",
-           "kernels_sde.hip", "qtamd_sde.cpp", "qtamd_noalloc.hip",
+           "kernels_sde.hip", "qtamd_sde.cpp", "qtamd_noalloc.hip", "kernels_util.hip",
            "qtamd_runtime.cpp", "qtamd_me.cpp", "qtamd_mc.cpp", "qtamd_server.cpp", "qtamd_tune.cpp"]
 ARCH = "gfx950"
 

@@ -125,6 +125,92 @@ __device__ __forceinline__ void csr_rows(const RowBounds<RG> &b, const int32_t *
         for (int m = LPR / 2; m >= 1; m >>= 1) acc[g] = cadd(acc[g], shfl_xor_c(acc[g], m));
 }
 
+// Tile shapes built with 16-byte matrix loads (cached_matrix = 2).
+template <int LPR, int RG> constexpr bool csr_wide_shape()
+{
+    return (LPR == 4 && RG == 1) || (LPR == 8 && (RG == 1 || RG == 2)) || (LPR == 16 && RG == 1);
+}
+
+typedef int32_t ci4 __attribute__((ext_vector_type(4)));
+typedef float cf4 __attribute__((ext_vector_type(4)));
+// Four consecutive stored values (k a multiple of 4: 32- / 64-byte aligned).
+__device__ __forceinline__ void ld_quad(const float2 *__restrict__ p, float2 (&v)[4])
+{
+    const cf4 a = *(const cf4 *)p, b = *(const cf4 *)(p + 2);
+    v[0] = make_float2(a.x, a.y);
+    v[1] = make_float2(a.z, a.w);
+    v[2] = make_float2(b.x, b.y);
+    v[3] = make_float2(b.z, b.w);
+}
+__device__ __forceinline__ void ld_quad(const double2 *__restrict__ p, double2 (&v)[4])
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = p[j];
+}
+
+// Row sums as csr_rows, with each lane taking runs of 4 consecutive stored entries: one 16-byte
+// load of the column indices and 16-byte loads of the values.  Needs rows padded to multiples of 4
+// stored entries (every CSR Liouvillian is).  Matrix loads go through the caches.
+template <typename V, int LPR, int RG, bool TD, typename X>
+__device__ __forceinline__ void csr_rows4(const RowBounds<RG> &b, const int32_t *__restrict__ col,
+                                          const V *__restrict__ val, int q, X x, V (&acc)[RG],
+                                          const V *__restrict__ cw = nullptr)
+{
+    constexpr int U = LPR >= 8 ? 1 : 2;  // runs of 4 per row in flight per lane
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+        acc[g].x = 0;
+        acc[g].y = 0;
+    }
+    for (int base = 4 * q;; base += 4 * LPR * U) {
+        ci4 cc[RG][U];
+        V vv[RG][U][4];
+        bool ok[RG][U];
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = b.s[g] + base + u * 4 * LPR;
+                ok[g][u] = k < b.e[g];
+                if (ok[g][u]) {
+                    cc[g][u] = *(const ci4 *)(col + k);
+                    ld_quad(val + k, vv[g][u]);
+                    any = true;
+                }
+            }
+        if (!any) break;
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[g][u]) {
+                    const int cs[4] = {cc[g][u].x, cc[g][u].y, cc[g][u].z, cc[g][u].w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if constexpr (TD)
+                            cfma(acc[g], cmul(vv[g][u][j], cw[cs[j] >> TD_TAG_SHIFT]), x(cs[j] & TD_COL_MASK));
+                        else
+                            cfma(acc[g], vv[g][u][j], x(cs[j]));
+                    }
+                }
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int m = LPR / 2; m >= 1; m >>= 1) acc[g] = cadd(acc[g], shfl_xor_c(acc[g], m));
+}
+
+// Row sums with the kernel's matrix load kind.
+template <typename V, int LPR, int RG, bool KEEP, bool WIDE, bool TD, typename X>
+__device__ __forceinline__ void csr_rows_k(const RowBounds<RG> &b, const int32_t *__restrict__ col,
+                                           const V *__restrict__ val, int q, X x, V (&acc)[RG],
+                                           const V *__restrict__ cw = nullptr)
+{
+    if constexpr (WIDE) csr_rows4<V, LPR, RG, TD>(b, col, val, q, x, acc, cw);
+    else csr_rows<V, LPR, RG, KEEP, TD>(b, col, val, q, x, acc, cw);
+}
+
 // acc[q] without dynamic register indexing
 template <typename V, int RG> __device__ __forceinline__ V pick(const V (&a)[RG], int q)
 {
@@ -237,7 +323,7 @@ template <int LPR, int RG> struct RowSlot {
 // ---------------------------------------------------------------------------------------------
 
 // Starting step, first evaluation: k1 = L rho0, y <- rho0, partials of |y|^2/sc^2 and |f(y)|^2/sc^2.
-template <typename T, int LPR, int RG, bool KEEP, bool TD>
+template <typename T, int LPR, int RG, bool KEEP, bool WIDE, bool TD>
 __device__ __forceinline__ void init0_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
@@ -248,7 +334,7 @@ __device__ __forceinline__ void init0_body(const CsrInst &I, const CsrCtl *C, in
     if (C->status != ST_RUNNING || C->phase != PH_INIT0) return;
     const V *__restrict__ x0 = (const V *)I.rho0;
     V acc[RG];
-    csr_rows<V, LPR, RG, KEEP, TD>(rb, I.col, (const V *)I.val, rs.q, [&](int c) { return x0[c]; }, acc,
+    csr_rows_k<V, LPR, RG, KEEP, WIDE, TD>(rb, I.col, (const V *)I.val, rs.q, [&](int c) { return x0[c]; }, acc,
                                    td_coefs<V, TD>(I, 0));
     double sa = 0.0, sb = 0.0;
     if (rs.valid) {
@@ -269,7 +355,7 @@ __device__ __forceinline__ void init0_body(const CsrInst &I, const CsrCtl *C, in
 }
 
 // Starting step, second evaluation: partials of |f(y + h0 f(y)) - f(y)|^2 / (h0 sc)^2.
-template <typename T, int LPR, int RG, bool KEEP, bool TD>
+template <typename T, int LPR, int RG, bool KEEP, bool WIDE, bool TD>
 __device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
@@ -283,7 +369,7 @@ __device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, in
     const V *__restrict__ y = (const V *)I.Y[0];
     const V *__restrict__ k1 = (const V *)I.K[0];
     V acc[RG];
-    csr_rows<V, LPR, RG, KEEP, TD>(rb, I.col, (const V *)I.val, rs.q,
+    csr_rows_k<V, LPR, RG, KEEP, WIDE, TD>(rb, I.col, (const V *)I.val, rs.q,
                                    [&](int c) {
                                        V v = y[c];
                                        caxpy(v, th0, k1[c]);
@@ -303,7 +389,7 @@ __device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, in
 }
 
 // One Runge-Kutta stage S (2..7) of a DP5 step.
-template <typename T, int LPR, int RG, int S, bool KEEP, bool TD>
+template <typename T, int LPR, int RG, int S, bool KEEP, bool WIDE, bool TD>
 __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
 {
     using V = typename vec2<T>::type;
@@ -349,10 +435,10 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
     // in a plan with time-dependent ones takes the same route through the weighted kernels.
     const bool lin2 = S == 2 && (!TD || I.nterms == 0);
     if (lin2) {
-        csr_rows<V, LPR, RG, KEEP, TD>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return k1[cc]; }, acc, cw);
+        csr_rows_k<V, LPR, RG, KEEP, WIDE, TD>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return k1[cc]; }, acc, cw);
     } else if (S == 2) {
         const T c = (T)(h * DP5::a21);
-        csr_rows<V, LPR, RG, KEEP, TD>(rb, I.col, (const V *)I.val, rs.q,
+        csr_rows_k<V, LPR, RG, KEEP, WIDE, TD>(rb, I.col, (const V *)I.val, rs.q,
                                        [&](int cc) {
                                            V v = y[cc];
                                            caxpy(v, c, k1[cc]);
@@ -360,7 +446,7 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
                                        },
                                        acc, cw);
     } else {
-        csr_rows<V, LPR, RG, KEEP, TD>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return xin[cc]; }, acc,
+        csr_rows_k<V, LPR, RG, KEEP, WIDE, TD>(rb, I.col, (const V *)I.val, rs.q, [&](int cc) { return xin[cc]; }, acc,
                                        cw);
     }
 
@@ -447,15 +533,17 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
 // Logical block -> (descriptor, control record, first row, partial slot), then the body.
 // FORM 0: several problems, block table.  FORM 1: one problem, descriptor by value.  FORM 2 / 3: as
 // 1 / 0, with the matrix read through the caches (temporal loads) instead of streamed past them, so
-// that what of the matrices fits the L2s and the MALL is still there at the next launch.
+// that what of the matrices fits the L2s and the MALL is still there at the next launch.  FORM 4 / 5:
+// as 2 / 3 with 16-byte loads of runs of 4 stored entries.
 #define QT_CSR_DISPATCH(BODY, ...)                                                                   \
     const int lb = csr_block(xcd);                                                                   \
-    if constexpr (FORM == 1 || FORM == 2) {                                                          \
-        BODY<__VA_ARGS__, FORM == 2, TD>(one, ctls, lb * CsrGeom<LPR, RG>::RPB, lb);                 \
+    constexpr bool KEEP_ = FORM >= 2, WIDE_ = FORM >= 4;                                             \
+    if constexpr (FORM == 1 || FORM == 2 || FORM == 4) {                                             \
+        BODY<__VA_ARGS__, KEEP_, WIDE_, TD>(one, ctls, lb * CsrGeom<LPR, RG>::RPB, lb);              \
     } else {                                                                                         \
         if (bound && lb >= bound[0]) return; /* grid sized for a capacity, table filled less */     \
         const int ii = bi[lb], row0 = br[lb];                                                        \
-        BODY<__VA_ARGS__, FORM == 3, TD>(insts[ii], ctls + ii, row0, row0 / CsrGeom<LPR, RG>::RPB); \
+        BODY<__VA_ARGS__, KEEP_, WIDE_, TD>(insts[ii], ctls + ii, row0, row0 / CsrGeom<LPR, RG>::RPB); \
     }
 
 template <typename T, int LPR, int RG, int FORM, bool TD>
@@ -498,7 +586,8 @@ struct CsrArgs {
     const CsrInst *insts;
     CsrInst one;  // used when ninst == 1 and the host descriptor was given
     bool use_one;
-    int form;  // kernel FORM: 0 block table, 1 one problem; 2 / 3: as 1 / 0 with temporal matrix loads
+    int form;  // kernel FORM: 0 block table, 1 one problem; 2 / 3: as 1 / 0 with temporal matrix loads;
+               // 4 / 5: as 2 / 3 with 16-byte matrix loads
     CsrCtl *ctls;
     const int32_t *bi, *br, *ilist, *bound, *ibound;
     int nblk, ninst, xcd;
@@ -512,7 +601,7 @@ static inline CsrArgs make_args(const CsrLaunch &L, hipStream_t s)
     a.use_one = L.ninst == 1 && L.one_host != nullptr;
     if (a.use_one) a.one = *L.one_host;
     else std::memset(&a.one, 0, sizeof(a.one));
-    a.form = a.use_one ? (L.keep ? 2 : 1) : (L.keep ? 3 : 0);
+    a.form = a.use_one ? (L.keep == 2 ? 4 : L.keep ? 2 : 1) : (L.keep == 2 ? 5 : L.keep ? 3 : 0);
     a.ctls = L.ctls;
     a.bi = L.bi;
     a.br = L.br;
@@ -558,6 +647,19 @@ static void launch_spmv_form(int which, const CsrArgs &a)
 #undef QT_ARGS
 }
 
+// The kernel FORM of a launch; the wide forms exist for the shapes csr_wide_shape admits.
+template <typename T, int LP, int RR, bool TD> static void launch_spmv_t(int w, const CsrArgs &a)
+{
+    if constexpr (csr_wide_shape<LP, RR>()) {
+        if (a.form == 5) return launch_spmv_form<T, LP, RR, 5, TD>(w, a);
+        if (a.form == 4) return launch_spmv_form<T, LP, RR, 4, TD>(w, a);
+    }
+    if (a.form == 3) launch_spmv_form<T, LP, RR, 3, TD>(w, a);
+    else if (a.form == 2) launch_spmv_form<T, LP, RR, 2, TD>(w, a);
+    else if (a.form == 1) launch_spmv_form<T, LP, RR, 1, TD>(w, a);
+    else launch_spmv_form<T, LP, RR, 0, TD>(w, a);
+}
+
 // SpMV kernels first..last of the step sequence (0 / 1: starting-step evaluations, 2..7: stages).
 template <bool TD>
 static void launch_spmv_range(const CsrLaunch &L, const CsrArgs &a, int first, int last)
@@ -565,17 +667,8 @@ static void launch_spmv_range(const CsrLaunch &L, const CsrArgs &a, int first, i
     for (int w = first; w <= last; ++w) {
 #define QT_CALL(LP, RR)                                                                        \
         {                                                                                      \
-            if (L.f64) {                                                                       \
-                if (a.form == 3) launch_spmv_form<double, LP, RR, 3, TD>(w, a);                \
-                else if (a.form == 2) launch_spmv_form<double, LP, RR, 2, TD>(w, a);           \
-                else if (a.form == 1) launch_spmv_form<double, LP, RR, 1, TD>(w, a);           \
-                else launch_spmv_form<double, LP, RR, 0, TD>(w, a);                            \
-            } else {                                                                           \
-                if (a.form == 3) launch_spmv_form<float, LP, RR, 3, TD>(w, a);                 \
-                else if (a.form == 2) launch_spmv_form<float, LP, RR, 2, TD>(w, a);            \
-                else if (a.form == 1) launch_spmv_form<float, LP, RR, 1, TD>(w, a);            \
-                else launch_spmv_form<float, LP, RR, 0, TD>(w, a);                             \
-            }                                                                                  \
+            if (L.f64) launch_spmv_t<double, LP, RR, TD>(w, a);                                \
+            else launch_spmv_t<float, LP, RR, TD>(w, a);                                       \
         }
         QT_SHAPE_DISPATCH(L.lpr, L.rg, QT_CALL)
 #undef QT_CALL

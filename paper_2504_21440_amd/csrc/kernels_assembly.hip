@@ -8,8 +8,11 @@
 // (A Hamiltonian term of a time-dependent problem uses a second operator B in the place of the
 // right-hand A; see qt_asm.h.)
 // Each thread builds one row: it gathers these candidates, sorts them by column, sums duplicates
-// and drops exact zeros.  A count pass, a three-kernel scan and a fill pass produce CSR directly
-// in device memory, values computed in FP64 and stored in the solve precision.
+// and drops entries that are zero in the storage precision.  A count pass, a three-kernel scan and
+// a fill pass produce CSR directly in device memory, values computed in FP64 and stored in the
+// solve precision.  Every row is padded to a multiple of 4 stored entries with explicit zeros
+// (column = the row itself), so each row starts 16-byte aligned in the column array and the SpMV
+// can load runs of 4 entries at once; every stored zero is padding.
 #include "qt_common.h"
 #include "qt_asm.h"
 #include "qt_csr.h"
@@ -69,19 +72,31 @@ __device__ int build_row(const AsmOps &op, int64_t r, int *cols, double2 *vals, 
     return n;
 }
 
-__global__ __launch_bounds__(128) void k_asm_count(AsmOps op, int32_t *counts, int *flags)
+// A candidate value survives when it is nonzero in the storage precision.
+__device__ __forceinline__ bool stored_nonzero(double2 v, bool f64)
+{
+    return f64 ? (v.x != 0.0 || v.y != 0.0) : ((float)v.x != 0.0f || (float)v.y != 0.0f);
+}
+
+// counts[r]: stored entries of row r (padded to a multiple of 4); real[0] += the entries that are
+// not padding.
+__global__ __launch_bounds__(128) void k_asm_count(AsmOps op, int32_t *counts, int *flags,
+                                                   unsigned long long *real, int f64)
 {
     const int64_t n = (int64_t)op.d * op.d;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int cols[ASM_MAXC];
-    double2 vals[ASM_MAXC];
-    int ovf = 0;
-    const int m = build_row(op, r, cols, vals, &ovf);
     int cnt = 0;
-    for (int k = 0; k < m; ++k) cnt += (vals[k].x != 0.0 || vals[k].y != 0.0);
-    counts[r] = cnt;
-    if (ovf) atomicOr(&flags[0], 1);
+    if (r < n) {
+        int cols[ASM_MAXC];
+        double2 vals[ASM_MAXC];
+        int ovf = 0;
+        const int m = build_row(op, r, cols, vals, &ovf);
+        for (int k = 0; k < m; ++k) cnt += stored_nonzero(vals[k], f64 != 0);
+        counts[r] = (cnt + 3) & ~3;
+        if (ovf) atomicOr(&flags[0], 1);
+    }
+    const int tot = wave_sum(cnt);
+    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(real, (unsigned long long)tot);
 }
 
 template <typename V>
@@ -96,10 +111,14 @@ __global__ __launch_bounds__(128) void k_asm_fill(AsmOps op, const int32_t *rowp
     const int m = build_row(op, r, cols, vals, &ovf);
     int o = rowptr[r];
     for (int k = 0; k < m; ++k) {
-        if (vals[k].x == 0.0 && vals[k].y == 0.0) continue;
+        if (!stored_nonzero(vals[k], sizeof(V) == 16)) continue;
         col[o] = cols[k];
         val[o] = from_d2<V>(vals[k]);
         ++o;
+    }
+    for (const int e = rowptr[r + 1]; o < e; ++o) {  // padding: explicit zeros in this row's own column
+        col[o] = (int32_t)r;
+        val[o] = from_d2<V>(make_double2(0.0, 0.0));
     }
 }
 
@@ -191,10 +210,12 @@ __global__ __launch_bounds__(SCAN_B) void k_scan_apply(const int32_t *counts, in
 }
 
 // Host launchers ------------------------------------------------------------------------------
-void asm_launch_count(const AsmOps &op, int32_t *counts, int *flags, hipStream_t s)
+void asm_launch_count(const AsmOps &op, int32_t *counts, int *flags, unsigned long long *real, bool f64,
+                      hipStream_t s)
 {
     const int64_t n = (int64_t)op.d * op.d;
-    hipLaunchKernelGGL(k_asm_count, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, op, counts, flags);
+    hipLaunchKernelGGL(k_asm_count, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, op, counts, flags, real,
+                       (int)f64);
 }
 
 void asm_launch_scan(const int32_t *counts, int64_t n, int64_t *bsum, int32_t *rowptr, int *flags, hipStream_t s)

@@ -315,6 +315,13 @@ bool csr_shape_supported(int lpr, int rg)
     return (lpr == 4 || lpr == 8 || lpr == 16) && (rg == 1 || rg == 2 || rg == 4);
 }
 
+bool csr_shape_supported(int lpr, int rg, int keep)
+{
+    if (!csr_shape_supported(lpr, rg) || keep < 0 || keep > 2) return false;
+    if (keep < 2) return true;
+    return (lpr == 4 && rg == 1) || (lpr == 8 && (rg == 1 || rg == 2)) || (lpr == 16 && rg == 1);
+}
+
 template <typename T>
 static void launch_control(const CsrArgs &a, int step_mode)
 {

@@ -533,18 +533,18 @@ static size_t mc_ell_lds(const McParams &p, bool f64) { return (size_t)p.W * p.d
 static size_t mc_lds_base(const McParams &p, bool f64) { return (size_t)2 * p.d * (f64 ? 16 : 8); }
 constexpr size_t MC_LDS_LIMIT = 160 * 1024 - 4096;  // gfx950 LDS per workgroup, less the static arrays
 
-// Ensembles whose complex64 ELL fits next to the state buffers in LDS (2 or 4 rows per thread,
-// constant A) read the matrix from LDS (QTAMD_MC_ELDS=0 turns this off, =1 forces it where it fits).
+// With QTAMD_MC_ELDS=1, complex64 ensembles whose ELL fits next to the state buffers in LDS (2 or 4
+// rows per thread, constant A) read the matrix from LDS.  Off by default: one such workgroup fills
+// a CU's LDS, and on the L = 10 ensemble (10,000 trajectories) that ran at 39,100 trajectories/s
+// against 57,800 for the L2 variant held to 3 waves per SIMD.
 static bool mc_elds(const McParams &p, bool f64, bool td)
 {
-    static const int mode = [] {
+    static const bool on = [] {
         const char *e = std::getenv("QTAMD_MC_ELDS");
-        return e ? std::atoi(e) : -1;
+        return e && std::atoi(e) == 1;
     }();
-    const bool fits = !f64 && !td && (p.rows == 2 || p.rows == 4) &&
-                      mc_lds_base(p, f64) + mc_ell_lds(p, f64) <= MC_LDS_LIMIT;
-    if (!fits || mode == 0) return false;
-    return mode == 1 || p.ntraj >= MC_DENSE_ENSEMBLE;
+    return on && !f64 && !td && (p.rows == 2 || p.rows == 4) &&
+           mc_lds_base(p, f64) + mc_ell_lds(p, f64) <= MC_LDS_LIMIT;
 }
 
 template <typename T, bool TD> static const void *mc_pick(int rows, bool occ3)

@@ -30,7 +30,10 @@ struct TdTerm {
     const void *v;
 };
 
-void asm_launch_count(const AsmOps &op, int32_t *counts, int *flags, hipStream_t s);
+// counts[r]: stored entries of row r, padded to a multiple of 4; *real (device) accumulates the
+// entries that are not padding.
+void asm_launch_count(const AsmOps &op, int32_t *counts, int *flags, unsigned long long *real, bool f64,
+                      hipStream_t s);
 void asm_launch_scan(const int32_t *counts, int64_t n, int64_t *bsum, int32_t *rowptr, int *flags, hipStream_t s);
 void asm_launch_fill(const AsmOps &op, const int32_t *rowptr, int32_t *col, void *val, bool f64, hipStream_t s);
 // Concatenate the rows of nt assembled terms (device array `terms`) into one CSR whose column

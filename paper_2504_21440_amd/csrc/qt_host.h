@@ -78,7 +78,8 @@ struct Liouv {
     int32_t form = QT_FORM_CSR;
     int32_t precision = QT_F64;
     int32_t d = 0;
-    int64_t nnz = 0;
+    int64_t nnz = 0;         // entries of L (CSR form)
+    int64_t nnz_stored = 0;  // stored entries: every row padded to a multiple of 4 with zeros
     int64_t bytes = 0;
     int32_t nc = 0;
     // CSR form
@@ -104,11 +105,14 @@ struct CsrInst;
 struct CsrCtl;
 int csr_rows_per_block(int lpr, int rg);
 bool csr_shape_supported(int lpr, int rg);
+// A tile shape with a matrix load kind: keep 0 streamed, 1 through the caches, 2 through the caches
+// with 16-byte loads of 4-entry runs (built for 4x1, 8x1, 8x2 and 16x1).
+bool csr_shape_supported(int lpr, int rg, int keep);
 // One launch configuration of the CSR step kernels.
 struct CsrLaunch {
     bool f64 = false;
     int lpr = 8, rg = 1, xcd = 0;  // tile shape and block order
-    int keep = 0;                  // one problem: read the matrix through the caches (temporal loads)
+    int keep = 0;                  // matrix loads: 0 streamed, 1 through the caches, 2 as 1 with 16-byte loads
     int nblk = 0, ninst = 0;       // workgroups, problems
     const CsrInst *insts = nullptr;
     CsrCtl *ctls = nullptr;

@@ -13,7 +13,8 @@ struct CsrShape {
     int lpr = 8;  // lanes per row group
     int rg = 1;   // rows per lane group
     int xcd = 0;   // 1: XCD-contiguous block order
-    int keep = 0;  // 1: temporal matrix loads, the matrix may stay in L2 / MALL across launches
+    int keep = 0;  // 1: temporal matrix loads, the matrix may stay in L2 / MALL across launches;
+                   // 2: as 1 with 16-byte loads of runs of 4 stored entries
 };
 
 // size bucket of a CSR right-hand side: log2 of the rows, rounded mean row length

@@ -247,7 +247,7 @@ static qt_status reset_lanes(qt_me_plan *P)
 // Lay the CSR problems out over the launch grid for a tile shape and upload the block tables.
 static qt_status apply_shape(qt_me_plan *P, CsrShape sh)
 {
-    if (!csr_shape_supported(sh.lpr, sh.rg)) return set_error(QT_EINVAL, "unsupported CSR tile shape");
+    if (!csr_shape_supported(sh.lpr, sh.rg, sh.keep)) return set_error(QT_EINVAL, "unsupported CSR tile shape");
     const int rpb = csr_rows_per_block(sh.lpr, sh.rg);
     for (int32_t i = 0; i < P->ncsr; ++i) P->h_ci[i].nblocks = (P->h_ci[i].n + rpb - 1) / rpb;
     P->shape = sh;
@@ -702,8 +702,8 @@ qt_status me_plan_autotune(qt_me_plan *P, int32_t reps)
     QT_HIP(hipSetDevice(P->ctx->device));
     if (reps <= 0) reps = 20;
     if (P->ncsr) {
-        CsrShape cand[32];
-        const int nc = csr_candidates(cand, 32, P->ncsr == 1);
+        CsrShape cand[64];
+        const int nc = csr_candidates(cand, 64, P->ncsr == 1);
         CsrShape best = P->shape;
         double best_ms = 1e300;
         for (int k = 0; k < nc; ++k) {
@@ -908,8 +908,8 @@ qt_status qt_me_plan_autotune(qt_me_plan *plan, int32_t reps)
 qt_status qt_me_plan_set_shape(qt_me_plan *plan, const qt_csr_shape *shape)
 {
     if (!plan || !shape) return set_error(QT_EINVAL, "qt_me_plan_set_shape: null argument");
-    if (!csr_shape_supported(shape->lanes_per_row, shape->rows_per_group) || shape->xcd_order < 0 ||
-        shape->xcd_order > 1 || shape->cached_matrix < 0 || shape->cached_matrix > 1)
+    if (!csr_shape_supported(shape->lanes_per_row, shape->rows_per_group, shape->cached_matrix) ||
+        shape->xcd_order < 0 || shape->xcd_order > 1)
         return set_error(QT_EINVAL, "unsupported CSR tile shape");
     if (!plan->ncsr) return QT_OK;
     QT_HIP(hipSetDevice(plan->ctx->device));

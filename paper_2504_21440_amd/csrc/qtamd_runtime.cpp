@@ -392,10 +392,12 @@ static qt_status upload_csr32(const HCsr &A, std::vector<int32_t> &rp, std::vect
 }
 
 // Device assembly of  L = A (x) I + I (x) conj(B) + sum_k C_k (x) conj(C_k)  (B null: B = A) into
-// CSR with int32 indices, values in the solve precision.  On success the caller owns the three
-// device arrays.
+// CSR with int32 indices, values in the solve precision, every row padded with zeros to a multiple
+// of 4 stored entries.  On success the caller owns the three device arrays; *nnz_out counts the
+// entries of L, *stored_out the stored ones.
 static qt_status assemble_csr(Ctx *ctx, const HCsr &A, const HCsr *B, const std::vector<HCsr> &cs, bool f64,
-                              int32_t **rowptr_out, int32_t **col_out, void **val_out, int64_t *nnz_out)
+                              int32_t **rowptr_out, int32_t **col_out, void **val_out, int64_t *nnz_out,
+                              int64_t *stored_out)
 {
     const int32_t d = A.d, n_c = (int32_t)cs.size();
     const size_t es = f64 ? sizeof(double2) : sizeof(float2);
@@ -460,11 +462,11 @@ static qt_status assemble_csr(Ctx *ctx, const HCsr &A, const HCsr *B, const std:
     void *val = nullptr;
     e = e ? e : hipMalloc(&rowptr, (size_t)(n + 1) * 4);
     if (e == hipSuccess) {
-        asm_launch_count(op, counts, flags, s);
+        asm_launch_count(op, counts, flags, (unsigned long long *)(flags + 4), f64, s);
         asm_launch_scan(counts, n, (int64_t *)tmp.at(o_bs), rowptr, flags, s);
         e = hipGetLastError();
     }
-    int hflags[2] = {0, 0};
+    int hflags[6] = {0, 0, 0, 0, 0, 0};  // overflow, too many entries, pad, pad, real count (uint64)
     int32_t total = 0;
     e = e ? e : hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s);
     e = e ? e : hipMemcpyAsync(&total, rowptr + n, 4, hipMemcpyDeviceToHost, s);
@@ -492,10 +494,13 @@ static qt_status assemble_csr(Ctx *ctx, const HCsr &A, const HCsr *B, const std:
         if (val) (void)hipFree(val);
         return set_error(QT_EDEVICE, std::string("Liouvillian assembly: ") + hipGetErrorString(e));
     }
+    unsigned long long real = 0;
+    std::memcpy(&real, hflags + 4, sizeof(real));
     *rowptr_out = rowptr;
     *col_out = col;
     *val_out = val;
-    *nnz_out = total;
+    *nnz_out = (int64_t)real;
+    *stored_out = total;
     return QT_OK;
 }
 
@@ -565,12 +570,13 @@ qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const 
     }
 
     // CSR form: device assembly
-    if ((st = assemble_csr(ctx, A, nullptr, cs, precision == QT_F64, &L->rowptr, &L->col, &L->val, &L->nnz))) {
+    if ((st = assemble_csr(ctx, A, nullptr, cs, precision == QT_F64, &L->rowptr, &L->col, &L->val, &L->nnz,
+                           &L->nnz_stored))) {
         delete L;
         return st;
     }
     const int64_t n = (int64_t)d * d;
-    L->bytes = (int64_t)((n + 1) * 4 + L->nnz * (4 + (int64_t)es));
+    L->bytes = (int64_t)((n + 1) * 4 + L->nnz_stored * (4 + (int64_t)es));
     ctx->refs++, *out = L;
     return QT_OK;
 }
@@ -652,7 +658,7 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
     struct Part {
         int32_t *rp = nullptr, *ci = nullptr;
         void *v = nullptr;
-        int64_t nnz = 0;
+        int64_t nnz = 0, stored = 0;
     };
     std::vector<Part> parts(1 + nterms);
     auto free_parts = [&]() {
@@ -671,7 +677,8 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
                 A = csr_axpby(cd(1.0, 0.0), A, cd(-0.5, 0.0), csr_matmul(csr_adjoint(cs[k]), cs[k]));
                 c0.push_back(cs[k]);
             }
-        st = assemble_csr(ctx, A, nullptr, c0, f64, &parts[0].rp, &parts[0].ci, &parts[0].v, &parts[0].nnz);
+        st = assemble_csr(ctx, A, nullptr, c0, f64, &parts[0].rp, &parts[0].ci, &parts[0].v, &parts[0].nnz,
+                          &parts[0].stored);
     }
     std::vector<CoefDev> cd_host(nterms);
     std::vector<const qt_coef *> src(nterms);
@@ -680,7 +687,8 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
         // -i (H rho - rho H):  A = -i H,  B = -i H^dag  (rho B^dag = i rho H)
         const HCsr A = csr_axpby(cd(0.0, -1.0), hs[i], cd(0.0, 0.0), csr_zero(d));
         const HCsr B = csr_axpby(cd(0.0, -1.0), csr_adjoint(hs[i]), cd(0.0, 0.0), csr_zero(d));
-        st = assemble_csr(ctx, A, &B, {}, f64, &parts[t].rp, &parts[t].ci, &parts[t].v, &parts[t].nnz);
+        st = assemble_csr(ctx, A, &B, {}, f64, &parts[t].rp, &parts[t].ci, &parts[t].v, &parts[t].nnz,
+                          &parts[t].stored);
         src[t - 1] = &h_coefs[i];
         cd_host[t - 1].modsq = 0;
     }
@@ -688,7 +696,8 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
         if (!weighted(k)) continue;
         // D[C]:  A = -1/2 C^dag C,  C (x) conj(C)
         const HCsr A = csr_axpby(cd(-0.5, 0.0), csr_matmul(csr_adjoint(cs[k]), cs[k]), cd(0.0, 0.0), csr_zero(d));
-        st = assemble_csr(ctx, A, nullptr, {cs[k]}, f64, &parts[t].rp, &parts[t].ci, &parts[t].v, &parts[t].nnz);
+        st = assemble_csr(ctx, A, nullptr, {cs[k]}, f64, &parts[t].rp, &parts[t].ci, &parts[t].v, &parts[t].nnz,
+                          &parts[t].stored);
         src[t - 1] = &c_coefs[k];
         cd_host[t - 1].modsq = 1;
         ++t;
@@ -697,8 +706,11 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
         free_parts();
         return st;
     }
-    int64_t total = 0;
-    for (auto &q : parts) total += q.nnz;
+    int64_t total = 0, real = 0;
+    for (auto &q : parts) {
+        total += q.stored;
+        real += q.nnz;
+    }
     if (total >= 2147483647LL) {
         free_parts();
         return set_error(QT_EINVAL, "Liouvillian has more than 2^31 non-zeros");
@@ -715,7 +727,8 @@ qt_status qt_liouvillian_build_td(qt_ctx *ctx, const qt_csr *H0, int32_t n_h, co
     L->d = d;
     L->nc = n_c;
     L->nterms = nterms;
-    L->nnz = total;
+    L->nnz = real;
+    L->nnz_stored = total;
     hipError_t e = hipMalloc(&L->coefs, head + std::max<size_t>(tab_bytes, 16));
     std::vector<char> hostbuf(head + tab_bytes, 0);
     size_t toff = head;
@@ -790,21 +803,33 @@ qt_status qt_liouv_export(const qt_liouv *L, int64_t *indptr, int32_t *indices, 
     if (!L || L->form != QT_FORM_CSR || !indptr || !indices || !values)
         return set_error(QT_EINVAL, "qt_liouv_export: CSR Liouvillian and output arrays required");
     QT_HIP(hipSetDevice(L->ctx->device));
-    const int64_t n = (int64_t)L->d * L->d;
-    std::vector<int32_t> rp(n + 1);
+    const int64_t n = (int64_t)L->d * L->d, ns = L->nnz_stored;
+    std::vector<int32_t> rp(n + 1), ci(ns);
+    std::vector<double2> v(ns);
     QT_HIP(hipMemcpy(rp.data(), L->rowptr, (n + 1) * 4, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i <= n; ++i) indptr[i] = rp[i];
-    if (L->nnz) QT_HIP(hipMemcpy(indices, L->col, L->nnz * 4, hipMemcpyDeviceToHost));
+    if (ns) QT_HIP(hipMemcpy(ci.data(), L->col, ns * 4, hipMemcpyDeviceToHost));
     if (L->precision == QT_F64) {
-        if (L->nnz) QT_HIP(hipMemcpy(values, L->val, L->nnz * 16, hipMemcpyDeviceToHost));
+        if (ns) QT_HIP(hipMemcpy(v.data(), L->val, ns * 16, hipMemcpyDeviceToHost));
     } else {
-        std::vector<float2> f(L->nnz);
-        if (L->nnz) QT_HIP(hipMemcpy(f.data(), L->val, L->nnz * 8, hipMemcpyDeviceToHost));
-        for (int64_t p = 0; p < L->nnz; ++p) {
-            values[2 * p] = f[p].x;
-            values[2 * p + 1] = f[p].y;
-        }
+        std::vector<float2> f(ns);
+        if (ns) QT_HIP(hipMemcpy(f.data(), L->val, ns * 8, hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < ns; ++p) v[p] = make_double2(f[p].x, f[p].y);
     }
+    // the stored zeros are the row padding: leave them out
+    int64_t o = 0;
+    indptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+            if (v[p].x == 0.0 && v[p].y == 0.0) continue;
+            if (o >= L->nnz) return set_error(QT_EDEVICE, "qt_liouv_export: more entries than counted");
+            indices[o] = ci[p];
+            values[2 * o] = v[p].x;
+            values[2 * o + 1] = v[p].y;
+            ++o;
+        }
+        indptr[i + 1] = o;
+    }
+    if (o != L->nnz) return set_error(QT_EDEVICE, "qt_liouv_export: fewer entries than counted");
     return QT_OK;
 }
 

@@ -90,11 +90,11 @@ int csr_candidates(CsrShape *out, int max, bool single)
 {
     static const int lprs[] = {4, 8, 16}, rgs[] = {1, 2, 4};
     int n = 0;
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 3; ++k)
         for (int x = 0; x < (single ? 2 : 1); ++x)
             for (int l : lprs)
                 for (int r : rgs)
-                    if (r <= l && n < max) out[n++] = CsrShape{l, r, x, k};
+                    if (r <= l && n < max && csr_shape_supported(l, r, k)) out[n++] = CsrShape{l, r, x, k};
     return n;
 }
 
@@ -143,8 +143,7 @@ qt_status qt_tune_load(const char *path)
         char key[128];
         int a = 0, b = 0, c = 0, e = 0;
         const int m = std::sscanf(line, " \"%127[^\"]\": [%d, %d, %d, %d]", key, &a, &b, &c, &e);
-        if (m >= 3 && std::strncmp(key, "csr:", 4) == 0 && csr_shape_supported(a, b) && (c == 0 || c == 1) &&
-            (e == 0 || e == 1)) {
+        if (m >= 3 && std::strncmp(key, "csr:", 4) == 0 && csr_shape_supported(a, b, e) && (c == 0 || c == 1)) {
             tune_store_csr(key, CsrShape{a, b, c, e});
             ++loaded;
         } else if (m >= 2 && std::strncmp(key, "dense:", 6) == 0 && dense_key_accepts(key, a)) {

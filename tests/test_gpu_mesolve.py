@@ -220,6 +220,9 @@ def test_batch_alone_vs_mix_bitwise(ctx):
 
 
 SHAPES = [(l, r) for l in (4, 8, 16) for r in (1, 2, 4) if r <= l]
+WIDE = [(4, 1), (8, 1), (8, 2), (16, 1)]  # also built with 16-byte matrix loads (cached_matrix = 2)
+# every (shape, block order, matrix load kind) the CSR kernels are built with
+LAUNCHES = [(sh, x, k) for k in (0, 1) for x in (0, 1) for sh in SHAPES] + [(sh, x, 2) for x in (0, 1) for sh in WIDE]
 
 
 def test_csr_every_tile_shape_vs_oracle(ctx):
@@ -236,7 +239,7 @@ def test_csr_every_tile_shape_vs_oracle(ctx):
             probs[prec].append((qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec), om.all_up_ket(Lc), tl, e_ops))
     for prec, tol in [(qt.F64, 1e-6), (qt.MIXED, 1e-4)]:
         plan = qt.MePlan(ctx, probs[prec], qt.opts(precision=prec))
-        for (lpr, rg), xcd, keep in [(sh, x, k) for k in (0, 1) for x in (0, 1) for sh in SHAPES]:
+        for (lpr, rg), xcd, keep in LAUNCHES:
             print(f"[gpu] CSR shape lpr={lpr} rg={rg} xcd={xcd} keep={keep} prec={prec}", flush=True)
             plan.set_shape(lpr, rg, xcd, keep)
             assert plan.shape()[:4] == (lpr, rg, 0, keep)  # two problems: round-robin order
@@ -249,6 +252,9 @@ def test_csr_every_tile_shape_vs_oracle(ctx):
     with pytest.raises(qt.QtError):
         plan = qt.MePlan(ctx, probs[qt.F64][:1], qt.opts())
         plan.set_shape(8, 8)
+    with pytest.raises(qt.QtError):  # 16-byte loads are not built for 4 rows per lane group
+        plan = qt.MePlan(ctx, probs[qt.F64][:1], qt.opts())
+        plan.set_shape(8, 4, 0, 2)
 
 
 def test_ising_l10_hbm_sized_every_shape_vs_golden(ctx):
@@ -263,7 +269,7 @@ def test_ising_l10_hbm_sized_every_shape_vs_golden(ctx):
         Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
         assert Lo.info()[1] == 24_641_535
         plan = qt.MePlan(ctx, [(Lo, om.all_up_ket(10), tl, e_ops)], qt.opts(precision=prec))
-        for (lpr, rg), xcd, keep in [(sh, x, k) for k in (0, 1) for x in (0, 1) for sh in SHAPES]:
+        for (lpr, rg), xcd, keep in LAUNCHES:
             print(f"[gpu] L=10 shape lpr={lpr} rg={rg} xcd={xcd} keep={keep} prec={prec}", flush=True)
             plan.set_shape(lpr, rg, xcd, keep)
             assert plan.shape()[:4] == (lpr, rg, xcd, keep)
@@ -382,7 +388,8 @@ def test_autotune_chooses_a_kernel_shape_and_keeps_parity(ctx, tmp_path):
              (qt.Liouvillian(ctx, Hk, ck, qt.FORM_DENSE, qt.MIXED), om.fock_dm(20, 0), tl, [om.number(20)])]
     plan = qt.MePlan(ctx, probs, o)
     lpr, rg, xcd, keep, waves = plan.shape()
-    assert (lpr, rg) in SHAPES and xcd in (0, 1) and keep in (0, 1) and waves in (1, 2, 4)
+    assert (lpr, rg) in SHAPES and xcd in (0, 1) and keep in (0, 1, 2) and waves in (1, 2, 4)
+    assert keep < 2 or (lpr, rg) in WIDE
     plan.run()
     assert np.abs(plan.result(0)[0] - ref).max() <= 1e-4
     assert np.abs(plan.result(1)[0] - refk).max() <= 1e-4

@@ -143,6 +143,7 @@ def test_td_collapse_weights_vs_oracle(ctx):
 
 
 SHAPES = [(l, r) for l in (4, 8, 16) for r in (1, 2, 4) if r <= l]
+WIDE = [(4, 1), (8, 1), (8, 2), (16, 1)]  # also built with 16-byte matrix loads (cached_matrix = 2)
 
 
 def test_td_optomechanics_every_launch_form_vs_oracle(ctx):
@@ -166,7 +167,7 @@ def test_td_optomechanics_every_launch_form_vs_oracle(ctx):
     for prec, tol in [(qt.F64, 1e-6), (qt.MIXED, 1e-4)]:
         for sel in ([0], [0, 1]):
             plan = qt.MePlan(ctx, [probs[prec][i] for i in sel], qt.opts(precision=prec))
-            for (lpr, rg), keep in [(sh, k) for k in (0, 1) for sh in SHAPES]:
+            for (lpr, rg), keep in [(sh, k) for k in (0, 1) for sh in SHAPES] + [(sh, 2) for sh in WIDE]:
                 print(f"[gpu] TD optomech n={len(sel)} lpr={lpr} rg={rg} keep={keep} prec={prec}", flush=True)
                 plan.set_shape(lpr, rg, 0, keep)
                 plan.run()
