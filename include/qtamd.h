@@ -433,8 +433,8 @@ qt_status qt_smesolve(qt_ctx *ctx, const qt_sde_problem *prob, const qt_opts *op
  * request does not fit now (QT_ENOMEM if it can never fit).  step runs one epoch and retires
  * finished requests; poll reports completion and copies results.  Requests of every size share
  * the CSR launches, which use 8 lanes per row and one row per lane group and read the matrices
- * through the caches; a request's results are bitwise those of a plan with that shape
- * (lanes_per_row 8, rows_per_group 1). */
+ * through the caches in 16-byte runs of 4 entries; a request's results are bitwise those of a plan
+ * with that shape (lanes_per_row 8, rows_per_group 1, cached_matrix 2). */
 typedef struct {
     int64_t pool_bytes;      /* device memory budget for resident requests */
     int32_t max_slots;       /* resident requests at most */

@@ -549,7 +549,9 @@ static CsrShape server_shape()
 {
     // requests of many sizes share one grid: the shape for small spin and oscillator Liouvillians
     CsrShape sh = csr_default_shape(0, 19.0);
-    sh.keep = 1;  // matrices read through the caches: many small resident ones fit the L2s / MALL
+    // matrices read through the caches (many small resident ones fit the L2s / MALL), runs of 4
+    // stored entries per 16-byte load
+    sh.keep = 2;
     return sh;
 }
 

@@ -70,7 +70,7 @@ def test_server_results_equal_alone_and_in_mix(ctx):
     assert len(results) == len(reqs)
     for i, (pr, ops) in enumerate(reqs):
         plan = qt.MePlan(ctx, [pr], o)
-        plan.set_shape(8, 1)  # the server's CSR launch shape
+        plan.set_shape(8, 1, 0, 2)  # the server's CSR launch shape
         plan.run()
         alone = plan.result(0)
         plan.close()
@@ -116,7 +116,7 @@ def test_server_large_and_small_lanes_match_alone(ctx):
         assert epochs < 100000
     for i, (pr, ops) in enumerate(probs):
         plan = qt.MePlan(ctx, [pr], o)
-        plan.set_shape(8, 1)  # the server's CSR launch shape
+        plan.set_shape(8, 1, 0, 2)  # the server's CSR launch shape
         plan.run()
         alone = plan.result(0)
         plan.close()
@@ -177,3 +177,59 @@ def test_server_slot_limit_and_errors(ctx):
         assert e.value.code == qt.QT_EMAXSTEPS
     assert srv.submit(*r3) is not None
     srv.close()
+
+
+SERVED_RTOL = 1e-4  # the served mixed tolerance the bench calibrates (loosest ladder rung meeting 1e-4)
+
+
+def test_served_stream_at_benched_size_matches_oracle_and_alone(ctx):
+    """Requests of the served stream exactly as benchmarked: Kerr cavities (up to N = 80) and chains
+    (up to L = 9) in the CSR form, 100 saves, mixed precision at the served tolerance, all submitted
+    together to a server configured as the bench's.  The stiffest cavities (largest U N^2), the first
+    L = 9 chains and a spread of smaller requests are each within 1e-4 of the stored oracle solution
+    (abstol 1e-10, reltol 1e-8) and bitwise equal to the same request solved alone."""
+    import json
+    import os
+    print("[gpu] served stream at benched size", flush=True)
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "serving_trace240.json")) as f:
+        refs = {r["id"]: np.array(r["expect_re"][0]) + 1j * np.array(r["expect_im"][0]) for r in json.load(f)["requests"]}
+    trace = workloads.serving_trace(n=240)
+    kerr = sorted((p for p in trace if p["kind"] == "kerr"), key=lambda p: -p["U"] * p["N"] ** 2)
+    chains = [p for p in trace if p["kind"] == "ising"]
+    pick = kerr[:4] + [p for p in chains if p["L"] == 9][:2] + [kerr[len(kerr) // 2], kerr[-1]]
+    pick += [next(p for p in chains if p["L"] == L) for L in (4, 6, 8)]
+    o = qt.opts(abstol=SERVED_RTOL / 100, reltol=SERVED_RTOL, precision=qt.MIXED)
+    reqs = []
+    for p in pick:
+        tl = workloads.tlist(p["t_end"], p["nt"])
+        if p["kind"] == "kerr":
+            H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
+            reqs.append((qt.Liouvillian(ctx, H, c, qt.FORM_CSR, qt.MIXED), om.fock_dm(p["N"], 0), tl, [om.number(p["N"])]))
+        else:
+            H, cs = qt.model_ising(p["L"], p["J"], p["h"], p["gamma"])
+            reqs.append((qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, qt.MIXED), om.all_up_ket(p["L"]), tl,
+                         [om.site_op(p["L"], 0, om.sigmaz())]))
+    srv = qt.Server(ctx, pool_bytes=16 << 30, max_slots=1024, steps_per_epoch=32, options=o)
+    tickets = {srv.submit(*pr): i for i, pr in enumerate(reqs)}
+    assert None not in tickets
+    results, epochs = {}, 0
+    while tickets:
+        srv.step()
+        epochs += 1
+        for t in list(tickets):
+            r = srv.poll(t)
+            if r is not None:
+                results[tickets.pop(t)] = r
+        assert epochs < 200000
+    srv.close()
+    for i, (p, pr) in enumerate(zip(pick, reqs)):
+        err = np.abs(results[i][0][0] - refs[p["id"]]).max()
+        print(f"[gpu]   request {p['id']} {p['kind']} {p.get('N', p.get('L'))}: max |d<O>| = {err:.2e}", flush=True)
+        assert err <= 1e-4
+        plan = qt.MePlan(ctx, [pr], o)
+        plan.set_shape(8, 1, 0, 2)  # the server's CSR launch shape: 16-byte matrix loads through the caches
+        plan.run()
+        alone = plan.result(0)
+        plan.close()
+        np.testing.assert_array_equal(results[i][0], alone[0])
+        pr[0].close()
