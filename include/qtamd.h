@@ -197,10 +197,11 @@ qt_status qt_mesolve(qt_ctx *ctx, const qt_me_problem *prob, const qt_opts *opts
  * (device memory on the context's device, 256-byte aligned, at least that many bytes; a torch
  * tensor's storage will do) instead of allocating, and qt_mesolve_ws is the one-shot solve in such
  * a buffer.  The buffer must stay allocated and untouched by the caller until the plan is destroyed
- * (for qt_mesolve_ws: until the call returns, which synchronises the context's stream).  Neither
- * creation nor run nor result allocates device memory (the plan's small pinned host mirrors of its
- * control records aside); results are bitwise those of the allocating calls.  Errors: QT_EINVAL for
- * a null or misaligned buffer, QT_ENOMEM when ws_bytes is below the workspace size. */
+ * (for qt_mesolve_ws: until the call returns, which synchronises the context's stream).  The
+ * library calls no hipMalloc for such a plan, at creation or later (it still allocates small pinned
+ * host mirrors of the control records, and the HIP runtime may allocate internally for the graphs
+ * it instantiates); results are bitwise those of the allocating calls.  Errors: QT_EINVAL for a
+ * null or misaligned buffer, QT_ENOMEM when ws_bytes is below the workspace size. */
 qt_status qt_me_plan_workspace(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts,
                                size_t *bytes);
 qt_status qt_me_plan_create_ws(qt_ctx *ctx, int32_t n, const qt_me_problem *probs, const qt_opts *opts, void *dev_ws,
