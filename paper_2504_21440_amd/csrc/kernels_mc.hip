@@ -101,26 +101,55 @@ __global__ __launch_bounds__(MC_THREADS) __attribute__((amdgpu_waves_per_eu(OCC)
             }
             __syncthreads();
         }
+        // complex64: entry k of all R rows of this thread at once, R independent load-gather-FMA
+        // chains per entry rather than one row's W entries after another (measured: the L = 10
+        // ensemble 58,700 -> 69,700 trajectories/s); complex128 keeps one row at a time, whose
+        // registers the wider values would otherwise spill (22,000 -> 17,800).  Each row is summed
+        // in the order k = 0 .. W-1 either way.  Global-only loads of the matrix stream: generic ones
+        // would be ordered against, and waited for with, the LDS gathers of the state.
+        V acc[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-            const int r = row(m);
-            V acc;
-            acc.x = 0;
-            acc.y = 0;
-            if (r < d)
-                for (int k = 0; k < P.W; ++k) {
-                    // global-only loads of the matrix stream (generic ones would be ordered against,
-                    // and waited for with, the LDS gathers of the state)
-                    const size_t at = (size_t)k * d + r;
-                    const int32_t c = ELDS ? ecs[at] : gld(ec + at);
-                    const V a = ELDS ? evs[at] : gld(ev + at);
-                    if constexpr (TD)
-                        cfma(acc, cmul(a, cwsh[c >> MC_TAG_SHIFT]), x[c & ((1 << MC_TAG_SHIFT) - 1)]);
-                    else
-                        cfma(acc, a, x[c]);
-                }
-            out[m] = acc;
+            acc[m].x = 0;
+            acc[m].y = 0;
         }
+        if constexpr (sizeof(T) == 8) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const int r = row(m);
+                if (r < d)
+                    for (int k = 0; k < P.W; ++k) {
+                        const size_t at = (size_t)k * d + r;
+                        const int32_t c = ELDS ? ecs[at] : gld(ec + at);
+                        const V a = ELDS ? evs[at] : gld(ev + at);
+                        if constexpr (TD)
+                            cfma(acc[m], cmul(a, cwsh[c >> MC_TAG_SHIFT]), x[c & ((1 << MC_TAG_SHIFT) - 1)]);
+                        else
+                            cfma(acc[m], a, x[c]);
+                    }
+            }
+        } else
+        for (int k = 0; k < P.W; ++k) {
+            int32_t c[R];
+            V a[R];
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                if (row(m) < d) {
+                    const size_t at = (size_t)k * d + row(m);
+                    c[m] = ELDS ? ecs[at] : gld(ec + at);
+                    a[m] = ELDS ? evs[at] : gld(ev + at);
+                }
+#pragma unroll
+            for (int m = 0; m < R; ++m)
+                if (row(m) < d) {
+                    if constexpr (TD)
+                        cfma(acc[m], cmul(a[m], cwsh[c[m] >> MC_TAG_SHIFT]), x[c[m] & ((1 << MC_TAG_SHIFT) - 1)]);
+                    else
+                        cfma(acc[m], a[m], x[c[m]]);
+                }
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) out[m] = acc[m];
     };
     // weight |g_k(t)|^2 of collapse channel k (1 when constant)
     auto cweight = [&](int k, double tt) {
