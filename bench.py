@@ -254,11 +254,13 @@ def section_sweep(ctx, n=512, nmax_dense=80):
     n_rhs = 0
     flops = 0.0
     res = []
+    worst = (0, -1)
     for i, p in enumerate(sweep):
         ex, st, _ = plan.result(i)
         res.append(ex)
         n_rhs += st["n_rhs"]
         flops += st["n_rhs"] * 24.0 * p["N"] ** 3
+        worst = max(worst, (st["n_rhs"], i))
     with open(os.path.join(ROOT, "tests", "golden", "kerr_sweep_samples.json")) as f:
         samples = json.load(f)["instances"]
     err = max(float(np.abs(res[q["index"]] - (np.array(q["expect_re"]) + 1j * np.array(q["expect_im"]))).max())
@@ -269,9 +271,22 @@ def section_sweep(ctx, n=512, nmax_dense=80):
            "max_err_vs_fp64_oracle_samples": err, "samples_checked": [q["index"] for q in samples]}
     if nmax_dense >= 80:
         # the concurrent run: all 512 dense instances in flight together, flops at the true N
+        # (24 N^3 per right-hand side: the 1 + 2K complex products of the operator form, K = 1)
         out.update({"algorithmic_TFLOPs_concurrent": flops / dt / 1e12,
                     "frac_of_fp32_matrix_peak_concurrent": flops / dt / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
                     "dense_waves_largest_bucket": waves})
+        # The stiffest cavity sets the makespan.  MFMA instructions per right-hand side at padded
+        # size NP (real collapse operator): P and X on every 16x16 tile (4 + 2 per inner step),
+        # C X^dag on the upper tiles (2), NP / 4 inner steps; 32 cycles each on one of 4 SIMDs.
+        nw, iw = worst
+        npad = -(-sweep[iw]["N"] // 16) * 16
+        nt, kf = npad // 16, npad // 4
+        mfma = nt * nt * kf * 6 + nt * (nt + 1) // 2 * kf * 2
+        us = dt / nw * 1e6
+        mfma_us = mfma * 32 / 4 / 2.4e3
+        out["stiffest_instance"] = {"index": iw, "N": sweep[iw]["N"], "n_rhs": nw, "us_per_rhs": us,
+                                    "mfma_instructions_per_rhs": mfma, "mfma_us_per_rhs_at_2400MHz": mfma_us,
+                                    "mfma_busy_share_of_its_cu": mfma_us / us}
     else:
         out["csr_shape"] = list(plan.shape()[:4])
     plan.close()

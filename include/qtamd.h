@@ -121,7 +121,9 @@ void qt_csr_free(qt_csr *A);
  * complex128 (QT_F64) or complex64 (QT_MIXED) with int32 indices (nnz < 2^31), and pads every row
  * with explicit zeros to a multiple of 4 stored entries (so the SpMV can load aligned runs of 4).
  * form QT_FORM_DENSE: stores A and the C_k as dense matrices zero-padded to a multiple of 16 for
- * the batched MFMA right-hand side; d <= 80 (QT_MIXED) or d <= 48 (QT_F64).
+ * the batched MFMA right-hand side (in the order the kernel's lanes read them; a C_k with no
+ * imaginary part keeps its real parts only); d <= 80 (QT_MIXED) or d <= 48 (QT_F64).  Solves in
+ * this form need a Hermitian initial state (their results are Hermitian by construction).
  * Errors: QT_EINVAL for mismatched sizes, malformed CSR, or a dense d above the limit. */
 qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const qt_csr *c_ops, int32_t form,
                                int32_t precision, qt_liouv **out);

@@ -1,21 +1,33 @@
 // kernels_dense.hip -- dense operator-form master-equation solver on the gfx950 matrix cores.
 //
-// L(rho) = A rho + (A rho)^dag + sum_k C_k rho C_k^dag (arXiv:2504.21440, Sec. 3.2, with
-// A = -i H - 1/2 sum_k C_k^dag C_k).  For Hermitian rho, C rho C^dag = C (C rho)^dag, so every
-// product takes the operator as its left factor:
-//     X_k = C_k rho,   Z = sum_k C_k X_k^dag,   M = A rho,   L(rho) = Z + M + M^dag,
-// i.e. 1 + 2K complex matrix products.  Complex products run on real MFMA instructions
-// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64): Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// The master equation of arXiv:2504.21440 (Sec. 3.2) in operator form,
+//     L(rho) = A rho + rho A^dag + sum_k C_k rho C_k^dag,   A = -i H - 1/2 sum_k C_k^dag C_k.
+// For Hermitian rho the result is Hermitian, and with P = A rho and X_k = C_k rho
+//     L(rho) = P + P^dag + sum_k C_k X_k^dag.
+// P and the X_k are formed on every 16x16 tile, the sum and the result only on the tiles on and
+// above the diagonal; each result element goes into the next stage input together with its mirror
+// image, so every stage input is exactly Hermitian.  Every product has the shape Op R^dag: Op an
+// operator (A or C_k, rows read from global memory into registers; stored in the order the lanes
+// consume them, so a load of the 64 lanes reads 1 KB of contiguous memory), R a matrix in LDS (rho,
+// which equals rho^dag, or X_k), read by rows:
+//     Re(Op R^dag) = Re Op Re R^T + Im Op Im R^T,   Im(Op R^dag) = Im Op Re R^T - Re Op Im R^T,
+// three accumulators and no negated operand.  A real collapse operator (Im C_k = 0) needs two real
+// products per complex one instead of four.  The real products run on v_mfma_f32_16x16x4f32 /
+// v_mfma_f64_16x16x4f64.  Lane l supplies k-slot l / 16 of each instruction, and over the NP / 4
+// instructions of a tile that slot walks the contiguous range [(l / 16) NP / 4, (l / 16 + 1) NP / 4)
+// of the inner index, so the lane's operator elements are contiguous in a row and its LDS operands
+// come in 16-byte reads of 4 (FP32) or 2 (FP64) inner steps.
 //
 // One workgroup owns one problem for the whole launch and runs the adaptive Dormand-Prince 5(4)
-// loop itself.  Wave w owns a contiguous run of output tiles (row-major tile order, near-equal runs
-// per wave); for each tile row its run touches it loads the 16 operator rows from L2 into
-// registers (all loads in flight at once), so the inner MFMA loop reads only LDS.  LDS holds two NP x (NP+1) planar (re, im)
-// matrices: B0 = the stage input rho_s, B1 = scratch for X_k and then M.  The odd row stride keeps
-// the transposed walks conflict-free.  Runge-Kutta stages of the elements a lane owns live in a
-// per-problem global buffer in tile order (contiguous per-lane accesses); the epilogue of each
-// stage is applied element by element as the right-hand side is produced.  Step control, error
-// norm, trace renormalisation and expectation values are FP64 and stay inside the workgroup.
+// loop itself.  LDS holds three NP x S planar (re, im) matrices: B0 = the stage input, B1 = X_k,
+// B2 = P.  The row stride S is NP plus 16 bytes, which puts the 16 rows of a 16-byte read on
+// distinct banks.  One right-hand side: phase 1 (P and X_0 on every tile, split over the waves by
+// matrix-core work), a barrier, phase 2 (C_k X_k^dag on the upper tiles, then the
+// stage epilogue, which writes the next stage input into B0), a barrier.  The Runge-Kutta stage
+// vectors live in a per-problem global buffer that holds the elements of the upper tiles in
+// (tile, lane, accumulator slot) order.  Step control, the error norm (an element above the diagonal
+// counts for itself and its mirror), trace renormalisation and expectation values are FP64 and stay
+// inside the workgroup.
 #include <algorithm>
 #include <vector>
 
@@ -27,11 +39,13 @@ namespace qt {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float lf4 __attribute__((ext_vector_type(4)));   // 16-byte LDS access, FP32
+typedef double ld2 __attribute__((ext_vector_type(2)));  // 16-byte LDS access, FP64
 
 // Every buffer access of this file goes through the global-only loads and stores of qt_common.h
 // (gld / gst and the wider ones below): the LDS traffic of the matrix products then neither
 // orders against nor waits for it.
-// The 4 consecutive tile-order elements a lane owns in one output tile, with 16-byte accesses.
+// The 4 consecutive elements a lane owns in one output tile, with 16-byte accesses.
 typedef float gf4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void gld4(const float2 *p, float2 (&r)[4])
 {
@@ -65,32 +79,6 @@ __device__ __forceinline__ void gst4(double2 *p, const double2 (&r)[4])
 #pragma unroll
     for (int v = 0; v < 4; ++v) gst(p + v, r[v]);
 }
-// Two consecutive elements (16 or 32 bytes).
-__device__ __forceinline__ void gld2(const float2 *p, float2 (&r)[2])
-{
-    const gf4 a = *(const QT_GLOBAL gf4 *)p;
-    r[0] = make_float2(a.x, a.y);
-    r[1] = make_float2(a.z, a.w);
-}
-__device__ __forceinline__ void gld2(const double2 *p, double2 (&r)[2])
-{
-    r[0] = gld(p);
-    r[1] = gld(p + 1);
-}
-__device__ __forceinline__ void gst2(float2 *p, const float2 &r0, const float2 &r1)
-{
-    gf4 a;
-    a.x = r0.x;
-    a.y = r0.y;
-    a.z = r1.x;
-    a.w = r1.y;
-    *(QT_GLOBAL gf4 *)p = a;
-}
-__device__ __forceinline__ void gst2(double2 *p, const double2 &r0, const double2 &r1)
-{
-    gst(p, r0);
-    gst(p + 1, r1);
-}
 
 template <typename T> struct Mfma;
 template <> struct Mfma<float> {
@@ -116,245 +104,422 @@ template <typename T> __device__ __forceinline__ int mrow(int k4, int v)
     return sizeof(T) == 8 ? k4 + 4 * v : 4 * k4 + v;
 }
 
-// Work split: the NT x NT output tiles, in row-major order, are cut into WV contiguous chunks of
-// near-equal size, one per wave, so the matrix-core work spreads evenly over the 4 SIMDs of the CU
-// (with one wave per 16-row tile row, NP = 80 would put 2 of its 5 waves, 40% of the work, on one
-// SIMD).  A wave reloads its operator fragments only when its chunk crosses into the next tile row.
+// Work split: phase 1 cuts the NT x NT tiles (row-major order), phase 2 the NT (NT + 1) / 2 tiles
+// on and above the diagonal (row-major order), into WV contiguous runs of near-equal length, one
+// per wave, so the matrix-core work spreads over the 4 SIMDs of the CU.  A wave reloads its operator
+// rows only when its run enters the next tile row.
 template <typename T, int NP, int WV> struct DenseGeom {
-    static constexpr int S = NP + 1;                   // LDS row stride
-    static constexpr int NT = NP / 16;                 // tiles per side
+    static constexpr int S = NP + 16 / (int)sizeof(T);  // LDS row stride (elements)
+    static constexpr int NT = NP / 16;                   // tiles per side
     static constexpr int TILES = NT * NT;
+    static constexpr int UT = NT * (NT + 1) / 2;         // tiles with I <= J
     static constexpr int WAVES = WV;
-    static constexpr int MAXJ = (TILES + WV - 1) / WV;  // tiles per wave (upper bound)
-    static constexpr int KF = NP / 4;                   // operator fragments per lane
+    static constexpr int KF = NP / 4;                    // inner steps per lane per tile
     static constexpr int PLANE = NP * S;
     static constexpr size_t LDS_BYTES = (size_t)6 * PLANE * sizeof(T);  // B0, B1, B2 (re, im)
-    // first tile of wave w's chunk (the chunk of w ends where that of w + 1 starts)
-    static __device__ __forceinline__ int chunk0(int w) { return (w * TILES) / WV; }
+    static __device__ __forceinline__ int tile0(int w) { return (w * TILES) / WV; }
+    static __device__ __forceinline__ int utile0(int w) { return (w * UT) / WV; }
 };
 
-// Element index of (tile t, lane, v) in the tile-ordered global vectors.
-__device__ __forceinline__ size_t tix(int t, int lane, int v) { return ((size_t)t * 64 + lane) * 4 + v; }
-
-// acc += a * b on the matrix cores, complex a = (ar, ai), b = (br, bi).
-template <typename T>
-__device__ __forceinline__ void cmma(typename Mfma<T>::acc &aR, typename Mfma<T>::acc &aI, T ar, T ai, T br, T bi)
+// Upper tile u (row-major order over I <= J) of an nt x nt tiling.
+__device__ __forceinline__ void upper_tile(int u, int nt, int &I, int &J)
 {
-    aR = Mfma<T>::mma(ar, br, aR);
-    aR = Mfma<T>::mma(-ai, bi, aR);
-    aI = Mfma<T>::mma(ar, bi, aI);
-    aI = Mfma<T>::mma(ai, br, aI);
+    int i = 0;
+    while (u >= nt - i) {
+        u -= nt - i;
+        ++i;
+    }
+    I = i;
+    J = i + u;
 }
 
-// Lane fragments of rows [I*16, I*16+16) of an np x np operator: frag[f] = Op(I*16 + lane%16, 4f + lane/16).
-template <typename T, int NP>
-__device__ __forceinline__ void load_frag(const typename vec2<T>::type *__restrict__ op, int I, int lane,
-                                          typename vec2<T>::type (&frag)[NP / 4])
+// Index of (upper tile u, lane, accumulator slot v) in the stage vectors.
+__device__ __forceinline__ size_t uix(int u, int lane, int v) { return ((size_t)u * 64 + lane) * 4 + v; }
+
+// Weight of element (i, j) of upper tile (I, J) in a sum over the whole matrix: above the diagonal
+// it stands for itself and its mirror, on it for itself; the elements below the diagonal inside a
+// diagonal tile are represented by their mirrors.
+__device__ __forceinline__ double uweight(int I, int J, int i, int j)
 {
-    const typename vec2<T>::type *row = op + (size_t)(I * 16 + (lane & 15)) * NP + (lane >> 4);
-#pragma unroll
-    for (int f = 0; f < NP / 4; ++f) frag[f] = gld(row + 4 * f);
+    return I < J ? 2.0 : (i < j ? 2.0 : (i == j ? 1.0 : 0.0));
 }
+
+// Stage-vector values a lane's epilogue needs for one tile, loaded before the tile's products.
+template <typename V> struct StageIn {
+    V y[4], k1[4], kv[5][4], yn[4];
+};
 
 template <typename T, int NP, int WV> struct DenseRhs {
     using G = DenseGeom<T, NP, WV>;
     using V = typename vec2<T>::type;
     using Acc = typename Mfma<T>::acc;
-    static constexpr int S = G::S;
+    static constexpr int S = G::S, KF = G::KF;
 
-    // C = frag (rows of this wave) times the LDS matrix R (re, im planes), one 16x16 tile J.
-    static __device__ __forceinline__ void tile_mm(const V (&frag)[G::KF], const T *Rre, const T *Rim, int J,
-                                                   int lane, Acc &cR, Acc &cI)
+    // Op R^dag on one tile: Re = p, Im = q - n.
+    struct Acc3 {
+        Acc p, q, n;
+    };
+    static __device__ __forceinline__ Acc3 acc0()
     {
-        const int r16 = lane & 15, k4 = lane >> 4;
+        Acc3 a;
+        a.p = Acc{0, 0, 0, 0};
+        a.q = Acc{0, 0, 0, 0};
+        a.n = Acc{0, 0, 0, 0};
+        return a;
+    }
+
+    // Operator rows [16 I, 16 I + 16) over the lane's inner range: f[c] = Op(16 I + lane % 16,
+    // (lane / 16) KF + c); complex, or the real parts only (real operators).  The operators are
+    // stored in fragment order (dense_pack_ops), so each 16-byte load of the 64 lanes reads 1 KB
+    // of contiguous memory.
+    static __device__ __forceinline__ void frag(const V *__restrict__ op, int I, int lane, V (&f)[KF])
+    {
+        constexpr int E = 16 / (int)sizeof(V);  // complex elements per 16 bytes
+        const T *p = (const T *)(op + ((size_t)I * (KF / E) * 64 + lane) * E);
 #pragma unroll
-        for (int f = 0; f < G::KF; ++f) {
-            const int kr = (4 * f + k4) * S + J * 16 + r16;
-            cmma<T>(cR, cI, frag[f].x, frag[f].y, Rre[kr], Rim[kr]);
+        for (int ch = 0; ch < KF / E; ++ch) {
+            if constexpr (sizeof(T) == 4) {
+                const gf4 a = *(const QT_GLOBAL gf4 *)(p + ch * 64 * 4);
+                f[2 * ch] = make_float2(a.x, a.y);
+                f[2 * ch + 1] = make_float2(a.z, a.w);
+            } else {
+                f[ch] = gld((const V *)(p + ch * 64 * 2));
+            }
         }
     }
-    // Same with the right factor X^dag: X^dag(kk, j) = conj(X(j, kk)).
-    static __device__ __forceinline__ void tile_mm_dag(const V (&frag)[G::KF], const T *Xre, const T *Xim, int J,
-                                                       int lane, Acc &cR, Acc &cI)
+    static __device__ __forceinline__ void frag(const V *__restrict__ op, int I, int lane, T (&f)[KF])
     {
-        const int r16 = lane & 15, k4 = lane >> 4;
+        constexpr int E = 16 / (int)sizeof(T);  // real elements per 16 bytes
+        const T *p = (const T *)op + ((size_t)I * (KF / E) * 64 + lane) * E;
 #pragma unroll
-        for (int f = 0; f < G::KF; ++f) {
-            const int kr = (J * 16 + r16) * S + 4 * f + k4;
-            cmma<T>(cR, cI, frag[f].x, frag[f].y, Xre[kr], -Xim[kr]);
+        for (int ch = 0; ch < KF / E; ++ch) {
+            if constexpr (sizeof(T) == 4) {
+                const gf4 a = *(const QT_GLOBAL gf4 *)(p + ch * 64 * 4);
+                f[4 * ch] = a.x, f[4 * ch + 1] = a.y, f[4 * ch + 2] = a.z, f[4 * ch + 3] = a.w;
+            } else {
+                const gd2 a = *(const QT_GLOBAL gd2 *)(p + ch * 64 * 2);
+                f[2 * ch] = a.x, f[2 * ch + 1] = a.y;
+            }
         }
     }
-    static __device__ __forceinline__ void tile_store(T *Dre, T *Dim, int I, int J, int lane, const Acc &cR,
-                                                      const Acc &cI)
+    // Rows [16 J, 16 J + 16) of an LDS matrix over the lane's inner range, 16-byte reads.
+    static __device__ __forceinline__ void rows(const T *Rre, const T *Rim, int J, int lane, T (&rr)[KF],
+                                                T (&ri)[KF])
+    {
+        const int o = (J * 16 + (lane & 15)) * S + (lane >> 4) * KF;
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int c = 0; c < KF / 4; ++c) {
+                const lf4 a = *(const lf4 *)(Rre + o + 4 * c), b = *(const lf4 *)(Rim + o + 4 * c);
+                rr[4 * c] = a.x, rr[4 * c + 1] = a.y, rr[4 * c + 2] = a.z, rr[4 * c + 3] = a.w;
+                ri[4 * c] = b.x, ri[4 * c + 1] = b.y, ri[4 * c + 2] = b.z, ri[4 * c + 3] = b.w;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < KF / 2; ++c) {
+                const ld2 a = *(const ld2 *)(Rre + o + 2 * c), b = *(const ld2 *)(Rim + o + 2 * c);
+                rr[2 * c] = a.x, rr[2 * c + 1] = a.y;
+                ri[2 * c] = b.x, ri[2 * c + 1] = b.y;
+            }
+        }
+    }
+    // a += Op R^dag on one tile, complex or real operator.
+    static __device__ __forceinline__ void mm(const V (&f)[KF], const T (&rr)[KF], const T (&ri)[KF], Acc3 &a)
+    {
+#pragma unroll
+        for (int c = 0; c < KF; ++c) {
+            a.p = Mfma<T>::mma(f[c].x, rr[c], a.p);
+            a.q = Mfma<T>::mma(f[c].y, rr[c], a.q);
+            a.n = Mfma<T>::mma(f[c].x, ri[c], a.n);
+            a.p = Mfma<T>::mma(f[c].y, ri[c], a.p);
+        }
+    }
+    static __device__ __forceinline__ void mm(const T (&f)[KF], const T (&rr)[KF], const T (&ri)[KF], Acc3 &a)
+    {
+#pragma unroll
+        for (int c = 0; c < KF; ++c) {
+            a.p = Mfma<T>::mma(f[c], rr[c], a.p);
+            a.n = Mfma<T>::mma(f[c], ri[c], a.n);
+        }
+    }
+    // One tile into an LDS matrix.
+    static __device__ __forceinline__ void put(T *Dre, T *Dim, int I, int J, int lane, const Acc3 &a)
     {
         const int r16 = lane & 15, k4 = lane >> 4;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
-            Dre[i * S + j] = cR[v];
-            Dim[i * S + j] = cI[v];
+            Dre[i * S + j] = a.p[v];
+            Dim[i * S + j] = a.q[v] - a.n[v];
+        }
+    }
+    // The lane's 4 elements of upper tile (I, J) into B0 with their mirror images; inside a
+    // diagonal tile the elements below the diagonal are left to their mirrors and the diagonal
+    // is written real.
+    static __device__ __forceinline__ void put_b0(T *B0re, T *B0im, int I, int J, int lane, const V (&o)[4])
+    {
+        const int r16 = lane & 15, k4 = lane >> 4, j = J * 16 + r16;
+        if (I < J) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = I * 16 + mrow<T>(k4, v);
+                B0re[i * S + j] = o[v].x;
+                B0im[i * S + j] = o[v].y;
+            }
+            if constexpr (sizeof(T) == 4) {
+                const int m = j * S + I * 16 + 4 * k4;  // rows 4 k4 .. 4 k4 + 3 of the tile: contiguous
+                lf4 a, b;
+                a.x = o[0].x, a.y = o[1].x, a.z = o[2].x, a.w = o[3].x;
+                b.x = -o[0].y, b.y = -o[1].y, b.z = -o[2].y, b.w = -o[3].y;
+                *(lf4 *)(B0re + m) = a;
+                *(lf4 *)(B0im + m) = b;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = I * 16 + mrow<T>(k4, v);
+                    B0re[j * S + i] = o[v].x;
+                    B0im[j * S + i] = -o[v].y;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = I * 16 + mrow<T>(k4, v);
+                if (i < j) {
+                    B0re[i * S + j] = o[v].x;
+                    B0im[i * S + j] = o[v].y;
+                    B0re[j * S + i] = o[v].x;
+                    B0im[j * S + i] = -o[v].y;
+                } else if (i == j) {
+                    B0re[i * S + i] = o[v].x;
+                    B0im[i * S + i] = T(0);
+                }
+            }
         }
     }
 
-    // Evaluates L(B0) and calls epi(q, value[4]) for the elements this lane owns in tile q of the
-    // wave's chunk (accumulator slots 0..3, consecutive in tile order).  B1 holds C_k B0, B2 holds
-    // A B0.  With several collapse channels the running sum Z is kept per element in zbuf (tile
-    // order, global).
-    template <typename Epi>
-    static __device__ __forceinline__ void eval(const V *__restrict__ ops, int nc, T *lds, V *__restrict__ zbuf,
-                                                Epi &&epi)
+    // Phase 1: P = A B0 into B2 (WP) and X = C B0 into B1 (WX) on every tile; F is the fragment
+    // type of C (V complex, T real).  With both, the work is a list of jobs, P then X for each tile
+    // in row-major order, weighted by their matrix-core instructions (4 per inner step for the
+    // complex A, 2 or 4 for C); each wave takes the jobs whose start falls in its share of the total
+    // weight, and a tile whose two jobs fall to one wave has its rows of B0 read once for both.
+    template <bool WP, bool WX, typename F>
+    static __device__ __forceinline__ void phase1(const V *__restrict__ A, const V *__restrict__ C, T *lds)
     {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int t0 = G::chunk0(w), nq = G::chunk0(w + 1) - t0;
-        const int r16 = lane & 15, k4 = lane >> 4;
-        T *B0re = lds, *B0im = lds + G::PLANE, *B1re = lds + 2 * G::PLANE, *B1im = lds + 3 * G::PLANE;
+        const T *B0re = lds, *B0im = lds + G::PLANE;
+        T *B1re = lds + 2 * G::PLANE, *B1im = lds + 3 * G::PLANE;
         T *B2re = lds + 4 * G::PLANE, *B2im = lds + 5 * G::PLANE;
-        const size_t mat = (size_t)NP * NP;
-        const int kmax = nc > 0 ? nc : 1;
-        // Project the stage input onto its Hermitian part.  The products below are exact only for
-        // Hermitian rho; without this, rounding noise in the anti-Hermitian part would evolve under a
-        // generator with the dissipative terms' signs flipped and grow exponentially.  Each pair
-        // (i, j), i <= j, is handled by one thread.
-        for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
-            const int i = e / NP, j = e % NP;
-            if (i < j) {
-                const T ar = T(0.5) * (B0re[i * S + j] + B0re[j * S + i]);
-                const T ai = T(0.5) * (B0im[i * S + j] - B0im[j * S + i]);
-                B0re[i * S + j] = ar;
-                B0im[i * S + j] = ai;
-                B0re[j * S + i] = ar;
-                B0im[j * S + i] = -ai;
-            } else if (i == j) {
-                B0im[i * S + i] = T(0);
+        // jobs: 2 t (P of tile t) and 2 t + 1 (X of tile t); with one kind only, every other job
+        int j0, j1;
+        if constexpr (WP && WX) {
+            constexpr int wp = 4, wx = sizeof(F) == sizeof(T) ? 2 : 4, wt = wp + wx;
+            auto first_job = [](int ww) {
+                const int b = (ww * G::TILES * wt) / WV, t = b / wt, r = b % wt;
+                return 2 * t + (r == 0 ? 0 : (r <= wp ? 1 : 2));
+            };
+            j0 = first_job(w);
+            j1 = first_job(w + 1);
+        } else {
+            j0 = 2 * G::tile0(w) + (WP ? 0 : 1);
+            j1 = 2 * G::tile0(w + 1) + (WP ? 0 : 1);
+        }
+        V fa[KF];
+        F fc[KF];
+        int Ia = -1, Ic = -1;
+#pragma unroll 1
+        for (int j = j0; j < j1;) {
+            const int t = j >> 1, I = t / G::NT, J = t % G::NT;
+            const bool doP = WP && !(j & 1), doX = WX && ((j & 1) || j + 1 < j1);
+            if (WP && doP && I != Ia) {
+                frag(A, I, lane, fa);
+                Ia = I;
+            }
+            if (WX && doX && I != Ic) {
+                frag(C, I, lane, fc);
+                Ic = I;
+            }
+            T rr[KF], ri[KF];
+            rows(B0re, B0im, J, lane, rr, ri);
+            Acc3 a = acc0(), x = acc0();
+            if (doP && doX) {
+                mm(fa, rr, ri, a);
+                mm(fc, rr, ri, x);
+                put(B2re, B2im, I, J, lane, a);
+                put(B1re, B1im, I, J, lane, x);
+                j += 2;
+            } else if (doP) {
+                mm(fa, rr, ri, a);
+                put(B2re, B2im, I, J, lane, a);
+                j += WX ? 1 : 2;
+            } else {
+                mm(fc, rr, ri, x);
+                put(B1re, B1im, I, J, lane, x);
+                j += WP ? 1 : 2;
             }
         }
-        __syncthreads();
-        V frag[G::KF];
-        for (int k = 0; k < kmax; ++k) {
-            if (k == 0) {
-                // M = A B0 -> B2
-                int Icur = -1;
-#pragma unroll 1
-                for (int q = 0; q < nq; ++q) {
-                    const int t = t0 + q, I = t / G::NT, J = t % G::NT;
-                    if (I != Icur) {
-                        load_frag<T, NP>(ops, I, lane, frag);
-                        Icur = I;
-                    }
-                    Acc mR = {0, 0, 0, 0}, mI = {0, 0, 0, 0};
-                    tile_mm(frag, B0re, B0im, J, lane, mR, mI);
-                    tile_store(B2re, B2im, I, J, lane, mR, mI);
+    }
+
+    // Phase 2 on the wave's run of upper tiles: Z = C X^dag (X in B1; WZ), plus the running sum of
+    // the earlier channels from zbuf unless first.  Not last: the sum goes back to zbuf.  Last:
+    // L = Z + P + P^dag (P in B2) goes to the epilogue, whose stage-vector loads (eload) are issued
+    // before the tile's products.  (Issuing them one tile earlier, with two sets in flight, spilled
+    // registers and was slower.)
+    template <bool WZ, typename F, typename Ld, typename Ap>
+    static __device__ __forceinline__ void phase2(const V *__restrict__ C, bool first, bool last, T *lds,
+                                                  V *__restrict__ zbuf, Ld &eload, Ap &eapply)
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int r16 = lane & 15, k4 = lane >> 4;
+        const T *B1re = lds + 2 * G::PLANE, *B1im = lds + 3 * G::PLANE;
+        const T *B2re = lds + 4 * G::PLANE, *B2im = lds + 5 * G::PLANE;
+        const int u0 = G::utile0(w), u1 = G::utile0(w + 1);
+        F fc[KF];
+        int Icur = -1;
+        auto tile = [&](int u, const StageIn<V> &in) {
+            int I, J;
+            upper_tile(u, G::NT, I, J);
+            Acc3 z = acc0();
+            if constexpr (WZ) {
+                if (I != Icur) {
+                    frag(C, I, lane, fc);
+                    Icur = I;
                 }
+                T rr[KF], ri[KF];
+                rows(B1re, B1im, J, lane, rr, ri);
+                mm(fc, rr, ri, z);
             }
-            const V *Ck = ops + (1 + k) * mat;
-            int Icur = -1;
-            if (nc > 0) {
-                // X = C_k B0 -> B1
-#pragma unroll 1
-                for (int q = 0; q < nq; ++q) {
-                    const int t = t0 + q, I = t / G::NT, J = t % G::NT;
-                    if (I != Icur) {
-                        load_frag<T, NP>(Ck, I, lane, frag);
-                        Icur = I;
-                    }
-                    Acc xR = {0, 0, 0, 0}, xI = {0, 0, 0, 0};
-                    tile_mm(frag, B0re, B0im, J, lane, xR, xI);
-                    tile_store(B1re, B1im, I, J, lane, xR, xI);
-                }
+            V o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                o[v].x = z.p[v];
+                o[v].y = z.q[v] - z.n[v];
             }
-            __syncthreads();
-#pragma unroll 1
-            for (int q = 0; q < nq; ++q) {
-                const int t = t0 + q, I = t / G::NT, J = t % G::NT;
-                Acc zR = {0, 0, 0, 0}, zI = {0, 0, 0, 0};
-                if (nc > 0) {
-                    // fragments reloaded per tile: keeping them across the epilogue would take
-                    // the registers its loads need to be in flight together
-                    V fz[G::KF];
-                    load_frag<T, NP>(Ck, I, lane, fz);
-                    tile_mm_dag(fz, B1re, B1im, J, lane, zR, zI);  // Z_k = C_k X_k^dag
-                }
-                const size_t zb = tix(t, lane, 0);
-                V z[4];
+            const size_t e = uix(u, lane, 0);
+            if (!first) {
+                V zp[4];
+                gld4(zbuf + e, zp);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = cadd(o[v], zp[v]);
+            }
+            if (!last) {
+                gst4(zbuf + e, o);
+                return;
+            }
+            // + P + P^dag: P(i, j) for the lane's elements, and P(j, i) from row j
+            const int j = J * 16 + r16;
+            T tr[4], ti[4];
+            if constexpr (sizeof(T) == 4) {
+                const int m = j * S + I * 16 + 4 * k4;
+                const lf4 a = *(const lf4 *)(B2re + m), b = *(const lf4 *)(B2im + m);
+                tr[0] = a.x, tr[1] = a.y, tr[2] = a.z, tr[3] = a.w;
+                ti[0] = b.x, ti[1] = b.y, ti[2] = b.z, ti[3] = b.w;
+            } else {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    z[v].x = zR[v];
-                    z[v].y = zI[v];
-                }
-                if (k > 0) {
-                    V zp[4];
-                    gld4(zbuf + zb, zp);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) z[v] = cadd(z[v], zp[v]);
-                }
-                if (k + 1 < kmax) {
-                    gst4(zbuf + zb, z);
-                } else {
-                    V o[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = I * 16 + mrow<T>(k4, v), j = J * 16 + r16;
-                        o[v].x = z[v].x + B2re[i * S + j] + B2re[j * S + i];
-                        o[v].y = z[v].y + B2im[i * S + j] - B2im[j * S + i];
-                    }
-                    epi(q, o);
+                    const int i = I * 16 + mrow<T>(k4, v);
+                    tr[v] = B2re[j * S + i];
+                    ti[v] = B2im[j * S + i];
                 }
             }
-            if (k + 1 < kmax) __syncthreads();  // B1 is rewritten by the next channel
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = I * 16 + mrow<T>(k4, v);
+                o[v].x = o[v].x + B2re[i * S + j] + tr[v];
+                o[v].y = o[v].y + B2im[i * S + j] - ti[v];
+            }
+            eapply(u, I, J, in, o);
+        };
+#pragma unroll 1
+        for (int u = u0; u < u1; ++u) {
+            StageIn<V> in;
+            if (last) eload(u, in);
+            tile(u, in);
+        }
+    }
+
+    // Evaluates L(B0) (B0 Hermitian) and hands the upper-tile elements to the epilogue:
+    // eload(u, in) fills the stage-vector values, eapply(u, I, J, in, o) receives L.  nc collapse
+    // channels; bit k of creal marks C_k real.  With several channels the running sum of
+    // C_k X_k^dag is kept in zbuf (upper-tile order, global).  Ends without a barrier: the caller
+    // synchronises before B0, B1 or B2 are read again.
+    template <typename Ld, typename Ap>
+    static __device__ __forceinline__ void eval(const V *__restrict__ ops, int nc, uint32_t creal, T *lds,
+                                                V *__restrict__ zbuf, Ld &&eload, Ap &&eapply)
+    {
+        const size_t mat = (size_t)NP * NP;
+        if (nc == 0) {
+            phase1<true, false, V>(ops, nullptr, lds);
+            __syncthreads();
+            phase2<false, V>(nullptr, true, true, lds, zbuf, eload, eapply);
+            return;
+        }
+        for (int k = 0; k < nc; ++k) {
+            const V *Ck = ops + (1 + k) * mat;
+            const bool cr = k < 32 && ((creal >> k) & 1u);
+            if (k > 0) __syncthreads();  // the previous channel's X is read until here
+            if (k == 0) {
+                if (cr) phase1<true, true, T>(ops, Ck, lds);
+                else phase1<true, true, V>(ops, Ck, lds);
+            } else {
+                if (cr) phase1<false, true, T>(ops, Ck, lds);
+                else phase1<false, true, V>(ops, Ck, lds);
+            }
+            __syncthreads();
+            if (cr) phase2<true, T>(Ck, k == 0, k + 1 == nc, lds, zbuf, eload, eapply);
+            else phase2<true, V>(Ck, k == 0, k + 1 == nc, lds, zbuf, eload, eapply);
         }
     }
 };
 
 template <typename T, int NP, int WV>
 __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__restrict__ insts,
-                                                                      DenseCtl *__restrict__ ctls,
-                                                                      const int32_t *__restrict__ order,
-                                                                      int max_steps_launch, int reset)
+                                                         DenseCtl *__restrict__ ctls,
+                                                         const int32_t *__restrict__ order,
+                                                         int max_steps_launch, int reset)
 {
     using G = DenseGeom<T, NP, WV>;
     using V = typename vec2<T>::type;
     using R = DenseRhs<T, NP, WV>;
+    using In = StageIn<V>;
     constexpr int S = G::S;
-    extern __shared__ char smem[];
+    extern __shared__ __align__(16) char smem[];
     T *lds = (T *)smem;
-    __shared__ double scr[16];
+    __shared__ double scr[48];
     T *B0re = lds, *B0im = lds + G::PLANE;
 
     const int ii = order[blockIdx.x];
-    const DenseInst &I = insts[ii];
+    const DenseInst &g = insts[ii];
     DenseCtl *C = ctls + ii;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r16 = lane & 15, k4 = lane >> 4;
-    const int t0 = G::chunk0(w), nq = G::chunk0(w + 1) - t0;  // this wave's tiles: t0 .. t0 + nq - 1
-    const int d = I.d;
+    const int u0 = G::utile0(w), u1 = G::utile0(w + 1);  // this wave's upper tiles
+    const int d = g.d;
+    const uint32_t creal = (uint32_t)g.creal;
     const size_t nvec = (size_t)NP * NP;
-    V *vec = (V *)I.vec;
+    V *vec = (V *)g.vec;
     V *Yb[2] = {vec, vec + nvec};
     V *Kb[2] = {vec + 2 * nvec, vec + 3 * nvec};
     V *ks[5] = {vec + 4 * nvec, vec + 5 * nvec, vec + 6 * nvec, vec + 7 * nvec, vec + 8 * nvec};
     V *zbuf = vec + 9 * nvec;  // running sum over collapse channels (used when nc > 1)
-    const V *ops = (const V *)I.ops;
+    const V *ops = (const V *)g.ops;
     const double nd = (double)d * d;
 
-    // element (q, v) of this lane: tile-order index and (row, column)
-    auto eidx = [&](int q, int v) { return tix(t0 + q, lane, v); };
-    auto erow = [&](int q, int v) { return ((t0 + q) / G::NT) * 16 + mrow<T>(k4, v); };
-    auto ecol = [&](int q) { return ((t0 + q) % G::NT) * 16 + r16; };
     auto record_expect = [&](int idx, double sc) {
-        for (int k = 0; k < I.ne; ++k) {
-            const int32_t *ep = I.eptr + (size_t)k * (d + 1);
+        for (int k = 0; k < g.ne; ++k) {
+            const int32_t *ep = g.eptr + (size_t)k * (d + 1);
             double sr = 0.0, si = 0.0;
             for (int i = threadIdx.x; i < d; i += blockDim.x)
                 for (int p = gld(ep + i), pe = gld(ep + i + 1); p < pe; ++p) {
-                    const double2 o = gld(I.eval + p);
-                    const int j = gld(I.ecol + p);
+                    const double2 o = gld(g.eval + p);
+                    const int j = gld(g.ecol + p);
                     const double rr = (double)B0re[j * S + i], ri = (double)B0im[j * S + i];
                     sr += o.x * rr - o.y * ri;
                     si += o.x * ri + o.y * rr;
                 }
-            sr = block_sum(sr, scr);
-            si = block_sum(si, scr);
-            if (threadIdx.x == 0) gst(I.expect + (size_t)k * I.nt + idx, make_double2(sr * sc, si * sc));
+            double v2[2] = {sr, si};
+            block_sum_n<2>(v2, scr);
+            if (threadIdx.x == 0) gst(g.expect + (size_t)k * g.nt + idx, make_double2(v2[0] * sc, v2[1] * sc));
         }
     };
     auto trace_b0 = [&]() {
@@ -368,23 +533,29 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
     int64_t n_accept, n_reject, n_steps, n_rhs;
 
     if (reset || C->status == DENSE_ST_INIT) {
-        // ---- initial state into B0 (planar, zero padded) and Y[0] (tile order) ----
-        const V *r0 = (const V *)I.rho0;
-        for (int q = 0; q < G::MAXJ; ++q) {
-            if (q >= nq) break;
+        // ---- initial state: its Hermitian part, into Y[0] (upper tiles) and B0 ----
+        const V *r0 = (const V *)g.rho0;
+        for (int u = u0; u < u1; ++u) {
+            int TI, TJ;
+            upper_tile(u, G::NT, TI, TJ);
+            V o[4];
+#pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = erow(q, v), j = ecol(q);
-                V y;
-                y.x = 0;
-                y.y = 0;
-                if (i < d && j < d) y = gld(r0 + (size_t)i * d + j);
-                gst(Yb[0] + eidx(q, v), y);
-                B0re[i * S + j] = y.x;
-                B0im[i * S + j] = y.y;
+                const int i = TI * 16 + mrow<T>(k4, v), j = TJ * 16 + r16;
+                V a, b;
+                a.x = a.y = b.x = b.y = T(0);
+                if (i < d && j < d) {
+                    a = gld(r0 + (size_t)i * d + j);
+                    b = gld(r0 + (size_t)j * d + i);
+                }
+                o[v].x = T(0.5) * (a.x + b.x);
+                o[v].y = T(0.5) * (a.y - b.y);
             }
+            gst4(Yb[0] + uix(u, lane, 0), o);
+            R::put_b0(B0re, B0im, TI, TJ, lane, o);
         }
         __syncthreads();
-        t = gld(I.tlist);
+        t = gld(g.tlist);
         err_prev = 1e-4;
         scale = 1.0;
         save_idx = 1;
@@ -395,63 +566,65 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
         status = ST_RUNNING;
         tr0 = trace_b0();
         record_expect(0, 1.0);
-        if (I.nt <= 1) status = ST_DONE;
+        if (g.nt <= 1) status = ST_DONE;
         h = 0.0;
         if (status == ST_RUNNING) {
             // k1 = L(y0); starting step from d0 = |y0|, d1 = |k1|, d2 = |f(y0 + h0 k1) - k1| / h0
-            double s0 = 0.0, s1 = 0.0;
-            R::eval(ops, I.nc, lds, zbuf, [&](int q, const V (&a)[4]) {
-                const size_t e = eidx(q, 0);
-                V y0[4];
-                gld4(Yb[0] + e, y0);
-                gst4(Kb[0] + e, a);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const double ya = sqrt(abs2d(y0[v]));
-                    const double sc = I.atol + I.rtol * ya;
-                    s0 += ya * ya / (sc * sc);
-                    s1 += abs2d(a[v]) / (sc * sc);
-                }
-            });
-            n_rhs += 1;
-            s0 = block_sum(s0, scr);
-            s1 = block_sum(s1, scr);
-            const double d0 = sqrt(s0 / nd), d1 = sqrt(s1 / nd);
-            if (I.use_h0) {
-                h = I.h0;
-            } else {
-                const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-                for (int q = 0; q < G::MAXJ; ++q) {
-                    if (q >= nq) break;
-                    V y0[4], f0[4];
-                    gld4(Yb[0] + eidx(q, 0), y0);
-                    gld4(Kb[0] + eidx(q, 0), f0);
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = erow(q, v), j = ecol(q);
-                        V y = y0[v];
-                        caxpy(y, (T)h0, f0[v]);
-                        B0re[i * S + j] = y.x;
-                        B0im[i * S + j] = y.y;
-                    }
-                }
-                __syncthreads();
-                double s2 = 0.0;
-                R::eval(ops, I.nc, lds, zbuf, [&](int q, const V (&a)[4]) {
-                    const size_t e = eidx(q, 0);
-                    V y0[4], k0[4];
-                    gld4(Kb[0] + e, k0);
-                    gld4(Yb[0] + e, y0);
+            double s01[2] = {0.0, 0.0};
+            R::eval(
+                ops, g.nc, creal, lds, zbuf, [&](int u, In &in) { gld4(Yb[0] + uix(u, lane, 0), in.y); },
+                [&](int u, int TI, int TJ, const In &in, const V (&a)[4]) {
+                    gst4(Kb[0] + uix(u, lane, 0), a);
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const double2 f1 = to_d2(a[v]), f0 = to_d2(k0[v]);
-                        const double sc = I.atol + I.rtol * sqrt(abs2d(y0[v]));
-                        const double dx = (f1.x - f0.x) / h0, dy = (f1.y - f0.y) / h0;
-                        s2 += (dx * dx + dy * dy) / (sc * sc);
+                        const double wt = uweight(TI, TJ, TI * 16 + mrow<T>(k4, v), TJ * 16 + r16);
+                        const double ya = sqrt(abs2d(in.y[v]));
+                        const double sc = g.atol + g.rtol * ya;
+                        s01[0] += wt * (ya * ya / (sc * sc));
+                        s01[1] += wt * (abs2d(a[v]) / (sc * sc));
                     }
                 });
+            n_rhs += 1;
+            block_sum_n<2>(s01, scr);
+            const double d0 = sqrt(s01[0] / nd), d1 = sqrt(s01[1] / nd);
+            if (g.use_h0) {
+                h = g.h0;
+            } else {
+                const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+                for (int u = u0; u < u1; ++u) {
+                    int TI, TJ;
+                    upper_tile(u, G::NT, TI, TJ);
+                    V y0[4], f0[4], o[4];
+                    gld4(Yb[0] + uix(u, lane, 0), y0);
+                    gld4(Kb[0] + uix(u, lane, 0), f0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        o[v] = y0[v];
+                        caxpy(o[v], (T)h0, f0[v]);
+                    }
+                    R::put_b0(B0re, B0im, TI, TJ, lane, o);
+                }
+                __syncthreads();
+                double s2[1] = {0.0};
+                R::eval(
+                    ops, g.nc, creal, lds, zbuf,
+                    [&](int u, In &in) {
+                        gld4(Kb[0] + uix(u, lane, 0), in.k1);
+                        gld4(Yb[0] + uix(u, lane, 0), in.y);
+                    },
+                    [&](int u, int TI, int TJ, const In &in, const V (&a)[4]) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const double wt = uweight(TI, TJ, TI * 16 + mrow<T>(k4, v), TJ * 16 + r16);
+                            const double2 f1 = to_d2(a[v]), f0 = to_d2(in.k1[v]);
+                            const double sc = g.atol + g.rtol * sqrt(abs2d(in.y[v]));
+                            const double dx = (f1.x - f0.x) / h0, dy = (f1.y - f0.y) / h0;
+                            s2[0] += wt * ((dx * dx + dy * dy) / (sc * sc));
+                        }
+                    });
                 n_rhs += 1;
-                s2 = block_sum(s2, scr);
-                const double d2 = sqrt(s2 / nd);
+                block_sum_n<1>(s2, scr);
+                const double d2 = sqrt(s2[0] / nd);
                 const double m = fmax(d1, d2);
                 const double h1 = (m <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / m, 0.2);
                 h = fmin(100.0 * h0, h1);
@@ -477,60 +650,61 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
     while (status == ST_RUNNING && budget != 0) {
         if (budget > 0) --budget;
         int32_t land;
-        const double ht = clip_step(t, h, gld(I.tlist + save_idx), &land);
+        const double ht = clip_step(t, h, gld(g.tlist + save_idx), &land);
         const T sc = (T)scale;
         V *y = Yb[parity], *ynew = Yb[1 - parity], *k1 = Kb[parity], *k7 = Kb[1 - parity];
         // stage-2 input: y + h a21 k1
         __syncthreads();
-        for (int q = 0; q < G::MAXJ; ++q) {
-            if (q >= nq) break;
-            V yv[4], kv[4];
-            gld4(y + eidx(q, 0), yv);
-            gld4(k1 + eidx(q, 0), kv);
+        for (int u = u0; u < u1; ++u) {
+            int TI, TJ;
+            upper_tile(u, G::NT, TI, TJ);
+            V yv[4], kv[4], o[4];
+            gld4(y + uix(u, lane, 0), yv);
+            gld4(k1 + uix(u, lane, 0), kv);
+#pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = erow(q, v), j = ecol(q);
-                V x = cscale(yv[v], sc);
-                caxpy(x, (T)(ht * DP5::a21), cscale(kv[v], sc));
-                B0re[i * S + j] = x.x;
-                B0im[i * S + j] = x.y;
+                o[v] = cscale(yv[v], sc);
+                caxpy(o[v], (T)(ht * DP5::a21), cscale(kv[v], sc));
             }
+            R::put_b0(B0re, B0im, TI, TJ, lane, o);
         }
         __syncthreads();
-        double e2 = 0.0, l2 = 0.0;  // error norm; |L y_new|^2 (steady-state mode)
+        // error norm; |L y_new|^2 (steady-state mode); trace of y_new (from the stage-7 input)
+        double acc3[3] = {0.0, 0.0, 0.0};
         for (int s = 2; s <= 7; ++s) {
-            R::eval(ops, I.nc, lds, zbuf, [&](int q, const V (&a)[4]) {
-                // Two elements at a time: every load of the pair first (the stores below go to
-                // other vectors, which the compiler cannot tell apart), then the combination, then
-                // the stores.  Pairs keep the loads in flight within the register budget.
-#pragma unroll 1
-                for (int p0 = 0; p0 < 4; p0 += 2) {
-                    const size_t e = eidx(q, p0);
-                    V yv[2], k1v[2], kv0[2], kv1[2], kv2[2], kv3[2], kv4[2], o[2];
-                    gld2(y + e, yv);
-                    gld2(k1 + e, k1v);
-                    if (s >= 3 && s <= 5) gld2(ks[0] + e, kv0);
-                    if (s >= 4) gld2(ks[1] + e, kv1);
-                    if (s >= 5) gld2(ks[2] + e, kv2);
-                    if (s >= 6) gld2(ks[3] + e, kv3);
+            R::eval(
+                ops, g.nc, creal, lds, zbuf,
+                [&](int u, In &in) {
+                    const size_t e = uix(u, lane, 0);
+                    gld4(y + e, in.y);
+                    gld4(k1 + e, in.k1);
+                    if (s >= 3 && s <= 5) gld4(ks[0] + e, in.kv[0]);
+                    if (s >= 4) gld4(ks[1] + e, in.kv[1]);
+                    if (s >= 5) gld4(ks[2] + e, in.kv[2]);
+                    if (s >= 6) gld4(ks[3] + e, in.kv[3]);
                     if (s == 7) {
-                        gld2(ks[4] + e, kv4);
-                        gld2(ynew + e, o);  // the candidate y_new, for the error weights
+                        gld4(ks[4] + e, in.kv[4]);
+                        gld4(ynew + e, in.yn);  // the candidate y_new, for the error weights
                     }
-                    const V ap[2] = {p0 == 0 ? a[0] : a[2], p0 == 0 ? a[1] : a[3]};
+                },
+                [&](int u, int TI, int TJ, const In &in, const V (&ap)[4]) {
+                    const size_t e = uix(u, lane, 0);
+                    V o[4];
 #pragma unroll
-                    for (int v = 0; v < 2; ++v) {
-                        const V yr = cscale(yv[v], sc), k1r = cscale(k1v[v], sc);
+                    for (int v = 0; v < 4; ++v) {
+                        const V yr = cscale(in.y[v], sc), k1r = cscale(in.k1[v], sc);
                         if (s == 7) {
+                            const double wt = uweight(TI, TJ, TI * 16 + mrow<T>(k4, v), TJ * 16 + r16);
                             double2 er = make_double2(0.0, 0.0);
                             caxpy(er, ht * DP5::e1, to_d2(k1r));
-                            caxpy(er, ht * DP5::e3, to_d2(kv1[v]));
-                            caxpy(er, ht * DP5::e4, to_d2(kv2[v]));
-                            caxpy(er, ht * DP5::e5, to_d2(kv3[v]));
-                            caxpy(er, ht * DP5::e6, to_d2(kv4[v]));
+                            caxpy(er, ht * DP5::e3, to_d2(in.kv[1][v]));
+                            caxpy(er, ht * DP5::e4, to_d2(in.kv[2][v]));
+                            caxpy(er, ht * DP5::e5, to_d2(in.kv[3][v]));
+                            caxpy(er, ht * DP5::e6, to_d2(in.kv[4][v]));
                             caxpy(er, ht * DP5::e7, to_d2(ap[v]));
-                            const double scl = I.atol + I.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(o[v])));
-                            e2 += (er.x * er.x + er.y * er.y) / (scl * scl);
-                            l2 += abs2d(ap[v]);
+                            const double scl = g.atol + g.rtol * fmax(sqrt(abs2d(yr)), sqrt(abs2d(in.yn[v])));
+                            acc3[0] += wt * ((er.x * er.x + er.y * er.y) / (scl * scl));
+                            acc3[1] += wt * abs2d(ap[v]);
                             continue;
                         }
                         o[v] = yr;
@@ -539,47 +713,45 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
                             caxpy(o[v], (T)(ht * DP5::a32), ap[v]);
                         } else if (s == 3) {
                             caxpy(o[v], (T)(ht * DP5::a41), k1r);
-                            caxpy(o[v], (T)(ht * DP5::a42), kv0[v]);
+                            caxpy(o[v], (T)(ht * DP5::a42), in.kv[0][v]);
                             caxpy(o[v], (T)(ht * DP5::a43), ap[v]);
                         } else if (s == 4) {
                             caxpy(o[v], (T)(ht * DP5::a51), k1r);
-                            caxpy(o[v], (T)(ht * DP5::a52), kv0[v]);
-                            caxpy(o[v], (T)(ht * DP5::a53), kv1[v]);
+                            caxpy(o[v], (T)(ht * DP5::a52), in.kv[0][v]);
+                            caxpy(o[v], (T)(ht * DP5::a53), in.kv[1][v]);
                             caxpy(o[v], (T)(ht * DP5::a54), ap[v]);
                         } else if (s == 5) {
                             caxpy(o[v], (T)(ht * DP5::a61), k1r);
-                            caxpy(o[v], (T)(ht * DP5::a62), kv0[v]);
-                            caxpy(o[v], (T)(ht * DP5::a63), kv1[v]);
-                            caxpy(o[v], (T)(ht * DP5::a64), kv2[v]);
+                            caxpy(o[v], (T)(ht * DP5::a62), in.kv[0][v]);
+                            caxpy(o[v], (T)(ht * DP5::a63), in.kv[1][v]);
+                            caxpy(o[v], (T)(ht * DP5::a64), in.kv[2][v]);
                             caxpy(o[v], (T)(ht * DP5::a65), ap[v]);
                         } else {
                             caxpy(o[v], (T)(ht * DP5::b1), k1r);
-                            caxpy(o[v], (T)(ht * DP5::b3), kv1[v]);
-                            caxpy(o[v], (T)(ht * DP5::b4), kv2[v]);
-                            caxpy(o[v], (T)(ht * DP5::b5), kv3[v]);
+                            caxpy(o[v], (T)(ht * DP5::b3), in.kv[1][v]);
+                            caxpy(o[v], (T)(ht * DP5::b4), in.kv[2][v]);
+                            caxpy(o[v], (T)(ht * DP5::b5), in.kv[3][v]);
                             caxpy(o[v], (T)(ht * DP5::b6), ap[v]);
+                            const int i = TI * 16 + mrow<T>(k4, v), j = TJ * 16 + r16;
+                            if (i == j) acc3[2] += (double)o[v].x;  // trace of y_new as B0 holds it
                         }
-                        const int i = erow(q, p0 + v), j = ecol(q);
-                        B0re[i * S + j] = o[v].x;
-                        B0im[i * S + j] = o[v].y;
                     }
                     if (s == 7) {
-                        gst2(k7 + e, ap[0], ap[1]);
+                        gst4(k7 + e, ap);
                     } else {
-                        gst2(vec + (size_t)(2 + s) * nvec + e, ap[0], ap[1]);  // k_s (ks[s - 2])
-                        if (s == 6) gst2(ynew + e, o[0], o[1]);
+                        gst4(ks[s - 2] + e, ap);
+                        if (s == 6) gst4(ynew + e, o);
+                        R::put_b0(B0re, B0im, TI, TJ, lane, o);
                     }
-                }
-            });
+                });
             __syncthreads();
         }
         n_rhs += 6;
         ++n_steps;
         // B0 now holds y_new (the stage-7 input)
-        e2 = block_sum(e2, scr);
-        const bool steady = I.steady_tol2 > 0.0;
-        if (steady) l2 = block_sum(l2, scr);
-        const double err = sqrt(e2 / nd);
+        block_sum_n<3>(acc3, scr);
+        const bool steady = g.steady_tol2 > 0.0;
+        const double err = sqrt(acc3[0] / nd);
         if (!isfinite(err)) {
             status = 6;  // QT_ENONFINITE
             break;
@@ -587,16 +759,16 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
         if (err <= 1.0) {
             ++n_accept;
             double sc_new = 1.0;
-            if (I.renorm) sc_new = tr0 / trace_b0();
+            if (g.renorm) sc_new = tr0 / acc3[2];
             // steady-state mode: |L y_new|_2 at or below the tolerance ends the solve, and every
             // remaining save time receives the expectation values of the converged state
-            const bool conv = steady && l2 * sc_new * sc_new <= I.steady_tol2;
+            const bool conv = steady && acc3[1] * sc_new * sc_new <= g.steady_tol2;
             if (conv) {
-                for (int k = save_idx; k < I.nt; ++k) record_expect(k, sc_new);
+                for (int k = save_idx; k < g.nt; ++k) record_expect(k, sc_new);
             } else if (land) {
                 record_expect(save_idx, sc_new);
             }
-            t = land ? gld(I.tlist + save_idx) : t + ht;
+            t = land ? gld(g.tlist + save_idx) : t + ht;
             parity = 1 - parity;
             double hn = ht * pi_factor(err, err_prev);
             if (last_rejected && hn > ht) hn = ht;
@@ -605,11 +777,11 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
             last_rejected = 0;
             scale = sc_new;
             if (conv) {
-                save_idx = I.nt;
+                save_idx = g.nt;
                 status = ST_DONE;
             } else if (land) {
                 ++save_idx;
-                if (save_idx >= I.nt) status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS: not converged
+                if (save_idx >= g.nt) status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS: not converged
             }
         } else {
             ++n_reject;
@@ -617,7 +789,7 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
             last_rejected = 1;
         }
         if (status == ST_RUNNING) {
-            if (n_steps >= I.max_steps) status = 4;  // QT_EMAXSTEPS
+            if (n_steps >= g.max_steps) status = 4;  // QT_EMAXSTEPS
             else if (h < 1e-14 * fmax(1.0, fabs(t))) status = 5;  // QT_EDTMIN
         }
     }
@@ -641,7 +813,7 @@ __global__ __launch_bounds__(WV * 64) void k_dense_solve(const DenseInst *__rest
 // ---------------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------------
-void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *ops, const void *rho0, void *vec,
+void dense_fill_inst(DenseInst *g, int d, int nc, uint32_t creal, int nt, int ne, const void *ops, const void *rho0, void *vec,
                      const double *tlist, const int32_t *eptr, const int32_t *ecol, const double2 *eval,
                      double2 *expect, const qt_opts &opts, int prec)
 {
@@ -652,7 +824,7 @@ void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *op
     g->ne = ne;
     g->use_h0 = opts.h0 > 0 ? 1 : 0;
     g->renorm = prec == QT_MIXED ? 1 : 0;
-    g->pad = 0;
+    g->creal = (int32_t)creal;
     g->atol = opts.abstol;
     g->rtol = opts.reltol;
     g->h0 = opts.h0;
@@ -666,6 +838,34 @@ void dense_fill_inst(DenseInst *g, int d, int nc, int nt, int ne, const void *op
     g->eval = eval;
     g->expect = expect;
     g->steady_tol2 = 0.0;
+}
+
+// Operators in fragment order: for tile row I, 16-byte chunk ch and lane l, the E elements
+// Op(16 I + l % 16, (l / 16) np / 4 + ch E + e), e < E, with E = 16 bytes / element size; a real
+// collapse operator C_k (bit k of creal) keeps only its real parts, packed the same way.
+void dense_pack_ops(const double2 *rowmajor, int np, int nops, uint32_t creal, int prec, std::vector<char> &out)
+{
+    const bool f64 = prec == QT_F64;
+    const size_t es = f64 ? sizeof(double2) : sizeof(float2), mat = (size_t)np * np;
+    const int kf = np / 4;
+    out.assign((size_t)nops * mat * es, 0);
+    for (int o = 0; o < nops; ++o) {
+        const double2 *M = rowmajor + (size_t)o * mat;
+        char *base = out.data() + (size_t)o * mat * es;
+        const bool real = o > 0 && o - 1 < 32 && ((creal >> (o - 1)) & 1u);
+        const int E = real ? (f64 ? 2 : 4) : (f64 ? 1 : 2);
+        for (int I = 0; I < np / 16; ++I)
+            for (int ch = 0; ch < kf / E; ++ch)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < E; ++e) {
+                        const double2 v = M[(size_t)(I * 16 + (l & 15)) * np + (l >> 4) * kf + ch * E + e];
+                        const size_t idx = (((size_t)I * (kf / E) + ch) * 64 + l) * E + e;
+                        if (real && f64) ((double *)base)[idx] = v.x;
+                        else if (real) ((float *)base)[idx] = (float)v.x;
+                        else if (f64) ((double2 *)base)[idx] = v;
+                        else ((float2 *)base)[idx] = make_float2((float)v.x, (float)v.y);
+                    }
+    }
 }
 
 // Wave counts built per padded size.  With one wave per tile row a size whose tile-row count is not
@@ -773,26 +973,33 @@ void dense_launch_bucket(int np, bool f64, int waves, const DenseInst *insts, De
 
 void dense_unpack(const void *host_vec, int d, int prec, double scale, double *out)
 {
+    // upper tiles in row-major order; (tile, lane, slot) -> element as the kernel's accumulators
     const int np = dense_np(d), nt = np / 16;
-    for (int t = 0; t < nt * nt; ++t)
-        for (int lane = 0; lane < 64; ++lane)
-            for (int v = 0; v < 4; ++v) {
-                const int q4 = lane >> 4;
-                const int i = (t / nt) * 16 + (prec == QT_F64 ? q4 + 4 * v : 4 * q4 + v);
-                const int j = (t % nt) * 16 + (lane & 15);
-                if (i >= d || j >= d) continue;
-                const size_t e = ((size_t)t * 64 + lane) * 4 + v;
-                double re, im;
-                if (prec == QT_F64) {
-                    re = ((const double *)host_vec)[2 * e];
-                    im = ((const double *)host_vec)[2 * e + 1];
-                } else {
-                    re = ((const float *)host_vec)[2 * e];
-                    im = ((const float *)host_vec)[2 * e + 1];
+    int u = 0;
+    for (int I = 0; I < nt; ++I)
+        for (int J = I; J < nt; ++J, ++u)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int v = 0; v < 4; ++v) {
+                    const int q4 = lane >> 4;
+                    const int i = I * 16 + (prec == QT_F64 ? q4 + 4 * v : 4 * q4 + v);
+                    const int j = J * 16 + (lane & 15);
+                    if (i > j || j >= d) continue;  // below the diagonal: the mirror of (j, i)
+                    const size_t e = ((size_t)u * 64 + lane) * 4 + v;
+                    double re, im;
+                    if (prec == QT_F64) {
+                        re = ((const double *)host_vec)[2 * e];
+                        im = ((const double *)host_vec)[2 * e + 1];
+                    } else {
+                        re = ((const float *)host_vec)[2 * e];
+                        im = ((const float *)host_vec)[2 * e + 1];
+                    }
+                    out[2 * ((size_t)i * d + j)] = re * scale;
+                    out[2 * ((size_t)i * d + j) + 1] = im * scale;
+                    if (i != j) {
+                        out[2 * ((size_t)j * d + i)] = re * scale;
+                        out[2 * ((size_t)j * d + i) + 1] = -im * scale;
+                    }
                 }
-                out[2 * ((size_t)i * d + j)] = re * scale;
-                out[2 * ((size_t)i * d + j) + 1] = im * scale;
-            }
 }
 
 }  // namespace qt

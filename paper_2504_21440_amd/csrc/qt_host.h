@@ -86,8 +86,10 @@ struct Liouv {
     int32_t *rowptr = nullptr;
     int32_t *col = nullptr;
     void *val = nullptr;
-    // dense form: A then C_k, each d x d row-major, in the solve precision
+    // dense form: A then C_k, each d x d row-major, in the solve precision; bit k of dense_creal
+    // set when C_k is real
     void *dense = nullptr;
+    uint32_t dense_creal = 0;
     // time dependence (CSR form): column tags 1..nterms select the coefficient of each entry
     int32_t nterms = 0;
     void *coefs = nullptr;  // device: CoefDev[nterms] followed by their sample tables

@@ -409,8 +409,8 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             }
         } else {
             DenseInst &g = di[m.slot];
-            dense_fill_inst(&g, m.d, m.L->nc, m.nt, m.ne, m.L->dense, A.at(m.o_rho0), A.at(m.o_vec),
-                            (const double *)A.at(m.o_tlist), (const int32_t *)A.at(m.o_eptr),
+            dense_fill_inst(&g, m.d, m.L->nc, m.L->dense_creal, m.nt, m.ne, m.L->dense, A.at(m.o_rho0),
+                            A.at(m.o_vec), (const double *)A.at(m.o_tlist), (const int32_t *)A.at(m.o_eptr),
                             (const int32_t *)A.at(m.o_ecol), (const double2 *)A.at(m.o_eval),
                             (double2 *)A.at(m.o_expect), opts, P->prec);
             g.steady_tol2 = steady_tol * steady_tol;

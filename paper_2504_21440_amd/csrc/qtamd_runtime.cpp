@@ -547,19 +547,21 @@ qt_status qt_liouvillian_build(qt_ctx *ctx, const qt_csr *H, int32_t n_c, const 
         };
         put(A, 0);
         for (int k = 0; k < n_c; ++k) put(cs[k], (1 + k) * mat);
-        L->bytes = (int64_t)(host.size() * es);
+        L->dense_creal = 0;
+        for (int k = 0; k < n_c && k < 32; ++k) {
+            bool real = true;
+            for (const cd &v : cs[k].val) real = real && v.imag() == 0.0;
+            if (real) L->dense_creal |= 1u << k;
+        }
+        std::vector<char> packed;
+        dense_pack_ops(host.data(), np, 1 + n_c, L->dense_creal, precision, packed);
+        L->bytes = (int64_t)packed.size();
         hipError_t e = hipMalloc(&L->dense, L->bytes);
         if (e != hipSuccess) {
             delete L;
             return set_error(QT_ENOMEM, "hipMalloc dense operators");
         }
-        if (precision == QT_F64) {
-            e = hipMemcpy(L->dense, host.data(), L->bytes, hipMemcpyHostToDevice);
-        } else {
-            std::vector<float2> hf(host.size());
-            for (size_t i = 0; i < host.size(); ++i) hf[i] = make_float2((float)host[i].x, (float)host[i].y);
-            e = hipMemcpy(L->dense, hf.data(), L->bytes, hipMemcpyHostToDevice);
-        }
+        e = hipMemcpy(L->dense, packed.data(), L->bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(L->dense);
             delete L;

@@ -257,7 +257,8 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
     qt_opts o = S->cfg.opts;
     if (dense) {
         DenseInst g;
-        dense_fill_inst(&g, d, p->L->nc, p->n_t, p->n_e, p->L->dense, base + Ly.o_rho0, base + Ly.o_vec,
+        dense_fill_inst(&g, d, p->L->nc, p->L->dense_creal, p->n_t, p->n_e, p->L->dense, base + Ly.o_rho0,
+                        base + Ly.o_vec,
                         (const double *)(base + Ly.o_tlist), (const int32_t *)(base + Ly.o_eptr),
                         (const int32_t *)(base + Ly.o_ecol), (const double2 *)(base + Ly.o_eval),
                         (double2 *)(base + Ly.o_expect), o, S->prec);
