@@ -87,6 +87,51 @@ __global__ void k_csr_reset(const CsrInst *__restrict__ insts, CsrCtl *__restric
 // Control: one workgroup per problem.  step_mode 0 completes a pending starting-step evaluation
 // (phases INIT0 / INIT1) and leaves stepping problems alone; step_mode 1 closes a Runge-Kutta step
 // (phase STEP) and leaves problems still in their starting phases alone.
+// The first XP entries per lane of one expectation operator (entries b + lane + 64 u of
+// ecol / eval / evidx), requested before the state they gather from is known; then the operator's
+// sum formed exactly as csr_expect_range forms it (entry order per lane, the same wave sums).
+template <int XP> struct ExpectPre {
+    int idx[XP];
+    double2 val[XP];
+    __device__ __forceinline__ void load(const CsrInst &I, int b, int e)
+    {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int u = 0; u < XP; ++u) {
+            const int q = b + lane + 64 * u;
+            idx[u] = 0;
+            val[u] = make_double2(0.0, 0.0);
+            if (q < e) {
+                idx[u] = I.evidx[q];
+                val[u] = I.eval[q];
+            }
+        }
+    }
+    template <typename V> __device__ __forceinline__ double2 sum(const CsrInst &I, const V *__restrict__ Y, int b, int e)
+    {
+        const int lane = threadIdx.x & 63;
+        V g[XP];
+#pragma unroll
+        for (int u = 0; u < XP; ++u)
+            if (b + lane + 64 * u < e) g[u] = Y[idx[u]];
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int u = 0; u < XP; ++u)
+            if (b + lane + 64 * u < e) {
+                const double2 r = to_d2(g[u]);
+                sr += val[u].x * r.x - val[u].y * r.y;
+                si += val[u].x * r.y + val[u].y * r.x;
+            }
+        for (int q = b + lane + 64 * XP; q < e; q += 64) {
+            const double2 o = I.eval[q];
+            const double2 r = to_d2(Y[I.evidx[q]]);
+            sr += o.x * r.x - o.y * r.y;
+            si += o.x * r.y + o.y * r.x;
+        }
+        return make_double2(wave_sum(sr), wave_sum(si));
+    }
+};
+
 template <typename T>
 __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int step_mode)
 {
@@ -95,20 +140,19 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
     __shared__ double2 exs[CTL_MAX_EOPS];
     __shared__ double td_t, td_h;  // a time-dependent problem's next evaluations: rows td_first..td_last
     __shared__ int td_first, td_last;
-    // Requests that do not depend on the control record go out with it: this thread's share of the
-    // block partials (column 0; column 1 as well when a steady-state test needs it) and the bounds
-    // of the first expectation operator of this wave.
-    const int status = C->status;
-    const int phase = C->phase;
+    // The whole control record, this thread's share of the block partials (column 0; column 1 as
+    // well when a steady-state test needs it) and the first entries of this wave's expectation
+    // operator (their ranges are in the descriptor) do not depend on one another: one round trip.
+    const CsrCtl c = *C;
+    const int status = c.status;
+    const int phase = c.phase;
     const double part0 = partials_part(I, 0);
     const double part1 = I.steady_tol2 > 0.0 ? partials_part(I, 1) : 0.0;
     const int k0 = threadIdx.x >> 6;
-    int eb0 = 0, ee0 = 0;
-    if (k0 < I.ne) {
-        const int32_t *ep = I.eptr + (size_t)k0 * (I.d + 1);
-        eb0 = ep[0];
-        ee0 = ep[I.d];
-    }
+    const bool own = k0 < I.ne && k0 < CSR_XOPS;
+    const int eb0 = own ? I.xbeg[k0] : 0, ee0 = own ? I.xbeg[k0] + I.xcnt[k0] : 0;
+    ExpectPre<4> pre;
+    pre.load(I, eb0, ee0);
     if (status != ST_RUNNING) return;
     if ((phase == PH_STEP) != (step_mode != 0)) return;
     // after thread 0 has decided: the coefficient rows of the evaluations the next launches make
@@ -167,31 +211,42 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
         return;
     }
     // ---- step control after stage 7 ----
-    const double h = C->h_try;
-    const int p = C->parity;
-    const int land = C->land;
-    const int sidx = C->save_idx;
+    const double h = c.h_try;
+    const int p = c.parity;
+    const int land = c.land;
+    const int sidx = c.save_idx;
     const V *ynew = (const V *)I.Y[1 - p];
     // Everything that only reads is issued before the decision: the error partials, the
-    // candidate's trace and, at a save time, the expectation sums (wasted on a rejection); the
-    // first operator's bounds and the partials were already requested with the control record.
+    // candidate's trace, the save times the update may need and, at a save time, the expectation
+    // sums (wasted on a rejection).  The partials and the first entries of each wave's operator
+    // went out with the control record; the rest goes out together here.
+    const double t_save = I.tlist[sidx];                               // sidx < nt while running
+    const double t_after = sidx + 1 < I.nt ? I.tlist[sidx + 1] : 0.0;  // the next save time
+    V dg{};
+    if (I.renorm && (int)threadIdx.x < I.d) dg = ynew[(size_t)threadIdx.x * (I.d + 1)];
     const bool spec = land && I.ne <= CTL_MAX_EOPS;
     if (spec) {
         for (int k = threadIdx.x >> 6; k < I.ne; k += blockDim.x >> 6) {
-            const double2 sk = k == k0 ? csr_expect_range(I, ynew, eb0, ee0) : csr_expect_one(I, ynew, k);
+            const double2 sk = k == k0 && own ? pre.sum(I, ynew, eb0, ee0) : csr_expect_one(I, ynew, k);
             if ((threadIdx.x & 63) == 0) exs[k] = sk;
         }
     }
     const bool steady = I.steady_tol2 > 0.0;
+    // this thread's share of the trace, summed as csr_trace_part sums it
+    double trp = 0.0;
+    if (I.renorm) {
+        if ((int)threadIdx.x < I.d) trp += (double)dg.x;
+        for (int i = threadIdx.x + blockDim.x; i < I.d; i += blockDim.x) trp += (double)ynew[(size_t)i * I.d + i].x;
+    }
     // one set of barriers for the error, trace and residual sums (each summed as block_sum would);
     // the barriers also publish exs
-    double sums[3] = {part0, I.renorm ? csr_trace_part(I, ynew) : 0.0, part1};
+    double sums[3] = {part0, trp, part1};
     block_sum_n<3>(sums, scr);
     const double err = sqrt(sums[0] / I.n);
     const bool finite = isfinite(err);
     const bool accept = finite && err <= 1.0;
     double scale_new = 1.0;
-    if (I.renorm && accept) scale_new = C->tr0 / sums[1];
+    if (I.renorm && accept) scale_new = c.tr0 / sums[1];
     // steady-state mode: |L y_new|_2 (of the rescaled state) at or below the tolerance ends the solve
     const bool conv = steady && accept && sums[2] * scale_new * scale_new <= I.steady_tol2;
     if (conv) {
@@ -206,46 +261,49 @@ __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int st
         }
     }
     if (threadIdx.x == 0) {
-        C->n_steps += 1;
-        C->n_rhs += 6;
+        // the new record, from the copy read at the start (no other writer in between)
+        CsrCtl n = c;
+        n.n_steps += 1;
+        n.n_rhs += 6;
         if (!finite) {
-            C->status = 6;  // QT_ENONFINITE
+            n.status = 6;  // QT_ENONFINITE
         } else if (accept) {
-            C->n_accept += 1;
-            C->t = land ? I.tlist[sidx] : C->t + h;
-            C->parity = 1 - p;
-            double hn = h * pi_factor(err, C->err_prev);
-            if (C->last_rejected && hn > h) hn = h;
-            C->h = hn;
-            C->err_prev = fmax(err, 1e-4);
-            C->last_rejected = 0;
-            C->scale = scale_new;
+            n.n_accept += 1;
+            n.t = land ? t_save : c.t + h;
+            n.parity = 1 - p;
+            double hn = h * pi_factor(err, c.err_prev);
+            if (c.last_rejected && hn > h) hn = h;
+            n.h = hn;
+            n.err_prev = fmax(err, 1e-4);
+            n.last_rejected = 0;
+            n.scale = scale_new;
             if (conv) {
-                C->save_idx = I.nt;
-                C->status = ST_DONE;
+                n.save_idx = I.nt;
+                n.status = ST_DONE;
             } else if (land) {
-                C->save_idx = sidx + 1;
+                n.save_idx = sidx + 1;
                 // in steady-state mode, passing the last save time unconverged is a failure
-                if (sidx + 1 >= I.nt) C->status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS
+                if (sidx + 1 >= I.nt) n.status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS
             }
         } else {
-            C->n_reject += 1;
-            C->h = h * reject_factor(err);
-            C->last_rejected = 1;
+            n.n_reject += 1;
+            n.h = h * reject_factor(err);
+            n.last_rejected = 1;
         }
-        C->last_err = err;
-        if (C->status == ST_RUNNING) {
-            if (C->n_steps >= I.max_steps) {
-                C->status = 4;  // QT_EMAXSTEPS
-            } else if (C->h < 1e-14 * fmax(1.0, fabs(C->t))) {
-                C->status = 5;  // QT_EDTMIN
+        n.last_err = err;
+        if (n.status == ST_RUNNING) {
+            if (n.n_steps >= I.max_steps) {
+                n.status = 4;  // QT_EMAXSTEPS
+            } else if (n.h < 1e-14 * fmax(1.0, fabs(n.t))) {
+                n.status = 5;  // QT_EDTMIN
             } else {
                 int32_t l2;
-                C->h_try = clip_step(C->t, C->h, I.tlist[C->save_idx], &l2);
-                C->land = l2;
-                td_first = 2, td_last = 7, td_t = C->t, td_h = C->h_try;
+                n.h_try = clip_step(n.t, n.h, n.save_idx == sidx ? t_save : t_after, &l2);
+                n.land = l2;
+                td_first = 2, td_last = 7, td_t = n.t, td_h = n.h_try;
             }
         }
+        *C = n;
     }
     td_next();
 }

@@ -21,6 +21,8 @@ constexpr int TD_SLOTS = 8;       // coefficient rows: two starting-step evaluat
 
 struct CoefDev;
 
+constexpr int CSR_XOPS = 8;  // expectation operators whose entry ranges the descriptor holds
+
 // Solve status kept in device control records (errors use the public QT_E* codes 1..7).
 enum : int32_t {
     ST_RUNNING = 0,
@@ -53,6 +55,10 @@ struct CsrInst {
     const int32_t *evidx; // per e_op entry (i, j): index j*d + i of rho_ji in vec(rho)
     double2 *expect;      // [ne][nt]
     double *partials;     // 2 * nblocks doubles
+    // entries of the first CSR_XOPS expectation operators (offsets into ecol / eval / evidx and
+    // counts), so that the control kernel can request them together with its control record
+    int32_t xbeg[CSR_XOPS];
+    int32_t xcnt[CSR_XOPS];
     // time dependence (nterms = 0: none)
     int32_t nterms;          // time-dependent terms (column tags 1..nterms)
     int32_t pad_td;
@@ -61,6 +67,16 @@ struct CsrInst {
     // steady-state mode (0: off): stop once |L y|_2^2 <= steady_tol2 after an accepted step
     double steady_tol2;
 };
+
+// Host: the entry ranges of the first CSR_XOPS of ne expectation operators, from their
+// instance-local CSR row pointers (ne * (d + 1) of them).
+inline void csr_set_expect_ranges(CsrInst &c, const int32_t *eptr, int ne, int d)
+{
+    for (int k = 0; k < CSR_XOPS; ++k) {
+        c.xbeg[k] = k < ne ? eptr[(size_t)k * (d + 1)] : 0;
+        c.xcnt[k] = k < ne ? eptr[(size_t)k * (d + 1) + d] - c.xbeg[k] : 0;
+    }
+}
 
 struct CsrCtl {
     double t;

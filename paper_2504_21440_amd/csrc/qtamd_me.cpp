@@ -399,6 +399,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
             c.evidx = (const int32_t *)A.at(m.o_evidx);
             c.expect = (double2 *)A.at(m.o_expect);
             c.partials = (double *)A.at(m.o_part);
+            csr_set_expect_ranges(c, m.eptr.data(), m.ne, m.d);
             c.steady_tol2 = steady_tol * steady_tol;
             if (P->td) {
                 // every CSR problem of the plan takes the weighted kernels; a constant one has only

@@ -302,6 +302,7 @@ static qt_status server_submit(qt_server *S, const qt_me_problem *p, uint64_t *t
         c.evidx = (const int32_t *)(base + Ly.o_evidx);
         c.expect = (double2 *)(base + Ly.o_expect);
         c.partials = (double *)(base + Ly.o_part);
+        csr_set_expect_ranges(c, eptr.data(), p->n_e, d);
         CsrCtl t;
         std::memset(&t, 0, sizeof(t));
         t.t = p->tlist[0];
