@@ -131,3 +131,31 @@ def test_single_point_tlist(n):
     out, st, rc = oracle.linear_solve(M, y0, np.linspace(0, 1, n))
     assert rc == 0
     np.testing.assert_array_equal(out[0], y0)
+
+
+def test_step_controller_fixed_point():
+    """The step-size controller (a reading: DOPRI5's PI law h <- h 0.9 err^-0.17 err_prev^0.04) is
+    pinned by its fixed point rather than by its formula.  On y' = i y the rtol-weighted error of a
+    step depends on h alone, err(h) = |E(ih)| / rtol with E(z) = z (b - bhat)^T (I - zA)^-1 1 the
+    stability-function difference of the pair; a constant err is a fixed point of the law only at
+    err* = 0.9^(1 / (0.17 - 0.04)).  So after a short transient every step has the size h* with
+    err(h*) = err*, and a long interval T = N h* takes N steps plus the transient.  A changed safety
+    factor or exponent (0.17 -> 0.2 shifts h* by 3%), a swapped or sign-flipped exponent, or a
+    changed error weighting moves the count far outside the window."""
+    c, A, b, bh = oracle.tableau()
+
+    def stab_diff(z):
+        return z * ((b - bh) @ np.linalg.solve(np.eye(len(b)) - z * A, np.ones(len(b))))
+
+    rtol = 1e-6
+    err_star = 0.9 ** (1.0 / (0.17 - 0.04))
+    lo, hi = 1e-4, 2.0
+    for _ in range(200):  # |E(ih)| grows with h on this range
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if abs(stab_diff(1j * mid)) / rtol < err_star else (lo, mid)
+    h_star = lo
+    for n in (1000, 2000):
+        _, st, rc = oracle.linear_solve(np.array([[1j]]), np.array([1.0 + 0j]), np.array([0.0, n * h_star]),
+                                        abstol=1e-12, reltol=rtol)
+        assert rc == 0 and st["n_reject"] == 0
+        assert n <= st["n_accept"] <= n + 6, (n, st["n_accept"])
