@@ -227,16 +227,52 @@ def section_hbm_spmv(ctx):
     return out
 
 
-def section_sweep(ctx, n=512, nmax_dense=80):
-    """512 driven Kerr cavities, N ~ U{10..80}, mixed precision, one plan.  Cavities with
-    N <= nmax_dense use the dense MFMA form; larger ones (if any) the CSR form, whose launches
-    run concurrently with the dense buckets."""
+def kerr_spectral_estimate(p):
+    """Estimate of the Kerr-cavity Liouvillian's spectral radius: the spread of the levels
+    E_n = -delta n + U n (n - 1) / 2 (the coherent part's largest frequency), plus the damping
+    (kappa N) and the drive (2 F sqrt N)."""
+    n = np.arange(p["N"])
+    lev = -p["delta"] * n + 0.5 * p["U"] * n * (n - 1)
+    return np.ptp(lev) + p["kappa"] * p["N"] + 2.0 * p["F"] * np.sqrt(p["N"])
+
+
+def kerr_dense_cost(p):
+    """A-priori cost of one cavity's dense-form solve, in MFMA instructions.  An explicit
+    Runge-Kutta step is held to h ~ 3 / rho(L), so the right-hand sides grow as t_end rho(L); each
+    costs the MFMA instructions of the operator-form products at the padded size (P and X on every
+    16 x 16 tile, C X^dag on the upper ones, real collapse operator)."""
+    npad = -(-p["N"] // 16) * 16
+    nt, kf = npad // 16, npad // 4
+    return p["t_end"] * kerr_spectral_estimate(p) * (nt * nt * kf * 6 + nt * (nt + 1) // 2 * kf * 2)
+
+
+def sweep_forms(sweep, policy):
+    """Form per cavity.  "dense": all dense.  "n<K>": dense up to N = K, CSR above.  "stiff<f>": dense
+    unless the cavity's estimated dense cost is at least f times the largest one's.  One cavity owns
+    one CU in the dense form, so the stiffest cavities set that form's makespan; the CSR form
+    spreads each of them over the whole chip (about 8 us per right-hand side alone, 13 us beside
+    the dense buckets, against 20 us for one NP = 80 cavity on its CU)."""
+    if policy == "dense":
+        return [qt.FORM_DENSE] * len(sweep)
+    if policy.startswith("n"):
+        k = int(policy[1:])
+        return [qt.FORM_DENSE if p["N"] <= k else qt.FORM_CSR for p in sweep]
+    if policy.startswith("stiff"):
+        f = float(policy[5:])
+        cost = np.array([kerr_dense_cost(p) for p in sweep])
+        return [qt.FORM_DENSE if c < f * cost.max() else qt.FORM_CSR for c in cost]
+    raise ValueError(f"unknown sweep form policy {policy!r}")
+
+
+def section_sweep(ctx, n=512, policy="dense"):
+    """512 driven Kerr cavities, N ~ U{10..80}, mixed precision, one plan.  The policy (sweep_forms)
+    picks each cavity's form; CSR-form launches run concurrently with the dense buckets."""
     sweep = workloads.kerr_sweep(n=n)
+    forms = sweep_forms(sweep, policy)
     probs = []
     Ls = []
-    for p in sweep:
+    for p, form in zip(sweep, forms):
         H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
-        form = qt.FORM_DENSE if p["N"] <= nmax_dense else qt.FORM_CSR
         Lo = qt.Liouvillian(ctx, H, c, form, qt.MIXED)
         Ls.append(Lo)
         rho0 = np.zeros((p["N"], p["N"]), complex)
@@ -266,10 +302,10 @@ def section_sweep(ctx, n=512, nmax_dense=80):
     err = max(float(np.abs(res[q["index"]] - (np.array(q["expect_re"]) + 1j * np.array(q["expect_im"]))).max())
               for q in samples)
     out = {"instances": n, "solves_per_s": n / dt, "ms_per_batch": dt * 1e3, "rhs_per_s": n_rhs / dt,
-           "rtol": o.reltol, "atol": o.abstol, "nmax_dense": nmax_dense,
-           "csr_instances": sum(1 for p in sweep if p["N"] > nmax_dense),
+           "rtol": o.reltol, "atol": o.abstol, "form_policy": policy,
+           "csr_instances": sum(1 for f in forms if f == qt.FORM_CSR),
            "max_err_vs_fp64_oracle_samples": err, "samples_checked": [q["index"] for q in samples]}
-    if nmax_dense >= 80:
+    if policy == "dense":
         # the concurrent run: all 512 dense instances in flight together, flops at the true N
         # (24 N^3 per right-hand side: the 1 + 2K complex products of the operator form, K = 1)
         out.update({"algorithmic_TFLOPs_concurrent": flops / dt / 1e12,
@@ -903,8 +939,10 @@ def main():
     ap.add_argument("--only", default="",
                     help="comma list of extra sections: hbm,sweep,mc,serving,td,sde,sesolve,steady")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sweep-splits", default="80,48,32",
-                    help="largest cutoff N solved in the dense form, one sweep per value (80: all dense)")
+    ap.add_argument("--sweep-forms", default="dense,stiff0.6",
+                    help="form policies of the 512-cavity sweep, one run each: dense (all dense), n<K> (dense up "
+                         "to N = K, CSR above), stiff<f> (CSR for cavities whose estimated dense cost is at least "
+                         "f times the largest)")
     ap.add_argument("--tune-in", default=os.path.join(ROOT, "paper_2504_21440_amd", "tuning", "mi355x.json"),
                     help="autotuner table loaded before measuring (size buckets it lacks are tuned live); "
                          "'' for none")
@@ -944,9 +982,9 @@ def main():
         extra["spmv_hbm_L10"] = section_hbm_spmv(ctx)
     if "sweep" in only:
         log("sweep")
-        for nd in [int(x) for x in args.sweep_splits.split(",") if x]:
-            key = "kerr_sweep_512" if nd >= 80 else f"kerr_sweep_512_dense_to_N{nd}_csr_above"
-            extra[key], _, _ = section_sweep(ctx, nmax_dense=nd)
+        for pol in [x for x in args.sweep_forms.split(",") if x]:
+            key = "kerr_sweep_512" if pol == "dense" else f"kerr_sweep_512_{pol}"
+            extra[key], _, _ = section_sweep(ctx, policy=pol)
     if "mc" in only:
         log("mc")
         extra["mcsolve_L10_10k"] = section_mc(ctx)

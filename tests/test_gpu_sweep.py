@@ -1,5 +1,5 @@
 """Parity of the parameter sweep at full size: 512 driven Kerr cavities (N from 10 to 80) in one
-plan, dense MFMA form, mixed precision, at the tolerances and with the autotuned launch shape the
+plan, mixed precision, at the tolerances, with the form choices and the autotuned launch shape the
 benchmark uses.  Sampled instances are checked one by one against stored FP64 oracle values
 (max |d<a^dag a>| <= 1e-4); every instance is checked for properties that hold at any size."""
 import json
@@ -11,6 +11,7 @@ import pytest
 from oracle import models as om
 import workloads
 import paper_2504_21440_amd as qt
+from bench import sweep_forms
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -23,16 +24,18 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("nmax_dense", [80, 48, 32])
-def test_sweep_512_full_size(ctx, nmax_dense):
-    """nmax_dense: cavities up to this cutoff use the dense form, larger ones the CSR form (the
-    benchmark runs all three splits)."""
-    print(f"[gpu] 512-cavity sweep, mixed, dense up to N={nmax_dense}", flush=True)
+@pytest.mark.parametrize("policy", ["dense", "stiff0.6", "n48", "n32"])
+def test_sweep_512_full_size(ctx, policy):
+    """policy: the benchmark's form choice per cavity -- all dense, the stiffest cavities on the CSR
+    form (sample 193 among them), or dense up to a cutoff N and CSR above."""
+    print(f"[gpu] 512-cavity sweep, mixed, form policy {policy}", flush=True)
     sweep = workloads.kerr_sweep(n=512)
+    forms = sweep_forms(sweep, policy)
+    if policy == "stiff0.6":
+        assert forms[193] == qt.FORM_CSR and sum(f == qt.FORM_CSR for f in forms) == 32
     probs = []
-    for p in sweep:
+    for p, form in zip(sweep, forms):
         H, c = qt.model_kerr(p["N"], p["delta"], p["U"], p["F"], p["kappa"])
-        form = qt.FORM_DENSE if p["N"] <= nmax_dense else qt.FORM_CSR
         probs.append((qt.Liouvillian(ctx, H, c, form, qt.MIXED), om.fock_dm(p["N"], 0),
                       workloads.tlist(p["t_end"], p["nt"]), [om.number(p["N"])]))
     plan = qt.MePlan(ctx, probs, qt.opts(abstol=1e-7, reltol=1e-5, precision=qt.MIXED, autotune=True))
