@@ -249,10 +249,19 @@ qt_status qt_steadystate(qt_ctx *ctx, const qt_liouv *L, const double *rho0, int
 qt_status qt_me_plan_time_rhs(qt_me_plan *plan, int32_t reps, double *ms_per_launch);
 
 /* Measurement: the achievable HBM bandwidth of the context's device, bytes read plus bytes written
- * per second of a streaming copy of `bytes` bytes (16-byte non-temporal loads and stores), repeated
- * `reps` times and timed with HIP events on the context's stream; the reference point for the
- * bandwidth-bound SpMV beside the published peak.  Allocates two buffers of `bytes` for the call. */
+ * per second of a streaming copy of `bytes` bytes (16-byte non-temporal loads and stores, four in
+ * flight per lane, 64 workgroups per compute unit), repeated `reps` times and timed with HIP events
+ * on the context's stream; the reference point for the bandwidth-bound SpMV beside the published
+ * peak.  Allocates two buffers of `bytes` for the call.  Errors: QT_EINVAL for a null argument,
+ * bytes < 16 or reps < 1; QT_EDEVICE for a HIP failure, allocation included. */
 qt_status qt_measure_copy_bandwidth(qt_ctx *ctx, int64_t bytes, int32_t reps, double *gbs);
+
+/* Measurement: as qt_measure_copy_bandwidth for a streaming read of `bytes` bytes (16-byte
+ * non-temporal loads summed in registers, 32 workgroups per compute unit, nothing written back):
+ * bytes read per second, the ceiling for kernels whose traffic is nearly all reads, such as the CSR
+ * SpMV.  Allocates one buffer of `bytes` and 4 bytes per workgroup for the call; errors as
+ * qt_measure_copy_bandwidth. */
+qt_status qt_measure_read_bandwidth(qt_ctx *ctx, int64_t bytes, int32_t reps, double *gbs);
 
 /* Autotuner.  The CSR stage kernels take a launch shape (qt_csr_shape):
  *   lanes_per_row   4, 8 or 16 lanes of a wavefront share a row;

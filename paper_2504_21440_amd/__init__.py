@@ -32,6 +32,7 @@ EXPORTED = [
     "qt_liouv_footprint", "qt_me_plan_workspace", "qt_me_plan_create_ws", "qt_mesolve_ws", "qt_mc_plan_workspace",
     "qt_mc_plan_create_ws", "qt_mcsolve_ws", "qt_server_workspace", "qt_server_create_ws",
     "qt_measure_copy_bandwidth",
+    "qt_measure_read_bandwidth",
 ]
 
 
@@ -443,6 +444,13 @@ def measure_copy_bandwidth(ctx, nbytes=2 << 30, reps=20):
     """GB/s (read + write) of the library's streaming copy kernel (qt_measure_copy_bandwidth)."""
     g = ctypes.c_double()
     _check(lib().qt_measure_copy_bandwidth(ctx.h, ctypes.c_int64(int(nbytes)), int(reps), ctypes.byref(g)))
+    return g.value
+
+
+def measure_read_bandwidth(ctx, nbytes=2 << 30, reps=20):
+    """GB/s read by the library's streaming read kernel (qt_measure_read_bandwidth)."""
+    g = ctypes.c_double()
+    _check(lib().qt_measure_read_bandwidth(ctx.h, ctypes.c_int64(int(nbytes)), int(reps), ctypes.byref(g)))
     return g.value
 
 
