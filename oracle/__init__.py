@@ -8,7 +8,8 @@ operators in ``models.py``.  Each function names the passage of arXiv:2504.21440
 its docstring or in the C source.
 
 Parity notes: every function here is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``
-against closed forms, brute-force matrix exponentials, order conditions or invariants.
+against closed forms, brute-force matrix exponentials, order conditions or invariants, with one
+exception inside the integrator: its starting-step heuristic is parity unpinned (see qtoracle.c).
 """
 import ctypes
 import os

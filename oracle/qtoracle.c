@@ -32,6 +32,13 @@
  * tlist point.  Random numbers come from Philox-4x32-10 (Salmon, Moraes, Dror,
  * Shaw, SC'11), written from that paper's definition.
  *
+ * Test infrastructure only: the tests, the smoke check and the benchmark's CPU
+ * baseline call it; the GPU library never does.
+ *
+ * Parity unpinned: the starting-step heuristic.  A mistake in it changes only
+ * the first few step sizes, which the tolerance tests absorb; no closed form or
+ * invariant fixes its value, so nothing independent of its formula checks it.
+ *
  * Every routine here is a direct transcription of a definition: sparse
  * operator times dense matrix as plain loops, no blocking, no fusion, no
  * reordering beyond what OpenMP row-parallelism implies (each output row is
