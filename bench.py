@@ -8,13 +8,15 @@ loosest tolerance whose result stays within 1e-4 of a tight FP64 oracle solution
 ``value`` = Liouvillian right-hand-side evaluations per second over the timed solves.
 
 The same JSON line carries: the FP64 single-solve path on the same problem, the roofline of the
-fused SpMV-stage kernel (live, HIP events) at this size and at an HBM-sized Liouvillian (L = 10),
-the 512-cavity dense parameter sweep on the matrix cores (batched solves/s, TFLOP/s), the
+fused SpMV-stage kernel (live, HIP events) at this size and at an HBM-sized Liouvillian (L = 10)
+beside the measured copy and read bandwidth, the 512-cavity parameter sweep (batched solves/s: all
+on the matrix cores, with TFLOP/s, and with the costliest cavities routed to the CSR form), the
 quantum-jump ensemble (trajectories/s), the served request stream (p50/p99 latency over a load
 sweep), the time-dependent, stochastic, Schrodinger and steady-state solvers, and the FP64 CPU
 oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--no-cpu]
+                       [--only SECTIONS] [--sweep-forms POLICIES]
 """
 import argparse
 import json
