@@ -270,14 +270,14 @@ template <typename V> __device__ double csr_trace(const CsrInst &I, const V *__r
     return block_sum(csr_trace_part(I, Y), scr);
 }
 
-// This thread's share of one partial column over the instance's blocks, in a fixed order: eight
-// loads in flight per thread, then the strided tail.
-__device__ __forceinline__ double partials_part(const CsrInst &I, int col)
+// Thread v's share of one partial column over the instance's blocks, as a block of T threads forms
+// it, in a fixed order: eight loads in flight per thread, then the strided tail.
+__device__ __forceinline__ double partials_part_at(const CsrInst &I, int col, int v, int T)
 {
-    const int nb = I.nblocks, T = blockDim.x;
+    const int nb = I.nblocks;
     const double *__restrict__ P = I.partials + col;
     double t = 0.0;
-    int k = threadIdx.x;
+    int k = v;
     for (; k + 7 * T < nb; k += 8 * T) {
         double a[8];
 #pragma unroll
@@ -287,6 +287,56 @@ __device__ __forceinline__ double partials_part(const CsrInst &I, int col)
     }
     for (; k < nb; k += T) t += P[2 * k];
     return t;
+}
+
+// This thread's share in the calling block's own order.
+__device__ __forceinline__ double partials_part(const CsrInst &I, int col)
+{
+    return partials_part_at(I, col, threadIdx.x, blockDim.x);
+}
+
+// The step control's two FP64 sums -- the error partials (column 0) and the trace of the candidate
+// y_new (when the problem renormalises) -- formed in a CSR_THREADS block exactly as a CTL_THREADS
+// control block forms them with block_sum_n: each thread takes the virtual threads t and
+// t + CSR_THREADS of the larger block, each virtual wave is reduced with the same butterfly by the
+// physical wave holding its lanes, and the virtual waves' sums are added in order.  So a stage
+// kernel that takes the decision reaches the control kernel's result bitwise.  Every thread of the
+// block receives both sums; scratch: >= 32 doubles of LDS.
+template <typename V>
+__device__ __forceinline__ void ctl_step_sums(const CsrInst &I, const V *__restrict__ ynew, double &err_sum,
+                                              double &tr_sum, double *scratch)
+{
+    static_assert(CTL_THREADS % CSR_THREADS == 0 && CTL_THREADS / 64 <= 16, "virtual control block");
+    constexpr int NV = CTL_THREADS / CSR_THREADS, PW = CSR_THREADS / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double e[NV], t[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int v = threadIdx.x + j * CSR_THREADS;
+        e[j] = partials_part_at(I, 0, v, CTL_THREADS);
+        double trp = 0.0;
+        if (I.renorm) {
+            if (v < I.d) trp += (double)ynew[(size_t)v * (I.d + 1)].x;
+            for (int i = v + CTL_THREADS; i < I.d; i += CTL_THREADS) trp += (double)ynew[(size_t)i * I.d + i].x;
+        }
+        t[j] = wave_sum(trp);
+        e[j] = wave_sum(e[j]);
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            scratch[w + j * PW] = e[j];
+            scratch[16 + w + j * PW] = t[j];
+        }
+    }
+    __syncthreads();
+    double se = 0.0, st = 0.0;
+    for (int i = 0; i < CTL_THREADS / 64; ++i) se += scratch[i];
+    for (int i = 0; i < CTL_THREADS / 64; ++i) st += scratch[16 + i];
+    err_sum = se;
+    tr_sum = st;
+    __syncthreads();
 }
 
 __device__ __forceinline__ double sum_partials(const CsrInst &I, int col, double *scr)

@@ -93,7 +93,7 @@ struct CsrCtl {
     int32_t last_rejected;
     int32_t save_idx;
     int32_t parity;
-    uint32_t arrive;  // blocks arrived at the reduction of the current kernel
+    int32_t pending;  // folded control: a stage 7 ran since this record was decided (its partials wait)
     int32_t pad;
     int64_t n_accept, n_reject, n_steps, n_rhs;
 };

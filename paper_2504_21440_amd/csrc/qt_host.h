@@ -126,11 +126,17 @@ struct CsrLaunch {
     const int32_t *bound = nullptr, *ibound = nullptr;
     const CsrInst *one_host = nullptr;           // host copy of the descriptor when ninst == 1
     bool td = false;  // some problem has a time-dependent Liouvillian: the SpMV kernels weight its terms
+    // One constant problem with runs of 4 stored entries and no steady-state test: the step control
+    // is folded into the next step's stage-2 launch (csr_launch_step).
+    bool fused = false;
 };
 // Resets the control records (and the coefficient rows of problems that have them).
 void csr_launch_reset(const CsrInst *insts, CsrCtl *ctls, int ninst, bool f64, hipStream_t s);
 void csr_launch_init(int which, const CsrLaunch &L, hipStream_t s);
-void csr_launch_step(const CsrLaunch &L, hipStream_t s);
+// One DP5 step: stages 2..7 and the control launch, or, with L.fused and the step's index j within
+// its graph (j >= 0), stage 2 with the previous step's control folded in and stages 3..7 (the
+// control record double-buffered in L.ctls[0..1]; an even number of steps ends in L.ctls[0]).
+void csr_launch_step(const CsrLaunch &L, hipStream_t s, int j = -1);
 void csr_launch_stage3(const CsrLaunch &L, hipStream_t s);
 constexpr int CSR_MIN_ROWS_PER_BLOCK = 16;  // smallest tile (16 lanes per row, one row per group)
 // Looks up the device address of the allocation-free scratch array on `device` (current).

@@ -332,7 +332,7 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
     }
     if (P->ncsr) {
         P->o_cinst = A.reserve(sizeof(CsrInst) * P->ncsr);
-        P->o_cctl = A.reserve(sizeof(CsrCtl) * P->ncsr);
+        P->o_cctl = A.reserve(sizeof(CsrCtl) * (P->ncsr + 1));  // + the second record of a folded control
         P->o_bi = A.reserve(sizeof(int32_t) * max_blocks);
         P->o_br = A.reserve(sizeof(int32_t) * max_blocks);
         P->o_ilist = A.reserve(sizeof(int32_t) * P->ncsr);
@@ -494,6 +494,10 @@ static CsrLaunch csr_args(const qt_me_plan *P, int k = 0)
     L.br = (const int32_t *)P->arena.at(P->o_br) + l.boff;
     L.one_host = P->ncsr == 1 ? &P->h_ci[0] : nullptr;
     L.td = P->td;
+    // the step control folds into stage 2 for one constant problem with runs of 4 stored entries and
+    // no steady-state test, over an even number of steps per graph (the record ends where it began)
+    L.fused = P->ncsr == 1 && !P->td && P->shape.keep == 2 && P->h_ci[0].steady_tol2 <= 0.0 &&
+              P->graph_steps % 2 == 0;
     return L;
 }
 
@@ -503,7 +507,7 @@ static qt_status capture_graph(qt_me_plan *P, int k = 0)
     if (l.gexec) return QT_OK;
     const CsrLaunch L = csr_args(P, k);
     QT_HIP(hipStreamBeginCapture(l.stream, hipStreamCaptureModeThreadLocal));
-    for (int j = 0; j < P->graph_steps; ++j) csr_launch_step(L, l.stream);
+    for (int j = 0; j < P->graph_steps; ++j) csr_launch_step(L, l.stream, j);
     hipError_t e = hipStreamEndCapture(l.stream, &l.graph);
     if (e) return set_error(QT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     QT_HIP(hipGraphInstantiate(&l.gexec, l.graph, nullptr, nullptr, 0));

@@ -430,3 +430,35 @@ def test_autotune_chooses_a_kernel_shape_and_keeps_parity(ctx, tmp_path):
     assert [lpr, rg, xcd, keep] in table.values()
     assert table.get("dense:mixed:np32:waves") == [waves]
     plan.close()
+
+
+@pytest.mark.parametrize("prec", [qt.F64, qt.MIXED])
+def test_folded_step_control_is_bitwise_the_control_kernel(ctx, prec):
+    """One constant problem with runs of 4 stored entries takes its step control inside the next
+    step's stage-2 launch (double-buffered control record); an odd number of steps per graph keeps
+    the separate control launch.  Both take the same decisions in the same reduction order, so the
+    solutions, save times and step counts agree bitwise -- with rejected steps (a first step far too
+    large) and with the trace renormalisation of the mixed path -- and match the oracle."""
+    print(f"[gpu] folded step control vs control kernel, prec={prec}", flush=True)
+    H, cs = qt.model_ising(6, 1.0, 0.8, 0.2)
+    e_ops = [om.site_op(6, 0, om.sigmaz()), om.site_op(6, 3, om.sigmax())]
+    tl = np.linspace(0.0, 3.0, 13)
+    Lo = qt.Liouvillian(ctx, H, cs, qt.FORM_CSR, prec)
+    out = []
+    for spl in (16, 15):  # 16: folded control; 15 (odd): the control kernel
+        o = qt.opts(abstol=1e-8, reltol=1e-6, precision=prec, h0=0.5, steps_per_launch=spl)
+        plan = qt.MePlan(ctx, [(Lo, om.all_up_ket(6), tl, e_ops)], o)
+        plan.set_shape(8, 2, 0, 2)
+        plan.run()
+        plan.run()  # a second run from the start: the record buffers are reset
+        out.append(plan.result(0))
+        plan.close()
+    (ea, sa, _), (eb, sb, _) = out
+    np.testing.assert_array_equal(ea, eb)
+    for k in ("n_accept", "n_reject", "n_rhs", "status"):
+        assert sa[k] == sb[k], (k, sa[k], sb[k])
+    assert sa["status"] == 0 and sa["n_reject"] > 0
+    Ho, co = om.ising(6, 1.0, 0.8, 0.2)
+    ref = oracle.mesolve(Ho, co, om.all_up_ket(6), tl, e_ops, abstol=1e-8, reltol=1e-6, h0=0.5)[0]
+    assert np.abs(ea - ref).max() <= (1e-6 if prec == qt.F64 else 1e-4)
+    Lo.close()
