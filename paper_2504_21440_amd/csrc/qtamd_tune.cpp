@@ -75,6 +75,8 @@ CsrShape csr_default_shape(int64_t rows, double mean_row)
     // small problems: one row per group keeps enough workgroups in flight to fill 256 CUs
     s.rg = rows >= (int64_t(1) << 19) ? 2 : 1;
     s.xcd = 0;
+    // the matrix through the caches, in 16-byte runs of 4 entries where the shape is built so
+    s.keep = csr_shape_supported(s.lpr, s.rg, 2) ? 2 : 1;
     return s;
 }
 
