@@ -83,7 +83,7 @@ typedef struct {
     int32_t precision;
     int32_t form;
     int32_t steps_per_launch; /* RK steps recorded per graph replay (CSR form; 0: 16).  With an even
-                                 count a single constant problem folds its step control into the
+                                 count a plan of one problem folds its step control into the
                                  next step's stage-2 launch (same results, one launch fewer) */
     int32_t autotune;         /* nonzero: tune unseen size buckets at plan creation */
 } qt_opts;

@@ -352,6 +352,79 @@ template <typename V, bool TD> __device__ __forceinline__ const V *td_coefs(cons
     else return nullptr;
 }
 
+// Coefficient rows first..last of a time-dependent problem, by every thread of the block: row 1 at
+// t + h (the second starting-step evaluation, h = h0), row S = 2..7 at t + c_S h (Runge-Kutta stage
+// S); column 0 is the constant part.  The time of each evaluation is formed exactly as the
+// integrator defines it, so the coefficients match the stage the SpMV kernel evaluates.
+template <typename V>
+__device__ void td_rows(const CsrInst &I, int first, int last, double t, double h, int tid, int nthr)
+{
+    const int nt = I.nterms, cols = nt + 1;
+    const int total = (last - first + 1) * cols;
+    for (int idx = tid; idx < total; idx += nthr) {
+        const int slot = first + idx / cols, k = idx % cols;
+        const double c = slot <= 1 ? (double)slot
+                                   : slot == 2 ? DP5::c2
+                                               : slot == 3 ? DP5::c3 : slot == 4 ? DP5::c4 : slot == 5 ? DP5::c5 : 1.0;
+        double2 w = make_double2(1.0, 0.0);
+        if (k > 0) w = coef_value(I.coefs[k - 1], t + c * h);
+        ((V *)I.cstage)[(size_t)slot * cols + k] = from_d2<V>(w);
+    }
+}
+
+// The step decision after stage 7: the new control record from the one the step ran with (c), its
+// error norm, whether it is accepted, the trace scale of the accepted state, steady-state
+// convergence, and the save times it may land on (t_save: the next one, t_after: the one after).
+// Taken by one thread, in the control kernel or in a stage-2 kernel that folds the control in.
+__device__ __forceinline__ CsrCtl step_record(const CsrInst &I, const CsrCtl &c, double err, bool accept,
+                                              double scale_new, bool conv, bool steady, double t_save,
+                                              double t_after)
+{
+    const double h = c.h_try;
+    const int sidx = c.save_idx;
+    CsrCtl n = c;
+    n.n_steps += 1;
+    n.n_rhs += 6;
+    if (!isfinite(err)) {
+        n.status = 6;  // QT_ENONFINITE
+    } else if (accept) {
+        n.n_accept += 1;
+        n.t = c.land ? t_save : c.t + h;
+        n.parity = 1 - c.parity;
+        double hn = h * pi_factor(err, c.err_prev);
+        if (c.last_rejected && hn > h) hn = h;
+        n.h = hn;
+        n.err_prev = fmax(err, 1e-4);
+        n.last_rejected = 0;
+        n.scale = scale_new;
+        if (conv) {
+            n.save_idx = I.nt;
+            n.status = ST_DONE;
+        } else if (c.land) {
+            n.save_idx = sidx + 1;
+            // in steady-state mode, passing the last save time unconverged is a failure
+            if (sidx + 1 >= I.nt) n.status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS
+        }
+    } else {
+        n.n_reject += 1;
+        n.h = h * reject_factor(err);
+        n.last_rejected = 1;
+    }
+    n.last_err = err;
+    if (n.status == ST_RUNNING) {
+        if (n.n_steps >= I.max_steps) {
+            n.status = 4;  // QT_EMAXSTEPS
+        } else if (n.h < 1e-14 * fmax(1.0, fabs(n.t))) {
+            n.status = 5;  // QT_EDTMIN
+        } else {
+            int32_t l2;
+            n.h_try = clip_step(n.t, n.h, n.save_idx == sidx ? t_save : t_after, &l2);
+            n.land = l2;
+        }
+    }
+    return n;
+}
+
 // Per-block row geometry shared by the SpMV kernels.
 template <int LPR, int RG> struct RowSlot {
     int q, r0, row;
@@ -440,7 +513,8 @@ __device__ __forceinline__ void init1_body(const CsrInst &I, const CsrCtl *C, in
 
 // One Runge-Kutta stage S (2..7) of a DP5 step.
 template <typename T, int LPR, int RG, int S, bool KEEP, bool WIDE, bool TD>
-__device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, int row0, int part)
+__device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, int row0, int part,
+                                           const typename vec2<T>::type *cw_row = nullptr)
 {
     using V = typename vec2<T>::type;
     using G = CsrGeom<LPR, RG>;
@@ -479,7 +553,7 @@ __device__ __forceinline__ void stage_body(const CsrInst &I, const CsrCtl *C, in
         }
     }
     V acc[RG];
-    const V *__restrict__ cw = td_coefs<V, TD>(I, S);
+    const V *__restrict__ cw = cw_row ? cw_row : td_coefs<V, TD>(I, S);  // this evaluation's coefficients
     // For a constant L, k1 = L y (first same as last), so the second stage's right-hand side
     // L (y + a21 h k1) = k1 + a21 h (L k1): one gather per entry instead of two.  A constant problem
     // in a plan with time-dependent ones takes the same route through the weighted kernels.
@@ -627,6 +701,66 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_stage(const CsrInst *__rest
 }
 #undef QT_CSR_DISPATCH
 
+// Stage 2 with the previous step's control folded in (one problem, runs of 4 stored entries, no
+// steady-state test).  The step control needs only what the previous launches wrote -- stage 7's
+// partials and the candidate y_new -- so every workgroup takes the decision itself, in the control
+// kernel's reduction order (bitwise the same record), and workgroup 0 writes the record, the
+// save-time expectations and, for a time-dependent problem, the coefficient rows of stages 2..7
+// at the new step; the kernel boundary publishes them, with no device-scope fence.  Each workgroup
+// forms stage 2's own coefficient row in LDS, exactly as the rows are formed.  The record is
+// double-buffered: this launch reads rd and writes wr, stages 3..7 read wr, and the next step's
+// launch swaps them.  rd->pending is 0 right after the starting step (no stage 7 to decide yet).
+// Removes the control launch from every step.
+template <typename T, int LPR, int RG, bool TD>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_stage2_ctl(const CsrInst one, const CsrCtl *__restrict__ rd,
+                                                                CsrCtl *__restrict__ wr)
+{
+    using V = typename vec2<T>::type;
+    const CsrInst &I = one;
+    __shared__ double scr[32];
+    __shared__ CsrCtl nsh;
+    __shared__ V cw2[TD ? TD_MAX_TERMS + 1 : 1];
+    const CsrCtl c = *rd;
+    if (c.status != ST_RUNNING || c.phase != PH_STEP) {  // finished: carry the record forward
+        if (blockIdx.x == 0 && threadIdx.x == 0) *wr = c;
+        return;
+    }
+    if (c.pending) {
+        const int sidx = c.save_idx;
+        const V *ynew = (const V *)I.Y[1 - c.parity];
+        const double t_save = I.tlist[sidx];                               // sidx < nt while running
+        const double t_after = sidx + 1 < I.nt ? I.tlist[sidx + 1] : 0.0;
+        double esum, trsum;
+        ctl_step_sums(I, ynew, esum, trsum, scr);
+        const double err = sqrt(esum / I.n);
+        const bool accept = isfinite(err) && err <= 1.0;
+        double scale_new = 1.0;
+        if (I.renorm && accept) scale_new = c.tr0 / trsum;
+        if (blockIdx.x == 0 && accept && c.land) csr_record_expect(I, ynew, scale_new, sidx);
+        if (threadIdx.x == 0) nsh = step_record(I, c, err, accept, scale_new, false, false, t_save, t_after);
+    } else if (threadIdx.x == 0) {
+        nsh = c;
+    }
+    if (threadIdx.x == 0) nsh.pending = 1;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *wr = nsh;
+    const V *cw = nullptr;  // stage 2's coefficient row (time-dependent problems)
+    if constexpr (TD) {
+        if (c.pending && nsh.status == ST_RUNNING && I.nterms > 0) {
+            // the rows of the new step's evaluations, as the control kernel forms them
+            if (blockIdx.x == 0) td_rows<V>(I, 2, 7, nsh.t, nsh.h_try, threadIdx.x, blockDim.x);
+            if ((int)threadIdx.x <= I.nterms) {
+                double2 w2 = make_double2(1.0, 0.0);
+                if (threadIdx.x > 0) w2 = coef_value(I.coefs[threadIdx.x - 1], nsh.t + DP5::c2 * nsh.h_try);
+                cw2[threadIdx.x] = from_d2<V>(w2);
+            }
+            __syncthreads();
+            cw = cw2;
+        }
+    }
+    stage_body<T, LPR, RG, 2, true, true, TD>(I, &nsh, blockIdx.x * CsrGeom<LPR, RG>::RPB, blockIdx.x, cw);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Launch plumbing
 // ---------------------------------------------------------------------------------------------
@@ -725,7 +859,28 @@ static void launch_spmv_range(const CsrLaunch &L, const CsrArgs &a, int first, i
     }
 }
 
+// Stage 2 with the folded step control for one problem (k_csr_stage2_ctl), reading record rd and
+// writing wr; false when the tile shape has no 16-byte-run kernels (then nothing is launched).
+template <bool TD> static bool launch_stage2_ctl(const CsrLaunch &L, const CsrArgs &a, const CsrCtl *rd, CsrCtl *wr)
+{
+    const dim3 g(a.nblk), t(CSR_THREADS);
+    bool launched = false;
+#define QT_CALL(LP, RR)                                                                                           \
+    {                                                                                                             \
+        if constexpr (csr_wide_shape<LP, RR>()) {                                                                 \
+            if (L.f64) hipLaunchKernelGGL((k_csr_stage2_ctl<double, LP, RR, TD>), g, t, 0, a.s, a.one, rd, wr);   \
+            else hipLaunchKernelGGL((k_csr_stage2_ctl<float, LP, RR, TD>), g, t, 0, a.s, a.one, rd, wr);          \
+            launched = true;                                                                                      \
+        }                                                                                                         \
+    }
+    QT_SHAPE_DISPATCH(L.lpr, L.rg, QT_CALL)
+#undef QT_CALL
+    return launched;
+}
+
 // Defined in kernels_csr_td.hip: the time-dependent SpMV kernels first..last.
 void csr_td_spmv(const CsrLaunch &L, const CsrArgs &a, int first, int last);
+// Defined in kernels_csr_td.hip: launch_stage2_ctl<true>.
+bool csr_td_stage2_ctl(const CsrLaunch &L, const CsrArgs &a, const CsrCtl *rd, CsrCtl *wr);
 
 }  // namespace qt

@@ -8,8 +8,8 @@
 // error contribution (stage 7, reduced per block).  The control kernel -- one workgroup per problem
 // -- sums the block partials in a fixed order (FP64), accepts or rejects, picks the next step size,
 // lands on save times, renormalises the trace (mixed precision) and records Tr(O rho), so the host
-// never sits inside the step loop and no block waits on another.  For one constant problem with
-// runs of 4 stored entries and no steady-state test, that control is folded into the next step's
+// never sits inside the step loop and no block waits on another.  For one problem (constant or
+// time-dependent) with runs of 4 stored entries and no steady-state test, that control is folded into the next step's
 // stage-2 launch instead (k_csr_stage2_ctl): every workgroup takes the same decision from the
 // previous launches' output, so a step is six launches.
 //
@@ -37,26 +37,6 @@
 #include "csr_kernels.h"
 
 namespace qt {
-
-// Coefficient rows first..last of a time-dependent problem, by every thread of the block: row 1 at
-// t + h (the second starting-step evaluation, h = h0), row S = 2..7 at t + c_S h (Runge-Kutta stage
-// S); column 0 is the constant part.  The time of each evaluation is formed exactly as the
-// integrator defines it, so the coefficients match the stage the SpMV kernel evaluates.
-template <typename V>
-__device__ void td_rows(const CsrInst &I, int first, int last, double t, double h, int tid, int nthr)
-{
-    const int nt = I.nterms, cols = nt + 1;
-    const int total = (last - first + 1) * cols;
-    for (int idx = tid; idx < total; idx += nthr) {
-        const int slot = first + idx / cols, k = idx % cols;
-        const double c = slot <= 1 ? (double)slot
-                                   : slot == 2 ? DP5::c2
-                                               : slot == 3 ? DP5::c3 : slot == 4 ? DP5::c4 : slot == 5 ? DP5::c5 : 1.0;
-        double2 w = make_double2(1.0, 0.0);
-        if (k > 0) w = coef_value(I.coefs[k - 1], t + c * h);
-        ((V *)I.cstage)[(size_t)slot * cols + k] = from_d2<V>(w);
-    }
-}
 
 template <typename T>
 __global__ void k_csr_reset(const CsrInst *__restrict__ insts, CsrCtl *__restrict__ ctls, int ninst)
@@ -134,59 +114,6 @@ template <int XP> struct ExpectPre {
         return make_double2(wave_sum(sr), wave_sum(si));
     }
 };
-
-// The step decision after stage 7: the new control record from the one the step ran with (c), its
-// error norm, whether it is accepted, the trace scale of the accepted state, steady-state
-// convergence, and the save times it may land on (t_save: the next one, t_after: the one after).
-// Taken by one thread, in the control kernel or in a stage-2 kernel that folds the control in.
-__device__ __forceinline__ CsrCtl step_record(const CsrInst &I, const CsrCtl &c, double err, bool accept,
-                                              double scale_new, bool conv, bool steady, double t_save,
-                                              double t_after)
-{
-    const double h = c.h_try;
-    const int sidx = c.save_idx;
-    CsrCtl n = c;
-    n.n_steps += 1;
-    n.n_rhs += 6;
-    if (!isfinite(err)) {
-        n.status = 6;  // QT_ENONFINITE
-    } else if (accept) {
-        n.n_accept += 1;
-        n.t = c.land ? t_save : c.t + h;
-        n.parity = 1 - c.parity;
-        double hn = h * pi_factor(err, c.err_prev);
-        if (c.last_rejected && hn > h) hn = h;
-        n.h = hn;
-        n.err_prev = fmax(err, 1e-4);
-        n.last_rejected = 0;
-        n.scale = scale_new;
-        if (conv) {
-            n.save_idx = I.nt;
-            n.status = ST_DONE;
-        } else if (c.land) {
-            n.save_idx = sidx + 1;
-            // in steady-state mode, passing the last save time unconverged is a failure
-            if (sidx + 1 >= I.nt) n.status = steady ? 4 : ST_DONE;  // QT_EMAXSTEPS
-        }
-    } else {
-        n.n_reject += 1;
-        n.h = h * reject_factor(err);
-        n.last_rejected = 1;
-    }
-    n.last_err = err;
-    if (n.status == ST_RUNNING) {
-        if (n.n_steps >= I.max_steps) {
-            n.status = 4;  // QT_EMAXSTEPS
-        } else if (n.h < 1e-14 * fmax(1.0, fabs(n.t))) {
-            n.status = 5;  // QT_EDTMIN
-        } else {
-            int32_t l2;
-            n.h_try = clip_step(n.t, n.h, n.save_idx == sidx ? t_save : t_after, &l2);
-            n.land = l2;
-        }
-    }
-    return n;
-}
 
 template <typename T>
 __device__ __forceinline__ void control_body(const CsrInst &I, CsrCtl *C, int step_mode)
@@ -342,49 +269,6 @@ __global__ __launch_bounds__(CTL_THREADS) void k_csr_control(const CsrInst *__re
     }
 }
 
-// Stage 2 with the previous step's control folded in (one constant problem, runs of 4 stored
-// entries, no steady-state test).  The step control needs only what the previous launches wrote --
-// stage 7's partials and the candidate y_new -- so every workgroup takes the decision itself, in
-// the control kernel's reduction order (bitwise the same record), and workgroup 0 writes the record
-// and the save-time expectations; the kernel boundary publishes them, with no device-scope fence.
-// The record is double-buffered: this launch reads rd and writes wr, stages 3..7 read wr, and the
-// next step's launch swaps them.  rd->pending is 0 right after the starting step (no stage 7 to
-// decide yet).  Removes the control launch from every step.
-template <typename T, int LPR, int RG>
-__global__ __launch_bounds__(CSR_THREADS) void k_csr_stage2_ctl(const CsrInst one, const CsrCtl *__restrict__ rd,
-                                                                CsrCtl *__restrict__ wr)
-{
-    using V = typename vec2<T>::type;
-    const CsrInst &I = one;
-    __shared__ double scr[32];
-    __shared__ CsrCtl nsh;
-    const CsrCtl c = *rd;
-    if (c.status != ST_RUNNING || c.phase != PH_STEP) {  // finished: carry the record forward
-        if (blockIdx.x == 0 && threadIdx.x == 0) *wr = c;
-        return;
-    }
-    if (c.pending) {
-        const int sidx = c.save_idx;
-        const V *ynew = (const V *)I.Y[1 - c.parity];
-        const double t_save = I.tlist[sidx];                               // sidx < nt while running
-        const double t_after = sidx + 1 < I.nt ? I.tlist[sidx + 1] : 0.0;
-        double esum, trsum;
-        ctl_step_sums(I, ynew, esum, trsum, scr);
-        const double err = sqrt(esum / I.n);
-        const bool accept = isfinite(err) && err <= 1.0;
-        double scale_new = 1.0;
-        if (I.renorm && accept) scale_new = c.tr0 / trsum;
-        if (blockIdx.x == 0 && accept && c.land) csr_record_expect(I, ynew, scale_new, sidx);
-        if (threadIdx.x == 0) nsh = step_record(I, c, err, accept, scale_new, false, false, t_save, t_after);
-    } else if (threadIdx.x == 0) {
-        nsh = c;
-    }
-    if (threadIdx.x == 0) nsh.pending = 1;
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) *wr = nsh;
-    stage_body<T, LPR, RG, 2, true, true, false>(I, &nsh, blockIdx.x * CsrGeom<LPR, RG>::RPB, blockIdx.x);
-}
-
 // ---- standalone expectation value (qt_expect) ----
 template <typename T>
 __global__ __launch_bounds__(256) void k_expect(int d, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -482,18 +366,7 @@ void csr_launch_step(const CsrLaunch &L, hipStream_t s, int j)
     if (L.fused && j >= 0 && a.use_one) {
         // step j reads record j % 2 and writes the other (see k_csr_stage2_ctl)
         CsrCtl *rd = L.ctls + (j & 1), *wr = L.ctls + ((j + 1) & 1);
-        const dim3 g(a.nblk), t(CSR_THREADS);
-        bool launched = false;
-#define QT_CALL(LP, RR)                                                                                       \
-        {                                                                                                     \
-            if constexpr (csr_wide_shape<LP, RR>()) {                                                         \
-                if (L.f64) hipLaunchKernelGGL((k_csr_stage2_ctl<double, LP, RR>), g, t, 0, s, a.one, rd, wr); \
-                else hipLaunchKernelGGL((k_csr_stage2_ctl<float, LP, RR>), g, t, 0, s, a.one, rd, wr);        \
-                launched = true;                                                                              \
-            }                                                                                                 \
-        }
-        QT_SHAPE_DISPATCH(L.lpr, L.rg, QT_CALL)
-#undef QT_CALL
+        const bool launched = L.td ? csr_td_stage2_ctl(L, a, rd, wr) : launch_stage2_ctl<false>(L, a, rd, wr);
         if (launched) {
             a.ctls = wr;
             spmv(L, a, 3, 7);

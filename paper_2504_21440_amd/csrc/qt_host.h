@@ -126,7 +126,7 @@ struct CsrLaunch {
     const int32_t *bound = nullptr, *ibound = nullptr;
     const CsrInst *one_host = nullptr;           // host copy of the descriptor when ninst == 1
     bool td = false;  // some problem has a time-dependent Liouvillian: the SpMV kernels weight its terms
-    // One constant problem with runs of 4 stored entries and no steady-state test: the step control
+    // One problem with runs of 4 stored entries and no steady-state test: the step control
     // is folded into the next step's stage-2 launch (csr_launch_step).
     bool fused = false;
 };

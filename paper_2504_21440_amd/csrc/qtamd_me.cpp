@@ -494,10 +494,9 @@ static CsrLaunch csr_args(const qt_me_plan *P, int k = 0)
     L.br = (const int32_t *)P->arena.at(P->o_br) + l.boff;
     L.one_host = P->ncsr == 1 ? &P->h_ci[0] : nullptr;
     L.td = P->td;
-    // the step control folds into stage 2 for one constant problem with runs of 4 stored entries and
-    // no steady-state test, over an even number of steps per graph (the record ends where it began)
-    L.fused = P->ncsr == 1 && !P->td && P->shape.keep == 2 && P->h_ci[0].steady_tol2 <= 0.0 &&
-              P->graph_steps % 2 == 0;
+    // the step control folds into stage 2 for one problem with runs of 4 stored entries and no
+    // steady-state test, over an even number of steps per graph (the record ends where it began)
+    L.fused = P->ncsr == 1 && P->shape.keep == 2 && P->h_ci[0].steady_tol2 <= 0.0 && P->graph_steps % 2 == 0;
     return L;
 }
 

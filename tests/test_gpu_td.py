@@ -350,3 +350,32 @@ def test_td_ensemble_matches_td_master_equation(ctx):
     z = np.abs(mean - me)[1:] / np.maximum(se[1:], 1e-12)
     print(f"[gpu]   max z = {z.max():.2f}", flush=True)
     assert (z > 3).sum() <= 1 and z.max() < 4.5
+
+
+@pytest.mark.parametrize("prec", [qt.F64, qt.MIXED])
+def test_td_folded_step_control_is_bitwise_the_control_kernel(ctx, prec):
+    """A time-dependent problem folds its step control, and the coefficient rows of the next step,
+    into stage 2 at an even number of steps per graph; an odd number keeps the control kernel.
+    Solutions, save times and step counts agree bitwise (with rejected steps from a first step far
+    too large), and match the oracle."""
+    print(f"[gpu] TD folded step control, prec={prec}", flush=True)
+    p, H0, terms, c, e_ops = _cavity()
+    tl = workloads.tlist(p["t_end"], p["nt"])
+    L = qt.Liouvillian(ctx, H0, c, qt.FORM_CSR, prec, h_terms=terms)
+    out = []
+    for spl in (16, 15):
+        o = qt.opts(precision=prec, h0=2.0, steps_per_launch=spl)
+        plan = qt.MePlan(ctx, [(L, om.fock_dm(p["N"], 0), tl, e_ops)], o)
+        plan.set_shape(8, 1, 0, 2)
+        plan.run()
+        plan.run()
+        out.append(plan.result(0))
+        plan.close()
+    (ea, sa, _), (eb, sb, _) = out
+    np.testing.assert_array_equal(ea, eb)
+    for k in ("n_accept", "n_reject", "n_rhs", "status"):
+        assert sa[k] == sb[k], (k, sa[k], sb[k])
+    assert sa["status"] == 0 and sa["n_reject"] > 0
+    ref = oracle.mesolve_td(H0, terms, c, om.fock_dm(p["N"], 0), tl, e_ops, h0=2.0)[0]
+    assert np.abs(ea - ref).max() <= (1e-6 if prec == qt.F64 else 1e-4)
+    L.close()
