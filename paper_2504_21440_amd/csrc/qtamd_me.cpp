@@ -476,6 +476,14 @@ qt_status me_plan_create(Ctx *ctx, int32_t n, const qt_me_problem *probs, const 
 }
 
 // Launch configuration of lane `k` of the plan's CSR problems at the current shape.
+// Whether a step's control folds into the next step's stage-2 launch at matrix load kind keep: one
+// problem stored in runs of 4 entries (keep 2) with no steady-state test, over an even number of
+// steps per graph (the double-buffered record ends where it began).
+static bool folds_control(const qt_me_plan *P, int keep)
+{
+    return P->ncsr == 1 && keep == 2 && P->h_ci[0].steady_tol2 <= 0.0 && P->graph_steps % 2 == 0;
+}
+
 static CsrLaunch csr_args(const qt_me_plan *P, int k = 0)
 {
     const auto &l = P->lanes[k];
@@ -494,9 +502,7 @@ static CsrLaunch csr_args(const qt_me_plan *P, int k = 0)
     L.br = (const int32_t *)P->arena.at(P->o_br) + l.boff;
     L.one_host = P->ncsr == 1 ? &P->h_ci[0] : nullptr;
     L.td = P->td;
-    // the step control folds into stage 2 for one problem with runs of 4 stored entries and no
-    // steady-state test, over an even number of steps per graph (the record ends where it began)
-    L.fused = P->ncsr == 1 && P->shape.keep == 2 && P->h_ci[0].steady_tol2 <= 0.0 && P->graph_steps % 2 == 0;
+    L.fused = folds_control(P, P->shape.keep);
     return L;
 }
 
@@ -710,7 +716,11 @@ qt_status me_plan_autotune(qt_me_plan *P, int32_t reps)
         const int nc = csr_candidates(cand, 64, P->ncsr == 1);
         CsrShape best = P->shape;
         double best_ms = 1e300;
+        // The stage timing below cannot see what folding the step control into stage 2 saves (one
+        // launch per step), so a plan that can fold chooses among the shapes that fold.
+        const bool fold = folds_control(P, 2);
         for (int k = 0; k < nc; ++k) {
+            if (fold && !folds_control(P, cand[k].keep)) continue;
             qt_status st = apply_shape(P, cand[k]);
             if (st) return st;
             double ms;
